@@ -1,0 +1,127 @@
+"""Workload definitions: event-sample recipes, cut chains and reconstruction
+parameters, as plain data.
+
+Nothing here computes anything of the method; both the product path (through
+its binding) and the oracle (through its own wrapper) translate these
+descriptions into their own structures.
+
+Cut chains follow the dileptonic selections of the paper (section 4, the
+18-cut ttH pipeline ending in the kinematic reconstruction; section 6.1, the
+HL-LHC selection: isolated opposite-sign leptons, missing transverse energy
+above 30 GeV, jet pseudorapidity regions, M_ll above 40 GeV).  Energies are in
+GeV throughout (the paper's example code uses MeV).
+"""
+
+import copy
+
+# Cut kinds understood by both implementations.  Parameters:
+#   LEP_N_OS      f=[pt_min, abs_eta_max]               i=[n_exact, need_opposite_sign]
+#   JET_N_MIN     f=[pt_min, abs_eta_max]               i=[n_min]
+#   BTAG_N_MIN    f=[pt_min, abs_eta_max, btag_min]     i=[n_min]
+#   BTAG_N_EQ     f=[pt_min, abs_eta_max, btag_min]     i=[n_exact]
+#   MET_MIN       f=[met_min]
+#   MLL_MIN       f=[lep_pt_min, lep_abs_eta_max, mll_min]
+#   FWD_JET_VETO  f=[pt_min, abs_eta_lo, abs_eta_hi]    (fails on any jet in [lo, hi))
+#   LEP_ISO       f=[lep_pt_min, lep_abs_eta_max, jet_pt_min, jet_abs_eta_max, dr_min]
+#   RECO          marker for the kinematic reconstruction (last cut)
+CUT_KINDS = ("LEP_N_OS", "JET_N_MIN", "BTAG_N_MIN", "BTAG_N_EQ", "MET_MIN",
+             "MLL_MIN", "FWD_JET_VETO", "LEP_ISO", "RECO")
+
+
+def _cut(name, kind, f=(), i=(), deps=()):
+    return {"name": name, "kind": kind, "f": list(f), "i": list(i), "deps": list(deps)}
+
+
+def chain_dilepton():
+    """Four-cut dileptonic chain plus the reconstruction."""
+    return [
+        _cut("LEP2OS", "LEP_N_OS", [20.0, 2.5], [2, 1]),
+        _cut("JETS2", "JET_N_MIN", [25.0, 2.5], [2]),
+        _cut("BTAG1", "BTAG_N_MIN", [25.0, 2.5, 0.5], [1]),
+        _cut("MET30", "MET_MIN", [30.0]),
+        _cut("RECO", "RECO", deps=["LEP2OS", "JETS2", "BTAG1", "MET30"]),
+    ]
+
+
+def chain_tth8():
+    """Eight-cut ttH-like chain (user order as written)."""
+    return [
+        _cut("LEP2OS", "LEP_N_OS", [20.0, 2.5], [2, 1]),
+        _cut("JETS4", "JET_N_MIN", [25.0, 2.5], [4]),
+        _cut("BTAG3", "BTAG_N_MIN", [25.0, 2.5, 0.5], [3]),
+        _cut("MET30", "MET_MIN", [30.0]),
+        _cut("MLL40", "MLL_MIN", [20.0, 2.5, 40.0], deps=["LEP2OS"]),
+        _cut("FWDVETO", "FWD_JET_VETO", [25.0, 2.5, 3.5]),
+        _cut("LEPISO", "LEP_ISO", [20.0, 2.5, 25.0, 2.5, 0.4], deps=["LEP2OS"]),
+        _cut("RECO", "RECO", deps=["LEP2OS", "JETS4", "BTAG3", "MET30",
+                                   "MLL40", "FWDVETO", "LEPISO"]),
+    ]
+
+
+RECO_DEFAULTS = {
+    "m_t": 172.5, "m_w": 80.4, "lambda_pt": 100.0,
+    "jet_a": 1.0, "jet_c": 0.05, "lep_sigma": 0.02, "met_sigma": 10.0,
+    "lep_pt_min": 20.0, "lep_eta_max": 2.5,
+    "jet_pt_min": 25.0, "jet_eta_max": 2.5, "btag_min": 0.5,
+    "seed": 0, "smear": 0, "n_var": 1,
+    "pair_mode": "BTAG_FILL", "max_cands": 12, "want_mbb": 0,
+}
+
+# Sample recipes.  kind: "ttbar" (dileptonic ttbar, optional background
+# fraction) or "tth" (ttbar + H->bb).  n_extra_max: extra light jets drawn
+# uniformly from 0..n_extra_max.  var_mode: "uniform" or "loguniform1024".
+CONFIGS = {
+    "ttbar10k": {
+        "index": 0, "n_events": 10_000, "kind": "ttbar", "n_extra_max": 4,
+        "bkg_frac": 0.0, "bkg_jet_max": 6, "chain": "dilepton",
+        "reco": {"smear": 0, "n_var": 1},
+        "desc": "10k dileptonic ttbar, 2-6 jets, no smearing, V=1",
+    },
+    "ttbar1M_v64": {
+        "index": 1, "n_events": 1_000_000, "kind": "ttbar", "n_extra_max": 8,
+        "bkg_frac": 0.2, "bkg_jet_max": 10, "chain": "dilepton",
+        "reco": {"smear": 1, "n_var": 64},
+        "desc": "1M events, 2-10 jets, 20% background, 64 smeared variations",
+    },
+    "tth4M_v256": {
+        "index": 2, "n_events": 4_000_000, "kind": "tth", "n_extra_max": 6,
+        "bkg_frac": 0.0, "bkg_jet_max": 10, "chain": "tth8",
+        "reco": {"smear": 1, "n_var": 256, "want_mbb": 1},
+        "desc": "4M ttH-like events, 4-10 jets, >=3 b-tags, 256 variations, 8 cuts",
+    },
+    "stress2M_heavytail": {
+        "index": 3, "n_events": 2_000_000, "kind": "ttbar", "n_extra_max": 10,
+        "bkg_frac": 0.2, "bkg_jet_max": 12, "chain": "dilepton",
+        "var_mode": "loguniform1024",
+        "reco": {"smear": 1, "n_var": 0},
+        "desc": "2M events, 2-12 jets, variations log-uniform in 1..1024",
+    },
+}
+
+
+def config(name):
+    c = copy.deepcopy(CONFIGS[name])
+    c["name"] = name
+    c["seed"] = 1000 + c["index"]
+    reco = dict(RECO_DEFAULTS)
+    reco.update(c["reco"])
+    reco["seed"] = c["seed"]
+    c["reco"] = reco
+    c["cuts"] = {"dilepton": chain_dilepton, "tth8": chain_tth8}[c["chain"]]()
+    return c
+
+
+def default_order(cuts):
+    return list(range(len(cuts)))
+
+
+def dep_masks(cuts):
+    """Dependency bit masks: bit j set in entry k means cut j must precede cut k."""
+    idx = {c["name"]: k for k, c in enumerate(cuts)}
+    out = []
+    for c in cuts:
+        m = 0
+        for d in c["deps"]:
+            m |= 1 << idx[d]
+        out.append(m)
+    return out

@@ -1,0 +1,247 @@
+"""ctypes wrapper around the FP64 CPU oracle (oracle/hf_oracle.c).
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, the smoke check and the
+benchmark's CPU-baseline leg, never by the product path.  It shares no code
+with the GPU library; it translates the plain-data workload descriptions of
+hfgen.configs into its own structures.
+"""
+
+import ctypes as C
+import os
+import subprocess
+import time
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhf_oracle.so")
+SRC_PATH = os.path.join(_HERE, "hf_oracle.c")
+
+KIND = {"LEP_N_OS": 0, "JET_N_MIN": 1, "BTAG_N_MIN": 2, "BTAG_N_EQ": 3, "MET_MIN": 4,
+        "MLL_MIN": 5, "FWD_JET_VETO": 6, "LEP_ISO": 7, "RECO": 8}
+PAIR_MODE = {"BTAG_FILL": 0, "ALL_JETS": 1}
+NOSOL = -9999.0
+
+
+def build(force=True):
+    """Compile the oracle: plain C, IEEE double, no contraction, OpenMP."""
+    if not force and os.path.exists(LIB_PATH) and os.path.getmtime(LIB_PATH) >= os.path.getmtime(SRC_PATH):
+        return LIB_PATH
+    tmp = LIB_PATH + ".tmp"
+    cmd = ["gcc", "-O2", "-std=c11", "-D_DEFAULT_SOURCE", "-fno-fast-math", "-ffp-contract=off",
+           "-fopenmp", "-fPIC", "-shared", "-Wall", "-o", tmp, SRC_PATH, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+class Events(C.Structure):
+    _fields_ = [("n", C.c_int64), ("index_base", C.c_int64),
+                ("lep_off", C.c_void_p), ("jet_off", C.c_void_p)] + \
+               [(k, C.c_void_p) for k in ("lep_pt", "lep_eta", "lep_phi", "lep_e", "lep_q",
+                                          "jet_pt", "jet_eta", "jet_phi", "jet_e", "jet_btag",
+                                          "met_x", "met_y", "n_var")]
+
+
+class Cut(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("pad", C.c_int32), ("f", C.c_double * 8),
+                ("i", C.c_int32 * 4), ("dep_mask", C.c_uint64)]
+
+
+class RecoParams(C.Structure):
+    _fields_ = [(k, C.c_double) for k in ("m_t", "m_w", "lambda_pt", "jet_a", "jet_c", "lep_sigma",
+                                          "met_sigma", "lep_pt_min", "lep_eta_max", "jet_pt_min",
+                                          "jet_eta_max", "btag_min")] + \
+               [("seed", C.c_uint64)] + \
+               [(k, C.c_int32) for k in ("smear", "n_var_uniform", "pair_mode", "max_cands",
+                                         "want_mbb", "pad")]
+
+
+class RecoOut(C.Structure):
+    _fields_ = [(k, C.c_void_p) for k in ("has_sol", "n_sol", "best_v", "best_i", "best_j", "nu",
+                                          "nubar", "m_t", "m_tbar", "m_wp", "m_wm", "logw", "m_bb")]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        L = C.CDLL(LIB_PATH)
+        P = C.c_void_p
+        L.orc_philox4x32_10.argtypes = [P, P, P]
+        L.orc_gauss.argtypes = [C.c_uint64, C.c_uint64, C.c_uint32, C.c_uint32]
+        L.orc_gauss.restype = C.c_double
+        L.orc_select.argtypes = [C.POINTER(Events), P, C.c_int, P, P, P, P]
+        L.orc_compact.argtypes = [P, C.c_int64, C.c_int64, P, P]
+        L.orc_compact.restype = C.c_int64
+        L.orc_reorder.argtypes = [P, P, P, P, C.c_int, P]
+        L.orc_real_roots.argtypes = [P, P]
+        L.orc_solve_pairing.argtypes = [P, P, P, P, C.c_double, C.c_double, C.c_double, C.c_double, P]
+        L.orc_pairing_quartic.argtypes = [P, P, P, P, C.c_double, C.c_double, C.c_double, C.c_double, P]
+        L.orc_ttbar_reco.argtypes = [C.POINTER(Events), P, C.c_int64, C.POINTER(RecoParams),
+                                     C.POINTER(RecoOut), C.c_int]
+        L.orc_ttbar_reco.restype = C.c_int64
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data
+
+
+class _EventsHolder:
+    """Widens a float32 SoA sample to FP64 (exact) and keeps the arrays alive."""
+
+    def __init__(self, ev, index_base=0, fp64=False):
+        src = ev["fp64"] if fp64 else ev
+        self.arrs = {}
+        for k in ("lep_pt", "lep_eta", "lep_phi", "lep_e", "lep_q", "jet_pt", "jet_eta", "jet_phi",
+                  "jet_e", "jet_btag", "met_x", "met_y"):
+            self.arrs[k] = np.ascontiguousarray(src[k] if k in src else ev[k], dtype=np.float64)
+        self.arrs["lep_off"] = np.ascontiguousarray(ev["lep_off"], dtype=np.uint32)
+        self.arrs["jet_off"] = np.ascontiguousarray(ev["jet_off"], dtype=np.uint32)
+        nv = ev.get("n_var")
+        self.arrs["n_var"] = None if nv is None else np.ascontiguousarray(nv, dtype=np.int32)
+        self.s = Events(n=int(ev["n"]), index_base=int(index_base),
+                        **{k: _ptr(v) for k, v in self.arrs.items()})
+
+
+def _cut_array(cuts):
+    from hfgen.configs import dep_masks
+    deps = dep_masks(cuts)
+    arr = (Cut * len(cuts))()
+    for k, c in enumerate(cuts):
+        arr[k].kind = KIND[c["kind"]]
+        for j, v in enumerate(c["f"]):
+            # thresholds are float32 values on the product side; use the same values
+            arr[k].f[j] = float(np.float32(v))
+        for j, v in enumerate(c["i"]):
+            arr[k].i[j] = int(v)
+        arr[k].dep_mask = deps[k]
+    return arr
+
+
+def select(ev, cuts, order, index_base=0):
+    """Returns (survive uint8[n], reached uint64[n_cuts], passed uint64[n_cuts])."""
+    h = _EventsHolder(ev, index_base)
+    n = int(ev["n"])
+    surv = np.zeros(n, dtype=np.uint8)
+    reached = np.zeros(len(cuts), dtype=np.uint64)
+    passed = np.zeros(len(cuts), dtype=np.uint64)
+    order = np.ascontiguousarray(order, dtype=np.int32)
+    arr = _cut_array(cuts)
+    lib().orc_select(C.byref(h.s), C.cast(arr, C.c_void_p), len(cuts), _ptr(order), _ptr(surv),
+                     _ptr(reached), _ptr(passed))
+    return surv, reached, passed
+
+
+def compact(mask, index_base=0, mapping=None):
+    mask = np.ascontiguousarray(mask, dtype=np.uint8)
+    idx = np.zeros(max(1, mask.size), dtype=np.int32)
+    m = None if mapping is None else np.ascontiguousarray(mapping, dtype=np.int32)
+    cnt = lib().orc_compact(_ptr(mask), mask.size, int(index_base), _ptr(m), _ptr(idx))
+    return idx[:cnt].copy()
+
+
+def reorder(reached, passed, cost, dep_mask):
+    n = len(reached)
+    r = np.ascontiguousarray(reached, dtype=np.uint64)
+    p = np.ascontiguousarray(passed, dtype=np.uint64)
+    c = np.ascontiguousarray(cost, dtype=np.uint64)
+    d = np.ascontiguousarray(dep_mask, dtype=np.uint64)
+    out = np.zeros(n, dtype=np.int32)
+    rc = lib().orc_reorder(_ptr(r), _ptr(p), _ptr(c), _ptr(d), n, _ptr(out))
+    if rc != 0:
+        raise ValueError("cyclic cut dependencies")
+    return out
+
+
+def philox(ctr, key):
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    o = np.zeros(4, dtype=np.uint32)
+    lib().orc_philox4x32_10(_ptr(c), _ptr(k), _ptr(o))
+    return o
+
+
+def gauss(seed, g, v, slot):
+    return lib().orc_gauss(int(seed), int(g), int(v), int(slot))
+
+
+def real_roots(c):
+    """Sign-changing real roots of c0 + c1 t + ... + c4 t^4 (ascending)."""
+    cc = np.zeros(5)
+    cc[:len(c)] = c
+    out = np.zeros(4)
+    n = lib().orc_real_roots(_ptr(cc), _ptr(out))
+    return out[:n].copy()
+
+
+def _v4(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def solve_pairing(lp, b, lm, bb, metx, mety, mt=172.5, mw=80.4):
+    """Accepted solutions for one pairing; 4-vectors as (E, px, py, pz).
+    Returns array [k, 8]: nu (x, y, z, E), nubar (x, y, z, E)."""
+    out = np.zeros(32)
+    n = lib().orc_solve_pairing(_ptr(_v4(lp)), _ptr(_v4(b)), _ptr(_v4(lm)), _ptr(_v4(bb)),
+                                float(metx), float(mety), float(mt), float(mw), _ptr(out))
+    return out[:8 * n].reshape(n, 8).copy()
+
+
+def pairing_quartic(lp, b, lm, bb, metx, mety, mt=172.5, mw=80.4):
+    out = np.zeros(5)
+    ok = lib().orc_pairing_quartic(_ptr(_v4(lp)), _ptr(_v4(b)), _ptr(_v4(lm)), _ptr(_v4(bb)),
+                                   float(metx), float(mety), float(mt), float(mw), _ptr(out))
+    return out if ok else None
+
+
+def reco_params(reco):
+    return RecoParams(
+        m_t=reco["m_t"], m_w=reco["m_w"], lambda_pt=reco["lambda_pt"], jet_a=reco["jet_a"],
+        jet_c=reco["jet_c"], lep_sigma=reco["lep_sigma"], met_sigma=reco["met_sigma"],
+        lep_pt_min=float(np.float32(reco["lep_pt_min"])), lep_eta_max=float(np.float32(reco["lep_eta_max"])),
+        jet_pt_min=float(np.float32(reco["jet_pt_min"])), jet_eta_max=float(np.float32(reco["jet_eta_max"])),
+        btag_min=float(np.float32(reco["btag_min"])), seed=int(reco["seed"]), smear=int(reco["smear"]),
+        n_var_uniform=int(reco["n_var"]), pair_mode=PAIR_MODE[reco["pair_mode"]],
+        max_cands=int(reco["max_cands"]), want_mbb=int(reco["want_mbb"]), pad=0)
+
+
+def ttbar_reco(ev, idx, reco, index_base=0, n_threads=0, fp64=False):
+    """Reconstruct compacted events (global ids idx).  Returns a dict of arrays."""
+    h = _EventsHolder(ev, index_base, fp64=fp64)
+    idx = np.ascontiguousarray(idx, dtype=np.int32)
+    S = idx.size
+    m = max(S, 1)
+    o = {"has_sol": np.zeros(m, np.uint8), "n_sol": np.zeros(m, np.int32), "best_v": np.zeros(m, np.int32),
+         "best_i": np.zeros(m, np.int16), "best_j": np.zeros(m, np.int16), "nu": np.zeros((m, 3)),
+         "nubar": np.zeros((m, 3)), "m_t": np.zeros(m), "m_tbar": np.zeros(m), "m_wp": np.zeros(m),
+         "m_wm": np.zeros(m), "logw": np.zeros(m), "m_bb": np.zeros(m)}
+    ro = RecoOut(**{k: _ptr(v) for k, v in o.items()})
+    prm = reco_params(reco)
+    npass = lib().orc_ttbar_reco(C.byref(h.s), _ptr(idx), S, C.byref(prm), C.byref(ro), int(n_threads))
+    res = {k: v[:S].copy() for k, v in o.items()}
+    res["n_pass"] = int(npass)
+    return res
+
+
+def run_chain(ev, cuts, reco, order=None, index_base=0, n_threads=0):
+    """select -> compact -> reco -> compact for one chunk; returns a dict."""
+    if order is None:
+        order = list(range(len(cuts)))
+    t0 = time.perf_counter()
+    surv, reached, passed = select(ev, cuts, order, index_base)
+    idx = compact(surv, index_base)
+    rec = ttbar_reco(ev, idx, reco, index_base, n_threads)
+    final = compact(rec["has_sol"], 0, idx)
+    rid = [k for k, c in enumerate(cuts) if c["kind"] == "RECO"]
+    if rid:
+        reached[rid[0]] += np.uint64(idx.size)
+        passed[rid[0]] += np.uint64(final.size)
+    return {"survive": surv, "reached": reached, "passed": passed, "idx": idx, "reco": rec,
+            "final": final, "seconds": time.perf_counter() - t0}
