@@ -1,0 +1,270 @@
+/*
+ * hf.h -- C ABI of the MI355X (gfx950) hot path of a HEP-Frame-style
+ * analysis: a chain of per-event cuts with adaptive ordering, on-device
+ * compaction of the surviving events, and the dileptonic ttbar kinematic
+ * reconstruction that ends the chain.
+ *
+ * Paper: A. Pereira, A. Onofre, A. Proenca, "HEP-Frame: an Efficient Tool for
+ * Big Data Applications at the LHC", arXiv:2211.14346.
+ *
+ * Conventions for every entry point:
+ *   - Pointers are DEVICE pointers unless their name starts with h_ (host).
+ *     Structures passed by pointer (hf_events_t, hf_reco_params_t,
+ *     hf_reco_out_t, hf_cut_t arrays) live in host memory and are read before
+ *     the call returns; the device pointers they hold must stay valid until
+ *     the queued work has finished.
+ *   - Device work is queued on the given stream and the call returns without
+ *     waiting.  No entry point allocates, frees or synchronises; scratch
+ *     memory is passed in as a workspace whose size the matching
+ *     *_workspace_size query reports.  Every entry point may be recorded into
+ *     a HIP graph (no memset nodes, no host reads of device data).
+ *   - The caller owns all memory.  Concurrent calls that share outputs,
+ *     counters or workspace race.
+ *   - Return value: HF_OK, or a negative HF_ERR_* code; no work is queued
+ *     when an error is returned.  hf_last_error() gives a message for the
+ *     last error raised on the calling host thread.
+ *   - Energies and momenta are in GeV.  Events are stored as structure of
+ *     arrays: per-object float32 columns in a ragged (CSR) layout, objects of
+ *     each event sorted by descending pT.
+ */
+#ifndef HF_H
+#define HF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HF_OK 0
+#define HF_ERR_INVAL (-1)       /* malformed argument (null pointer, size, enum) */
+#define HF_ERR_CAPACITY (-2)    /* workspace or output smaller than required */
+#define HF_ERR_DEVICE (-3)      /* the HIP runtime reported an error */
+#define HF_ERR_UNSUPPORTED (-4) /* valid request this build does not implement */
+
+#define HF_MAX_CUTS 32
+#define HF_MAX_CANDS 12
+#define HF_NO_SOLUTION (-9999.0) /* value of every float output without a solution */
+
+/* One chunk of events (section 3: the per-event variables the cuts read).
+ * Objects of event e are [lep_off[e], lep_off[e+1]) and
+ * [jet_off[e], jet_off[e+1]) in the column arrays.  lep_q is the charge
+ * (+1 or -1); jet_btag is the b-tag discriminant (tagged when above the
+ * threshold).  n_var optionally gives a per-event variation count (1..65535);
+ * when NULL every event uses hf_reco_params_t.n_var_uniform.  index_base is
+ * the global id of event 0: it keys the random streams and is added to the
+ * compaction output.  Capacity limits: n < 2^31, index_base + n < 2^31. */
+typedef struct hf_events {
+    int64_t n;
+    int64_t index_base;
+    const uint32_t *lep_off, *jet_off; /* [n+1] */
+    const float *lep_pt, *lep_eta, *lep_phi, *lep_e, *lep_q;
+    const float *jet_pt, *jet_eta, *jet_phi, *jet_e, *jet_btag;
+    const float *met_x, *met_y; /* [n] */
+    const uint16_t *n_var;      /* [n] or NULL */
+} hf_events_t;
+
+/* Cut kinds (section 3: each cut is a boolean predicate of one event;
+ * section 6.1: the HL-LHC selection).  Object selection inside a cut is
+ * pT > pt_min and |eta| < eta_max (strict); a jet is b-tagged when
+ * btag > btag_min.  Parameters:
+ *   HF_CUT_LEP_N_OS     f = {pt_min, eta_max}             i = {n_exact, opposite_sign}
+ *   HF_CUT_JET_N_MIN    f = {pt_min, eta_max}             i = {n_min}
+ *   HF_CUT_BTAG_N_MIN   f = {pt_min, eta_max, btag_min}   i = {n_min}
+ *   HF_CUT_BTAG_N_EQ    f = {pt_min, eta_max, btag_min}   i = {n_exact}
+ *   HF_CUT_MET_MIN      f = {met_min}                     (E_T^miss > met_min)
+ *   HF_CUT_MLL_MIN      f = {pt_min, eta_max, mll_min}    (two leading selected leptons)
+ *   HF_CUT_FWD_JET_VETO f = {pt_min, abs_eta_lo, abs_eta_hi} (fails on a jet in [lo, hi))
+ *   HF_CUT_LEP_ISO      f = {lep_pt_min, lep_eta_max, jet_pt_min, jet_eta_max, dr_min}
+ *                       (every selected lepton at Delta R >= dr_min from every
+ *                        selected jet; Delta R = sqrt(Delta eta^2 + Delta phi^2))
+ *   HF_CUT_RECO         the kinematic reconstruction (section 4: last cut);
+ *                       hf_select skips it, hf_ttbar_reco fills its counters. */
+enum {
+    HF_CUT_LEP_N_OS = 0,
+    HF_CUT_JET_N_MIN = 1,
+    HF_CUT_BTAG_N_MIN = 2,
+    HF_CUT_BTAG_N_EQ = 3,
+    HF_CUT_MET_MIN = 4,
+    HF_CUT_MLL_MIN = 5,
+    HF_CUT_FWD_JET_VETO = 6,
+    HF_CUT_LEP_ISO = 7,
+    HF_CUT_RECO = 8
+};
+
+/* A cut of the chain.  Its id is its index in the cut table.  Bit j of
+ * dep_mask means cut j must come earlier in any order (section 5.2:
+ * reordering respects the dependencies between cuts). */
+typedef struct hf_cut {
+    int32_t kind;
+    int32_t reserved; /* must be 0 */
+    uint64_t dep_mask;
+    float f[8];
+    int32_t i[4];
+} hf_cut_t;
+
+/* Per-cut counters, indexed by cut id, accumulated (+=) by every call.
+ * For the cut at position k of the order: reached = events that survived
+ * positions 0..k-1, passed = events that also pass position k, cost = device
+ * clock cycles spent evaluating it, summed over wavefronts (section 5.2: the
+ * filter ratio and the measured time of each cut drive the reordering). */
+typedef struct hf_counters {
+    uint64_t reached, passed, cost;
+} hf_counters_t;
+
+/* ---------------------------------------------------------------- errors */
+
+/* Message of the last error raised on this host thread ("" if none). */
+const char *hf_last_error(void);
+
+/* Library version string. */
+const char *hf_version(void);
+
+/* ------------------------------------------------------------- selection */
+
+/* Workspace bytes hf_select needs for n events and n_cuts cuts. */
+size_t hf_select_workspace_size(int64_t n, int n_cuts);
+
+/* Evaluate the cut chain on every event of ev (sections 3 and 5.2).
+ *   h_cuts[n_cuts]  cut table (host), 1 <= n_cuts <= HF_MAX_CUTS;
+ *   d_order[n_cuts] device int32: cut ids in evaluation order (a permutation;
+ *                   ids out of range are skipped); kept on the device so that
+ *                   a recorded graph picks up a new order without re-recording;
+ *   d_survive[n]    out: 1 if the event passes every non-RECO cut, else 0;
+ *   d_counters      in/out: hf_counters_t[n_cuts], accumulated;
+ *   d_ws, ws_bytes  workspace of at least hf_select_workspace_size(n, n_cuts).
+ * An event stops at its first failed cut; a wavefront whose 64 events have
+ * all failed skips the remaining cuts and their loads.  Errors: HF_ERR_INVAL
+ * for null pointers, n < 0 or a bad cut table; HF_ERR_CAPACITY for a short
+ * workspace. */
+int hf_select(const hf_events_t *ev, const hf_cut_t *h_cuts, int n_cuts, const int32_t *d_order,
+              uint8_t *d_survive, hf_counters_t *d_counters, void *d_ws, size_t ws_bytes,
+              hipStream_t stream);
+
+/* ------------------------------------------------------------ compaction */
+
+/* Workspace bytes hf_compact needs for up to `capacity` mask entries. */
+size_t hf_compact_workspace_size(int64_t capacity);
+
+/* Indices of the set entries of a byte mask, in ascending order (section 3:
+ * the events passing all cuts form the filtered output).
+ *   d_mask[capacity]  1 = keep, 0 = drop (any nonzero byte keeps);
+ *   d_n               device int64 holding the number of mask entries to use
+ *                     (clamped to capacity), or NULL to use all of them; lets
+ *                     the count produced by an earlier call drive this one;
+ *   d_map             device int32[capacity] or NULL: the output for entry e is
+ *                     d_map[e] if given, else index_base + e;
+ *   d_idx[capacity]   out: the kept indices, ascending;
+ *   d_count           out: device int64, number of kept entries.
+ * Errors: HF_ERR_INVAL for null pointers or capacity < 0; HF_ERR_CAPACITY
+ * for a short workspace or capacity >= 2^31. */
+int hf_compact(const uint8_t *d_mask, int64_t capacity, const int64_t *d_n, int64_t index_base,
+               const int32_t *d_map, int32_t *d_idx, int64_t *d_count, void *d_ws, size_t ws_bytes,
+               hipStream_t stream);
+
+/* ------------------------------------------------------- reconstruction */
+
+#define HF_PREC_FP64 0  /* every step in FP64 */
+#define HF_PREC_MIXED 1 /* draws, smearing, kinematic staging and root seeds in FP32;
+                           quartic assembly, root polishing, back-substitution and
+                           scores in FP64 */
+#define HF_PAIR_BTAG_FILL 0 /* b candidates: tagged selected jets (pT order, at most
+                               max_cands), filled up to two with leading untagged ones */
+#define HF_PAIR_ALL_JETS 1  /* b candidates: every selected jet (at most max_cands) */
+
+/* Reconstruction parameters (section 4; the resolution model and the choice
+ * rule are the readings listed in the design notes).  m_t and m_w are the
+ * top and W masses of the constraints (172.5 and 80.4 GeV in the paper);
+ * lambda_pt scales the top-pT term of the score.  Each variation scales
+ * every component of a 4-vector by max(1 + sigma z, 0.01) with z a standard
+ * normal: jets sigma = sqrt(jet_a^2 / E + jet_c^2) at the nominal energy,
+ * leptons sigma = lep_sigma; MET components are shifted by met_sigma z.
+ * smear = 0 gives every variation z = 0.  Random streams: Philox4x32-10
+ * keyed by seed, counter (global event id, variation, block).  reco_cut is
+ * the id of the RECO cut whose counters the call updates (-1: none). */
+typedef struct hf_reco_params {
+    double m_t, m_w, lambda_pt;
+    double jet_a, jet_c, lep_sigma, met_sigma;
+    float lep_pt_min, lep_eta_max, jet_pt_min, jet_eta_max, btag_min;
+    int32_t reco_cut;
+    uint64_t seed;
+    int32_t smear, n_var_uniform, precision, pair_mode, max_cands, want_mbb;
+} hf_reco_params_t;
+
+/* Outputs, structure of arrays over the compacted positions [0, capacity);
+ * entries at positions >= *d_count are left untouched.  nu and nubar hold
+ * (px, py, pz) per position ([capacity][3]).  best_i/best_j are the jet
+ * indices (within the event) paired with l+ and l-; best_v the variation.
+ * n_sol counts the accepted solutions over all variations and pairings.
+ * Masses are recomputed from the chosen solution; logw is its score; m_bb
+ * (may be NULL) is the mass of the two leading remaining b jets.  Positions
+ * without a solution get has_sol = 0, best_* = -1 and HF_NO_SOLUTION in every
+ * float output.  stats (may be NULL) accumulates 4 uint64 counts: events,
+ * variations, pairings solved, accepted solutions. */
+typedef struct hf_reco_out {
+    uint8_t *has_sol;
+    int32_t *n_sol, *best_v;
+    int16_t *best_i, *best_j;
+    double *nu, *nubar;
+    double *m_t, *m_tbar, *m_wp, *m_wm, *logw, *m_bb;
+    uint64_t *stats;
+} hf_reco_out_t;
+
+/* Workspace bytes hf_ttbar_reco needs for `capacity` compacted events. */
+size_t hf_ttbar_reco_workspace_size(int64_t capacity);
+
+/* Dileptonic ttbar kinematic reconstruction of the compacted events
+ * (section 4): for each event d_idx[k] (global id, k < *d_count <= capacity),
+ * every variation and every ordered pairing of two b candidates (the first
+ * with l+, the second with l-), solve the two-neutrino system from the W and
+ * top mass constraints (a quartic in the neutrino px), keep the solution
+ * with the highest score, and mark the event as passing the RECO cut when at
+ * least one solution exists.  Updates d_counters[reco_cut] (reached += count,
+ * passed += events with a solution).  Errors: HF_ERR_INVAL for null pointers,
+ * bad enums or parameters; HF_ERR_CAPACITY for a short workspace. */
+int hf_ttbar_reco(const hf_events_t *ev, const int32_t *d_idx, const int64_t *d_count, int64_t capacity,
+                  const hf_reco_params_t *h_params, const hf_reco_out_t *out, hf_counters_t *d_counters,
+                  void *d_ws, size_t ws_bytes, hipStream_t stream);
+
+/* -------------------------------------------------------- random draws */
+
+/* The variation draws the reconstruction uses (paper section 5.3 draws its
+ * pseudo-experiment numbers from Mersenne Twister; here a counter-based
+ * Philox4x32-10, Salmon et al. SC'11, so any implementation reproduces them).
+ * hf_philox_blocks: raw generator output, d_out[k][0..3] =
+ * Philox4x32-10(counter d_ctr[k][0..3], key (seed low, seed high)).
+ * hf_gauss_draws: standard normal of Gaussian slot d_slot[k] for variation
+ * d_v[k] of global event d_g[k], computed exactly as the reconstruction does
+ * in the given precision (HF_PREC_MIXED: FP32, HF_PREC_FP64), widened to
+ * double.  Slot s uses Philox block s/4 (counter = (g low, g high, v, s/4));
+ * lanes (0,1) and (2,3) of a block are Box-Muller pairs with
+ * u = (top 24 bits + 1/2) / 2^24, r = sqrt(-2 ln u_first),
+ * z = r cos(2 pi u_second) for the even lane, r sin(...) for the odd one.
+ * Errors: HF_ERR_INVAL for null pointers, n < 0 or a bad precision. */
+int hf_philox_blocks(const uint32_t *d_ctr, uint64_t seed, uint32_t *d_out, int64_t n, hipStream_t stream);
+int hf_gauss_draws(uint64_t seed, const int64_t *d_g, const int32_t *d_v, const int32_t *d_slot, int64_t n,
+                   int precision, double *d_z, hipStream_t stream);
+
+/* ------------------------------------------------------- cut reordering */
+
+/* New cut order from accumulated counters (section 5.2: cuts that reject
+ * more events and cost less go first, respecting dependencies; the user's
+ * order is the starting point).  Host only.  For each cut: pass rate
+ * p = passed/reached (1 if never reached), per-event cost c = cost/reached
+ * (0 if never reached), rank r = c / max(1 - p, 1e-9).  Cuts are placed one
+ * at a time: among those whose dependencies are all placed, the smallest
+ * rank first, ties to the lower id.  For independent cuts this minimises the
+ * expected cost sum_k c_k prod_{m<k} p_m.
+ *   h_counters[n_cuts], h_cuts[n_cuts] in; h_order[n_cuts] out.
+ * Errors: HF_ERR_INVAL for null pointers, n_cuts out of range or cyclic
+ * dependencies (h_order is left unchanged). */
+int hf_reorder_stats(const hf_counters_t *h_counters, const hf_cut_t *h_cuts, int n_cuts, int32_t *h_order);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HF_H */

@@ -1,0 +1,226 @@
+"""ctypes binding of libhf (include/hf.h).  Argument marshalling only: every
+step of the path runs in the HIP kernels behind the C ABI; PyTorch supplies
+device memory and the stream.  Importing fails loudly if libhf.so is absent.
+"""
+
+import ctypes as C
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhf.so")
+
+HF_OK = 0
+HF_ERR = {-1: "HF_ERR_INVAL", -2: "HF_ERR_CAPACITY", -3: "HF_ERR_DEVICE", -4: "HF_ERR_UNSUPPORTED"}
+HF_MAX_CUTS = 32
+HF_MAX_CANDS = 12
+HF_NO_SOLUTION = -9999.0
+CUT_KIND = {"LEP_N_OS": 0, "JET_N_MIN": 1, "BTAG_N_MIN": 2, "BTAG_N_EQ": 3, "MET_MIN": 4, "MLL_MIN": 5,
+            "FWD_JET_VETO": 6, "LEP_ISO": 7, "RECO": 8}
+PREC = {"fp64": 0, "mixed": 1}
+PAIR = {"BTAG_FILL": 0, "ALL_JETS": 1}
+
+
+class HFError(RuntimeError):
+    pass
+
+
+class Events(C.Structure):
+    _fields_ = [("n", C.c_int64), ("index_base", C.c_int64), ("lep_off", C.c_void_p), ("jet_off", C.c_void_p)] + \
+               [(k, C.c_void_p) for k in ("lep_pt", "lep_eta", "lep_phi", "lep_e", "lep_q", "jet_pt", "jet_eta",
+                                          "jet_phi", "jet_e", "jet_btag", "met_x", "met_y", "n_var")]
+
+
+class Cut(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("reserved", C.c_int32), ("dep_mask", C.c_uint64), ("f", C.c_float * 8),
+                ("i", C.c_int32 * 4)]
+
+
+class Counters(C.Structure):
+    _fields_ = [("reached", C.c_uint64), ("passed", C.c_uint64), ("cost", C.c_uint64)]
+
+
+class RecoParams(C.Structure):
+    _fields_ = [(k, C.c_double) for k in ("m_t", "m_w", "lambda_pt", "jet_a", "jet_c", "lep_sigma",
+                                          "met_sigma")] + \
+               [(k, C.c_float) for k in ("lep_pt_min", "lep_eta_max", "jet_pt_min", "jet_eta_max", "btag_min")] + \
+               [("reco_cut", C.c_int32), ("seed", C.c_uint64)] + \
+               [(k, C.c_int32) for k in ("smear", "n_var_uniform", "precision", "pair_mode", "max_cands",
+                                         "want_mbb")]
+
+
+class RecoOut(C.Structure):
+    _fields_ = [(k, C.c_void_p) for k in ("has_sol", "n_sol", "best_v", "best_i", "best_j", "nu", "nubar", "m_t",
+                                          "m_tbar", "m_wp", "m_wm", "logw", "m_bb", "stats")]
+
+
+assert C.sizeof(Cut) == 64 and C.sizeof(RecoParams) == 112 and C.sizeof(Counters) == 24
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise HFError(f"libhf.so is not built ({LIB_PATH}); run __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        P = C.c_void_p
+        L.hf_last_error.restype = C.c_char_p
+        L.hf_version.restype = C.c_char_p
+        L.hf_select_workspace_size.argtypes = [C.c_int64, C.c_int]
+        L.hf_select_workspace_size.restype = C.c_size_t
+        L.hf_select.argtypes = [C.POINTER(Events), P, C.c_int, P, P, P, P, C.c_size_t, P]
+        L.hf_compact_workspace_size.argtypes = [C.c_int64]
+        L.hf_compact_workspace_size.restype = C.c_size_t
+        L.hf_compact.argtypes = [P, C.c_int64, P, C.c_int64, P, P, P, P, C.c_size_t, P]
+        L.hf_ttbar_reco_workspace_size.argtypes = [C.c_int64]
+        L.hf_ttbar_reco_workspace_size.restype = C.c_size_t
+        L.hf_ttbar_reco.argtypes = [C.POINTER(Events), P, P, C.c_int64, C.POINTER(RecoParams), C.POINTER(RecoOut), P,
+                                    P, C.c_size_t, P]
+        L.hf_reorder_stats.argtypes = [P, P, C.c_int, P]
+        L.hf_philox_blocks.argtypes = [P, C.c_uint64, P, C.c_int64, P]
+        L.hf_gauss_draws.argtypes = [C.c_uint64, P, P, P, C.c_int64, C.c_int, P, P]
+        for f in ("hf_select", "hf_compact", "hf_ttbar_reco", "hf_reorder_stats", "hf_philox_blocks",
+                  "hf_gauss_draws"):
+            getattr(L, f).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc, what):
+    if rc != HF_OK:
+        msg = lib().hf_last_error().decode()
+        raise HFError(f"{what} failed with {HF_ERR.get(rc, rc)}: {msg}")
+
+
+def _p(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+# ----------------------------------------------------------------- structures
+
+def cut_table(cuts):
+    """hfgen-style cut descriptions -> (ctypes array of Cut, n)."""
+    names = {c["name"]: k for k, c in enumerate(cuts)}
+    arr = (Cut * len(cuts))()
+    for k, c in enumerate(cuts):
+        arr[k].kind = CUT_KIND[c["kind"]]
+        arr[k].reserved = 0
+        m = 0
+        for d in c.get("deps", []):
+            m |= 1 << names[d]
+        arr[k].dep_mask = m
+        for j, v in enumerate(c.get("f", [])):
+            arr[k].f[j] = float(v)
+        for j, v in enumerate(c.get("i", [])):
+            arr[k].i[j] = int(v)
+    return arr
+
+
+def reco_params(reco, precision="mixed", reco_cut=-1):
+    return RecoParams(
+        m_t=reco["m_t"], m_w=reco["m_w"], lambda_pt=reco["lambda_pt"], jet_a=reco["jet_a"], jet_c=reco["jet_c"],
+        lep_sigma=reco["lep_sigma"], met_sigma=reco["met_sigma"], lep_pt_min=reco["lep_pt_min"],
+        lep_eta_max=reco["lep_eta_max"], jet_pt_min=reco["jet_pt_min"], jet_eta_max=reco["jet_eta_max"],
+        btag_min=reco["btag_min"], reco_cut=int(reco_cut), seed=int(reco["seed"]), smear=int(reco["smear"]),
+        n_var_uniform=int(reco["n_var"]) if reco["n_var"] else 1, precision=PREC[precision],
+        pair_mode=PAIR[reco["pair_mode"]], max_cands=int(reco["max_cands"]), want_mbb=int(reco["want_mbb"]))
+
+
+class DeviceEvents:
+    """A chunk of events resident in device memory (torch tensors) and the
+    hf_events_t that points at them."""
+
+    COLS = ("lep_pt", "lep_eta", "lep_phi", "lep_e", "lep_q", "jet_pt", "jet_eta", "jet_phi", "jet_e", "jet_btag",
+            "met_x", "met_y")
+
+    def __init__(self, ev, device="cuda", index_base=0):
+        self.n = int(ev["n"])
+        self.index_base = int(index_base)
+        self.t = {}
+        for k in self.COLS:
+            self.t[k] = torch.as_tensor(ev[k], dtype=torch.float32).to(device)
+        self.t["lep_off"] = torch.as_tensor(ev["lep_off"].astype("int64")).to(torch.int32).to(device)
+        self.t["jet_off"] = torch.as_tensor(ev["jet_off"].astype("int64")).to(torch.int32).to(device)
+        nv = ev.get("n_var")
+        self.t["n_var"] = None if nv is None else torch.as_tensor(nv.astype("int32")).to(torch.int16).to(device)
+        self.s = Events(n=self.n, index_base=self.index_base,
+                        **{k: (None if v is None else v.data_ptr()) for k, v in self.t.items()})
+
+    @property
+    def ptr(self):
+        return C.byref(self.s)
+
+
+def select(dev, cuts_arr, n_cuts, order, survive, counters, ws, stream=None):
+    rc = lib().hf_select(dev.ptr, C.cast(cuts_arr, C.c_void_p), n_cuts, _p(order), _p(survive), _p(counters),
+                         _p(ws), ws.numel() * ws.element_size(), _stream(stream))
+    _check(rc, "hf_select")
+
+
+def compact(mask, capacity, idx, count, ws, d_n=None, index_base=0, mapping=None, stream=None):
+    rc = lib().hf_compact(_p(mask), int(capacity), _p(d_n), int(index_base), _p(mapping), _p(idx), _p(count),
+                          _p(ws), ws.numel() * ws.element_size(), _stream(stream))
+    _check(rc, "hf_compact")
+
+
+class RecoOutputs:
+    """Device output arrays of hf_ttbar_reco for `capacity` positions."""
+
+    def __init__(self, capacity, device="cuda", want_mbb=True):
+        cap = max(1, int(capacity))
+        f64 = dict(dtype=torch.float64, device=device)
+        self.t = {
+            "has_sol": torch.zeros(cap, dtype=torch.uint8, device=device),
+            "n_sol": torch.zeros(cap, dtype=torch.int32, device=device),
+            "best_v": torch.zeros(cap, dtype=torch.int32, device=device),
+            "best_i": torch.zeros(cap, dtype=torch.int16, device=device),
+            "best_j": torch.zeros(cap, dtype=torch.int16, device=device),
+            "nu": torch.zeros(cap, 3, **f64), "nubar": torch.zeros(cap, 3, **f64),
+            "m_t": torch.zeros(cap, **f64), "m_tbar": torch.zeros(cap, **f64), "m_wp": torch.zeros(cap, **f64),
+            "m_wm": torch.zeros(cap, **f64), "logw": torch.zeros(cap, **f64),
+            "m_bb": torch.zeros(cap, **f64) if want_mbb else None,
+            "stats": torch.zeros(4, dtype=torch.int64, device=device),
+        }
+        self.s = RecoOut(**{k: (None if v is None else v.data_ptr()) for k, v in self.t.items()})
+
+    def host(self, n):
+        return {k: (v[:n].cpu().numpy() if k != "stats" else v.cpu().numpy()) for k, v in self.t.items()
+                if v is not None}
+
+
+def ttbar_reco(dev, idx, count, capacity, params, outs, counters, ws, stream=None):
+    rc = lib().hf_ttbar_reco(dev.ptr, _p(idx), _p(count), int(capacity), C.byref(params), C.byref(outs.s),
+                             _p(counters), _p(ws), ws.numel() * ws.element_size(), _stream(stream))
+    _check(rc, "hf_ttbar_reco")
+
+
+def reorder_stats(counters_host, cuts_arr, n_cuts):
+    """counters_host: uint64 numpy array [n_cuts, 3]; returns the new order (list)."""
+    import numpy as np
+    cnt = np.ascontiguousarray(counters_host, dtype=np.uint64)
+    order = (C.c_int32 * n_cuts)()
+    rc = lib().hf_reorder_stats(C.c_void_p(cnt.ctypes.data), C.cast(cuts_arr, C.c_void_p), n_cuts,
+                                C.cast(order, C.c_void_p))
+    _check(rc, "hf_reorder_stats")
+    return list(order)
+
+
+def philox_blocks(ctr, seed, out, stream=None):
+    _check(lib().hf_philox_blocks(_p(ctr), int(seed), _p(out), ctr.shape[0], _stream(stream)), "hf_philox_blocks")
+
+
+def gauss_draws(seed, g, v, slot, z, precision="mixed", stream=None):
+    _check(lib().hf_gauss_draws(int(seed), _p(g), _p(v), _p(slot), g.shape[0], PREC[precision], _p(z),
+                                _stream(stream)), "hf_gauss_draws")
+
+
+def workspace(nbytes, device="cuda"):
+    return torch.empty(max(256, int(nbytes)), dtype=torch.uint8, device=device)

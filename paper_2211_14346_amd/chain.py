@@ -1,0 +1,107 @@
+"""One chunk of the hot path: select -> compact -> ttbar reconstruction ->
+compact, with per-cut counters, adaptive reordering between steps and an
+optional HIP-graph recording of the four calls.
+
+PyTorch allocates the device buffers and provides the stream; every step
+runs in libhf's kernels through the C ABI (binding.py).
+"""
+
+import numpy as np
+import torch
+
+from . import binding as B
+
+
+class Chain:
+    def __init__(self, ev, cuts, reco, precision="mixed", device="cuda", index_base=0, order=None):
+        self.device = device
+        self.cuts = cuts
+        self.n_cuts = len(cuts)
+        self.cut_arr = B.cut_table(cuts)
+        kinds = [c["kind"] for c in cuts]
+        self.reco_id = kinds.index("RECO") if "RECO" in kinds else -1
+        self.dev = B.DeviceEvents(ev, device=device, index_base=index_base)
+        n = self.dev.n
+        self.n = n
+        self.params = B.reco_params(reco, precision=precision, reco_cut=self.reco_id)
+        self.want_mbb = bool(reco.get("want_mbb", 0))
+        if self.want_mbb:
+            self.params.want_mbb = 1
+        self.order_host = list(range(self.n_cuts)) if order is None else list(order)
+        self.order = torch.tensor(self.order_host, dtype=torch.int32, device=device)
+        self.counters = torch.zeros(self.n_cuts, 3, dtype=torch.int64, device=device)
+        self.survive = torch.zeros(max(n, 1), dtype=torch.uint8, device=device)
+        self.idx = torch.zeros(max(n, 1), dtype=torch.int32, device=device)
+        self.count = torch.zeros(1, dtype=torch.int64, device=device)
+        self.final_idx = torch.zeros(max(n, 1), dtype=torch.int32, device=device)
+        self.final_count = torch.zeros(1, dtype=torch.int64, device=device)
+        self.out = B.RecoOutputs(n, device=device, want_mbb=self.want_mbb)
+        self.ws_sel = B.workspace(B.lib().hf_select_workspace_size(n, self.n_cuts), device)
+        self.ws_cmp = B.workspace(B.lib().hf_compact_workspace_size(n), device)
+        self.ws_cmp2 = B.workspace(B.lib().hf_compact_workspace_size(n), device)
+        self.ws_reco = B.workspace(B.lib().hf_ttbar_reco_workspace_size(n), device)
+        self.graph = None
+
+    # -------------------------------------------------------------- stages
+    def run_select(self, stream=None):
+        B.select(self.dev, self.cut_arr, self.n_cuts, self.order, self.survive, self.counters, self.ws_sel, stream)
+
+    def run_compact(self, stream=None):
+        B.compact(self.survive, self.n, self.idx, self.count, self.ws_cmp, index_base=self.dev.index_base,
+                  stream=stream)
+
+    def run_reco(self, stream=None):
+        B.ttbar_reco(self.dev, self.idx, self.count, self.n, self.params, self.out, self.counters, self.ws_reco,
+                     stream)
+
+    def run_final(self, stream=None):
+        B.compact(self.out.t["has_sol"], self.n, self.final_idx, self.final_count, self.ws_cmp2, d_n=self.count,
+                  mapping=self.idx, stream=stream)
+
+    def step(self, stream=None):
+        self.run_select(stream)
+        self.run_compact(stream)
+        self.run_reco(stream)
+        self.run_final(stream)
+
+    # -------------------------------------------------------------- graph
+    def capture(self):
+        """Record the four calls into a HIP graph (torch.cuda.CUDAGraph)."""
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            self.step(s)  # warm-up outside the graph (kernel loading)
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.step()
+        self.graph = g
+        return g
+
+    def replay(self):
+        self.graph.replay()
+
+    # -------------------------------------------------------------- host side
+    def counters_host(self):
+        return self.counters.cpu().numpy().astype(np.uint64)
+
+    def reorder(self):
+        """New order from the accumulated counters (host), written to the
+        device order buffer that the recorded graph reads."""
+        new = B.reorder_stats(self.counters_host(), self.cut_arr, self.n_cuts)
+        self.order_host = new
+        self.order.copy_(torch.tensor(new, dtype=torch.int32), non_blocking=False)
+        return new
+
+    def reset_counters(self):
+        self.counters.zero_()
+
+    def results(self):
+        torch.cuda.synchronize()
+        S = int(self.count.item())
+        F = int(self.final_count.item())
+        out = self.out.host(S)
+        return {"survive": self.survive[:self.n].cpu().numpy(), "idx": self.idx[:S].cpu().numpy(),
+                "count": S, "final": self.final_idx[:F].cpu().numpy(), "reco": out,
+                "counters": self.counters_host()}

@@ -1,0 +1,229 @@
+// C-ABI front end of libhf: argument validation, error reporting and kernel
+// launches.  Host code only; every device launch lives in the .hip units.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+
+#include "../../include/hf.h"
+#include "hf_internal.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int device_fail(const char *what, hipError_t e) {
+    return fail(HF_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool events_ok(const hf_events_t *ev, bool need_phi_e, const char **why) {
+    if (!ev) return *why = "ev is NULL", false;
+    if (ev->n < 0 || ev->n >= (int64_t)1 << 31) return *why = "n out of range [0, 2^31)", false;
+    if (ev->index_base < 0 || ev->index_base + ev->n > ((int64_t)1 << 31))
+        return *why = "index_base + n must lie in [0, 2^31]", false;
+    if (ev->n == 0) return true;
+    if (!ev->lep_off || !ev->jet_off || !ev->lep_pt || !ev->lep_eta || !ev->lep_q || !ev->jet_pt ||
+        !ev->jet_eta || !ev->jet_btag || !ev->met_x || !ev->met_y)
+        return *why = "a required event column is NULL", false;
+    if (need_phi_e && (!ev->lep_phi || !ev->lep_e || !ev->jet_phi || !ev->jet_e))
+        return *why = "phi/E columns are NULL", false;
+    return true;
+}
+
+int check_cuts(const hf_cut_t *h_cuts, int n_cuts, bool *need_phi_e) {
+    if (!h_cuts) return fail(HF_ERR_INVAL, "h_cuts is NULL");
+    if (n_cuts < 1 || n_cuts > HF_MAX_CUTS) return fail(HF_ERR_INVAL, "n_cuts=%d outside [1, %d]", n_cuts, HF_MAX_CUTS);
+    *need_phi_e = false;
+    for (int c = 0; c < n_cuts; ++c) {
+        const hf_cut_t &k = h_cuts[c];
+        if (k.kind < HF_CUT_LEP_N_OS || k.kind > HF_CUT_RECO)
+            return fail(HF_ERR_INVAL, "cut %d: unknown kind %d", c, k.kind);
+        if (k.reserved != 0) return fail(HF_ERR_INVAL, "cut %d: reserved field must be 0", c);
+        if (k.dep_mask >> n_cuts) return fail(HF_ERR_INVAL, "cut %d: dependency on a cut id >= n_cuts", c);
+        if (k.dep_mask & (1ull << c)) return fail(HF_ERR_INVAL, "cut %d depends on itself", c);
+        for (int q = 0; q < 8; ++q)
+            if (!isfinite(k.f[q])) return fail(HF_ERR_INVAL, "cut %d: non-finite parameter f[%d]", c, q);
+        if (k.kind == HF_CUT_MLL_MIN || k.kind == HF_CUT_LEP_ISO) *need_phi_e = true;
+    }
+    return HF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *hf_last_error(void) { return g_err.c_str(); }
+
+const char *hf_version(void) { return "hf 0.1 gfx950"; }
+
+size_t hf_select_workspace_size(int64_t n, int n_cuts) {
+    if (n < 0 || n_cuts < 1 || n_cuts > HF_MAX_CUTS) return 0;
+    return hf::select_ws_bytes(n, n_cuts);
+}
+
+int hf_select(const hf_events_t *ev, const hf_cut_t *h_cuts, int n_cuts, const int32_t *d_order,
+              uint8_t *d_survive, hf_counters_t *d_counters, void *d_ws, size_t ws_bytes, hipStream_t stream) {
+    bool need_pe = false;
+    int rc = check_cuts(h_cuts, n_cuts, &need_pe);
+    if (rc != HF_OK) return rc;
+    const char *why = nullptr;
+    if (!events_ok(ev, need_pe, &why)) return fail(HF_ERR_INVAL, "hf_select: %s", why);
+    if (!d_order || !d_counters) return fail(HF_ERR_INVAL, "hf_select: order or counters is NULL");
+    if (ev->n > 0 && !d_survive) return fail(HF_ERR_INVAL, "hf_select: survive is NULL");
+    const size_t need = hf::select_ws_bytes(ev->n, n_cuts);
+    if (!d_ws || ws_bytes < need)
+        return fail(HF_ERR_CAPACITY, "hf_select: workspace %zu bytes < %zu required", ws_bytes, need);
+    hf::CutTable ct;
+    memset(&ct, 0, sizeof ct);
+    for (int c = 0; c < n_cuts; ++c) ct.c[c] = h_cuts[c];
+    ct.n = n_cuts;
+    hipError_t e = hf::launch_select(hf::make_view(*ev), ct, d_order, d_survive, d_counters, d_ws, stream);
+    if (e != hipSuccess) return device_fail("hf_select launch", e);
+    return HF_OK;
+}
+
+size_t hf_compact_workspace_size(int64_t capacity) {
+    if (capacity < 0) return 0;
+    return hf::compact_ws_bytes(capacity);
+}
+
+int hf_compact(const uint8_t *d_mask, int64_t capacity, const int64_t *d_n, int64_t index_base,
+               const int32_t *d_map, int32_t *d_idx, int64_t *d_count, void *d_ws, size_t ws_bytes,
+               hipStream_t stream) {
+    if (capacity < 0) return fail(HF_ERR_INVAL, "hf_compact: capacity < 0");
+    if (capacity >= ((int64_t)1 << 31)) return fail(HF_ERR_CAPACITY, "hf_compact: capacity >= 2^31");
+    if (!d_count) return fail(HF_ERR_INVAL, "hf_compact: count is NULL");
+    if (capacity > 0 && (!d_mask || !d_idx)) return fail(HF_ERR_INVAL, "hf_compact: mask or idx is NULL");
+    if (!d_map && (index_base < 0 || index_base + capacity > ((int64_t)1 << 31)))
+        return fail(HF_ERR_INVAL, "hf_compact: index_base + capacity must lie in [0, 2^31]");
+    const size_t need = hf::compact_ws_bytes(capacity);
+    if (!d_ws || ws_bytes < need)
+        return fail(HF_ERR_CAPACITY, "hf_compact: workspace %zu bytes < %zu required", ws_bytes, need);
+    hipError_t e = hf::launch_compact(d_mask, capacity, d_n, index_base, d_map, d_idx, d_count, d_ws, stream);
+    if (e != hipSuccess) return device_fail("hf_compact launch", e);
+    return HF_OK;
+}
+
+size_t hf_ttbar_reco_workspace_size(int64_t capacity) {
+    if (capacity < 0) return 0;
+    return hf::reco_ws_bytes(capacity);
+}
+
+int hf_ttbar_reco(const hf_events_t *ev, const int32_t *d_idx, const int64_t *d_count, int64_t capacity,
+                  const hf_reco_params_t *p, const hf_reco_out_t *out, hf_counters_t *d_counters, void *d_ws,
+                  size_t ws_bytes, hipStream_t stream) {
+    const char *why = nullptr;
+    if (!events_ok(ev, true, &why)) return fail(HF_ERR_INVAL, "hf_ttbar_reco: %s", why);
+    if (!p || !out) return fail(HF_ERR_INVAL, "hf_ttbar_reco: params or out is NULL");
+    if (capacity < 0 || capacity >= ((int64_t)1 << 31)) return fail(HF_ERR_INVAL, "hf_ttbar_reco: capacity out of range");
+    if (!d_count) return fail(HF_ERR_INVAL, "hf_ttbar_reco: count is NULL");
+    if (capacity > 0) {
+        if (!d_idx || !out->has_sol || !out->n_sol || !out->best_v || !out->best_i || !out->best_j || !out->nu ||
+            !out->nubar || !out->m_t || !out->m_tbar || !out->m_wp || !out->m_wm || !out->logw)
+            return fail(HF_ERR_INVAL, "hf_ttbar_reco: an index or output array is NULL");
+        if (p->want_mbb && !out->m_bb) return fail(HF_ERR_INVAL, "hf_ttbar_reco: want_mbb needs out->m_bb");
+    }
+    if (p->precision != HF_PREC_FP64 && p->precision != HF_PREC_MIXED)
+        return fail(HF_ERR_INVAL, "hf_ttbar_reco: unknown precision %d", p->precision);
+    if (p->pair_mode != HF_PAIR_BTAG_FILL && p->pair_mode != HF_PAIR_ALL_JETS)
+        return fail(HF_ERR_INVAL, "hf_ttbar_reco: unknown pair_mode %d", p->pair_mode);
+    if (p->max_cands < 2 || p->max_cands > HF_MAX_CANDS)
+        return fail(HF_ERR_INVAL, "hf_ttbar_reco: max_cands %d outside [2, %d]", p->max_cands, HF_MAX_CANDS);
+    if (!ev->n_var && (p->n_var_uniform < 1 || p->n_var_uniform > 65535))
+        return fail(HF_ERR_INVAL, "hf_ttbar_reco: n_var_uniform %d outside [1, 65535]", p->n_var_uniform);
+    if (!(p->m_t > p->m_w && p->m_w > 0.0) || !(p->lambda_pt > 0.0) || !isfinite(p->m_t))
+        return fail(HF_ERR_INVAL, "hf_ttbar_reco: masses or lambda_pt invalid");
+    if (!(p->jet_a >= 0.0) || !(p->jet_c >= 0.0) || !(p->lep_sigma >= 0.0) || !(p->met_sigma >= 0.0))
+        return fail(HF_ERR_INVAL, "hf_ttbar_reco: resolutions must be finite and >= 0");
+    if (p->smear != 0 && p->smear != 1) return fail(HF_ERR_INVAL, "hf_ttbar_reco: smear must be 0 or 1");
+    const size_t need = hf::reco_ws_bytes(capacity);
+    if (!d_ws || ws_bytes < need)
+        return fail(HF_ERR_CAPACITY, "hf_ttbar_reco: workspace %zu bytes < %zu required", ws_bytes, need);
+    hf::RecoArgs a;
+    a.m_t = p->m_t;
+    a.m_w = p->m_w;
+    a.lambda_pt = p->lambda_pt;
+    a.jet_a = p->jet_a;
+    a.jet_c = p->jet_c;
+    a.lep_sigma = p->lep_sigma;
+    a.met_sigma = p->met_sigma;
+    a.lep_pt_min = p->lep_pt_min;
+    a.lep_eta_max = p->lep_eta_max;
+    a.jet_pt_min = p->jet_pt_min;
+    a.jet_eta_max = p->jet_eta_max;
+    a.btag_min = p->btag_min;
+    a.seed = p->seed;
+    a.smear = p->smear;
+    a.n_var_uniform = p->n_var_uniform;
+    a.pair_mode = p->pair_mode;
+    a.max_cands = p->max_cands;
+    a.want_mbb = p->want_mbb;
+    hf::RecoOutView o{out->has_sol, out->n_sol, out->best_v, out->best_i, out->best_j, out->nu, out->nubar,
+                      out->m_t,     out->m_tbar, out->m_wp,  out->m_wm,   out->logw, out->m_bb, out->stats};
+    hf_counters_t *rc = (d_counters && p->reco_cut >= 0) ? d_counters + p->reco_cut : nullptr;
+    hipError_t e = hf::launch_reco(hf::make_view(*ev), d_idx, d_count, capacity, a, p->precision, o, rc, d_ws, stream);
+    if (e != hipSuccess) return device_fail("hf_ttbar_reco launch", e);
+    return HF_OK;
+}
+
+int hf_philox_blocks(const uint32_t *d_ctr, uint64_t seed, uint32_t *d_out, int64_t n, hipStream_t stream) {
+    if (n < 0 || n >= ((int64_t)1 << 31)) return fail(HF_ERR_INVAL, "hf_philox_blocks: n out of range");
+    if (n > 0 && (!d_ctr || !d_out)) return fail(HF_ERR_INVAL, "hf_philox_blocks: NULL pointer");
+    hipError_t e = hf::launch_philox(d_ctr, seed, d_out, n, stream);
+    if (e != hipSuccess) return device_fail("hf_philox_blocks launch", e);
+    return HF_OK;
+}
+
+int hf_gauss_draws(uint64_t seed, const int64_t *d_g, const int32_t *d_v, const int32_t *d_slot, int64_t n,
+                   int precision, double *d_z, hipStream_t stream) {
+    if (n < 0 || n >= ((int64_t)1 << 31)) return fail(HF_ERR_INVAL, "hf_gauss_draws: n out of range");
+    if (n > 0 && (!d_g || !d_v || !d_slot || !d_z)) return fail(HF_ERR_INVAL, "hf_gauss_draws: NULL pointer");
+    if (precision != HF_PREC_FP64 && precision != HF_PREC_MIXED)
+        return fail(HF_ERR_INVAL, "hf_gauss_draws: unknown precision %d", precision);
+    hipError_t e = hf::launch_gauss(seed, d_g, d_v, d_slot, n, precision, d_z, stream);
+    if (e != hipSuccess) return device_fail("hf_gauss_draws launch", e);
+    return HF_OK;
+}
+
+int hf_reorder_stats(const hf_counters_t *h_counters, const hf_cut_t *h_cuts, int n_cuts, int32_t *h_order) {
+    if (!h_counters || !h_cuts || !h_order) return fail(HF_ERR_INVAL, "hf_reorder_stats: NULL argument");
+    if (n_cuts < 1 || n_cuts > HF_MAX_CUTS) return fail(HF_ERR_INVAL, "hf_reorder_stats: n_cuts out of range");
+    double rank[HF_MAX_CUTS];
+    for (int c = 0; c < n_cuts; ++c) {
+        const hf_counters_t &k = h_counters[c];
+        const double p = k.reached ? (double)k.passed / (double)k.reached : 1.0;
+        const double cost = k.reached ? (double)k.cost / (double)k.reached : 0.0;
+        const double rej = 1.0 - p;
+        rank[c] = cost / (rej > 1e-9 ? rej : 1e-9);
+        if (h_cuts[c].dep_mask >> n_cuts) return fail(HF_ERR_INVAL, "hf_reorder_stats: dependency out of range");
+    }
+    int32_t order[HF_MAX_CUTS];
+    uint64_t placed = 0;
+    for (int pos = 0; pos < n_cuts; ++pos) {
+        int best = -1;
+        for (int c = 0; c < n_cuts; ++c) {
+            if ((placed >> c) & 1ull) continue;
+            if (h_cuts[c].dep_mask & ~placed) continue;
+            if (best < 0 || rank[c] < rank[best]) best = c;
+        }
+        if (best < 0) return fail(HF_ERR_INVAL, "hf_reorder_stats: cyclic dependencies");
+        order[pos] = best;
+        placed |= 1ull << best;
+    }
+    memcpy(h_order, order, sizeof(int32_t) * (size_t)n_cuts);
+    return HF_OK;
+}
+
+}  // extern "C"

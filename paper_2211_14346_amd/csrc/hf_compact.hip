@@ -1,0 +1,154 @@
+// Stream compaction of a byte mask into ascending indices (paper section 3:
+// the events that pass every cut form the filtered output).
+//
+// Single pass with decoupled look-back.  A tile is 256 threads x 16 bytes;
+// tiles are numbered by an atomic ticket in the order blocks start, so a
+// tile only ever waits on tiles whose blocks are already running.  Each
+// thread loads its 16 mask bytes with one 128-bit load when aligned, counts
+// them, the block scans the counts (wave64 shuffles + LDS), publishes its
+// aggregate, looks back over the predecessors' published values to obtain
+// its exclusive prefix, publishes its inclusive prefix and scatters.  HBM
+// traffic: 1 byte per entry read, 4 bytes per kept entry written.
+//
+// Status words (64 bit): bits 62-63 = 0 (not ready), 1 (aggregate), 2
+// (inclusive prefix); bits 0-61 the value.  A tiny first kernel clears the
+// status words and the ticket, so the pair can be recorded in a graph.
+#include "hf_device.hpp"
+#include "hf_internal.hpp"
+
+namespace hf {
+namespace {
+
+constexpr int kCB = 256;
+constexpr int kCPT = 16;
+constexpr int kTile = kCB * kCPT;
+constexpr uint64_t kFlagAgg = 1ull << 62;
+constexpr uint64_t kFlagInc = 2ull << 62;
+constexpr uint64_t kValMask = (1ull << 62) - 1;
+constexpr size_t kHeader = 256;  // ticket lives in the first 256 bytes
+
+__global__ void k_compact_init(uint64_t *status, int64_t n_tiles, uint32_t *ticket) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) *ticket = 0;
+    for (int64_t t = i; t < n_tiles; t += (int64_t)gridDim.x * blockDim.x) status[t] = 0;
+}
+
+__device__ __forceinline__ uint64_t load_status(const uint64_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void store_status(uint64_t *p, uint64_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ __launch_bounds__(kCB) void k_compact(const uint8_t *__restrict__ mask, int64_t capacity,
+                                                 const int64_t *__restrict__ d_n, int64_t index_base,
+                                                 const int32_t *__restrict__ map, int32_t *__restrict__ idx,
+                                                 int64_t *__restrict__ count, uint64_t *status, uint32_t *ticket,
+                                                 int64_t n_tiles, int aligned) {
+    __shared__ uint32_t s_tile;
+    __shared__ uint32_t s_wsum[kCB / kWave];
+    __shared__ uint64_t s_prefix;
+    const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
+    if (tid == 0) s_tile = atomicAdd(ticket, 1u);
+    __syncthreads();
+    const int64_t tile = s_tile;
+    int64_t n = capacity;
+    if (d_n) {
+        const int64_t dn = *d_n;
+        n = dn < 0 ? 0 : (dn < capacity ? dn : capacity);
+    }
+    const int64_t first = tile * kTile + (int64_t)tid * kCPT;
+
+    // ---- load 16 flags
+    uint32_t bits = 0;
+    if (aligned && first + kCPT <= n) {
+        const uint4 v = *reinterpret_cast<const uint4 *>(mask + first);
+        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) bits |= (((w[q] >> (8 * b)) & 0xffu) ? 1u : 0u) << (4 * q + b);
+    } else {
+#pragma unroll
+        for (int j = 0; j < kCPT; ++j)
+            if (first + j < n && mask[first + j]) bits |= 1u << j;
+    }
+    const uint32_t cnt = (uint32_t)__popc(bits);
+
+    // ---- block exclusive scan of the per-thread counts
+    uint32_t incl = cnt;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        const uint32_t o = __shfl_up(incl, off);
+        if (lane >= off) incl += o;
+    }
+    if (lane == kWave - 1) s_wsum[wave] = incl;
+    __syncthreads();
+    uint32_t wbase = 0, total = 0;
+#pragma unroll
+    for (int w = 0; w < kCB / kWave; ++w) {
+        if (w < wave) wbase += s_wsum[w];
+        total += s_wsum[w];
+    }
+    const uint32_t excl_thread = wbase + incl - cnt;
+
+    // ---- publish aggregate, look back, publish inclusive prefix
+    if (tid == 0) {
+        uint64_t prefix = 0;
+        if (tile == 0) {
+            store_status(&status[0], kFlagInc | (uint64_t)total);
+        } else {
+            store_status(&status[tile], kFlagAgg | (uint64_t)total);
+            int64_t j = tile - 1;
+            while (true) {
+                const uint64_t s = load_status(&status[j]);
+                const uint64_t flag = s & ~kValMask;
+                if (flag == 0) continue;  // predecessor still counting
+                prefix += s & kValMask;
+                if (flag == kFlagInc) break;
+                --j;
+            }
+            store_status(&status[tile], kFlagInc | (prefix + total));
+        }
+        s_prefix = prefix;
+        if (tile == n_tiles - 1) *count = (int64_t)(prefix + total);
+    }
+    __syncthreads();
+
+    // ---- scatter
+    int64_t out = (int64_t)s_prefix + excl_thread;
+    while (bits) {
+        const int j = __ffs(bits) - 1;
+        bits &= bits - 1;
+        const int64_t e = first + j;
+        idx[out++] = map ? map[e] : (int32_t)(index_base + e);
+    }
+}
+
+}  // namespace
+
+static int64_t n_tiles_for(int64_t capacity) {
+    const int64_t t = (capacity + kTile - 1) / kTile;
+    return t < 1 ? 1 : t;
+}
+
+size_t compact_ws_bytes(int64_t capacity) { return kHeader + (size_t)n_tiles_for(capacity) * sizeof(uint64_t); }
+
+hipError_t launch_compact(const uint8_t *mask, int64_t capacity, const int64_t *d_n, int64_t index_base,
+                          const int32_t *map, int32_t *idx, int64_t *count, void *ws, hipStream_t s) {
+    const int64_t nt = n_tiles_for(capacity);
+    uint32_t *ticket = static_cast<uint32_t *>(ws);
+    uint64_t *status = reinterpret_cast<uint64_t *>(static_cast<char *>(ws) + kHeader);
+    int init_grid = (int)((nt + 255) / 256);
+    if (init_grid > 1024) init_grid = 1024;
+    hipLaunchKernelGGL(k_compact_init, dim3(init_grid), dim3(256), 0, s, status, nt, ticket);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    const int aligned = (reinterpret_cast<uintptr_t>(mask) % 16) == 0;
+    hipLaunchKernelGGL(k_compact, dim3((unsigned)nt), dim3(kCB), 0, s, mask, capacity, d_n, index_base, map, idx,
+                       count, status, ticket, nt, aligned);
+    return hipGetLastError();
+}
+
+}  // namespace hf

@@ -1,0 +1,100 @@
+// Device helpers shared by the gfx950 kernels: wave64 primitives, the
+// Philox4x32-10 counter-based generator and Box-Muller normals.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hf {
+
+constexpr int kWave = 64;
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// Bits of lanes below the calling lane.
+__device__ __forceinline__ uint64_t lanemask_lt() {
+    const int l = lane_id();
+    return l == 0 ? 0ull : (~0ull >> (64 - l));
+}
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+__device__ __forceinline__ int popc64(uint64_t x) { return __popcll(x); }
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11): ten rounds; each round multiplies
+// counter words 0 and 2 by the two round constants (32x32 -> 64) and mixes
+// the halves with words 1 and 3 and the round key; the key is bumped by the
+// two Weyl constants between rounds.
+struct U4 {
+    uint32_t x, y, z, w;
+};
+
+__device__ __forceinline__ U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
+        U4 n;
+        n.x = (uint32_t)(p1 >> 32) ^ c.y ^ k0;
+        n.y = (uint32_t)p1;
+        n.z = (uint32_t)(p0 >> 32) ^ c.w ^ k1;
+        n.w = (uint32_t)p0;
+        c = n;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return c;
+}
+
+// Uniform in (0, 1) from the top 24 bits; exact in FP32 and FP64.
+template <typename T>
+__device__ __forceinline__ T uniform24(uint32_t x) {
+    return ((T)(x >> 8) + (T)0.5) * (T)(1.0 / 16777216.0);
+}
+
+// Box-Muller pair from two raw words: (r cos 2 pi u2, r sin 2 pi u2),
+// r = sqrt(-2 ln u1).
+__device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, float &z0, float &z1) {
+    const float u1 = uniform24<float>(a);
+    const float u2 = uniform24<float>(b);
+    const float r = sqrtf(-2.0f * logf(u1));
+    float s, c;
+    sincospif(2.0f * u2, &s, &c);
+    z0 = r * c;
+    z1 = r * s;
+}
+
+__device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, double &z0, double &z1) {
+    const double u1 = uniform24<double>(a);
+    const double u2 = uniform24<double>(b);
+    const double r = sqrt(-2.0 * log(u1));
+    double s, c;
+    sincospi(2.0 * u2, &s, &c);
+    z0 = r * c;
+    z1 = r * s;
+}
+
+// Gaussian draws of one Philox block: slot 4*blk + j for j = 0..3.
+template <typename T>
+__device__ __forceinline__ void gauss_block(uint64_t seed, uint64_t g, uint32_t v, uint32_t blk, T z[4]) {
+    U4 c{(uint32_t)g, (uint32_t)(g >> 32), v, blk};
+    const U4 r = philox4x32_10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+    box_muller(r.x, r.y, z[0], z[1]);
+    box_muller(r.z, r.w, z[2], z[3]);
+}
+
+// Gaussian draw of a single slot (computes only the Box-Muller pair it needs).
+template <typename T>
+__device__ __forceinline__ T gauss_slot(uint64_t seed, uint64_t g, uint32_t v, uint32_t slot) {
+    U4 c{(uint32_t)g, (uint32_t)(g >> 32), v, slot >> 2};
+    const U4 r = philox4x32_10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+    T z0, z1;
+    if (slot & 2u)
+        box_muller(r.z, r.w, z0, z1);
+    else
+        box_muller(r.x, r.y, z0, z1);
+    return (slot & 1u) ? z1 : z0;
+}
+
+}  // namespace hf

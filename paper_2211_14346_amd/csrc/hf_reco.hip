@@ -1,0 +1,539 @@
+// Dileptonic ttbar kinematic reconstruction over the compacted events
+// (paper section 4: W and top mass constraints for every lepton / b-jet
+// pairing, over resolution-smeared pseudo-experiments, the most probable
+// solution kept; the event fails the last cut when no solution exists).
+//
+// Two kernels.
+//
+// k_search: one wavefront per event, lanes = variations (chunks of 64),
+// persistent grid with events dealt round-robin to wavefronts.  The
+// wavefront stages its event into LDS in FP64: the two leptons, the b
+// candidates (ballot-ranked in pT order) and, per candidate and lepton side,
+// the constants of the linear maps and of the conic's quadratic part.  Each
+// lane draws its variation (Philox4x32-10 + Box-Muller in precision T), and
+// for every pairing assembles the eliminant quartic in FP64, finds its real
+// roots (critical points from the closed-form cubic in T, Newton in FP64),
+// recovers and polishes (x, y), rejects negative-energy branches and scores
+// the solution in FP64.  A wave-wide argmax with a total-order tie-break
+// (score, then smallest variation, pairing, x) picks the winner, which lane
+// 0 writes to a per-event record.
+//
+// k_epilogue: one thread per event; recomputes the winner's kinematics in
+// FP64 from the record (draws recomputed bit-identically in T), writes the
+// outputs, the H -> bb candidate mass, and folds the RECO counters.
+//
+// T = float (HF_PREC_MIXED): draws and root seeds in FP32.
+// T = double (HF_PREC_FP64): everything in FP64.
+#include <math.h>
+
+#include "hf_device.hpp"
+#include "hf_internal.hpp"
+#include "hf_reco_math.hpp"
+
+namespace hf {
+namespace {
+
+constexpr int kRecoBlock = 256;
+constexpr int kRecoWaves = kRecoBlock / kWave;
+constexpr int kMaxC = HF_MAX_CANDS;
+constexpr int kNoBest = 0x7fffffff;
+constexpr size_t kWsHeader = 256;
+
+// Per-event result of the search, read by the epilogue.
+struct BestRec {
+    double score, x, y;
+    int32_t v, p, nsol, nc;
+};
+
+template <typename T>
+struct WaveStage {
+    double lp[4], lm[4];      // nominal (E, px, py, pz) of l+ and l-
+    double cand[kMaxC][4];    // nominal b candidates
+    double sp[kMaxC][kSide];  // side constants with l+
+    double sm[kMaxC][kSide];  // side constants with l-
+    double sigma[kMaxC];
+    double ml2p, ml2m;
+    int jidx[kMaxC];
+    int okp[kMaxC], okm[kMaxC];
+    int lsel[2];
+    T z[kMaxC][kWave];  // per-lane draw of each candidate
+};
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// Nominal Cartesian 4-vector (E, px, py, pz) from the float32 columns, FP64.
+__device__ __forceinline__ void polar_to_cart(float pt, float eta, float phi, float e, double out[4]) {
+    double s, c;
+    sincos((double)phi, &s, &c);
+    out[0] = (double)e;
+    out[1] = (double)pt * c;
+    out[2] = (double)pt * s;
+    out[3] = (double)pt * sinh((double)eta);
+}
+
+// "a is better than b": higher score, then smaller variation, pairing, x.
+__device__ __forceinline__ bool better(double sa, int va, int pa, double xa, double sb, int vb, int pb, double xb) {
+    if (sa != sb) return sa > sb;
+    if (va != vb) return va < vb;
+    if (pa != pb) return pa < pb;
+    return xa < xb;
+}
+
+// Scale factor max(1 + sigma z, 0.01), formed in FP64 from a draw in T.
+template <typename T>
+__device__ __forceinline__ double smear(double sigma, T z) {
+    const double s = 1.0 + sigma * (double)z;
+    return s > 0.01 ? s : 0.01;
+}
+
+__device__ __forceinline__ bool lep_sel(const EvView &ev, uint32_t k, const RecoArgs &a) {
+    return ev.lep_pt[k] > a.lep_pt_min && fabsf(ev.lep_eta[k]) < a.lep_eta_max;
+}
+
+__device__ __forceinline__ bool jet_sel(const EvView &ev, uint32_t k, const RecoArgs &a) {
+    return ev.jet_pt[k] > a.jet_pt_min && fabsf(ev.jet_eta[k]) < a.jet_eta_max;
+}
+
+__device__ __forceinline__ int64_t clamp_count(const int64_t *count, int64_t capacity) {
+    const int64_t S = *count;
+    return S < 0 ? 0 : (S > capacity ? capacity : S);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kRecoBlock, 2) void k_search(EvView ev, const int32_t *__restrict__ idx,
+                                                          const int64_t *__restrict__ count, int64_t capacity,
+                                                          RecoArgs a, BestRec *__restrict__ best_out,
+                                                          uint64_t *__restrict__ wstats) {
+    __shared__ WaveStage<T> stage_all[kRecoWaves];
+    const int lane = lane_id();
+    const int wave = threadIdx.x / kWave;
+    WaveStage<T> &st = stage_all[wave];
+    const int64_t S = clamp_count(count, capacity);
+    const int64_t nwaves = (int64_t)gridDim.x * kRecoWaves;
+    const double mt2_mw2 = a.m_t * a.m_t - a.m_w * a.m_w;
+    const double mw2 = a.m_w * a.m_w;
+    uint64_t acc_var = 0, acc_pair = 0, acc_sol = 0;
+
+    for (int64_t k = (int64_t)blockIdx.x * kRecoWaves + wave; k < S; k += nwaves) {
+        const int64_t e = (int64_t)idx[k] - ev.index_base;
+        const bool in_chunk = e >= 0 && e < ev.n;  // ids outside the chunk get no solution
+        // ------------------------------------------------------------ leptons
+        const uint32_t l0 = in_chunk ? ev.lep_off[e] : 0u;
+        const uint32_t nl = in_chunk ? ev.lep_off[e + 1] - l0 : 0u;
+        int nsel = 0;
+        if (lane < 2) st.lsel[lane] = -1;
+        wave_sync();
+        for (uint32_t cb = 0; cb < nl; cb += kWave) {
+            const uint32_t kk = cb + lane;
+            const bool sel = kk < nl && lep_sel(ev, l0 + kk, a);
+            const uint64_t m = ballot(sel);
+            const int r = nsel + popc64(m & lanemask_lt());
+            if (sel && r < 2) st.lsel[r] = (int)kk;
+            nsel += popc64(m);
+        }
+        wave_sync();
+        bool ok = false;
+        if (nsel == 2) {
+            const uint32_t ka = l0 + st.lsel[0], kb = l0 + st.lsel[1];
+            const float qa = ev.lep_q[ka], qb = ev.lep_q[kb];
+            ok = qa * qb < 0.0f;
+            if (ok && lane < 2) {
+                const uint32_t kl = (lane == 0) == (qa > 0.0f) ? ka : kb;  // lane 0 -> l+, lane 1 -> l-
+                double v[4];
+                polar_to_cart(ev.lep_pt[kl], ev.lep_eta[kl], ev.lep_phi[kl], ev.lep_e[kl], v);
+                double *dst = lane == 0 ? st.lp : st.lm;
+                for (int q = 0; q < 4; ++q) dst[q] = v[q];
+                const double m2 = v[0] * v[0] - v[1] * v[1] - v[2] * v[2] - v[3] * v[3];
+                if (lane == 0)
+                    st.ml2p = m2;
+                else
+                    st.ml2m = m2;
+            }
+        }
+        // --------------------------------------------------------- candidates
+        const uint32_t j0 = in_chunk ? ev.jet_off[e] : 0u;
+        const uint32_t nj = in_chunk ? ev.jet_off[e + 1] - j0 : 0u;
+        const int cap = a.max_cands;
+        int nc = 0;
+        if (ok) {
+            int ntag = 0;
+            for (uint32_t cb = 0; cb < nj; cb += kWave) {
+                const uint32_t kk = cb + lane;
+                const bool tag = kk < nj && jet_sel(ev, j0 + kk, a) &&
+                                 (a.pair_mode == HF_PAIR_ALL_JETS || ev.jet_btag[j0 + kk] > a.btag_min);
+                const uint64_t m = ballot(tag);
+                const int r = ntag + popc64(m & lanemask_lt());
+                if (tag && r < cap) st.jidx[r] = (int)kk;
+                ntag += popc64(m);
+            }
+            nc = ntag < cap ? ntag : cap;
+            if (a.pair_mode == HF_PAIR_BTAG_FILL && nc < 2) {
+                int nfill = 0;
+                for (uint32_t cb = 0; cb < nj && nc + nfill < 2; cb += kWave) {
+                    const uint32_t kk = cb + lane;
+                    const bool un = kk < nj && jet_sel(ev, j0 + kk, a) && !(ev.jet_btag[j0 + kk] > a.btag_min);
+                    const uint64_t m = ballot(un);
+                    const int r = nc + nfill + popc64(m & lanemask_lt());
+                    if (un && r < 2) st.jidx[r] = (int)kk;
+                    nfill += popc64(m);
+                }
+                nc = nc + nfill < 2 ? nc + nfill : 2;
+            }
+        }
+        ok = ok && nc >= 2;
+        wave_sync();
+        if (ok) {
+            if (lane < nc) {
+                const uint32_t kk = j0 + st.jidx[lane];
+                const float je = ev.jet_e[kk];
+                polar_to_cart(ev.jet_pt[kk], ev.jet_eta[kk], ev.jet_phi[kk], je, st.cand[lane]);
+                st.sigma[lane] = sqrt(a.jet_a * a.jet_a / (double)je + a.jet_c * a.jet_c);
+            }
+            wave_sync();
+            // side constants: lanes [0, nc) with l+, lanes [16, 16 + nc) with l-
+            if (lane < nc) {
+                st.okp[lane] = make_side(st.lp, st.cand[lane], st.sp[lane]) ? 1 : 0;
+            } else if (lane >= 16 && lane < 16 + nc) {
+                const int c = lane - 16;
+                st.okm[c] = make_side(st.lm, st.cand[c], st.sm[c]) ? 1 : 0;
+            }
+            wave_sync();
+        }
+
+        // ------------------------------------------------------- variations
+        const int V = !in_chunk ? 0 : ev.n_var ? (int)ev.n_var[e] : a.n_var_uniform;
+        double best_s = -INFINITY, best_x = 0.0, best_y = 0.0;
+        int best_v = kNoBest, best_p = kNoBest;
+        int nsol = 0;
+        int npair_valid = 0;
+        if (ok) {
+            for (int i = 0; i < nc; ++i)
+                for (int j = 0; j < nc; ++j) npair_valid += (i != j && st.okp[i] && st.okm[j]) ? 1 : 0;
+        }
+        if (npair_valid > 0) {
+            const double metx = ev.met_x[e], mety = ev.met_y[e];
+            const uint64_t g = (uint64_t)idx[k];
+            for (int vb = 0; vb < V; vb += kWave) {
+                const int v = vb + lane;
+                const bool act = v < V;
+                T zl[4] = {(T)0, (T)0, (T)0, (T)0};
+                if (a.smear && act) {
+                    gauss_block<T>(a.seed, g, (uint32_t)v, 0u, zl);
+                    uint32_t last_blk = 0xffffffffu;
+                    T zb[4];
+                    for (int c = 0; c < nc; ++c) {
+                        const uint32_t slot = 4u + (uint32_t)st.jidx[c];
+                        const uint32_t blk = slot >> 2;
+                        if (blk != last_blk) {
+                            gauss_block<T>(a.seed, g, (uint32_t)v, blk, zb);
+                            last_blk = blk;
+                        }
+                        const uint32_t ln = slot & 3u;
+                        st.z[c][lane] = ln == 0 ? zb[0] : ln == 1 ? zb[1] : ln == 2 ? zb[2] : zb[3];
+                    }
+                } else {
+                    for (int c = 0; c < nc; ++c) st.z[c][lane] = (T)0;
+                }
+                if (!act) continue;
+                const double slp = smear(a.lep_sigma, zl[0]);
+                const double slm = smear(a.lep_sigma, zl[1]);
+                const double mx = metx + a.met_sigma * (double)zl[2];
+                const double my = mety + a.met_sigma * (double)zl[3];
+                const double zz4 = (double)zl[0] * zl[0] + (double)zl[1] * zl[1] + (double)zl[2] * zl[2] +
+                                   (double)zl[3] * zl[3];
+                const double Wp = mw2 / (2.0 * slp) - 0.5 * slp * st.ml2p;
+                const double Wm = mw2 / (2.0 * slm) - 0.5 * slm * st.ml2m;
+                for (int i = 0; i < nc; ++i) {
+                    if (!st.okp[i]) continue;
+                    const T zi = st.z[i][lane];
+                    const double si = smear(st.sigma[i], zi);
+                    const SideVar A = side_var(st.sp[i], Wp, slp, si, mt2_mw2);
+                    const double tx = si * st.cand[i][1] + slp * st.lp[1];  // (b + l+)_T
+                    const double ty = si * st.cand[i][2] + slp * st.lp[2];
+                    for (int j = 0; j < nc; ++j) {
+                        if (j == i || !st.okm[j]) continue;
+                        const T zj = st.z[j][lane];
+                        const double sj = smear(st.sigma[j], zj);
+                        const SideVar B = side_var(st.sm[j], Wm, slm, sj, mt2_mw2);
+                        const Conic Q = reflect(B.q, mx, my);
+                        double qc[5];
+                        eliminant(A.q, Q, qc);
+                        const Roots4 R = quartic_real_roots<T>(qc);
+                        const int p = i * nc + j;
+                        const double zz = zz4 + (double)zi * zi + (double)zj * zj;
+                        const double tbx = sj * st.cand[j][1] + slm * st.lm[1];
+                        const double tby = sj * st.cand[j][2] + slm * st.lm[2];
+                        for (int r = 0; r < 4; ++r) {
+                            if (!((R.mask >> r) & 1)) continue;
+                            double x = pick4(R.r, r), y;
+                            if (!recover_y(A.q, Q, x, y)) continue;
+                            polish_xy(A.q, Q, x, y, 1);
+                            const double en = st.sp[i][kE1] * x + st.sp[i][kE2] * y + A.e0;
+                            const double xb = mx - x, yb = my - y;
+                            const double eb = st.sm[j][kE1] * xb + st.sm[j][kE2] * yb + B.e0;
+                            if (en < 0.0 || eb < 0.0) continue;
+                            ++nsol;
+                            const double ptt = sqrt((tx + x) * (tx + x) + (ty + y) * (ty + y));
+                            const double pttb = sqrt((tbx + xb) * (tbx + xb) + (tby + yb) * (tby + yb));
+                            const double w = -0.5 * zz - (ptt + pttb) / a.lambda_pt;
+                            if (better(w, v, p, x, best_s, best_v, best_p, best_x)) {
+                                best_s = w;
+                                best_v = v;
+                                best_p = p;
+                                best_x = x;
+                                best_y = y;
+                            }
+                        }
+                    }
+                }
+            }
+        }
+        // --------------------------------------------------- wave argmax
+        for (int off = kWave / 2; off > 0; off >>= 1) {
+            const double os = __shfl_xor(best_s, off);
+            const int ov = __shfl_xor(best_v, off);
+            const int op = __shfl_xor(best_p, off);
+            const double ox = __shfl_xor(best_x, off);
+            const double oy = __shfl_xor(best_y, off);
+            if (better(os, ov, op, ox, best_s, best_v, best_p, best_x)) {
+                best_s = os;
+                best_v = ov;
+                best_p = op;
+                best_x = ox;
+                best_y = oy;
+            }
+            nsol += __shfl_xor(nsol, off);
+        }
+        acc_var += (uint64_t)V;
+        acc_pair += (uint64_t)V * (uint64_t)npair_valid;
+        acc_sol += (uint64_t)nsol;
+        if (lane == 0) {
+            BestRec r;
+            r.score = best_s;
+            r.x = best_x;
+            r.y = best_y;
+            r.v = best_v;
+            r.p = best_p;
+            r.nsol = nsol;
+            r.nc = nc;
+            best_out[k] = r;
+        }
+        wave_sync();
+    }
+    if (lane == 0 && wstats) {
+        atomicAdd((unsigned long long *)&wstats[1], (unsigned long long)acc_var);
+        atomicAdd((unsigned long long *)&wstats[2], (unsigned long long)acc_pair);
+        atomicAdd((unsigned long long *)&wstats[3], (unsigned long long)acc_sol);
+    }
+}
+
+__global__ void k_reco_init(uint64_t *wstats) {
+    if (threadIdx.x < 4) wstats[threadIdx.x] = 0;
+}
+
+__device__ __forceinline__ double mass4(double E, double X, double Y, double Z) {
+    const double m2 = E * E - X * X - Y * Y - Z * Z;
+    return m2 > 0.0 ? sqrt(m2) : 0.0;
+}
+
+// One thread per compacted event: outputs of the chosen solution, the
+// H -> bb candidate, and the RECO counters (one atomic per block).
+template <typename T>
+__global__ __launch_bounds__(256) void k_epilogue(EvView ev, const int32_t *__restrict__ idx,
+                                                  const int64_t *__restrict__ count, int64_t capacity, RecoArgs a,
+                                                  const BestRec *__restrict__ best, RecoOutView out,
+                                                  hf_counters_t *__restrict__ counter, const uint64_t *wstats) {
+    __shared__ uint32_t s_pass[256 / kWave];
+    const int64_t S = clamp_count(count, capacity);
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    bool have = false;
+    if (k < S) {
+        const BestRec r = best[k];
+        have = r.v != kNoBest;
+        out.has_sol[k] = have ? 1 : 0;
+        out.n_sol[k] = r.nsol;
+        if (!have) {
+            out.best_v[k] = -1;
+            out.best_i[k] = -1;
+            out.best_j[k] = -1;
+            for (int q = 0; q < 3; ++q) out.nu[3 * k + q] = out.nubar[3 * k + q] = HF_NO_SOLUTION;
+            out.m_t[k] = out.m_tbar[k] = out.m_wp[k] = out.m_wm[k] = out.logw[k] = HF_NO_SOLUTION;
+            if (out.m_bb) out.m_bb[k] = HF_NO_SOLUTION;
+        } else {
+            const uint64_t g = (uint64_t)idx[k];
+            const int64_t e = (int64_t)g - ev.index_base;  // in the chunk: a solution exists
+            const uint32_t l0 = ev.lep_off[e], l1 = ev.lep_off[e + 1];
+            const uint32_t j0 = ev.jet_off[e], j1 = ev.jet_off[e + 1];
+            uint32_t ls[2] = {0, 0};
+            int nl = 0;
+            for (uint32_t q = l0; q < l1 && nl < 2; ++q)
+                if (lep_sel(ev, q, a)) ls[nl++] = q;
+            const uint32_t kp = ev.lep_q[ls[0]] > 0.0f ? ls[0] : ls[1];
+            const uint32_t km = ev.lep_q[ls[0]] > 0.0f ? ls[1] : ls[0];
+            // the r.p-th ordered pair of the candidate list, rebuilt with the same rule
+            const int nc = r.nc, ci = r.p / nc, cj = r.p % nc;
+            int jidx[2] = {-1, -1}, rank = 0;
+            for (uint32_t q = j0; q < j1 && rank < a.max_cands; ++q)
+                if (jet_sel(ev, q, a) && (a.pair_mode == HF_PAIR_ALL_JETS || ev.jet_btag[q] > a.btag_min)) {
+                    if (rank == ci) jidx[0] = (int)(q - j0);
+                    if (rank == cj) jidx[1] = (int)(q - j0);
+                    ++rank;
+                }
+            for (uint32_t q = j0; q < j1 && rank < 2 && a.pair_mode == HF_PAIR_BTAG_FILL; ++q)
+                if (jet_sel(ev, q, a) && !(ev.jet_btag[q] > a.btag_min)) {
+                    if (rank == ci) jidx[0] = (int)(q - j0);
+                    if (rank == cj) jidx[1] = (int)(q - j0);
+                    ++rank;
+                }
+            double lp[4], lm[4], b[4], bb[4];
+            polar_to_cart(ev.lep_pt[kp], ev.lep_eta[kp], ev.lep_phi[kp], ev.lep_e[kp], lp);
+            polar_to_cart(ev.lep_pt[km], ev.lep_eta[km], ev.lep_phi[km], ev.lep_e[km], lm);
+            const uint32_t bi = j0 + jidx[0], bj = j0 + jidx[1];
+            polar_to_cart(ev.jet_pt[bi], ev.jet_eta[bi], ev.jet_phi[bi], ev.jet_e[bi], b);
+            polar_to_cart(ev.jet_pt[bj], ev.jet_eta[bj], ev.jet_phi[bj], ev.jet_e[bj], bb);
+            double sp[kSide], sm[kSide];
+            make_side(lp, b, sp);
+            make_side(lm, bb, sm);
+            T zl[4] = {(T)0, (T)0, (T)0, (T)0};
+            T zi = (T)0, zj = (T)0;
+            if (a.smear) {
+                gauss_block<T>(a.seed, g, (uint32_t)r.v, 0u, zl);
+                zi = gauss_slot<T>(a.seed, g, (uint32_t)r.v, 4u + (uint32_t)jidx[0]);
+                zj = gauss_slot<T>(a.seed, g, (uint32_t)r.v, 4u + (uint32_t)jidx[1]);
+            }
+            const double slp = smear(a.lep_sigma, zl[0]), slm = smear(a.lep_sigma, zl[1]);
+            const double si = smear(sqrt(a.jet_a * a.jet_a / (double)ev.jet_e[bi] + a.jet_c * a.jet_c), zi);
+            const double sj = smear(sqrt(a.jet_a * a.jet_a / (double)ev.jet_e[bj] + a.jet_c * a.jet_c), zj);
+            const double mx = (double)ev.met_x[e] + a.met_sigma * (double)zl[2];
+            const double my = (double)ev.met_y[e] + a.met_sigma * (double)zl[3];
+            const double mw2 = a.m_w * a.m_w, mt2_mw2 = a.m_t * a.m_t - mw2;
+            const double ml2p = lp[0] * lp[0] - lp[1] * lp[1] - lp[2] * lp[2] - lp[3] * lp[3];
+            const double ml2m = lm[0] * lm[0] - lm[1] * lm[1] - lm[2] * lm[2] - lm[3] * lm[3];
+            const SideVar A = side_var(sp, mw2 / (2.0 * slp) - 0.5 * slp * ml2p, slp, si, mt2_mw2);
+            const SideVar Bv = side_var(sm, mw2 / (2.0 * slm) - 0.5 * slm * ml2m, slm, sj, mt2_mw2);
+            const double x = r.x, y = r.y, xb = mx - x, yb = my - y;
+            const double nu[4] = {sp[kE1] * x + sp[kE2] * y + A.e0, x, y, sp[kZ1] * x + sp[kZ2] * y + A.z0};
+            const double nb[4] = {sm[kE1] * xb + sm[kE2] * yb + Bv.e0, xb, yb, sm[kZ1] * xb + sm[kZ2] * yb + Bv.z0};
+            for (int q = 0; q < 4; ++q) {
+                lp[q] *= slp;
+                lm[q] *= slm;
+                b[q] *= si;
+                bb[q] *= sj;
+            }
+            out.best_v[k] = r.v;
+            out.best_i[k] = (int16_t)jidx[0];
+            out.best_j[k] = (int16_t)jidx[1];
+            out.nu[3 * k + 0] = nu[1];
+            out.nu[3 * k + 1] = nu[2];
+            out.nu[3 * k + 2] = nu[3];
+            out.nubar[3 * k + 0] = nb[1];
+            out.nubar[3 * k + 1] = nb[2];
+            out.nubar[3 * k + 2] = nb[3];
+            out.m_wp[k] = mass4(lp[0] + nu[0], lp[1] + nu[1], lp[2] + nu[2], lp[3] + nu[3]);
+            out.m_wm[k] = mass4(lm[0] + nb[0], lm[1] + nb[1], lm[2] + nb[2], lm[3] + nb[3]);
+            out.m_t[k] = mass4(b[0] + lp[0] + nu[0], b[1] + lp[1] + nu[1], b[2] + lp[2] + nu[2], b[3] + lp[3] + nu[3]);
+            out.m_tbar[k] =
+                mass4(bb[0] + lm[0] + nb[0], bb[1] + lm[1] + nb[1], bb[2] + lm[2] + nb[2], bb[3] + lm[3] + nb[3]);
+            out.logw[k] = r.score;
+            if (out.m_bb) {
+                // H -> b bbar from the remaining jets (section 4): the two leading remaining
+                // b-tagged selected jets; with only one, the leading remaining untagged one joins it.
+                double mbb = HF_NO_SOLUTION;
+                if (a.want_mbb) {
+                    uint32_t pick[2] = {0, 0};
+                    int got = 0;
+                    for (uint32_t q = j0; q < j1 && got < 2; ++q)
+                        if (q != bi && q != bj && jet_sel(ev, q, a) && ev.jet_btag[q] > a.btag_min) pick[got++] = q;
+                    if (got == 1)
+                        for (uint32_t q = j0; q < j1 && got < 2; ++q)
+                            if (q != bi && q != bj && jet_sel(ev, q, a) && !(ev.jet_btag[q] > a.btag_min))
+                                pick[got++] = q;
+                    if (got == 2) {
+                        double p0[4], p1[4];
+                        polar_to_cart(ev.jet_pt[pick[0]], ev.jet_eta[pick[0]], ev.jet_phi[pick[0]], ev.jet_e[pick[0]],
+                                      p0);
+                        polar_to_cart(ev.jet_pt[pick[1]], ev.jet_eta[pick[1]], ev.jet_phi[pick[1]], ev.jet_e[pick[1]],
+                                      p1);
+                        mbb = mass4(p0[0] + p1[0], p0[1] + p1[1], p0[2] + p1[2], p0[3] + p1[3]);
+                    }
+                }
+                out.m_bb[k] = mbb;
+            }
+        }
+    }
+    // RECO counters: reached += S (once), passed += events with a solution
+    const uint64_t m = ballot(have);
+    if (lane_id() == 0) s_pass[threadIdx.x / kWave] = (uint32_t)popc64(m);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t tot = 0;
+        for (int w = 0; w < 256 / kWave; ++w) tot += s_pass[w];
+        if (counter && tot) atomicAdd((unsigned long long *)&counter->passed, (unsigned long long)tot);
+        if (blockIdx.x == 0) {
+            if (counter) atomicAdd((unsigned long long *)&counter->reached, (unsigned long long)S);
+            if (out.stats) {
+                atomicAdd((unsigned long long *)&out.stats[0], (unsigned long long)S);
+                for (int q = 1; q < 4; ++q) atomicAdd((unsigned long long *)&out.stats[q], (unsigned long long)wstats[q]);
+            }
+        }
+    }
+}
+
+template <typename T>
+int search_grid(int64_t capacity) {
+    static int per_cu = -1, n_cu = 0;
+    if (per_cu < 0) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) == hipSuccess) n_cu = prop.multiProcessorCount;
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void *>(&k_search<T>),
+                                                         kRecoBlock, 0) != hipSuccess)
+            nb = 1;
+        per_cu = nb > 0 ? nb : 1;
+        if (n_cu <= 0) n_cu = 256;
+    }
+    int64_t g = (int64_t)n_cu * per_cu;
+    const int64_t need = (capacity + kRecoWaves - 1) / kRecoWaves;
+    if (g > need) g = need;
+    return (int)(g < 1 ? 1 : g);
+}
+
+template <typename T>
+hipError_t launch_t(const EvView &ev, const int32_t *idx, const int64_t *count, int64_t capacity, const RecoArgs &a,
+                    const RecoOutView &out, hf_counters_t *reco_counter, uint64_t *wstats, BestRec *best,
+                    hipStream_t s) {
+    if (capacity > 0) {
+        hipLaunchKernelGGL(k_search<T>, dim3(search_grid<T>(capacity)), dim3(kRecoBlock), 0, s, ev, idx, count,
+                           capacity, a, best, wstats);
+        hipError_t err = hipGetLastError();
+        if (err != hipSuccess) return err;
+    }
+    const int64_t eg = capacity > 0 ? (capacity + 255) / 256 : 1;
+    hipLaunchKernelGGL(k_epilogue<T>, dim3((unsigned)eg), dim3(256), 0, s, ev, idx, count, capacity, a, best, out,
+                       reco_counter, wstats);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+size_t reco_ws_bytes(int64_t capacity) { return kWsHeader + (size_t)(capacity > 0 ? capacity : 0) * sizeof(BestRec); }
+
+hipError_t launch_reco(const EvView &ev, const int32_t *idx, const int64_t *count, int64_t capacity,
+                       const RecoArgs &a, int precision, const RecoOutView &out, hf_counters_t *reco_counter,
+                       void *ws, hipStream_t s) {
+    uint64_t *wstats = static_cast<uint64_t *>(ws);
+    BestRec *best = reinterpret_cast<BestRec *>(static_cast<char *>(ws) + kWsHeader);
+    hipLaunchKernelGGL(k_reco_init, dim3(1), dim3(64), 0, s, wstats);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    if (precision == HF_PREC_MIXED) return launch_t<float>(ev, idx, count, capacity, a, out, reco_counter, wstats, best, s);
+    return launch_t<double>(ev, idx, count, capacity, a, out, reco_counter, wstats, best, s);
+}
+
+}  // namespace hf

@@ -1,0 +1,56 @@
+"""Comparison of reconstruction outputs: product (GPU) vs oracle.
+
+Readings of the agreement targets:
+  * the RECO pass/fail decision and the chosen (variation, jet pair) must agree
+    in >= 99.9 % of events (a floating-point decision, not bit-exact);
+  * where the chosen solution is the same, every reconstructed quantity agrees
+    within 1e-4 relative: momenta as |dp| / max(|p_ref|, 1 GeV), masses and the
+    score as |d| / max(|ref|, 1).
+"""
+
+import numpy as np
+
+FLOAT_KEYS = ("m_t", "m_tbar", "m_wp", "m_wm", "logw")
+
+
+def compare(g, w, n=None):
+    """g, w: dicts of arrays over the same compacted positions.  Returns stats."""
+    S = len(w["has_sol"]) if n is None else n
+    hs_g, hs_w = g["has_sol"][:S].astype(bool), w["has_sol"][:S].astype(bool)
+    both = hs_g & hs_w
+    same = both & (g["best_v"][:S] == w["best_v"][:S]) & (g["best_i"][:S] == w["best_i"][:S]) & \
+        (g["best_j"][:S] == w["best_j"][:S])
+    st = {"S": int(S), "decision_agree": float(np.mean(hs_g == hs_w)) if S else 1.0,
+          "n_both": int(both.sum()), "n_same": int(same.sum()),
+          "choice_agree": float(same.sum() / both.sum()) if both.sum() else 1.0,
+          "nsol_agree": float(np.mean(g["n_sol"][:S] == w["n_sol"][:S])) if S else 1.0}
+    rels = []
+    for k in ("nu", "nubar"):
+        d = np.linalg.norm(g[k][:S][same] - w[k][:S][same], axis=1)
+        r = d / np.maximum(np.linalg.norm(w[k][:S][same], axis=1), 1.0)
+        st["max_rel_" + k] = float(r.max()) if r.size else 0.0
+        rels.append(r)
+    for k in FLOAT_KEYS:
+        r = np.abs(g[k][:S][same] - w[k][:S][same]) / np.maximum(np.abs(w[k][:S][same]), 1.0)
+        st["max_rel_" + k] = float(r.max()) if r.size else 0.0
+        rels.append(r)
+    allr = np.max(np.stack(rels), axis=0) if same.sum() else np.zeros(0)
+    st["frac_within_1e-4"] = float(np.mean(allr <= 1e-4)) if allr.size else 1.0
+    st["max_rel_any"] = float(allr.max()) if allr.size else 0.0
+    # sentinel outputs where there is no solution
+    nos = ~hs_g
+    st["sentinel_ok"] = bool(np.all(g["m_t"][:S][nos] == -9999.0) and np.all(g["nu"][:S][nos] == -9999.0)
+                             and np.all(g["best_v"][:S][nos] == -1))
+    if "m_bb" in g and "m_bb" in w and g["m_bb"] is not None:
+        r = np.abs(g["m_bb"][:S][same] - w["m_bb"][:S][same]) / np.maximum(np.abs(w["m_bb"][:S][same]), 1.0)
+        st["max_rel_m_bb"] = float(r.max()) if r.size else 0.0
+    return st
+
+
+def assert_agree(st, min_agree=0.999, tol=1e-4, min_within=1.0):
+    assert st["sentinel_ok"], st
+    assert st["decision_agree"] >= min_agree, st
+    assert st["choice_agree"] >= min_agree, st
+    assert st["frac_within_1e-4"] >= min_within, st
+    if min_within >= 1.0:
+        assert st["max_rel_any"] <= tol, st
