@@ -1,0 +1,183 @@
+"""Throughput of the hot path on one MI355X.
+
+Workload: 1M synthetic events (80 % dileptonic ttbar, 20 % background, 2-10
+jets), cut chain of four cuts plus the reconstruction at 64 smeared
+variations per event.  One step = one pass of the whole path over the
+batch: hf_select -> hf_compact -> hf_ttbar_reco -> hf_compact (recorded as one
+HIP graph) followed by the host-side reordering from the counters.  Inputs
+are resident in HBM before timing starts.
+
+Prints one JSON line.  --gpus above 1 is refused: this build runs on one GPU.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+WORKLOAD = "ttbar1M_v64"
+
+# Algorithmic FP operations of the reconstruction search kernel per unit of
+# work, counted on the kernel's formulas for real (non-padded) work items:
+# per variation (draws, smearing, lepton-side terms), per pairing solved
+# (side terms, conic substitution, eliminant, normalisation, critical points
+# and their signs) and per accepted solution (y recovery, one conic polish,
+# energies and score).  Root-finding iterations are counted per pairing at
+# their mean.  FMA counts as two operations.  Derivation in the design notes.
+FLOP_PER_VARIATION = 60
+FLOP_PER_PAIRING = 420
+FLOP_PER_SOLUTION = 150
+
+# MI355X vector peaks (256 CUs at 2.4 GHz): FP64 78.6 TFLOP/s; FP32 157.3 with
+# packed FP32, which this build does not use (non-packed FP32 issues at the
+# FP64 rate).  The search kernel's arithmetic is FP64 apart from the draws and
+# the cubic seeds, so the FP64 vector peak is its ceiling.
+PEAK_ALU_TFLOPS = 78.6
+PEAK_HBM_GBS = 8000.0
+
+
+def _parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64-form", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=200_000)
+    ap.add_argument("--profile-only", action="store_true", help="few steps, no CPU baseline (for profilers)")
+    return ap.parse_args()
+
+
+def main():
+    args = _parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU in this build; the path shards by event ranges and "
+              "needs no collective, but multi-GPU runs are not part of it.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import hfgen
+    from paper_2211_14346_amd import binding as B
+    from paper_2211_14346_amd.chain import Chain
+
+    if not torch.cuda.is_available():
+        print("no GPU", file=sys.stderr)
+        sys.exit(1)
+    cfg = hfgen.config(WORKLOAD)
+    t0 = time.time()
+    ev = hfgen.generate(cfg)
+    print(f"[bench] generated {ev['n']} events in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+
+    def run_form(precision, steps, warmup):
+        ch = Chain(ev, cfg["cuts"], cfg["reco"], precision=precision)
+        for _ in range(max(1, warmup)):
+            ch.step()
+        torch.cuda.synchronize()
+        ch.capture()
+        ch.reset_counters()
+        torch.cuda.synchronize()
+        t_start = time.perf_counter()
+        for _ in range(steps):
+            ch.replay()
+            ch.reorder()  # counters to host, new order to the device buffer
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t_start
+        return ch, dt
+
+    ch, dt = run_form(args.precision, args.steps, args.warmup)
+    n = ev["n"]
+    ms_per_step = 1e3 * dt / args.steps
+    value = n * args.steps / dt
+    print(f"[bench] {args.precision}: {ms_per_step:.3f} ms/step, {value:.4g} events/s", file=sys.stderr, flush=True)
+
+    # ---- dominant kernel: the reconstruction search, timed alone with HIP events
+    res = ch.results()
+    stats0 = ch.out.t["stats"].cpu().numpy().astype(np.int64).copy()
+    timer = B.KernelTimer()
+    kms = []
+    with timer:
+        for _ in range(max(3, min(10, args.steps))):
+            ch.run_reco()
+            kms.append(timer.elapsed_ms())
+    timer.close()
+    stats1 = ch.out.t["stats"].cpu().numpy().astype(np.int64)
+    per = (stats1 - stats0) / len(kms)  # events, variations, pairings, solutions per launch
+    kernel_ms = float(np.mean(kms))
+    flops = FLOP_PER_VARIATION * per[1] + FLOP_PER_PAIRING * per[2] + FLOP_PER_SOLUTION * per[3]
+    achieved = flops / (kernel_ms * 1e-3) / 1e12
+    roofline = {"bound": "alu", "kernel": "k_search<float>" if args.precision == "mixed" else "k_search<double>",
+                "achieved": round(achieved, 3), "peak": PEAK_ALU_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK_ALU_TFLOPS, 4), "traffic": None,
+                "kernel_ms": round(kernel_ms, 4), "flop_per_launch": float(flops),
+                "units_per_launch": {"events": int(per[0]), "variations": int(per[1]), "pairings": int(per[2]),
+                                     "solutions": int(per[3])}}
+
+    out = {"metric": cfg_metric(), "value": round(value, 1), "unit": "events/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32+f64" if args.precision == "mixed" else "f64", "data": "synthetic",
+           "config": {"workload": WORKLOAD, "events": n, "variations": cfg["reco"]["n_var"],
+                      "cuts": [c["name"] for c in cfg["cuts"]], "precision": args.precision,
+                      "survivors": int(res["count"]), "reconstructed": int(len(res["final"])),
+                      "parallelism": "1 GPU"},
+           "roofline": roofline}
+
+    if not args.profile_only and not args.no_fp64_form and args.precision == "mixed":
+        del ch
+        torch.cuda.empty_cache()
+        ch64, dt64 = run_form("fp64", max(3, args.steps // 2), 1)
+        out["fp64_form"] = {"value": round(n * max(3, args.steps // 2) / dt64, 1), "unit": "events/s",
+                            "ms_per_step": round(1e3 * dt64 / max(3, args.steps // 2), 4)}
+        ch = ch64
+
+    if not args.profile_only and not args.no_cpu_baseline:
+        out["cpu_baseline"], acc = cpu_baseline(ev, cfg, args, torch)
+        out["accuracy_vs_oracle"] = acc
+    print(json.dumps(out))
+
+
+def cfg_metric():
+    return "events/s through cut chain + ttbar reco @64 variations; % HBM/VALU roofline"
+
+
+def cpu_baseline(ev, cfg, args, torch):
+    """The FP64 oracle on the first `cpu_sample` events of the same batch, on
+    the host's cores; and the GPU forms' agreement with it on that sample."""
+    import hfgen
+    import oracle
+    from paper_2211_14346_amd.chain import Chain
+    from tests.gpu_compare import compare
+
+    m = min(args.cpu_sample, ev["n"])
+    sub = hfgen.subset(ev, np.arange(m))
+    threads = min(os.cpu_count() or 1, 16)
+    oracle.lib()
+    t0 = time.perf_counter()
+    surv, reached, passed = oracle.select(sub, cfg["cuts"], list(range(len(cfg["cuts"]))))
+    idx = oracle.compact(surv)
+    rec = oracle.ttbar_reco(sub, idx, cfg["reco"], n_threads=threads)
+    oracle.compact(rec["has_sol"], 0, idx)
+    dt = time.perf_counter() - t0
+    base = {"value": round(m / dt, 1), "unit": "events/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {m} events of the {WORKLOAD} batch, select+compact+reco+compact, "
+                      f"{dt:.1f} s wall on {threads} threads"}
+    acc = {}
+    for prec in ("mixed", "fp64"):
+        ch = Chain(sub, cfg["cuts"], cfg["reco"], precision=prec)
+        ch.step()
+        r = ch.results()
+        st = compare(r["reco"], rec)
+        acc[prec] = {k: (round(v, 8) if isinstance(v, float) else v) for k, v in st.items()}
+        del ch
+    return base, acc
+
+
+if __name__ == "__main__":
+    main()

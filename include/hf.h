@@ -229,6 +229,15 @@ int hf_ttbar_reco(const hf_events_t *ev, const int32_t *d_idx, const int64_t *d_
                   const hf_reco_params_t *h_params, const hf_reco_out_t *out, hf_counters_t *d_counters,
                   void *d_ws, size_t ws_bytes, hipStream_t stream);
 
+/* Instrumentation: from the next call on, hf_ttbar_reco records `start` just
+ * before and `stop` just after its search kernel (the kernel that solves the
+ * quartics), on the stream of the call, so that the caller can time that
+ * kernel alone with hipEventElapsedTime.  Both NULL switches it off.  The
+ * events are created and owned by the caller and must outlive the calls that
+ * record them.  Process-wide setting; calls from several threads race.
+ * Errors: HF_ERR_INVAL if exactly one of the two is NULL. */
+int hf_reco_timing_events(hipEvent_t start, hipEvent_t stop);
+
 /* -------------------------------------------------------- random draws */
 
 /* The variation draws the reconstruction uses (paper section 5.3 draws its

@@ -653,6 +653,16 @@ int orc_solve_pairing_v(vec4 lp, vec4 b, vec4 lm, vec4 bb, double metx, double m
             x = xn;
             y = yn;
         }
+        /* A root of the eliminant only says the two conics share a root in y; the
+         * point is a solution of the mass constraints (section 4) only if both
+         * conics vanish there.  Reading: both relative residuals <= 1e-6 after
+         * the polish, which separates true intersections (<= 1e-9) from
+         * near-tangent artefacts. */
+        {
+            double g1 = orc_conic_rel(c1, x, y, orc_conic_eval(c1, x, y));
+            double g2 = orc_conic_rel(c2, x, y, orc_conic_eval(c2, x, y));
+            if (!(g1 <= 1e-6 && g2 <= 1e-6)) continue;
+        }
         double xb = metx - x, yb = mety - y;
         double en = m1.ex * x + m1.ey * y + m1.e0;
         double zn = m1.zx * x + m1.zy * y + m1.z0;

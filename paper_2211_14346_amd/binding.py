@@ -80,6 +80,8 @@ def lib():
         L.hf_ttbar_reco.argtypes = [C.POINTER(Events), P, P, C.c_int64, C.POINTER(RecoParams), C.POINTER(RecoOut), P,
                                     P, C.c_size_t, P]
         L.hf_reorder_stats.argtypes = [P, P, C.c_int, P]
+        L.hf_reco_timing_events.argtypes = [P, P]
+        L.hf_reco_timing_events.restype = C.c_int
         L.hf_philox_blocks.argtypes = [P, C.c_uint64, P, C.c_int64, P]
         L.hf_gauss_draws.argtypes = [C.c_uint64, P, P, P, C.c_int64, C.c_int, P, P]
         for f in ("hf_select", "hf_compact", "hf_ttbar_reco", "hf_reorder_stats", "hf_philox_blocks",
@@ -220,6 +222,39 @@ def philox_blocks(ctr, seed, out, stream=None):
 def gauss_draws(seed, g, v, slot, z, precision="mixed", stream=None):
     _check(lib().hf_gauss_draws(int(seed), _p(g), _p(v), _p(slot), g.shape[0], PREC[precision], _p(z),
                                 _stream(stream)), "hf_gauss_draws")
+
+
+class KernelTimer:
+    """HIP events that hf_ttbar_reco records around its search kernel."""
+
+    def __init__(self):
+        self.hip = C.CDLL("libamdhip64.so")
+        self.hip.hipEventCreate.argtypes = [C.POINTER(C.c_void_p)]
+        self.hip.hipEventElapsedTime.argtypes = [C.POINTER(C.c_float), C.c_void_p, C.c_void_p]
+        self.hip.hipEventSynchronize.argtypes = [C.c_void_p]
+        self.hip.hipEventDestroy.argtypes = [C.c_void_p]
+        self.start, self.stop = C.c_void_p(), C.c_void_p()
+        for ev in (self.start, self.stop):
+            if self.hip.hipEventCreate(C.byref(ev)) != 0:
+                raise HFError("hipEventCreate failed")
+
+    def __enter__(self):
+        _check(lib().hf_reco_timing_events(self.start, self.stop), "hf_reco_timing_events")
+        return self
+
+    def __exit__(self, *exc):
+        lib().hf_reco_timing_events(None, None)
+
+    def elapsed_ms(self):
+        self.hip.hipEventSynchronize(self.stop)
+        ms = C.c_float()
+        if self.hip.hipEventElapsedTime(C.byref(ms), self.start, self.stop) != 0:
+            raise HFError("hipEventElapsedTime failed")
+        return float(ms.value)
+
+    def close(self):
+        self.hip.hipEventDestroy(self.start)
+        self.hip.hipEventDestroy(self.stop)
 
 
 def workspace(nbytes, device="cuda"):

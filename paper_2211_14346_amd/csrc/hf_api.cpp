@@ -178,6 +178,12 @@ int hf_ttbar_reco(const hf_events_t *ev, const int32_t *d_idx, const int64_t *d_
     return HF_OK;
 }
 
+int hf_reco_timing_events(hipEvent_t start, hipEvent_t stop) {
+    if ((start == nullptr) != (stop == nullptr)) return fail(HF_ERR_INVAL, "hf_reco_timing_events: one event is NULL");
+    hf::set_reco_timing(start, stop);
+    return HF_OK;
+}
+
 int hf_philox_blocks(const uint32_t *d_ctr, uint64_t seed, uint32_t *d_out, int64_t n, hipStream_t stream) {
     if (n < 0 || n >= ((int64_t)1 << 31)) return fail(HF_ERR_INVAL, "hf_philox_blocks: n out of range");
     if (n > 0 && (!d_ctr || !d_out)) return fail(HF_ERR_INVAL, "hf_philox_blocks: NULL pointer");

@@ -55,14 +55,14 @@ __device__ __forceinline__ T uniform24(uint32_t x) {
 
 // Box-Muller pair from two raw words: (r cos 2 pi u2, r sin 2 pi u2),
 // r = sqrt(-2 ln u1).
+// FP32: the hardware base-2 logarithm and the revolution-scaled sine/cosine
+// units (sin(2 pi u) is one instruction on u itself).
 __device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, float &z0, float &z1) {
     const float u1 = uniform24<float>(a);
     const float u2 = uniform24<float>(b);
-    const float r = sqrtf(-2.0f * logf(u1));
-    float s, c;
-    sincospif(2.0f * u2, &s, &c);
-    z0 = r * c;
-    z1 = r * s;
+    const float r = __builtin_amdgcn_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u1));  // -2 ln u1
+    z0 = r * __builtin_amdgcn_cosf(u2);
+    z1 = r * __builtin_amdgcn_sinf(u2);
 }
 
 __device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, double &z0, double &z1) {

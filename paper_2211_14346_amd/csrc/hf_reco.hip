@@ -267,11 +267,12 @@ __global__ __launch_bounds__(kRecoBlock, 2) void k_search(EvView ev, const int32
                         const double zz = zz4 + (double)zi * zi + (double)zj * zj;
                         const double tbx = sj * st.cand[j][1] + slm * st.lm[1];
                         const double tby = sj * st.cand[j][2] + slm * st.lm[2];
+                        const int nr = __popc(R.mask);  // roots are compacted into slots 0 .. nr-1
                         for (int r = 0; r < 4; ++r) {
-                            if (!((R.mask >> r) & 1)) continue;
+                            if (r >= nr) break;
                             double x = pick4(R.r, r), y;
                             if (!recover_y(A.q, Q, x, y)) continue;
-                            polish_xy(A.q, Q, x, y, 1);
+                            if (!(polish_xy(A.q, Q, x, y, 1) <= kMaxResidual)) continue;
                             const double en = st.sp[i][kE1] * x + st.sp[i][kE2] * y + A.e0;
                             const double xb = mx - x, yb = my - y;
                             const double eb = st.sm[j][kE1] * xb + st.sm[j][kE2] * yb + B.e0;
@@ -504,15 +505,25 @@ int search_grid(int64_t capacity) {
     return (int)(g < 1 ? 1 : g);
 }
 
+hipEvent_t g_time_start = nullptr, g_time_stop = nullptr;
+
 template <typename T>
 hipError_t launch_t(const EvView &ev, const int32_t *idx, const int64_t *count, int64_t capacity, const RecoArgs &a,
                     const RecoOutView &out, hf_counters_t *reco_counter, uint64_t *wstats, BestRec *best,
                     hipStream_t s) {
     if (capacity > 0) {
+        if (g_time_start) {
+            const hipError_t e0 = hipEventRecord(g_time_start, s);
+            if (e0 != hipSuccess) return e0;
+        }
         hipLaunchKernelGGL(k_search<T>, dim3(search_grid<T>(capacity)), dim3(kRecoBlock), 0, s, ev, idx, count,
                            capacity, a, best, wstats);
         hipError_t err = hipGetLastError();
         if (err != hipSuccess) return err;
+        if (g_time_stop) {
+            err = hipEventRecord(g_time_stop, s);
+            if (err != hipSuccess) return err;
+        }
     }
     const int64_t eg = capacity > 0 ? (capacity + 255) / 256 : 1;
     hipLaunchKernelGGL(k_epilogue<T>, dim3((unsigned)eg), dim3(256), 0, s, ev, idx, count, capacity, a, best, out,
@@ -521,6 +532,11 @@ hipError_t launch_t(const EvView &ev, const int32_t *idx, const int64_t *count, 
 }
 
 }  // namespace
+
+void set_reco_timing(hipEvent_t start, hipEvent_t stop) {
+    g_time_start = start;
+    g_time_stop = stop;
+}
 
 size_t reco_ws_bytes(int64_t capacity) { return kWsHeader + (size_t)(capacity > 0 ? capacity : 0) * sizeof(BestRec); }
 

@@ -176,15 +176,43 @@ HF_HD __forceinline__ double peval_d2(const Poly4 &c, double t) {
     return fma(fma(12.0 * c.c4, t, 6.0 * c.c3), t, 2.0 * c.c2);
 }
 
-// Precision-explicit elementary functions for the templated cubic.
+// Elementary functions for the templated cubic.  FP64: the accurate library
+// functions.  FP32 (seeds only, refined in FP64 afterwards): hardware
+// approximations -- cube root through the base-2 exponential and logarithm
+// units, arc cosine by the four-term approximation of Abramowitz & Stegun
+// 4.4.45 (|error| < 7e-5 rad), cosine/sine through the revolution-scaled
+// hardware units.
 HF_HD __forceinline__ float tsqrt(float v) { return sqrtf(v); }
 HF_HD __forceinline__ double tsqrt(double v) { return sqrt(v); }
-HF_HD __forceinline__ float tcbrt(float v) { return cbrtf(v); }
 HF_HD __forceinline__ double tcbrt(double v) { return cbrt(v); }
-HF_HD __forceinline__ float tacos(float v) { return acosf(v); }
+HF_HD __forceinline__ float tcbrt(float v) {
+#ifdef __HIP_DEVICE_COMPILE__
+    const float m = __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(fabsf(v)) * (1.0f / 3.0f));
+#else
+    const float m = exp2f(log2f(fabsf(v)) * (1.0f / 3.0f));
+#endif
+    return v == 0.0f ? 0.0f : copysignf(m, v);
+}
 HF_HD __forceinline__ double tacos(double v) { return acos(v); }
-HF_HD __forceinline__ float tcos(float v) { return cosf(v); }
-HF_HD __forceinline__ double tcos(double v) { return cos(v); }
+HF_HD __forceinline__ float tacos(float x) {
+    const float ax = fabsf(x);
+    const float r = sqrtf(1.0f - ax) * (1.5707288f + ax * (-0.2121144f + ax * (0.0742610f - 0.0187293f * ax)));
+    return x < 0.0f ? 3.14159265358979f - r : r;
+}
+HF_HD __forceinline__ void tsincos(double a, double &s, double &c) {
+    s = sin(a);
+    c = cos(a);
+}
+HF_HD __forceinline__ void tsincos(float a, float &s, float &c) {
+#ifdef __HIP_DEVICE_COMPILE__
+    const float rev = a * 0.15915494309189535f;  // radians -> revolutions
+    s = __builtin_amdgcn_sinf(rev);
+    c = __builtin_amdgcn_cosf(rev);
+#else
+    s = sinf(a);
+    c = cosf(a);
+#endif
+}
 HF_HD __forceinline__ float tmin(float a, float b) { return fminf(a, b); }
 HF_HD __forceinline__ double tmin(double a, double b) { return fmin(a, b); }
 HF_HD __forceinline__ float tmax(float a, float b) { return fmaxf(a, b); }
@@ -213,10 +241,13 @@ HF_HD __forceinline__ int cubic_roots(T A, T B, T C, T &r0, T &r1, T &r2) {
     T cosarg = (rr > (T)0) ? -h / (rr * rr * rr) : (T)0;
     cosarg = tmin(tmax(cosarg, (T)-1), (T)1);
     const T phi = tacos(cosarg) * third;
-    const T tpi3 = (T)(2.0943951023931954923);
-    const T x0 = (T)2 * rr * tcos(phi) - a3;         // largest
-    const T x1 = (T)2 * rr * tcos(phi - tpi3) - a3;  // middle
-    const T x2 = (T)2 * rr * tcos(phi + tpi3) - a3;  // smallest
+    T sn, cs;
+    tsincos(phi, sn, cs);
+    // cos(phi -+ 2 pi / 3) = -cos(phi) / 2 +- sin(phi) sqrt(3) / 2
+    const T h3 = (T)0.86602540378443865 * sn;
+    const T x0 = (T)2 * rr * cs - a3;                        // largest
+    const T x1 = (T)2 * rr * ((T)-0.5 * cs + h3) - a3;       // middle
+    const T x2 = (T)2 * rr * ((T)-0.5 * cs - h3) - a3;       // smallest
     r0 = tmin(tmin(x0, x1), x2);
     r2 = tmax(tmax(x0, x1), x2);
     r1 = x0 + x1 + x2 - r0 - r2;
@@ -248,7 +279,7 @@ HF_HD __forceinline__ double bracket_newton(const Poly4 &c, double lo, double hi
 }
 
 // Sign-changing real roots (in x units) of q0 + q1 x + ... + q4 x^4, at most
-// four, ascending over the slots whose bit is set in the returned mask.
+// four, ascending in slots 0 .. popcount(mask) - 1.
 struct Roots4 {
     double r[4];
     int mask;
@@ -394,16 +425,39 @@ HF_HD Roots4 quartic_real_roots(const double qx[5]) {
     const double f1 = e1 < bound ? peval(c, e1) : sb;
     const double f2 = e2 < bound ? peval(c, e2) : sb;
     const double f3 = e3 < bound ? peval(c, e3) : sb;
-    bool found;
-    double rt;
-    solve_interval(c, -bound, e1, f0, f1, false, e1 < bound, rt, found);
-    if (found) { out.r[0] = rt; out.mask |= 1; }
-    solve_interval(c, e1, e2, f1, f2, e1 < bound, e2 < bound, rt, found);
-    if (found) { out.r[1] = rt; out.mask |= 2; }
-    solve_interval(c, e2, e3, f2, f3, e2 < bound, e3 < bound, rt, found);
-    if (found) { out.r[2] = rt; out.mask |= 4; }
-    solve_interval(c, e3, bound, f3, sb, e3 < bound, false, rt, found);
-    if (found) { out.r[3] = rt; out.mask |= 8; }
+    // brackets of the four intervals, compacted so that the Newton loops run
+    // only as many times as the lane with the most roots needs
+    const double lo[4] = {-bound, e1, e2, e3}, hi[4] = {e1, e2, e3, bound};
+    const double flo[4] = {f0, f1, f2, f3}, fhi[4] = {f1, f2, f3, sb};
+    const bool clo[4] = {false, e1 < bound, e2 < bound, e3 < bound};
+    const bool chi[4] = {e1 < bound, e2 < bound, e3 < bound, false};
+    double blo[4] = {0, 0, 0, 0}, bhi[4] = {0, 0, 0, 0}, bfl[4] = {0, 0, 0, 0}, bfh[4] = {0, 0, 0, 0};
+    bool bcl[4] = {false, false, false, false}, bch[4] = {false, false, false, false};
+    int nb = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const bool sc = ((flo[k] < 0.0 && fhi[k] > 0.0) || (flo[k] > 0.0 && fhi[k] < 0.0)) && hi[k] > lo[k];
+#pragma unroll
+        for (int b = 0; b <= k; ++b)
+            if (sc && nb == b) {
+                blo[b] = lo[k];
+                bhi[b] = hi[k];
+                bfl[b] = flo[k];
+                bfh[b] = fhi[k];
+                bcl[b] = clo[k];
+                bch[b] = chi[k];
+            }
+        nb += sc ? 1 : 0;
+    }
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        if (b >= nb) break;
+        bool found;
+        double rt;
+        solve_interval(c, blo[b], bhi[b], bfl[b], bfh[b], bcl[b], bch[b], rt, found);
+        out.r[b] = rt;
+    }
+    out.mask = (1 << nb) - 1;
     return out;
 }
 
@@ -457,12 +511,18 @@ HF_HD __forceinline__ bool recover_y(const Conic &P, const Conic &Q, double x, d
 }
 
 // Newton's method on the two conics for (x, y), each step kept only while it
-// lowers the larger relative residual.
-HF_HD __forceinline__ void polish_xy(const Conic &P, const Conic &Q, double &x, double &y, int iters) {
+// lowers the larger relative residual; returns that residual at the final
+// point (an intersection is accepted only if it is <= kMaxResidual).
+constexpr double kMaxResidual = 1e-6;
+
+// Points already at a residual <= kPolishFrom are left as they are.
+constexpr double kPolishFrom = 1e-10;
+
+HF_HD __forceinline__ double polish_xy(const Conic &P, const Conic &Q, double &x, double &y, int iters) {
     double f1 = conic_eval(P, x, y), f2 = conic_eval(Q, x, y);
     double res = fmax(fabs(f1) * fast_rcp(conic_mag(P, x, y)), fabs(f2) * fast_rcp(conic_mag(Q, x, y)));
     for (int it = 0; it < iters; ++it) {
-        if (!(res > 0.0)) break;
+        if (!(res > kPolishFrom)) break;
         const double a11 = 2.0 * P.xx * x + P.xy * y + P.x, a12 = P.xy * x + 2.0 * P.yy * y + P.y;
         const double a21 = 2.0 * Q.xx * x + Q.xy * y + Q.x, a22 = Q.xy * x + 2.0 * Q.yy * y + Q.y;
         const double det = a11 * a22 - a12 * a21;
@@ -479,6 +539,7 @@ HF_HD __forceinline__ void polish_xy(const Conic &P, const Conic &Q, double &x, 
         f2 = g2;
         res = rn;
     }
+    return res;
 }
 
 }  // namespace hf

@@ -3,6 +3,9 @@
 Readings of the agreement targets:
   * the RECO pass/fail decision and the chosen (variation, jet pair) must agree
     in >= 99.9 % of events (a floating-point decision, not bit-exact);
+  * the choice is the variation, the jet pair and the root of that pairing's
+    quartic (two nearly coincident roots score almost alike, so rounding may
+    swap them: a swap is a choice difference);
   * where the chosen solution is the same, every reconstructed quantity agrees
     within 1e-4 relative: momenta as |dp| / max(|p_ref|, 1 GeV), masses and the
     score as |d| / max(|ref|, 1).
@@ -18,8 +21,12 @@ def compare(g, w, n=None):
     S = len(w["has_sol"]) if n is None else n
     hs_g, hs_w = g["has_sol"][:S].astype(bool), w["has_sol"][:S].astype(bool)
     both = hs_g & hs_w
+    # same choice = same variation, same jet pair and the same root of that
+    # pairing's quartic (identified by (px, py) of the neutrino within 1e-3)
+    same_root = np.all(np.abs(g["nu"][:S, :2] - w["nu"][:S, :2]) <= 1e-3 * np.maximum(np.abs(w["nu"][:S, :2]), 1.0),
+                       axis=1)
     same = both & (g["best_v"][:S] == w["best_v"][:S]) & (g["best_i"][:S] == w["best_i"][:S]) & \
-        (g["best_j"][:S] == w["best_j"][:S])
+        (g["best_j"][:S] == w["best_j"][:S]) & same_root
     st = {"S": int(S), "decision_agree": float(np.mean(hs_g == hs_w)) if S else 1.0,
           "n_both": int(both.sum()), "n_same": int(same.sum()),
           "choice_agree": float(same.sum() / both.sum()) if both.sum() else 1.0,
