@@ -465,7 +465,12 @@ static orc_linmap orc_linear_map(vec4 l, vec4 b, double mt, double mw)
     double kb = 0.5 * (mt * mt - mw * mw - mb2 - 2.0 * orc_dot(b, l));
     /* system  [El -lz; Eb -bz] [E; z] = [r1; r2] */
     double det = l.z * b.e - l.e * b.z; /* = El*(-bz) - (-lz)*Eb */
-    m.ok = fabs(det) > 1e-12 * l.e * b.e;
+    /* Reading: the system is treated as degenerate when |det| <= 1e-5 El Eb
+     * (for massless l and b: their direction cosines along the beam agree to
+     * 1e-5).  The map's coefficients grow as 1/det and the rounding of the
+     * mass shell faster still; below this bound FP64 no longer resolves the
+     * constraints to the acceptance bound used below. */
+    m.ok = fabs(det) > 1e-5 * l.e * b.e;
     if (!m.ok) return m;
     /* Cramer: E = (r1*(-bz) - (-lz)*r2)/det, z = (El*r2 - Eb*r1)/det, applied to
      * each of the three right-hand-side components (x coeff, y coeff, constant). */
@@ -655,13 +660,15 @@ int orc_solve_pairing_v(vec4 lp, vec4 b, vec4 lm, vec4 bb, double metx, double m
         }
         /* A root of the eliminant only says the two conics share a root in y; the
          * point is a solution of the mass constraints (section 4) only if both
-         * conics vanish there.  Reading: both relative residuals <= 1e-6 after
-         * the polish, which separates true intersections (<= 1e-9) from
-         * near-tangent artefacts. */
+         * conics vanish there.  The W and top constraints hold by construction
+         * of the linear maps, and each conic's value is that neutrino's squared
+         * mass E^2 - p^2 in GeV^2, so (l + nu)^2 - mW^2 and (b + l + nu)^2 - mt^2
+         * both equal it.  Reading: accept when both squared masses are within
+         * 2e-6 mW^2 of zero after the polish (every mass constraint then holds to
+         * 1e-6 relative), which also rejects near-tangent artefacts. */
         {
-            double g1 = orc_conic_rel(c1, x, y, orc_conic_eval(c1, x, y));
-            double g2 = orc_conic_rel(c2, x, y, orc_conic_eval(c2, x, y));
-            if (!(g1 <= 1e-6 && g2 <= 1e-6)) continue;
+            double tol = 2e-6 * mw * mw;
+            if (!(fabs(orc_conic_eval(c1, x, y)) <= tol && fabs(orc_conic_eval(c2, x, y)) <= tol)) continue;
         }
         double xb = metx - x, yb = mety - y;
         double en = m1.ex * x + m1.ey * y + m1.e0;

@@ -38,9 +38,17 @@ def _nu(s):
 def test_closure_on_generated_truth(orc, truth_sample):
     tr = truth_sample["truth"]
     errs = []
+    n_degenerate = 0
     for e in range(truth_sample["n"]):
         lp, lm, b, bb, nu, nub = (tr[k][e] for k in ("lp", "lm", "b", "bbar", "nu", "nubar"))
         sol = orc.solve_pairing(lp, b, lm, bb, nu[1] + nub[1], nu[2] + nub[2])
+        # reading: a side whose linear maps are degenerate (|det| <= 1e-5 El Eb)
+        # gives the pairing no solution
+        degenerate = any(abs(l[3] * q[0] - l[0] * q[3]) <= 1e-5 * l[0] * q[0] for l, q in ((lp, b), (lm, bb)))
+        if degenerate:
+            assert len(sol) == 0
+            n_degenerate += 1
+            continue
         assert 1 <= len(sol) <= 4
         d1 = np.abs(sol[:, 0:3] - nu[1:4]).max(axis=1) / np.linalg.norm(nu[1:4])
         d2 = np.abs(sol[:, 4:7] - nub[1:4]).max(axis=1) / np.linalg.norm(nub[1:4])
@@ -51,6 +59,7 @@ def test_closure_on_generated_truth(orc, truth_sample):
     assert errs.max() < 1e-4
     assert np.quantile(errs, 0.99) < 1e-9
     assert np.median(errs) < 1e-12
+    assert n_degenerate <= 2
 
 
 def test_closure_float32_inputs(orc):
@@ -132,6 +141,55 @@ def test_brute_force_50_digits(orc, truth_sample):
             assert np.abs(g - wv).max() <= tol * scale, (k, g, wv)
         checked += 1
     assert checked > 100
+
+
+def _align(lep, b, d):
+    """b made massless with its direction cosine along the beam equal to the
+    (massless) lepton's shifted by d, azimuth and momentum kept: then
+    |lz Eb - El bz| = d El Eb, the determinant of the linear maps."""
+    pl = np.linalg.norm(lep[1:])
+    ct = lep[3] / pl
+    ctb = ct - d * np.sign(ct)
+    stb = np.sqrt(1.0 - ctb * ctb)
+    pb, phb = np.linalg.norm(b[1:]), np.arctan2(b[2], b[1])
+    return np.array([pb, pb * stb * np.cos(phb), pb * stb * np.sin(phb), pb * ctb])
+
+
+def test_near_degenerate_pairings(orc, truth_sample):
+    """A lepton and b jet of nearly equal rapidity make the two linear mass
+    conditions nearly dependent.  Readings pinned: below |det| = 1e-5 El Eb
+    the pairing has no solution; above it every accepted solution satisfies
+    the mass constraints to the acceptance bound (2e-6 mW^2 on m_nu^2, i.e.
+    1e-6 relative on the masses, plus rounding) and matches the 50-digit
+    brute force."""
+    tr = truth_sample["truth"]
+    n_sol = n_brute = 0
+    for e in range(24):
+        lp, lm, b, bb, nu, nub = (tr[k][e] for k in ("lp", "lm", "b", "bbar", "nu", "nubar"))
+        lp0 = np.array([np.linalg.norm(lp[1:]), *lp[1:]])
+        mx, my = nu[1] + nub[1], nu[2] + nub[2]
+        assert len(orc.solve_pairing(lp0, _align(lp0, b, 3e-6), lm, bb, mx, my)) == 0
+        assert len(orc.solve_pairing(lp0, _align(lp0, b, 0.0), lm, bb, mx, my)) == 0
+        for d in (1e-3, 1e-4, 2e-5):
+            b2 = _align(lp0, b, d)
+            got = orc.solve_pairing(lp0, b2, lm, bb, mx, my)
+            for sol in got:
+                nv, nbv = _nu(sol)
+                for m, want in ((_mass(lp0 + nv), M_W), (_mass(b2 + lp0 + nv), M_T),
+                                (_mass(lm + nbv), M_W), (_mass(bb + lm + nbv), M_T)):
+                    assert abs(m - want) <= 2e-6 * want, (e, d, m)
+            n_sol += len(got)
+            if d != 1e-3:
+                want, sep = brute_mp.solve(lp0, b2, lm, bb, mx, my)
+                if float(sep) < 1e-6:
+                    continue
+                assert len(got) == len(want), (e, d)
+                for g, w in zip(got, want):
+                    wv = np.array([float(v) for v in w])
+                    scale = np.linalg.norm(wv[0:3]) + np.linalg.norm(wv[4:7])
+                    assert np.abs(g - wv).max() <= 1e-6 * scale, (e, d, g, wv)
+                n_brute += len(want)
+    assert n_sol > 20 and n_brute > 8
 
 
 def _rot(v, th):
