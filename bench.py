@@ -24,15 +24,16 @@ sys.path.insert(0, ROOT)
 WORKLOAD = "ttbar1M_v64"
 
 # Algorithmic FP operations of the reconstruction search kernel per unit of
-# work, counted on the kernel's formulas for real (non-padded) work items:
-# per variation (draws, smearing, lepton-side terms), per pairing solved
-# (side terms, conic substitution, eliminant, normalisation, critical points
-# and their signs) and per accepted solution (y recovery, one conic polish,
-# energies and score).  Root-finding iterations are counted per pairing at
-# their mean.  FMA counts as two operations.  Derivation in the design notes.
-FLOP_PER_VARIATION = 60
-FLOP_PER_PAIRING = 420
-FLOP_PER_SOLUTION = 150
+# work (one each for add, mul, div, sqrt, transcendental; two for FMA),
+# measured by paper_2211_14346_amd/perf/opcount.py, which runs the kernel's
+# own math header on the host with counting scalar types over a sample of
+# this workload: per variation the Box-Muller draws, smear factors, MET shifts
+# and lepton-side terms; per pairing the side terms, MET substitution,
+# eliminant and root intervals; per root interval the Newton solve, recovery
+# of y, acceptance test and score.
+FLOP_PER_VARIATION = 78
+FLOP_PER_PAIRING = 286
+FLOP_PER_INTERVAL = 223
 
 # MI355X vector peaks (256 CUs at 2.4 GHz): FP64 78.6 TFLOP/s; FP32 157.3 with
 # packed FP32, which this build does not use (non-packed FP32 issues at the
@@ -52,6 +53,9 @@ def _parse():
     ap.add_argument("--no-fp64-form", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=200_000)
     ap.add_argument("--profile-only", action="store_true", help="few steps, no CPU baseline (for profilers)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB a few times (to scale the "
+                         "FETCH_SIZE / WRITE_SIZE counters into bytes) and exit")
     return ap.parse_args()
 
 
@@ -70,6 +74,15 @@ def main():
     if not torch.cuda.is_available():
         print("no GPU", file=sys.stderr)
         sys.exit(1)
+    if args.copy_calibration:
+        nbytes = args.copy_calibration << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": nbytes, "copies": 5}))
+        return
     cfg = hfgen.config(WORKLOAD)
     t0 = time.time()
     ev = hfgen.generate(cfg)
@@ -108,16 +121,19 @@ def main():
             kms.append(timer.elapsed_ms())
     timer.close()
     stats1 = ch.out.t["stats"].cpu().numpy().astype(np.int64)
-    per = (stats1 - stats0) / len(kms)  # events, variations, pairings, solutions per launch
+    per = (stats1 - stats0) / len(kms)  # events, variations, pairings, intervals, solutions per launch
     kernel_ms = float(np.mean(kms))
-    flops = FLOP_PER_VARIATION * per[1] + FLOP_PER_PAIRING * per[2] + FLOP_PER_SOLUTION * per[3]
+    flops = FLOP_PER_VARIATION * per[1] + FLOP_PER_PAIRING * per[2] + FLOP_PER_INTERVAL * per[3]
     achieved = flops / (kernel_ms * 1e-3) / 1e12
-    roofline = {"bound": "alu", "kernel": "k_search<float>" if args.precision == "mixed" else "k_search<double>",
+    kname = "k_search<float>" if args.precision == "mixed" else "k_search<double>"
+    roofline = {"bound": "alu", "kernel": kname,
                 "achieved": round(achieved, 3), "peak": PEAK_ALU_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_ALU_TFLOPS, 4), "traffic": None,
+                "frac": round(achieved / PEAK_ALU_TFLOPS, 4), "traffic": measured_traffic(kname),
                 "kernel_ms": round(kernel_ms, 4), "flop_per_launch": float(flops),
                 "units_per_launch": {"events": int(per[0]), "variations": int(per[1]), "pairings": int(per[2]),
-                                     "solutions": int(per[3])}}
+                                     "intervals": int(per[3]), "solutions": int(per[4])},
+                "flop_per_unit": {"variation": FLOP_PER_VARIATION, "pairing": FLOP_PER_PAIRING,
+                                  "interval": FLOP_PER_INTERVAL}}
 
     out = {"metric": cfg_metric(), "value": round(value, 1), "unit": "events/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
@@ -141,6 +157,28 @@ def main():
         out["cpu_baseline"], acc = cpu_baseline(ev, cfg, args, torch)
         out["accuracy_vs_oracle"] = acc
     print(json.dumps(out))
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of the search kernel from the committed rocprofv3
+    counter summary (FETCH_SIZE + WRITE_SIZE scaled by a device-copy
+    calibration), or None when the summary is for another kernel or for
+    different kernel sources than the ones built here."""
+    from paper_2211_14346_amd.perf import built_source_hash, search_source_hash
+    built = built_source_hash()
+    if built is None or built != search_source_hash():
+        return None  # library and sources differ: the counters cannot be attributed
+    path = os.path.join(ROOT, "profiles", "k_search_ttbar1M_v64_counters.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("search_kernel") != kernel or kv.get("search_source_hash") != built:
+        return None
+    return int(kv["search_traffic_bytes_per_launch"])
 
 
 def cfg_metric():

@@ -202,8 +202,8 @@ typedef struct hf_reco_params {
  * Masses are recomputed from the chosen solution; logw is its score; m_bb
  * (may be NULL) is the mass of the two leading remaining b jets.  Positions
  * without a solution get has_sol = 0, best_* = -1 and HF_NO_SOLUTION in every
- * float output.  stats (may be NULL) accumulates 4 uint64 counts: events,
- * variations, pairings solved, accepted solutions. */
+ * float output.  stats (may be NULL) accumulates 5 uint64 counts: events,
+ * variations, pairings solved, root intervals solved, accepted solutions. */
 typedef struct hf_reco_out {
     uint8_t *has_sol;
     int32_t *n_sol, *best_v;

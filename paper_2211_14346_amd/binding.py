@@ -189,7 +189,7 @@ class RecoOutputs:
             "m_t": torch.zeros(cap, **f64), "m_tbar": torch.zeros(cap, **f64), "m_wp": torch.zeros(cap, **f64),
             "m_wm": torch.zeros(cap, **f64), "logw": torch.zeros(cap, **f64),
             "m_bb": torch.zeros(cap, **f64) if want_mbb else None,
-            "stats": torch.zeros(4, dtype=torch.int64, device=device),
+            "stats": torch.zeros(5, dtype=torch.int64, device=device),
         }
         self.s = RecoOut(**{k: (None if v is None else v.data_ptr()) for k, v in self.t.items()})
 

@@ -54,6 +54,11 @@ def build(verbose=False):
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
     os.replace(tmp, LIB)
+    # identity of the search kernel's sources this library was built from
+    sys.path.insert(0, os.path.dirname(HERE))
+    from paper_2211_14346_amd.perf import search_source_hash
+    with open(LIB + ".srchash", "w") as f:
+        f.write(search_source_hash() + "\n")
     return LIB
 
 

@@ -9,6 +9,7 @@
 
 #include "../../include/hf.h"
 #include "hf_internal.hpp"
+#include "hf_reco_math.hpp"
 
 namespace {
 
@@ -155,6 +156,9 @@ int hf_ttbar_reco(const hf_events_t *ev, const int32_t *d_idx, const int64_t *d_
     a.m_t = p->m_t;
     a.m_w = p->m_w;
     a.lambda_pt = p->lambda_pt;
+    a.inv_lambda = 1.0 / p->lambda_pt;
+    a.accept_m2 = hf::kAcceptM2 * p->m_w * p->m_w;
+    a.polish_skip_m2 = hf::kPolishSkip * a.accept_m2;
     a.jet_a = p->jet_a;
     a.jet_c = p->jet_c;
     a.lep_sigma = p->lep_sigma;

@@ -1,13 +1,15 @@
 // Stream compaction of a byte mask into ascending indices (paper section 3:
 // the events that pass every cut form the filtered output).
 //
-// Single pass with decoupled look-back.  A tile is 256 threads x 16 bytes;
+// Single pass with decoupled look-back.  A tile is 512 threads x 16 bytes;
 // tiles are numbered by an atomic ticket in the order blocks start, so a
 // tile only ever waits on tiles whose blocks are already running.  Each
 // thread loads its 16 mask bytes with one 128-bit load when aligned, counts
 // them, the block scans the counts (wave64 shuffles + LDS), publishes its
-// aggregate, looks back over the predecessors' published values to obtain
-// its exclusive prefix, publishes its inclusive prefix and scatters.  HBM
+// aggregate, and its first wavefront looks back over a window of 64
+// predecessors per round trip (one device-scope load per lane, a ballot for
+// the nearest inclusive prefix, a wave reduction of the aggregates before
+// it), then publishes its inclusive prefix and the block scatters.  HBM
 // traffic: 1 byte per entry read, 4 bytes per kept entry written.
 //
 // Status words (64 bit): bits 62-63 = 0 (not ready), 1 (aggregate), 2
@@ -19,7 +21,7 @@
 namespace hf {
 namespace {
 
-constexpr int kCB = 256;
+constexpr int kCB = 512;
 constexpr int kCPT = 16;
 constexpr int kTile = kCB * kCPT;
 constexpr uint64_t kFlagAgg = 1ull << 62;
@@ -93,26 +95,36 @@ __global__ __launch_bounds__(kCB) void k_compact(const uint8_t *__restrict__ mas
     }
     const uint32_t excl_thread = wbase + incl - cnt;
 
-    // ---- publish aggregate, look back, publish inclusive prefix
-    if (tid == 0) {
+    // ---- publish aggregate, look back (first wavefront), publish inclusive prefix
+    if (wave == 0) {
         uint64_t prefix = 0;
         if (tile == 0) {
-            store_status(&status[0], kFlagInc | (uint64_t)total);
+            if (lane == 0) store_status(&status[0], kFlagInc | (uint64_t)total);
         } else {
-            store_status(&status[tile], kFlagAgg | (uint64_t)total);
-            int64_t j = tile - 1;
+            if (lane == 0) store_status(&status[tile], kFlagAgg | (uint64_t)total);
+            int64_t top = tile - 1;  // newest predecessor of the current window
             while (true) {
-                const uint64_t s = load_status(&status[j]);
-                const uint64_t flag = s & ~kValMask;
-                if (flag == 0) continue;  // predecessor still counting
-                prefix += s & kValMask;
-                if (flag == kFlagInc) break;
-                --j;
+                const int64_t j = top - lane;
+                const uint64_t st = j >= 0 ? load_status(&status[j]) : kFlagInc;  // before tile 0: prefix 0
+                const uint64_t flag = st & ~kValMask;
+                const uint64_t inc = ballot(flag == kFlagInc);
+                const uint64_t ready = ballot(flag != 0);
+                // lanes up to and including the nearest inclusive prefix must all be ready
+                const int first = inc ? __ffsll((unsigned long long)inc) - 1 : kWave - 1;
+                const uint64_t need = first == kWave - 1 ? ~0ull : ((2ull << first) - 1);
+                if ((ready & need) != need) continue;  // a predecessor is still counting
+                uint64_t v = (lane <= first && j >= 0) ? (st & kValMask) : 0;
+                for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off);
+                prefix += v;
+                if (inc) break;
+                top -= kWave;
             }
-            store_status(&status[tile], kFlagInc | (prefix + total));
+            if (lane == 0) store_status(&status[tile], kFlagInc | (prefix + total));
         }
-        s_prefix = prefix;
-        if (tile == n_tiles - 1) *count = (int64_t)(prefix + total);
+        if (lane == 0) {
+            s_prefix = prefix;
+            if (tile == n_tiles - 1) *count = (int64_t)(prefix + total);
+        }
     }
     __syncthreads();
 

@@ -46,7 +46,8 @@ hipError_t launch_compact(const uint8_t *mask, int64_t capacity, const int64_t *
 
 // ---- reconstruction (hf_reco.hip)
 struct RecoArgs {
-    double m_t, m_w, lambda_pt;
+    double m_t, m_w, lambda_pt, inv_lambda;
+    double accept_m2, polish_skip_m2;  // GeV^2: acceptance bound and no-polish bound on m_nu^2
     double jet_a, jet_c, lep_sigma, met_sigma;
     float lep_pt_min, lep_eta_max, jet_pt_min, jet_eta_max, btag_min;
     uint64_t seed;

@@ -57,6 +57,7 @@ struct WaveStage {
     int okp[kMaxC], okm[kMaxC];
     int lsel[2];
     T z[kMaxC][kWave];  // per-lane draw of each candidate
+    T zl[4][kWave];     // per-lane draws of l+, l-, MET x, MET y
 };
 
 __device__ __forceinline__ void wave_sync() {
@@ -98,6 +99,25 @@ __device__ __forceinline__ bool jet_sel(const EvView &ev, uint32_t k, const Reco
     return ev.jet_pt[k] > a.jet_pt_min && fabsf(ev.jet_eta[k]) < a.jet_eta_max;
 }
 
+// Index of the r-th set bit (from 0) of m; r < popcount(m).
+__device__ __forceinline__ int nth_set_bit(uint64_t m, int r) {
+    int pos = 0;
+#pragma unroll
+    for (int w = 32; w >= 1; w >>= 1) {
+        const int c = popc64((m >> pos) & ((1ull << w) - 1));
+        if (r >= c) {
+            r -= c;
+            pos += w;
+        }
+    }
+    return pos;
+}
+
+template <typename X>
+__device__ __forceinline__ X from_lane(X v, int src) {
+    return __shfl(v, src);
+}
+
 __device__ __forceinline__ int64_t clamp_count(const int64_t *count, int64_t capacity) {
     const int64_t S = *count;
     return S < 0 ? 0 : (S > capacity ? capacity : S);
@@ -116,7 +136,7 @@ __global__ __launch_bounds__(kRecoBlock, 2) void k_search(EvView ev, const int32
     const int64_t nwaves = (int64_t)gridDim.x * kRecoWaves;
     const double mt2_mw2 = a.m_t * a.m_t - a.m_w * a.m_w;
     const double mw2 = a.m_w * a.m_w;
-    uint64_t acc_var = 0, acc_pair = 0, acc_sol = 0;
+    uint64_t acc_var = 0, acc_pair = 0, acc_int = 0, acc_sol = 0;
 
     for (int64_t k = (int64_t)blockIdx.x * kRecoWaves + wave; k < S; k += nwaves) {
         const int64_t e = (int64_t)idx[k] - ev.index_base;
@@ -220,70 +240,135 @@ __global__ __launch_bounds__(kRecoBlock, 2) void k_search(EvView ev, const int32
             for (int vb = 0; vb < V; vb += kWave) {
                 const int v = vb + lane;
                 const bool act = v < V;
-                T zl[4] = {(T)0, (T)0, (T)0, (T)0};
-                if (a.smear && act) {
-                    gauss_block<T>(a.seed, g, (uint32_t)v, 0u, zl);
-                    uint32_t last_blk = 0xffffffffu;
-                    T zb[4];
-                    for (int c = 0; c < nc; ++c) {
-                        const uint32_t slot = 4u + (uint32_t)st.jidx[c];
-                        const uint32_t blk = slot >> 2;
-                        if (blk != last_blk) {
-                            gauss_block<T>(a.seed, g, (uint32_t)v, blk, zb);
-                            last_blk = blk;
+                // ---- draws of this lane's variation, kept in LDS so that any lane can
+                // rebuild another lane's smear factors
+                {
+                    T zl[4] = {(T)0, (T)0, (T)0, (T)0};
+                    if (a.smear && act) {
+                        gauss_block<T>(a.seed, g, (uint32_t)v, 0u, zl);
+                        uint32_t last_blk = 0xffffffffu;
+                        T zb[4];
+                        for (int c = 0; c < nc; ++c) {
+                            const uint32_t slot = 4u + (uint32_t)st.jidx[c];
+                            const uint32_t blk = slot >> 2;
+                            if (blk != last_blk) {
+                                gauss_block<T>(a.seed, g, (uint32_t)v, blk, zb);
+                                last_blk = blk;
+                            }
+                            const uint32_t ln = slot & 3u;
+                            st.z[c][lane] = ln == 0 ? zb[0] : ln == 1 ? zb[1] : ln == 2 ? zb[2] : zb[3];
                         }
-                        const uint32_t ln = slot & 3u;
-                        st.z[c][lane] = ln == 0 ? zb[0] : ln == 1 ? zb[1] : ln == 2 ? zb[2] : zb[3];
+                    } else {
+                        for (int c = 0; c < nc; ++c) st.z[c][lane] = (T)0;
                     }
-                } else {
-                    for (int c = 0; c < nc; ++c) st.z[c][lane] = (T)0;
+                    st.zl[0][lane] = zl[0];
+                    st.zl[1][lane] = zl[1];
+                    st.zl[2][lane] = zl[2];
+                    st.zl[3][lane] = zl[3];
                 }
-                if (!act) continue;
-                const double slp = smear(a.lep_sigma, zl[0]);
-                const double slm = smear(a.lep_sigma, zl[1]);
-                const double mx = metx + a.met_sigma * (double)zl[2];
-                const double my = mety + a.met_sigma * (double)zl[3];
-                const double zz4 = (double)zl[0] * zl[0] + (double)zl[1] * zl[1] + (double)zl[2] * zl[2] +
-                                   (double)zl[3] * zl[3];
+                wave_sync();
+                const double slp = smear(a.lep_sigma, st.zl[0][lane]);
+                const double slm = smear(a.lep_sigma, st.zl[1][lane]);
+                const double mx = metx + a.met_sigma * (double)st.zl[2][lane];
+                const double my = mety + a.met_sigma * (double)st.zl[3][lane];
                 const double Wp = mw2 / (2.0 * slp) - 0.5 * slp * st.ml2p;
                 const double Wm = mw2 / (2.0 * slm) - 0.5 * slm * st.ml2m;
                 for (int i = 0; i < nc; ++i) {
                     if (!st.okp[i]) continue;
-                    const T zi = st.z[i][lane];
-                    const double si = smear(st.sigma[i], zi);
+                    const double si = smear(st.sigma[i], st.z[i][lane]);
                     const SideVar A = side_var(st.sp[i], Wp, slp, si, mt2_mw2);
-                    const double tx = si * st.cand[i][1] + slp * st.lp[1];  // (b + l+)_T
-                    const double ty = si * st.cand[i][2] + slp * st.lp[2];
                     for (int j = 0; j < nc; ++j) {
                         if (j == i || !st.okm[j]) continue;
-                        const T zj = st.z[j][lane];
-                        const double sj = smear(st.sigma[j], zj);
-                        const SideVar B = side_var(st.sm[j], Wm, slm, sj, mt2_mw2);
-                        const Conic Q = reflect(B.q, mx, my);
-                        double qc[5];
-                        eliminant(A.q, Q, qc);
-                        const Roots4 R = quartic_real_roots<T>(qc);
+                        // ---- stage 1 (own variation): eliminant quartic and its root intervals
+                        const double sj = smear(st.sigma[j], st.z[j][lane]);
+                        const SideVar Bv = side_var(st.sm[j], Wm, slm, sj, mt2_mw2);
+                        const Conic Q = reflect(Bv.q, mx, my);
+                        Brackets Bk;
+                        Bk.mask = 0;
+                        if (act) {
+                            double qc[5];
+                            eliminant(A.q, Q, qc);
+                            Bk = quartic_brackets<T>(qc);
+                        }
+                        // ---- stage 2: the wave's root intervals dealt out to lanes, 64 at a time
+                        const uint64_t m0 = ballot(Bk.mask & 1), m1 = ballot(Bk.mask & 2);
+                        const uint64_t m2 = ballot(Bk.mask & 4), m3 = ballot(Bk.mask & 8);
+                        const int n0 = popc64(m0), n1 = popc64(m1), n2 = popc64(m2), n3 = popc64(m3);
+                        const int total = n0 + n1 + n2 + n3;
                         const int p = i * nc + j;
-                        const double zz = zz4 + (double)zi * zi + (double)zj * zj;
-                        const double tbx = sj * st.cand[j][1] + slm * st.lm[1];
-                        const double tby = sj * st.cand[j][2] + slm * st.lm[2];
-                        const int nr = __popc(R.mask);  // roots are compacted into slots 0 .. nr-1
-                        for (int r = 0; r < 4; ++r) {
-                            if (r >= nr) break;
-                            double x = pick4(R.r, r), y;
-                            if (!recover_y(A.q, Q, x, y)) continue;
-                            if (!(polish_xy(A.q, Q, x, y, 1) <= kMaxResidual)) continue;
-                            const double en = st.sp[i][kE1] * x + st.sp[i][kE2] * y + A.e0;
-                            const double xb = mx - x, yb = my - y;
-                            const double eb = st.sm[j][kE1] * xb + st.sm[j][kE2] * yb + B.e0;
+                        const int packed = Bk.mask | (Bk.direct << 4) | (Bk.signs << 5);
+                        for (int base = 0; base < total; base += kWave) {
+                            const int t = base + lane;
+                            int k, r;
+                            uint64_t mk;
+                            if (t < n0) {
+                                k = 0; r = t; mk = m0;
+                            } else if (t < n0 + n1) {
+                                k = 1; r = t - n0; mk = m1;
+                            } else if (t < n0 + n1 + n2) {
+                                k = 2; r = t - n0 - n1; mk = m2;
+                            } else {
+                                k = 3; r = t - n0 - n1 - n2; mk = m3;
+                            }
+                            const bool live = t < total;
+                            const int src = live ? nth_set_bit(mk, r) : lane;
+                            // the source lane's intervals, as plain values (no aggregate whose
+                            // fields get selected by k, which would force it into scratch)
+                            const Poly4 fc{from_lane(Bk.c.c0, src), from_lane(Bk.c.c1, src),
+                                           from_lane(Bk.c.c2, src), from_lane(Bk.c.c3, src),
+                                           from_lane(Bk.c.c4, src)};
+                            const double fe1 = from_lane(Bk.e1, src), fe2 = from_lane(Bk.e2, src);
+                            const double fe3 = from_lane(Bk.e3, src), fbd = from_lane(Bk.bound, src);
+                            const double ff1 = from_lane(Bk.f1, src), ff2 = from_lane(Bk.f2, src);
+                            const double ff3 = from_lane(Bk.f3, src);
+                            const int fp = from_lane(packed, src);
+                            const Conic P{st.sp[i][kQxx], st.sp[i][kQxy], st.sp[i][kQyy], from_lane(A.q.x, src),
+                                          from_lane(A.q.y, src), from_lane(A.q.c, src)};
+                            const Conic Qs{Q.xx, Q.xy, Q.yy, from_lane(Q.x, src), from_lane(Q.y, src),
+                                           from_lane(Q.c, src)};
+                            const double ae0 = from_lane(A.e0, src), be0 = from_lane(Bv.e0, src);
+                            if (!live) continue;
+                            ++acc_int;
+                            double x;
+                            if ((fp >> 4) & 1) {  // degree <= 2: the roots are given
+                                x = kXScale * (k == 0 ? fe1 : fe2);
+                            } else {
+                                const double f0 = (fp & 32) ? -1.0 : 1.0, f4 = (fp & 64) ? -1.0 : 1.0;
+                                const double lo = k == 0 ? -fbd : k == 1 ? fe1 : k == 2 ? fe2 : fe3;
+                                const double hi = k == 0 ? fe1 : k == 1 ? fe2 : k == 2 ? fe3 : fbd;
+                                const double flo = k == 0 ? f0 : k == 1 ? ff1 : k == 2 ? ff2 : ff3;
+                                const double fhi = k == 0 ? ff1 : k == 1 ? ff2 : k == 2 ? ff3 : f4;
+                                bool found;
+                                solve_interval(fc, lo, hi, flo, fhi, k > 0 && lo < fbd, k < 3 && hi < fbd, x, found);
+                            }
+                            double y;
+                            if (!recover_y(P, Qs, x, y)) continue;
+                            if (!(polish_xy(P, Qs, x, y, 2, a.polish_skip_m2) <= a.accept_m2)) continue;
+                            // the source variation's smear factors and MET, rebuilt from its draws
+                            const T zli0 = st.zl[0][src], zli1 = st.zl[1][src];
+                            const T zi = st.z[i][src], zj = st.z[j][src];
+                            const double rslp = smear(a.lep_sigma, zli0), rslm = smear(a.lep_sigma, zli1);
+                            const double rsi = smear(st.sigma[i], zi), rsj = smear(st.sigma[j], zj);
+                            const double rmx = metx + a.met_sigma * (double)st.zl[2][src];
+                            const double rmy = mety + a.met_sigma * (double)st.zl[3][src];
+                            const double en = st.sp[i][kE1] * x + st.sp[i][kE2] * y + ae0;
+                            const double xb = rmx - x, yb = rmy - y;
+                            const double eb = st.sm[j][kE1] * xb + st.sm[j][kE2] * yb + be0;
                             if (en < 0.0 || eb < 0.0) continue;
                             ++nsol;
-                            const double ptt = sqrt((tx + x) * (tx + x) + (ty + y) * (ty + y));
-                            const double pttb = sqrt((tbx + xb) * (tbx + xb) + (tby + yb) * (tby + yb));
-                            const double w = -0.5 * zz - (ptt + pttb) / a.lambda_pt;
-                            if (better(w, v, p, x, best_s, best_v, best_p, best_x)) {
+                            const double tx = rsi * st.cand[i][1] + rslp * st.lp[1] + x;  // top pT components
+                            const double ty = rsi * st.cand[i][2] + rslp * st.lp[2] + y;
+                            const double tbx = rsj * st.cand[j][1] + rslm * st.lm[1] + xb;
+                            const double tby = rsj * st.cand[j][2] + rslm * st.lm[2] + yb;
+                            const double zz = (double)zli0 * zli0 + (double)zli1 * zli1 +
+                                              (double)st.zl[2][src] * st.zl[2][src] +
+                                              (double)st.zl[3][src] * st.zl[3][src] + (double)zi * zi + (double)zj * zj;
+                            const double w = -0.5 * zz - (sqrt(tx * tx + ty * ty) + sqrt(tbx * tbx + tby * tby)) *
+                                                             a.inv_lambda;
+                            const int vs = vb + src;
+                            if (better(w, vs, p, x, best_s, best_v, best_p, best_x)) {
                                 best_s = w;
-                                best_v = v;
+                                best_v = vs;
                                 best_p = p;
                                 best_x = x;
                                 best_y = y;
@@ -291,6 +376,7 @@ __global__ __launch_bounds__(kRecoBlock, 2) void k_search(EvView ev, const int32
                         }
                     }
                 }
+                wave_sync();
             }
         }
         // --------------------------------------------------- wave argmax
@@ -325,15 +411,21 @@ __global__ __launch_bounds__(kRecoBlock, 2) void k_search(EvView ev, const int32
         }
         wave_sync();
     }
+    // intervals are counted per lane (each lane solves its own queue entries)
+    uint32_t ni = (uint32_t)acc_int;
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) ni += __shfl_xor(ni, off);
+    acc_int = ni;
     if (lane == 0 && wstats) {
         atomicAdd((unsigned long long *)&wstats[1], (unsigned long long)acc_var);
         atomicAdd((unsigned long long *)&wstats[2], (unsigned long long)acc_pair);
-        atomicAdd((unsigned long long *)&wstats[3], (unsigned long long)acc_sol);
+        atomicAdd((unsigned long long *)&wstats[3], (unsigned long long)acc_int);
+        atomicAdd((unsigned long long *)&wstats[4], (unsigned long long)acc_sol);
     }
 }
 
 __global__ void k_reco_init(uint64_t *wstats) {
-    if (threadIdx.x < 4) wstats[threadIdx.x] = 0;
+    if (threadIdx.x < 5) wstats[threadIdx.x] = 0;
 }
 
 __device__ __forceinline__ double mass4(double E, double X, double Y, double Z) {
@@ -478,7 +570,7 @@ __global__ __launch_bounds__(256) void k_epilogue(EvView ev, const int32_t *__re
             if (counter) atomicAdd((unsigned long long *)&counter->reached, (unsigned long long)S);
             if (out.stats) {
                 atomicAdd((unsigned long long *)&out.stats[0], (unsigned long long)S);
-                for (int q = 1; q < 4; ++q) atomicAdd((unsigned long long *)&out.stats[q], (unsigned long long)wstats[q]);
+                for (int q = 1; q < 5; ++q) atomicAdd((unsigned long long *)&out.stats[q], (unsigned long long)wstats[q]);
             }
         }
     }

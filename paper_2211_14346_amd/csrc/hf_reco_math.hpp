@@ -62,10 +62,13 @@ HF_HD __forceinline__ double conic_mag(const Conic &q, double x, double y) {
 }
 
 // Side constants from nominal 4-vectors (E, px, py, pz); returns false when
-// the 2x2 system is degenerate (|D| <= 1e-12 El Eb, invariant under scaling).
+// the 2x2 system is degenerate: |D| <= 1e-5 El Eb (for massless l and b their
+// direction cosines along the beam agree to 1e-5; the map's coefficients grow
+// as 1/D, the mass shell's rounding faster, and FP64 no longer resolves the
+// constraints below that).  The test is invariant under scaling.
 HF_HD __forceinline__ bool make_side(const double l[4], const double b[4], double s[kSide]) {
     const double D = l[3] * b[0] - l[0] * b[3];
-    if (!(fabs(D) > 1e-12 * l[0] * b[0])) {
+    if (!(fabs(D) > 1e-5 * l[0] * b[0])) {
         for (int k = 0; k < kSide; ++k) s[k] = 0.0;
         return false;
     }
@@ -258,7 +261,11 @@ HF_HD __forceinline__ int cubic_roots(T A, T B, T C, T &r0, T &r1, T &r2) {
 // Newton steps that leave the bracket are replaced by bisection.  Stops once
 // the Newton step is below 1e-12 max(1, |t|) (t = x / 100 GeV), tested
 // before the bracket so that an iterate sitting on a bracket end at
-// convergence is not bisected away.
+// convergence is not bisected away.  A root next to a critical point (a near
+// double root) is fixed only to the polynomial's rounding, where that step
+// test can fail forever: from the sixth iterate on, the search also stops
+// when |p| is at its rounding floor (1e-15 of the sum of its terms'
+// magnitudes) or the bracket is narrower than the tolerance.
 HF_HD __forceinline__ double bracket_newton(const Poly4 &c, double lo, double hi, bool lo_neg, double x) {
     for (int it = 0; it < 60; ++it) {
         HF_NEWTON_HOOK();
@@ -270,7 +277,16 @@ HF_HD __forceinline__ double bracket_newton(const Poly4 &c, double lo, double hi
         else
             hi = x;
         const double dx = p * fast_rcp(dp);
-        if (fabs(dx) <= 1e-12 * fmax(1.0, fabs(x))) return x - dx;
+        const double tol = 1e-12 * fmax(1.0, fabs(x));
+        if (fabs(dx) <= tol) return x - dx;
+        if (it >= 5) {
+            // slow convergence (a root next to a critical point): stop once p is
+            // at its rounding floor or the bracket is below the tolerance
+            const double ax = fabs(x);
+            const double mag =
+                (((fabs(c.c4) * ax + fabs(c.c3)) * ax + fabs(c.c2)) * ax + fabs(c.c1)) * ax + fabs(c.c0);
+            if (fabs(p) <= 1e-15 * mag || hi - lo <= tol) return x;
+        }
         double xn = x - dx;
         if (!(xn > lo && xn < hi)) xn = 0.5 * (lo + hi);
         x = xn;
@@ -278,27 +294,17 @@ HF_HD __forceinline__ double bracket_newton(const Poly4 &c, double lo, double hi
     return x;
 }
 
-// Sign-changing real roots (in x units) of q0 + q1 x + ... + q4 x^4, at most
-// four, ascending in slots 0 .. popcount(mask) - 1.
-struct Roots4 {
-    double r[4];
-    int mask;
-};
-
-HF_HD __forceinline__ double pick4(const double r[4], int k) {
-    return k == 0 ? r[0] : k == 1 ? r[1] : k == 2 ? r[2] : r[3];
-}
-
-// Solve the sign change on [lo, hi] into slot k (constant after unrolling).
+// Root of the interval [lo, hi] (values flo, fhi of opposite signs), in x
+// units.  First iterate: the quadratic model at a finite critical end
+// (p(c + d) ~ p(c) + p''(c) d^2 / 2), the secant when both ends are critical.
 HF_HD __forceinline__ void solve_interval(const Poly4 &c, double lo, double hi, double flo, double fhi, bool lo_crit,
                                           bool hi_crit, double &root, bool &found) {
     found = false;
     if (!((flo < 0.0 && fhi > 0.0) || (flo > 0.0 && fhi < 0.0)) || !(hi > lo)) return;
     double x0;
     if (lo_crit && hi_crit) {
-        x0 = lo - flo * (hi - lo) * fast_rcp(fhi - flo);  // secant of the two end values
+        x0 = lo - flo * (hi - lo) * fast_rcp(fhi - flo);
     } else if (lo_crit || hi_crit) {
-        // quadratic model at the finite critical end: p(c + d) ~ p(c) + p''(c) d^2 / 2
         const double cp = lo_crit ? lo : hi;
         const double fv = lo_crit ? flo : fhi;
         const double r = -2.0 * fv * fast_rcp(peval_d2(c, cp));
@@ -312,23 +318,40 @@ HF_HD __forceinline__ void solve_interval(const Poly4 &c, double lo, double hi, 
     found = true;
 }
 
-// Real roots by critical points: the roots of the derivative (closed-form
-// cubic in precision T, one FP64 Newton step each) split the line into
-// monotone intervals; each interval whose end values differ in sign holds one
-// root, found by safeguarded Newton in FP64.  As in the oracle, the
-// polynomial is taken in t = x / 100 GeV, normalised by its largest
-// coefficient, and leading coefficients <= 1e-14 are dropped; the outer
-// intervals end at the Cauchy bound.
+// Sign-changing real roots of q0 + q1 x + ... + q4 x^4 by critical points:
+// the roots of the derivative (closed-form cubic in precision T, one FP64
+// Newton step each) split the line into monotone intervals; each interval
+// whose end values differ in sign holds one root, found by safeguarded Newton
+// in FP64.  As in the oracle, the polynomial is taken in t = x / 100 GeV,
+// normalised by its largest coefficient, and leading coefficients <= 1e-14
+// are dropped; the outer intervals end at the Cauchy bound.
+//
+// quartic_brackets does everything up to the intervals; bracket_root solves
+// one interval.  The search kernel runs the two on different lanes.
+struct Brackets {
+    Poly4 c;             // normalised polynomial in t
+    double e1, e2, e3;   // inner interval ends (critical points); direct roots for degree <= 2
+    double bound;        // intervals are [-bound, e1], [e1, e2], [e2, e3], [e3, bound]
+    double f1, f2, f3;   // polynomial values at e1, e2, e3
+    int mask;            // bit k: interval k holds a root (or: direct root k exists)
+    int direct;          // 1: degree <= 2, roots given directly in e1, e2
+    int signs;           // bit 0: p(-bound) < 0; bit 1: p(+bound) < 0
+};
+
 template <typename T>
-HF_HD Roots4 quartic_real_roots(const double qx[5]) {
-    Roots4 out;
-    out.mask = 0;
-    out.r[0] = out.r[1] = out.r[2] = out.r[3] = 0.0;
-    Poly4 c{qx[0], qx[1] * kXScale, qx[2] * (kXScale * kXScale), qx[3] * (kXScale * kXScale * kXScale),
-            qx[4] * (kXScale * kXScale * kXScale * kXScale)};
+HF_HD __forceinline__ Brackets quartic_brackets(const double qx[5]) {
+    Brackets B;
+    B.mask = 0;
+    B.direct = 0;
+    B.signs = 0;
+    B.e1 = B.e2 = B.e3 = B.f1 = B.f2 = B.f3 = 0.0;
+    B.bound = 1.0;
+    Poly4 &c = B.c;
+    c = Poly4{qx[0], qx[1] * kXScale, qx[2] * (kXScale * kXScale), qx[3] * (kXScale * kXScale * kXScale),
+              qx[4] * (kXScale * kXScale * kXScale * kXScale)};
     const double mx = fmax(fmax(fmax(fabs(c.c0), fabs(c.c1)), fmax(fabs(c.c2), fabs(c.c3))), fabs(c.c4));
-    if (!(mx > 0.0) || !isfinite(mx)) return out;
-    const double inv = 1.0 / mx;
+    if (!(mx > 0.0) || !isfinite(mx)) return B;
+    const double inv = fast_rcp(mx);
     c.c0 *= inv;
     c.c1 *= inv;
     c.c2 *= inv;
@@ -344,28 +367,30 @@ HF_HD Roots4 quartic_real_roots(const double qx[5]) {
             if (fabs(c.c2) <= 1e-14) {
                 c.c2 = 0.0;
                 n = 1;
-                if (fabs(c.c1) <= 1e-14) return out;
+                if (fabs(c.c1) <= 1e-14) return B;
             }
         }
     }
-    if (n == 1) {
-        out.r[0] = kXScale * (-c.c0 / c.c1);
-        out.mask = 1;
-        return out;
-    }
-    if (n == 2) {
-        const double disc = c.c1 * c.c1 - 4.0 * c.c2 * c.c0;
-        if (!(disc > 0.0)) return out;
-        const double sq = sqrt(disc);
-        const double t = -0.5 * (c.c1 + (c.c1 >= 0.0 ? sq : -sq));
-        const double a = t / c.c2, b = c.c0 / t;
-        out.r[0] = kXScale * fmin(a, b);
-        out.r[1] = kXScale * fmax(a, b);
-        out.mask = 3;
-        return out;
+    if (n <= 2) {
+        B.direct = 1;
+        if (n == 1) {
+            B.e1 = -c.c0 / c.c1;
+            B.mask = 1;
+        } else {
+            const double disc = c.c1 * c.c1 - 4.0 * c.c2 * c.c0;
+            if (disc > 0.0) {
+                const double sq = sqrt(disc);
+                const double t = -0.5 * (c.c1 + (c.c1 >= 0.0 ? sq : -sq));
+                const double a = t / c.c2, b = c.c0 / t;
+                B.e1 = fmin(a, b);
+                B.e2 = fmax(a, b);
+                B.mask = 3;
+            }
+        }
+        return B;
     }
     const double lead = n == 4 ? c.c4 : c.c3;
-    const double il = 1.0 / lead;
+    const double il = fast_rcp(lead);
     double bound = fmax(fmax(fabs(c.c0 * il), fabs(c.c1 * il)), fabs(c.c2 * il));
     if (n == 4) bound = fmax(bound, fabs(c.c3 * il));
     bound += 1.0;
@@ -373,15 +398,15 @@ HF_HD Roots4 quartic_real_roots(const double qx[5]) {
     double k0 = 0.0, k1 = 0.0, k2 = 0.0;
     int nk = 0;
     if (n == 4) {
-        const double A = 0.75 * c.c3 * il, B = 0.5 * c.c2 * il, C = 0.25 * c.c1 * il;
-        if (fmax(fabs(A), fmax(fabs(B), fabs(C))) < 1e6) {
+        const double A = 0.75 * c.c3 * il, Bc = 0.5 * c.c2 * il, C = 0.25 * c.c1 * il;
+        if (fmax(fabs(A), fmax(fabs(Bc), fabs(C))) < 1e6) {
             T a0, a1, a2;
-            nk = cubic_roots<T>((T)A, (T)B, (T)C, a0, a1, a2);
+            nk = cubic_roots<T>((T)A, (T)Bc, (T)C, a0, a1, a2);
             k0 = (double)a0;
             k1 = (double)a1;
             k2 = (double)a2;
         } else {
-            nk = cubic_roots<double>(A, B, C, k0, k1, k2);
+            nk = cubic_roots<double>(A, Bc, C, k0, k1, k2);
         }
     } else {  // n == 3: derivative 3 c3 t^2 + 2 c2 t + c1
         const double a = 3.0 * c.c3, b = 2.0 * c.c2, cc = c.c1;
@@ -416,7 +441,6 @@ HF_HD Roots4 quartic_real_roots(const double qx[5]) {
     const bool u1 = nk >= 2 && k1 > -bound && k1 < bound;
     const bool u2 = nk >= 3 && k2 > -bound && k2 < bound;
     double e1 = u0 ? k0 : bound, e2 = u1 ? k1 : bound, e3 = u2 ? k2 : bound;
-    // keep ascending after the polish (sorting network on three values)
     if (e2 < e1) { const double t = e1; e1 = e2; e2 = t; }
     if (e3 < e2) { const double t = e2; e2 = e3; e3 = t; }
     if (e2 < e1) { const double t = e1; e1 = e2; e2 = t; }
@@ -425,37 +449,63 @@ HF_HD Roots4 quartic_real_roots(const double qx[5]) {
     const double f1 = e1 < bound ? peval(c, e1) : sb;
     const double f2 = e2 < bound ? peval(c, e2) : sb;
     const double f3 = e3 < bound ? peval(c, e3) : sb;
-    // brackets of the four intervals, compacted so that the Newton loops run
-    // only as many times as the lane with the most roots needs
-    const double lo[4] = {-bound, e1, e2, e3}, hi[4] = {e1, e2, e3, bound};
-    const double flo[4] = {f0, f1, f2, f3}, fhi[4] = {f1, f2, f3, sb};
-    const bool clo[4] = {false, e1 < bound, e2 < bound, e3 < bound};
-    const bool chi[4] = {e1 < bound, e2 < bound, e3 < bound, false};
-    double blo[4] = {0, 0, 0, 0}, bhi[4] = {0, 0, 0, 0}, bfl[4] = {0, 0, 0, 0}, bfh[4] = {0, 0, 0, 0};
-    bool bcl[4] = {false, false, false, false}, bch[4] = {false, false, false, false};
+    B.e1 = e1;
+    B.e2 = e2;
+    B.e3 = e3;
+    B.bound = bound;
+    B.f1 = f1;
+    B.f2 = f2;
+    B.f3 = f3;
+    B.signs = (neg_lo ? 1 : 0) | (pos_hi ? 0 : 2);
+    auto change = [](double a, double b, double lo, double hi) {
+        return ((a < 0.0 && b > 0.0) || (a > 0.0 && b < 0.0)) && hi > lo;
+    };
+    B.mask = (change(f0, f1, -bound, e1) ? 1 : 0) | (change(f1, f2, e1, e2) ? 2 : 0) |
+             (change(f2, f3, e2, e3) ? 4 : 0) | (change(f3, sb, e3, bound) ? 8 : 0);
+    return B;
+}
+
+// Root (in t units) in interval k of a Brackets record, or direct root k.
+HF_HD __forceinline__ double bracket_root(const Brackets &B, int k) {
+    if (B.direct) return k == 0 ? B.e1 : B.e2;
+    const double lo = k == 0 ? -B.bound : k == 1 ? B.e1 : k == 2 ? B.e2 : B.e3;
+    const double hi = k == 0 ? B.e1 : k == 1 ? B.e2 : k == 2 ? B.e3 : B.bound;
+    const double f0 = (B.signs & 1) ? -1.0 : 1.0, f4 = (B.signs & 2) ? -1.0 : 1.0;
+    const double flo = k == 0 ? f0 : k == 1 ? B.f1 : k == 2 ? B.f2 : B.f3;
+    const double fhi = k == 0 ? B.f1 : k == 1 ? B.f2 : k == 2 ? B.f3 : f4;
+    const bool lo_crit = k > 0 && lo < B.bound;
+    const bool hi_crit = k < 3 && hi < B.bound;
+    double root = 0.0;
+    bool found;
+    solve_interval(B.c, lo, hi, flo, fhi, lo_crit, hi_crit, root, found);
+    return root * (1.0 / kXScale);  // solve_interval returns x units
+}
+
+// Sign-changing real roots (in x units), ascending in slots 0 .. popcount(mask) - 1.
+struct Roots4 {
+    double r[4];
+    int mask;
+};
+
+HF_HD __forceinline__ double pick4(const double r[4], int k) {
+    return k == 0 ? r[0] : k == 1 ? r[1] : k == 2 ? r[2] : r[3];
+}
+
+template <typename T>
+HF_HD Roots4 quartic_real_roots(const double qx[5]) {
+    const Brackets B = quartic_brackets<T>(qx);
+    Roots4 out;
+    out.r[0] = out.r[1] = out.r[2] = out.r[3] = 0.0;
     int nb = 0;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        const bool sc = ((flo[k] < 0.0 && fhi[k] > 0.0) || (flo[k] > 0.0 && fhi[k] < 0.0)) && hi[k] > lo[k];
-#pragma unroll
-        for (int b = 0; b <= k; ++b)
-            if (sc && nb == b) {
-                blo[b] = lo[k];
-                bhi[b] = hi[k];
-                bfl[b] = flo[k];
-                bfh[b] = fhi[k];
-                bcl[b] = clo[k];
-                bch[b] = chi[k];
-            }
-        nb += sc ? 1 : 0;
-    }
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-        if (b >= nb) break;
-        bool found;
-        double rt;
-        solve_interval(c, blo[b], bhi[b], bfl[b], bfh[b], bcl[b], bch[b], rt, found);
-        out.r[b] = rt;
+        if (!((B.mask >> k) & 1)) continue;
+        const double x = kXScale * bracket_root(B, k);
+        out.r[0] = nb == 0 ? x : out.r[0];
+        out.r[1] = nb == 1 ? x : out.r[1];
+        out.r[2] = nb == 2 ? x : out.r[2];
+        out.r[3] = nb == 3 ? x : out.r[3];
+        ++nb;
     }
     out.mask = (1 << nb) - 1;
     return out;
@@ -510,19 +560,30 @@ HF_HD __forceinline__ bool recover_y(const Conic &P, const Conic &Q, double x, d
     return any;
 }
 
+// Acceptance of an intersection (section 4 constraints).  The W and top
+// constraints hold by construction of the linear maps, and each conic's value
+// is that neutrino's squared mass E^2 - p^2 in GeV^2, which is also the offset
+// of (l + nu)^2 from mW^2 and of (b + l + nu)^2 from mt^2.  A point is a
+// solution when both squared masses are within kAcceptM2 mW^2 of zero: every
+// mass constraint then holds to 1e-6 relative.
+constexpr double kAcceptM2 = 2e-6;
+
+// Points whose squared masses are already 1e4 times inside the acceptance
+// bound are not polished.
+constexpr double kPolishSkip = 1e-4;
+
 // Newton's method on the two conics for (x, y), each step kept only while it
-// lowers the larger relative residual; returns that residual at the final
-// point (an intersection is accepted only if it is <= kMaxResidual).
-constexpr double kMaxResidual = 1e-6;
-
-// Points already at a residual <= kPolishFrom are left as they are.
-constexpr double kPolishFrom = 1e-10;
-
-HF_HD __forceinline__ double polish_xy(const Conic &P, const Conic &Q, double &x, double &y, int iters) {
+// lowers the larger relative residual (|value| over the sum of the magnitudes
+// of the conic's terms).  Returns max(|P(x, y)|, |Q(x, y)|) in GeV^2 at the
+// final point; skip_below: no step is taken from a point already below it.
+HF_HD __forceinline__ double polish_xy(const Conic &P, const Conic &Q, double &x, double &y, int iters,
+                                       double skip_below) {
     double f1 = conic_eval(P, x, y), f2 = conic_eval(Q, x, y);
+    double phys = fmax(fabs(f1), fabs(f2));
+    if (!(phys > skip_below)) return phys;
     double res = fmax(fabs(f1) * fast_rcp(conic_mag(P, x, y)), fabs(f2) * fast_rcp(conic_mag(Q, x, y)));
     for (int it = 0; it < iters; ++it) {
-        if (!(res > kPolishFrom)) break;
+        if (res == 0.0) break;
         const double a11 = 2.0 * P.xx * x + P.xy * y + P.x, a12 = P.xy * x + 2.0 * P.yy * y + P.y;
         const double a21 = 2.0 * Q.xx * x + Q.xy * y + Q.x, a22 = Q.xy * x + 2.0 * Q.yy * y + Q.y;
         const double det = a11 * a22 - a12 * a21;
@@ -538,8 +599,10 @@ HF_HD __forceinline__ double polish_xy(const Conic &P, const Conic &Q, double &x
         f1 = g1;
         f2 = g2;
         res = rn;
+        phys = fmax(fabs(f1), fabs(f2));
+        if (!(phys > skip_below)) break;
     }
-    return res;
+    return phys;
 }
 
 }  // namespace hf

@@ -1,0 +1,112 @@
+"""Short text summaries of rocprofv3 runs of bench.py, for profiles/.
+
+    python -m paper_2211_14346_amd.perf.profile_summary \\
+        --trace DIR --pmc DIR [DIR ...] --cal-fetch DIR --cal-write DIR \\
+        --cal-bytes N --hash H --out profiles/
+
+DIR arguments are rocprofv3 output directories written with
+`-o run --output-format csv` (run_kernel_stats.csv / run_counter_collection.csv).
+
+Writes
+  k_search_ttbar1M_v64_kernel_stats.txt   per-kernel calls and durations
+  k_search_ttbar1M_v64_counters.txt       per-dispatch counters of each kernel,
+                                          HBM traffic of the search kernel
+FETCH_SIZE and WRITE_SIZE (KiB per dispatch) are scaled into bytes by what
+each reads for a plain device copy of known size (--cal-bytes read and
+written once per copy): factor = copy bytes / (counter KiB * 1024).
+"""
+
+import argparse
+import collections
+import csv
+import os
+
+SEARCH = "k_search<float>"
+TRACE_CMD = ("rocprofv3 --kernel-trace --stats -d <dir> -o run --output-format csv -- "
+             "python3 bench.py --profile-only --steps 5 --warmup 1")
+PMC_CMD = ("rocprofv3 --pmc <counters> -d <dir> -o run --output-format csv -- "
+           "python3 bench.py --profile-only --steps 2 --warmup 1")
+CAL_CMD = ("rocprofv3 --pmc <FETCH_SIZE|WRITE_SIZE> -d <dir> -o run --output-format csv -- "
+           "python3 bench.py --copy-calibration 256")
+
+
+def _short(name):
+    n = name.replace("hf::(anonymous namespace)::", "").replace("void ", "")
+    return n.split("(")[0]
+
+
+def kernel_stats(d):
+    rows = list(csv.DictReader(open(os.path.join(d, "run_kernel_stats.csv"))))
+    return [(_short(r["Name"]), int(r["Calls"]), float(r["AverageNs"]), float(r["MinNs"]), float(r["MaxNs"]),
+             float(r["Percentage"])) for r in rows]
+
+
+def counters(d):
+    """{(kernel, counter): mean value per dispatch}, plus dispatch counts."""
+    vals = collections.defaultdict(list)
+    for r in csv.DictReader(open(os.path.join(d, "run_counter_collection.csv"))):
+        vals[(_short(r["Kernel_Name"]), r["Counter_Name"])].append(float(r["Counter_Value"]))
+    return {k: (sum(v) / len(v), len(v)) for k, v in vals.items()}
+
+
+def copy_factor(d, counter, nbytes):
+    c = counters(d)
+    kib = [v for (k, name), (v, n) in c.items() if name == counter and "copyBuffer" in k]
+    if not kib:
+        raise SystemExit(f"no copy kernel with {counter} in {d}")
+    return nbytes / (kib[0] * 1024.0)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--trace", required=True)
+    ap.add_argument("--pmc", nargs="+", required=True)
+    ap.add_argument("--cal-fetch", required=True)
+    ap.add_argument("--cal-write", required=True)
+    ap.add_argument("--cal-bytes", type=int, default=256 << 20)
+    ap.add_argument("--hash", required=True, help="search kernel source hash of the profiled tree")
+    ap.add_argument("--out", default="profiles")
+    a = ap.parse_args()
+    os.makedirs(a.out, exist_ok=True)
+
+    ks = kernel_stats(a.trace)
+    lines = ["# Kernel durations, bench workload ttbar1M_v64 (1M events, 64 variations, mixed precision)",
+             f"# command: {TRACE_CMD}", f"# search kernel source hash: {a.hash}", "",
+             f"{'kernel':40s} {'calls':>6s} {'avg_us':>10s} {'min_us':>10s} {'max_us':>10s} {'pct':>7s}"]
+    for name, calls, avg, mn, mx, pct in ks:
+        lines.append(f"{name[:40]:40s} {calls:6d} {avg / 1e3:10.2f} {mn / 1e3:10.2f} {mx / 1e3:10.2f} {pct:7.2f}")
+    with open(os.path.join(a.out, "k_search_ttbar1M_v64_kernel_stats.txt"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+    fetch_f = copy_factor(a.cal_fetch, "FETCH_SIZE", a.cal_bytes)
+    write_f = copy_factor(a.cal_write, "WRITE_SIZE", a.cal_bytes)
+    merged = {}
+    for d in a.pmc:
+        merged.update(counters(d))
+    kernels = sorted({k for k, _ in merged if k.startswith("k_")}, key=lambda k: (k != SEARCH, k))
+    names = sorted({c for _, c in merged})
+    lines = ["# Per-dispatch counters, bench workload ttbar1M_v64 (mixed precision)",
+             f"# command (one run per counter group): {PMC_CMD}",
+             f"# calibration: {CAL_CMD}",
+             f"# calibration on a {a.cal_bytes} B device copy: bytes = FETCH_SIZE * 1024 * {fetch_f:.4f}, "
+             f"bytes = WRITE_SIZE * 1024 * {write_f:.4f}",
+             f"# search kernel source hash: {a.hash}", ""]
+    for k in kernels:
+        lines.append(f"[{k}]")
+        for c in names:
+            if (k, c) in merged:
+                v, n = merged[(k, c)]
+                lines.append(f"  {c:28s} {v:18.1f}   ({n} dispatches)")
+    sf = merged.get((SEARCH, "FETCH_SIZE"))
+    sw = merged.get((SEARCH, "WRITE_SIZE"))
+    if sf and sw:
+        fb, wb = sf[0] * 1024.0 * fetch_f, sw[0] * 1024.0 * write_f
+        lines += ["", f"search_kernel: {SEARCH}", f"search_fetch_bytes_per_launch: {fb:.0f}",
+                  f"search_write_bytes_per_launch: {wb:.0f}", f"search_traffic_bytes_per_launch: {fb + wb:.0f}",
+                  f"search_source_hash: {a.hash}"]
+    with open(os.path.join(a.out, "k_search_ttbar1M_v64_counters.txt"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
+if __name__ == "__main__":
+    main()

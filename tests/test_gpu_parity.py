@@ -158,7 +158,7 @@ def test_select_and_compact_samples(B, orc, name, n):
 
 # -------------------------------------------------------------- compaction
 
-@pytest.mark.parametrize("n", [0, 1, 63, 64, 65, 4095, 4096, 4097, 99991, (1 << 20) + 3])
+@pytest.mark.parametrize("n", [0, 1, 63, 64, 65, 4095, 4096, 4097, 8191, 8192, 8193, 99991, (1 << 20) + 3, 64 * 8192 + 5])
 def test_compact_adversarial(B, n):
     _say("compact n =", n)
     rng = np.random.default_rng(n)
@@ -167,7 +167,7 @@ def test_compact_adversarial(B, n):
         "zeros": np.zeros(n, np.uint8), "ones": np.ones(n, np.uint8),
         "alternate": (np.arange(n) % 2).astype(np.uint8),
         "every64": (np.arange(n) % 64 == 63).astype(np.uint8),
-        "tile_edges": (np.isin(np.arange(n) % 4096, [0, 4095])).astype(np.uint8),
+        "tile_edges": (np.isin(np.arange(n) % 8192, [0, 8191])).astype(np.uint8),
         "random": (rng.uniform(size=n) < 0.37).astype(np.uint8),
         "bytes": rng.integers(0, 256, n).astype(np.uint8),
     }
@@ -376,12 +376,24 @@ def test_full_size_bench_config_sampled(B, orc):
     assert_agree(st, min_agree=0.995)
     r = got["reco"]
     hs = r["has_sol"].astype(bool)
-    # every accepted solution satisfies the mass constraints (relative 1e-4)
+    # Every accepted solution satisfies the mass constraints: a point is
+    # accepted when both neutrinos' squared masses are within 2e-6 mW^2 of
+    # zero, which bounds each mass's offset by 1e-6 relative; 2e-6 leaves room
+    # for the rounding of the output masses.
+    dev = np.zeros(S)
     for k, m in (("m_wp", 80.4), ("m_wm", 80.4), ("m_t", 172.5), ("m_tbar", 172.5)):
-        assert np.abs(r[k][hs] - m).max() <= 1e-4 * m, k
+        d = np.abs(r[k] - m) / m
+        dev = np.maximum(dev, np.where(hs, d, 0.0))
+    assert dev.max() <= 2e-6, dev.max()
+    # the most off-shell accepted solutions are the oracle's solutions too
+    worst = np.sort(np.argsort(-dev)[:32])
+    want_w = orc.ttbar_reco(ev, got["idx"][worst], cfg["reco"])
+    st_w = compare({k: v[worst] for k, v in r.items() if k != "stats"}, want_w)
+    _say("most off-shell", float(dev.max()), st_w)
+    assert st_w["decision_agree"] >= 0.9 and st_w["choice_agree"] >= 0.9, st_w
     assert np.array_equal(got["final"], got["idx"][hs])
     stats = r["stats"]
-    assert stats[0] == S and stats[3] == r["n_sol"].sum()
+    assert stats[0] == S and stats[4] == r["n_sol"].sum() and stats[3] >= stats[4]
 
 
 def test_graph_replay_matches_eager(B):
