@@ -272,6 +272,18 @@ int hf_gauss_draws(uint64_t seed, const int64_t *d_g, const int32_t *d_v, const 
  * dependencies (h_order is left unchanged). */
 int hf_reorder_stats(const hf_counters_t *h_counters, const hf_cut_t *h_cuts, int n_cuts, int32_t *h_order);
 
+/* The same rule on the device: reads d_counters and writes d_order on
+ * `stream`, so that a step recorded into a HIP graph reorders its own cuts
+ * for the next step without a host round trip (section 5.2's reordering
+ * during the run).  Produces exactly the order hf_reorder_stats gives for
+ * the same counters.  Asynchronous; allocates nothing.
+ *   d_counters[n_cuts] device in; h_cuts[n_cuts] host in (dependencies);
+ *   d_order[n_cuts] device out (also the order the next hf_select reads).
+ * Errors: HF_ERR_INVAL for null pointers, n_cuts out of range, dependencies
+ * out of range or cyclic (checked on the host at the call). */
+int hf_reorder_device(const hf_counters_t *d_counters, const hf_cut_t *h_cuts, int n_cuts, int32_t *d_order,
+                      hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -80,12 +80,13 @@ def lib():
         L.hf_ttbar_reco.argtypes = [C.POINTER(Events), P, P, C.c_int64, C.POINTER(RecoParams), C.POINTER(RecoOut), P,
                                     P, C.c_size_t, P]
         L.hf_reorder_stats.argtypes = [P, P, C.c_int, P]
+        L.hf_reorder_device.argtypes = [P, P, C.c_int, P, P]
         L.hf_reco_timing_events.argtypes = [P, P]
         L.hf_reco_timing_events.restype = C.c_int
         L.hf_philox_blocks.argtypes = [P, C.c_uint64, P, C.c_int64, P]
         L.hf_gauss_draws.argtypes = [C.c_uint64, P, P, P, C.c_int64, C.c_int, P, P]
-        for f in ("hf_select", "hf_compact", "hf_ttbar_reco", "hf_reorder_stats", "hf_philox_blocks",
-                  "hf_gauss_draws"):
+        for f in ("hf_select", "hf_compact", "hf_ttbar_reco", "hf_reorder_stats", "hf_reorder_device",
+                  "hf_philox_blocks", "hf_gauss_draws"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -213,6 +214,12 @@ def reorder_stats(counters_host, cuts_arr, n_cuts):
                                 C.cast(order, C.c_void_p))
     _check(rc, "hf_reorder_stats")
     return list(order)
+
+
+def reorder_device(counters, cuts_arr, n_cuts, order, stream=None):
+    """New order from the device counters [n_cuts, 3] into the device order buffer, on the stream."""
+    _check(lib().hf_reorder_device(_p(counters), C.cast(cuts_arr, C.c_void_p), n_cuts, _p(order), _stream(stream)),
+           "hf_reorder_device")
 
 
 def philox_blocks(ctr, seed, out, stream=None):

@@ -58,24 +58,35 @@ class Chain:
         B.compact(self.out.t["has_sol"], self.n, self.final_idx, self.final_count, self.ws_cmp2, d_n=self.count,
                   mapping=self.idx, stream=stream)
 
-    def step(self, stream=None):
+    def run_reorder(self, stream=None):
+        """New cut order from the accumulated counters, computed on the device."""
+        B.reorder_device(self.counters, self.cut_arr, self.n_cuts, self.order, stream)
+
+    def step(self, stream=None, reorder=False):
+        """select -> compact -> reconstruction -> compact; with reorder=True also
+        the device-side reordering, so that the next step runs the new order."""
         self.run_select(stream)
         self.run_compact(stream)
         self.run_reco(stream)
         self.run_final(stream)
+        if reorder:
+            self.run_reorder(stream)
 
     # -------------------------------------------------------------- graph
-    def capture(self):
-        """Record the four calls into a HIP graph (torch.cuda.CUDAGraph)."""
+    def capture(self, reorder=False):
+        """Record one step into a HIP graph (torch.cuda.CUDAGraph); with
+        reorder=True the step ends with the device-side reordering."""
         s = torch.cuda.Stream()
         s.wait_stream(torch.cuda.current_stream())
+        order0 = self.order.clone()
         with torch.cuda.stream(s):
-            self.step(s)  # warm-up outside the graph (kernel loading)
+            self.step(s, reorder=reorder)  # warm-up outside the graph (kernel loading)
         torch.cuda.current_stream().wait_stream(s)
         torch.cuda.synchronize()
+        self.order.copy_(order0)  # the warm-up must not change the order
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g):
-            self.step()
+            self.step(reorder=reorder)
         self.graph = g
         return g
 

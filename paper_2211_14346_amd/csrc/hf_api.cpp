@@ -236,4 +236,28 @@ int hf_reorder_stats(const hf_counters_t *h_counters, const hf_cut_t *h_cuts, in
     return HF_OK;
 }
 
+int hf_reorder_device(const hf_counters_t *d_counters, const hf_cut_t *h_cuts, int n_cuts, int32_t *d_order,
+                      hipStream_t stream) {
+    if (!d_counters || !h_cuts || !d_order) return fail(HF_ERR_INVAL, "hf_reorder_device: NULL argument");
+    if (n_cuts < 1 || n_cuts > HF_MAX_CUTS) return fail(HF_ERR_INVAL, "hf_reorder_device: n_cuts out of range");
+    uint64_t placed = 0;
+    for (int c = 0; c < n_cuts; ++c)
+        if (h_cuts[c].dep_mask >> n_cuts) return fail(HF_ERR_INVAL, "hf_reorder_device: dependency out of range");
+    // a placement exists for any ranks iff the dependencies are acyclic
+    for (int pos = 0; pos < n_cuts; ++pos) {
+        int pick = -1;
+        for (int c = 0; c < n_cuts && pick < 0; ++c)
+            if (!((placed >> c) & 1ull) && !(h_cuts[c].dep_mask & ~placed)) pick = c;
+        if (pick < 0) return fail(HF_ERR_INVAL, "hf_reorder_device: cyclic dependencies");
+        placed |= 1ull << pick;
+    }
+    hf::CutTable ct;
+    memset(&ct, 0, sizeof ct);
+    for (int c = 0; c < n_cuts; ++c) ct.c[c] = h_cuts[c];
+    ct.n = n_cuts;
+    hipError_t e = hf::launch_reorder(d_counters, ct, d_order, stream);
+    if (e != hipSuccess) return device_fail("hf_reorder_device launch", e);
+    return HF_OK;
+}
+
 }  // extern "C"

@@ -38,6 +38,7 @@ int select_grid(int64_t n);
 size_t select_ws_bytes(int64_t n, int n_cuts);
 hipError_t launch_select(const EvView &ev, const CutTable &ct, const int32_t *order, uint8_t *survive,
                          hf_counters_t *counters, void *ws, hipStream_t s);
+hipError_t launch_reorder(const hf_counters_t *counters, const CutTable &ct, int32_t *order, hipStream_t s);
 
 // ---- compaction (hf_compact.hip)
 size_t compact_ws_bytes(int64_t capacity);

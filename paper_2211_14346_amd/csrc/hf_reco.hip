@@ -45,17 +45,30 @@ struct BestRec {
     int32_t v, p, nsol, nc;
 };
 
+// One compacted event as the reconstruction sees it, built by k_stage: the
+// two selected leptons and the b candidates as nominal FP64 (E, px, py, pz),
+// in the order of the candidate rule; nc = 0 when the lepton selection
+// fails (or the id lies outside the chunk).  640 bytes = 80 words, copied
+// into LDS by a wavefront with two loads per lane.
+struct StageRec {
+    double lp[4], lm[4];    // l+ and l-
+    double met[2];          // nominal MET x, y
+    double ml2p, ml2m;      // squared masses of l+ and l-
+    double sigma[kMaxC];    // jet energy resolution at the nominal energy
+    uint64_t g;             // global event id (the generator's counter)
+    int32_t jidx[kMaxC];    // candidate -> jet index within the event
+    int32_t nc, V;          // number of candidates, of variations
+    double cand[kMaxC][4];  // b candidates
+};
+constexpr int kRecWords = (int)(sizeof(StageRec) / 8);
+static_assert(sizeof(StageRec) == 640 && kRecWords > kWave && kRecWords <= 2 * kWave, "record layout");
+
 template <typename T>
 struct WaveStage {
-    double lp[4], lm[4];      // nominal (E, px, py, pz) of l+ and l-
-    double cand[kMaxC][4];    // nominal b candidates
+    StageRec rec;
     double sp[kMaxC][kSide];  // side constants with l+
     double sm[kMaxC][kSide];  // side constants with l-
-    double sigma[kMaxC];
-    double ml2p, ml2m;
-    int jidx[kMaxC];
     int okp[kMaxC], okm[kMaxC];
-    int lsel[2];
     T z[kMaxC][kWave];  // per-lane draw of each candidate
     T zl[4][kWave];     // per-lane draws of l+, l-, MET x, MET y
 };
@@ -123,10 +136,148 @@ __device__ __forceinline__ int64_t clamp_count(const int64_t *count, int64_t cap
     return S < 0 ? 0 : (S > capacity ? capacity : S);
 }
 
+// One thread per compacted event: selection of the two leptons (exactly two
+// selected, opposite charges; l+ first) and of the b candidates (b-tagged
+// selected jets in input order up to max_cands, filled up to two with the
+// leading untagged selected jets; or every selected jet), converted to FP64
+// Cartesian 4-vectors.  Objects are examined in chunks whose columns are
+// loaded together, and the selected objects' columns are loaded together
+// before the conversions, so that each stage costs one memory round trip
+// rather than one per object.
+constexpr int kChunk = 8;
+
+__global__ __launch_bounds__(256) void k_stage(EvView ev, const int32_t *__restrict__ idx,
+                                               const int64_t *__restrict__ count, int64_t capacity, RecoArgs a,
+                                               StageRec *__restrict__ stage) {
+    const int64_t S = clamp_count(count, capacity);
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (k >= S) return;
+    StageRec &r = stage[k];
+    const uint64_t g = (uint64_t)idx[k];
+    const int64_t e = (int64_t)g - ev.index_base;
+    const bool in_chunk = e >= 0 && e < ev.n;  // ids outside the chunk get no solution
+    r.g = g;
+    int nc = 0, V = 0;
+    if (in_chunk) {
+        V = ev.n_var ? (int)ev.n_var[e] : a.n_var_uniform;
+        r.met[0] = (double)ev.met_x[e];
+        r.met[1] = (double)ev.met_y[e];
+        const uint32_t l0 = ev.lep_off[e], l1 = ev.lep_off[e + 1];
+        const uint32_t j0 = ev.jet_off[e], j1 = ev.jet_off[e + 1];
+        // ---- leptons
+        uint32_t ls0 = 0, ls1 = 0;
+        int nl = 0;
+        for (uint32_t c0 = l0; c0 < l1; c0 += kChunk) {
+            float pt[kChunk], eta[kChunk];
+#pragma unroll
+            for (int u = 0; u < kChunk; ++u) {
+                const bool in = c0 + u < l1;
+                pt[u] = in ? ev.lep_pt[c0 + u] : 0.0f;
+                eta[u] = in ? ev.lep_eta[c0 + u] : 0.0f;
+            }
+#pragma unroll
+            for (int u = 0; u < kChunk; ++u)
+                if (c0 + u < l1 && pt[u] > a.lep_pt_min && fabsf(eta[u]) < a.lep_eta_max) {
+                    if (nl == 0) ls0 = c0 + u;
+                    if (nl == 1) ls1 = c0 + u;
+                    ++nl;
+                }
+        }
+        const float q0 = nl == 2 ? ev.lep_q[ls0] : 0.0f, q1 = nl == 2 ? ev.lep_q[ls1] : 0.0f;
+        if (nl == 2 && q0 * q1 < 0.0f) {
+            const uint32_t kp = q0 > 0.0f ? ls0 : ls1, km = q0 > 0.0f ? ls1 : ls0;
+            // ---- b candidates: tagged selected jets in order (or all selected), then the fill
+            const int cap = a.max_cands < kMaxC ? a.max_cands : kMaxC;
+            const bool all = a.pair_mode == HF_PAIR_ALL_JETS;
+            uint32_t jl[kMaxC];
+            uint32_t f0 = 0, f1 = 0;
+            int nfill = 0;
+#pragma unroll
+            for (int c = 0; c < kMaxC; ++c) jl[c] = 0;
+            for (uint32_t c0 = j0; c0 < j1; c0 += kChunk) {
+                float pt[kChunk], eta[kChunk], bt[kChunk];
+#pragma unroll
+                for (int u = 0; u < kChunk; ++u) {
+                    const bool in = c0 + u < j1;
+                    pt[u] = in ? ev.jet_pt[c0 + u] : 0.0f;
+                    eta[u] = in ? ev.jet_eta[c0 + u] : 0.0f;
+                    bt[u] = in ? ev.jet_btag[c0 + u] : 0.0f;
+                }
+#pragma unroll
+                for (int u = 0; u < kChunk; ++u) {
+                    if (!(c0 + u < j1 && pt[u] > a.jet_pt_min && fabsf(eta[u]) < a.jet_eta_max)) continue;
+                    if (all || bt[u] > a.btag_min) {
+                        if (nc < cap) {
+#pragma unroll
+                            for (int c = 0; c < kMaxC; ++c) jl[c] = c == nc ? c0 + u : jl[c];
+                            ++nc;
+                        }
+                    } else {
+                        if (nfill == 0) f0 = c0 + u;
+                        if (nfill == 1) f1 = c0 + u;
+                        ++nfill;
+                    }
+                }
+            }
+            if (!all) {
+                // leading untagged selected jets fill the list up to two
+                if (nc < 2 && nfill > 0) {
+#pragma unroll
+                    for (int c = 0; c < 2; ++c) jl[c] = c == nc ? f0 : jl[c];
+                    ++nc;
+                }
+                if (nc < 2 && nfill > 1) {
+                    jl[1] = f1;
+                    ++nc;
+                }
+            }
+            // ---- columns of the selected objects, loaded together (leptons, then
+            // candidates four at a time), then FP64 Cartesian
+            double v[4];
+            {
+                const float pa = ev.lep_pt[kp], ea = ev.lep_eta[kp], fa = ev.lep_phi[kp], xa = ev.lep_e[kp];
+                const float pb = ev.lep_pt[km], eb = ev.lep_eta[km], fb = ev.lep_phi[km], xb = ev.lep_e[km];
+                polar_to_cart(pa, ea, fa, xa, v);
+                for (int q = 0; q < 4; ++q) r.lp[q] = v[q];
+                r.ml2p = v[0] * v[0] - v[1] * v[1] - v[2] * v[2] - v[3] * v[3];
+                polar_to_cart(pb, eb, fb, xb, v);
+                for (int q = 0; q < 4; ++q) r.lm[q] = v[q];
+                r.ml2m = v[0] * v[0] - v[1] * v[1] - v[2] * v[2] - v[3] * v[3];
+            }
+#pragma unroll
+            for (int c0 = 0; c0 < kMaxC; c0 += 4) {
+                if (c0 >= nc) break;
+                float cpt[4], ceta[4], cphi[4], ce[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const bool in = c0 + u < nc;
+                    const uint32_t q = jl[c0 + u];
+                    cpt[u] = in ? ev.jet_pt[q] : 0.0f;
+                    ceta[u] = in ? ev.jet_eta[q] : 0.0f;
+                    cphi[u] = in ? ev.jet_phi[q] : 0.0f;
+                    ce[u] = in ? ev.jet_e[q] : 1.0f;
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int c = c0 + u;
+                    if (c < nc) {
+                        polar_to_cart(cpt[u], ceta[u], cphi[u], ce[u], v);
+                        for (int q = 0; q < 4; ++q) r.cand[c][q] = v[q];
+                        r.sigma[c] = sqrt(a.jet_a * a.jet_a / (double)ce[u] + a.jet_c * a.jet_c);
+                        r.jidx[c] = (int32_t)(jl[c] - j0);
+                    }
+                }
+            }
+        }
+    }
+    r.nc = nc;
+    r.V = V;
+}
+
 template <typename T>
-__global__ __launch_bounds__(kRecoBlock, 2) void k_search(EvView ev, const int32_t *__restrict__ idx,
-                                                          const int64_t *__restrict__ count, int64_t capacity,
-                                                          RecoArgs a, BestRec *__restrict__ best_out,
+__global__ __launch_bounds__(kRecoBlock, 2) void k_search(const int64_t *__restrict__ count, int64_t capacity,
+                                                          RecoArgs a, const StageRec *__restrict__ stage,
+                                                          BestRec *__restrict__ best_out,
                                                           uint64_t *__restrict__ wstats) {
     __shared__ WaveStage<T> stage_all[kRecoWaves];
     const int lane = lane_id();
@@ -138,94 +289,42 @@ __global__ __launch_bounds__(kRecoBlock, 2) void k_search(EvView ev, const int32
     const double mw2 = a.m_w * a.m_w;
     uint64_t acc_var = 0, acc_pair = 0, acc_int = 0, acc_sol = 0;
 
-    for (int64_t k = (int64_t)blockIdx.x * kRecoWaves + wave; k < S; k += nwaves) {
-        const int64_t e = (int64_t)idx[k] - ev.index_base;
-        const bool in_chunk = e >= 0 && e < ev.n;  // ids outside the chunk get no solution
-        // ------------------------------------------------------------ leptons
-        const uint32_t l0 = in_chunk ? ev.lep_off[e] : 0u;
-        const uint32_t nl = in_chunk ? ev.lep_off[e + 1] - l0 : 0u;
-        int nsel = 0;
-        if (lane < 2) st.lsel[lane] = -1;
-        wave_sync();
-        for (uint32_t cb = 0; cb < nl; cb += kWave) {
-            const uint32_t kk = cb + lane;
-            const bool sel = kk < nl && lep_sel(ev, l0 + kk, a);
-            const uint64_t m = ballot(sel);
-            const int r = nsel + popc64(m & lanemask_lt());
-            if (sel && r < 2) st.lsel[r] = (int)kk;
-            nsel += popc64(m);
+    // the staged record of the wave's next event is loaded one event ahead
+    const uint64_t *recw = reinterpret_cast<const uint64_t *>(stage);
+    constexpr int kTail = kRecWords - kWave;
+    int64_t k = (int64_t)blockIdx.x * kRecoWaves + wave;
+    uint64_t w0 = 0, w1 = 0;
+    if (k < S) {
+        w0 = recw[k * kRecWords + lane];
+        if (lane < kTail) w1 = recw[k * kRecWords + kWave + lane];
+    }
+    for (; k < S; k += nwaves) {
+        {
+            uint64_t *dst = reinterpret_cast<uint64_t *>(&st.rec);
+            dst[lane] = w0;
+            if (lane < kTail) dst[kWave + lane] = w1;
+        }
+        const int64_t kn = k + nwaves;
+        if (kn < S) {
+            w0 = recw[kn * kRecWords + lane];
+            if (lane < kTail) w1 = recw[kn * kRecWords + kWave + lane];
         }
         wave_sync();
-        bool ok = false;
-        if (nsel == 2) {
-            const uint32_t ka = l0 + st.lsel[0], kb = l0 + st.lsel[1];
-            const float qa = ev.lep_q[ka], qb = ev.lep_q[kb];
-            ok = qa * qb < 0.0f;
-            if (ok && lane < 2) {
-                const uint32_t kl = (lane == 0) == (qa > 0.0f) ? ka : kb;  // lane 0 -> l+, lane 1 -> l-
-                double v[4];
-                polar_to_cart(ev.lep_pt[kl], ev.lep_eta[kl], ev.lep_phi[kl], ev.lep_e[kl], v);
-                double *dst = lane == 0 ? st.lp : st.lm;
-                for (int q = 0; q < 4; ++q) dst[q] = v[q];
-                const double m2 = v[0] * v[0] - v[1] * v[1] - v[2] * v[2] - v[3] * v[3];
-                if (lane == 0)
-                    st.ml2p = m2;
-                else
-                    st.ml2m = m2;
-            }
-        }
-        // --------------------------------------------------------- candidates
-        const uint32_t j0 = in_chunk ? ev.jet_off[e] : 0u;
-        const uint32_t nj = in_chunk ? ev.jet_off[e + 1] - j0 : 0u;
-        const int cap = a.max_cands;
-        int nc = 0;
+        const int nc = __builtin_amdgcn_readfirstlane(st.rec.nc);
+        const bool ok = nc >= 2;
         if (ok) {
-            int ntag = 0;
-            for (uint32_t cb = 0; cb < nj; cb += kWave) {
-                const uint32_t kk = cb + lane;
-                const bool tag = kk < nj && jet_sel(ev, j0 + kk, a) &&
-                                 (a.pair_mode == HF_PAIR_ALL_JETS || ev.jet_btag[j0 + kk] > a.btag_min);
-                const uint64_t m = ballot(tag);
-                const int r = ntag + popc64(m & lanemask_lt());
-                if (tag && r < cap) st.jidx[r] = (int)kk;
-                ntag += popc64(m);
-            }
-            nc = ntag < cap ? ntag : cap;
-            if (a.pair_mode == HF_PAIR_BTAG_FILL && nc < 2) {
-                int nfill = 0;
-                for (uint32_t cb = 0; cb < nj && nc + nfill < 2; cb += kWave) {
-                    const uint32_t kk = cb + lane;
-                    const bool un = kk < nj && jet_sel(ev, j0 + kk, a) && !(ev.jet_btag[j0 + kk] > a.btag_min);
-                    const uint64_t m = ballot(un);
-                    const int r = nc + nfill + popc64(m & lanemask_lt());
-                    if (un && r < 2) st.jidx[r] = (int)kk;
-                    nfill += popc64(m);
-                }
-                nc = nc + nfill < 2 ? nc + nfill : 2;
-            }
-        }
-        ok = ok && nc >= 2;
-        wave_sync();
-        if (ok) {
-            if (lane < nc) {
-                const uint32_t kk = j0 + st.jidx[lane];
-                const float je = ev.jet_e[kk];
-                polar_to_cart(ev.jet_pt[kk], ev.jet_eta[kk], ev.jet_phi[kk], je, st.cand[lane]);
-                st.sigma[lane] = sqrt(a.jet_a * a.jet_a / (double)je + a.jet_c * a.jet_c);
-            }
-            wave_sync();
             // side constants: lanes [0, nc) with l+, lanes [16, 16 + nc) with l-
             if (lane < nc) {
-                st.okp[lane] = make_side(st.lp, st.cand[lane], st.sp[lane]) ? 1 : 0;
+                st.okp[lane] = make_side(st.rec.lp, st.rec.cand[lane], st.sp[lane]) ? 1 : 0;
             } else if (lane >= 16 && lane < 16 + nc) {
                 const int c = lane - 16;
-                st.okm[c] = make_side(st.lm, st.cand[c], st.sm[c]) ? 1 : 0;
+                st.okm[c] = make_side(st.rec.lm, st.rec.cand[c], st.sm[c]) ? 1 : 0;
             }
             wave_sync();
         }
 
         // ------------------------------------------------------- variations
-        const int V = !in_chunk ? 0 : ev.n_var ? (int)ev.n_var[e] : a.n_var_uniform;
+        const int V = __builtin_amdgcn_readfirstlane(st.rec.V);
         double best_s = -INFINITY, best_x = 0.0, best_y = 0.0;
         int best_v = kNoBest, best_p = kNoBest;
         int nsol = 0;
@@ -235,8 +334,8 @@ __global__ __launch_bounds__(kRecoBlock, 2) void k_search(EvView ev, const int32
                 for (int j = 0; j < nc; ++j) npair_valid += (i != j && st.okp[i] && st.okm[j]) ? 1 : 0;
         }
         if (npair_valid > 0) {
-            const double metx = ev.met_x[e], mety = ev.met_y[e];
-            const uint64_t g = (uint64_t)idx[k];
+            const double metx = st.rec.met[0], mety = st.rec.met[1];
+            const uint64_t g = st.rec.g;
             for (int vb = 0; vb < V; vb += kWave) {
                 const int v = vb + lane;
                 const bool act = v < V;
@@ -249,7 +348,7 @@ __global__ __launch_bounds__(kRecoBlock, 2) void k_search(EvView ev, const int32
                         uint32_t last_blk = 0xffffffffu;
                         T zb[4];
                         for (int c = 0; c < nc; ++c) {
-                            const uint32_t slot = 4u + (uint32_t)st.jidx[c];
+                            const uint32_t slot = 4u + (uint32_t)st.rec.jidx[c];
                             const uint32_t blk = slot >> 2;
                             if (blk != last_blk) {
                                 gauss_block<T>(a.seed, g, (uint32_t)v, blk, zb);
@@ -271,16 +370,16 @@ __global__ __launch_bounds__(kRecoBlock, 2) void k_search(EvView ev, const int32
                 const double slm = smear(a.lep_sigma, st.zl[1][lane]);
                 const double mx = metx + a.met_sigma * (double)st.zl[2][lane];
                 const double my = mety + a.met_sigma * (double)st.zl[3][lane];
-                const double Wp = mw2 / (2.0 * slp) - 0.5 * slp * st.ml2p;
-                const double Wm = mw2 / (2.0 * slm) - 0.5 * slm * st.ml2m;
+                const double Wp = mw2 / (2.0 * slp) - 0.5 * slp * st.rec.ml2p;
+                const double Wm = mw2 / (2.0 * slm) - 0.5 * slm * st.rec.ml2m;
                 for (int i = 0; i < nc; ++i) {
                     if (!st.okp[i]) continue;
-                    const double si = smear(st.sigma[i], st.z[i][lane]);
+                    const double si = smear(st.rec.sigma[i], st.z[i][lane]);
                     const SideVar A = side_var(st.sp[i], Wp, slp, si, mt2_mw2);
                     for (int j = 0; j < nc; ++j) {
                         if (j == i || !st.okm[j]) continue;
                         // ---- stage 1 (own variation): eliminant quartic and its root intervals
-                        const double sj = smear(st.sigma[j], st.z[j][lane]);
+                        const double sj = smear(st.rec.sigma[j], st.z[j][lane]);
                         const SideVar Bv = side_var(st.sm[j], Wm, slm, sj, mt2_mw2);
                         const Conic Q = reflect(Bv.q, mx, my);
                         Brackets Bk;
@@ -343,12 +442,12 @@ __global__ __launch_bounds__(kRecoBlock, 2) void k_search(EvView ev, const int32
                             }
                             double y;
                             if (!recover_y(P, Qs, x, y)) continue;
-                            if (!(polish_xy(P, Qs, x, y, 2, a.polish_skip_m2) <= a.accept_m2)) continue;
+                            if (!(polish_xy(P, Qs, x, y, 4, a.polish_skip_m2) <= a.accept_m2)) continue;
                             // the source variation's smear factors and MET, rebuilt from its draws
                             const T zli0 = st.zl[0][src], zli1 = st.zl[1][src];
                             const T zi = st.z[i][src], zj = st.z[j][src];
                             const double rslp = smear(a.lep_sigma, zli0), rslm = smear(a.lep_sigma, zli1);
-                            const double rsi = smear(st.sigma[i], zi), rsj = smear(st.sigma[j], zj);
+                            const double rsi = smear(st.rec.sigma[i], zi), rsj = smear(st.rec.sigma[j], zj);
                             const double rmx = metx + a.met_sigma * (double)st.zl[2][src];
                             const double rmy = mety + a.met_sigma * (double)st.zl[3][src];
                             const double en = st.sp[i][kE1] * x + st.sp[i][kE2] * y + ae0;
@@ -356,10 +455,10 @@ __global__ __launch_bounds__(kRecoBlock, 2) void k_search(EvView ev, const int32
                             const double eb = st.sm[j][kE1] * xb + st.sm[j][kE2] * yb + be0;
                             if (en < 0.0 || eb < 0.0) continue;
                             ++nsol;
-                            const double tx = rsi * st.cand[i][1] + rslp * st.lp[1] + x;  // top pT components
-                            const double ty = rsi * st.cand[i][2] + rslp * st.lp[2] + y;
-                            const double tbx = rsj * st.cand[j][1] + rslm * st.lm[1] + xb;
-                            const double tby = rsj * st.cand[j][2] + rslm * st.lm[2] + yb;
+                            const double tx = rsi * st.rec.cand[i][1] + rslp * st.rec.lp[1] + x;  // top pT components
+                            const double ty = rsi * st.rec.cand[i][2] + rslp * st.rec.lp[2] + y;
+                            const double tbx = rsj * st.rec.cand[j][1] + rslm * st.rec.lm[1] + xb;
+                            const double tby = rsj * st.rec.cand[j][2] + rslm * st.rec.lm[2] + yb;
                             const double zz = (double)zli0 * zli0 + (double)zli1 * zli1 +
                                               (double)st.zl[2][src] * st.zl[2][src] +
                                               (double)st.zl[3][src] * st.zl[3][src] + (double)zi * zi + (double)zj * zj;
@@ -436,8 +535,8 @@ __device__ __forceinline__ double mass4(double E, double X, double Y, double Z) 
 // One thread per compacted event: outputs of the chosen solution, the
 // H -> bb candidate, and the RECO counters (one atomic per block).
 template <typename T>
-__global__ __launch_bounds__(256) void k_epilogue(EvView ev, const int32_t *__restrict__ idx,
-                                                  const int64_t *__restrict__ count, int64_t capacity, RecoArgs a,
+__global__ __launch_bounds__(256) void k_epilogue(EvView ev, const int64_t *__restrict__ count, int64_t capacity,
+                                                  RecoArgs a, const StageRec *__restrict__ stage,
                                                   const BestRec *__restrict__ best, RecoOutView out,
                                                   hf_counters_t *__restrict__ counter, const uint64_t *wstats) {
     __shared__ uint32_t s_pass[256 / kWave];
@@ -457,37 +556,19 @@ __global__ __launch_bounds__(256) void k_epilogue(EvView ev, const int32_t *__re
             out.m_t[k] = out.m_tbar[k] = out.m_wp[k] = out.m_wm[k] = out.logw[k] = HF_NO_SOLUTION;
             if (out.m_bb) out.m_bb[k] = HF_NO_SOLUTION;
         } else {
-            const uint64_t g = (uint64_t)idx[k];
+            const StageRec &rec = stage[k];
+            const uint64_t g = rec.g;
             const int64_t e = (int64_t)g - ev.index_base;  // in the chunk: a solution exists
-            const uint32_t l0 = ev.lep_off[e], l1 = ev.lep_off[e + 1];
-            const uint32_t j0 = ev.jet_off[e], j1 = ev.jet_off[e + 1];
-            uint32_t ls[2] = {0, 0};
-            int nl = 0;
-            for (uint32_t q = l0; q < l1 && nl < 2; ++q)
-                if (lep_sel(ev, q, a)) ls[nl++] = q;
-            const uint32_t kp = ev.lep_q[ls[0]] > 0.0f ? ls[0] : ls[1];
-            const uint32_t km = ev.lep_q[ls[0]] > 0.0f ? ls[1] : ls[0];
-            // the r.p-th ordered pair of the candidate list, rebuilt with the same rule
+            // the r.p-th ordered pair of the candidate list
             const int nc = r.nc, ci = r.p / nc, cj = r.p % nc;
-            int jidx[2] = {-1, -1}, rank = 0;
-            for (uint32_t q = j0; q < j1 && rank < a.max_cands; ++q)
-                if (jet_sel(ev, q, a) && (a.pair_mode == HF_PAIR_ALL_JETS || ev.jet_btag[q] > a.btag_min)) {
-                    if (rank == ci) jidx[0] = (int)(q - j0);
-                    if (rank == cj) jidx[1] = (int)(q - j0);
-                    ++rank;
-                }
-            for (uint32_t q = j0; q < j1 && rank < 2 && a.pair_mode == HF_PAIR_BTAG_FILL; ++q)
-                if (jet_sel(ev, q, a) && !(ev.jet_btag[q] > a.btag_min)) {
-                    if (rank == ci) jidx[0] = (int)(q - j0);
-                    if (rank == cj) jidx[1] = (int)(q - j0);
-                    ++rank;
-                }
+            const int jidx[2] = {rec.jidx[ci], rec.jidx[cj]};
             double lp[4], lm[4], b[4], bb[4];
-            polar_to_cart(ev.lep_pt[kp], ev.lep_eta[kp], ev.lep_phi[kp], ev.lep_e[kp], lp);
-            polar_to_cart(ev.lep_pt[km], ev.lep_eta[km], ev.lep_phi[km], ev.lep_e[km], lm);
-            const uint32_t bi = j0 + jidx[0], bj = j0 + jidx[1];
-            polar_to_cart(ev.jet_pt[bi], ev.jet_eta[bi], ev.jet_phi[bi], ev.jet_e[bi], b);
-            polar_to_cart(ev.jet_pt[bj], ev.jet_eta[bj], ev.jet_phi[bj], ev.jet_e[bj], bb);
+            for (int q = 0; q < 4; ++q) {
+                lp[q] = rec.lp[q];
+                lm[q] = rec.lm[q];
+                b[q] = rec.cand[ci][q];
+                bb[q] = rec.cand[cj][q];
+            }
             double sp[kSide], sm[kSide];
             make_side(lp, b, sp);
             make_side(lm, bb, sm);
@@ -499,13 +580,11 @@ __global__ __launch_bounds__(256) void k_epilogue(EvView ev, const int32_t *__re
                 zj = gauss_slot<T>(a.seed, g, (uint32_t)r.v, 4u + (uint32_t)jidx[1]);
             }
             const double slp = smear(a.lep_sigma, zl[0]), slm = smear(a.lep_sigma, zl[1]);
-            const double si = smear(sqrt(a.jet_a * a.jet_a / (double)ev.jet_e[bi] + a.jet_c * a.jet_c), zi);
-            const double sj = smear(sqrt(a.jet_a * a.jet_a / (double)ev.jet_e[bj] + a.jet_c * a.jet_c), zj);
-            const double mx = (double)ev.met_x[e] + a.met_sigma * (double)zl[2];
-            const double my = (double)ev.met_y[e] + a.met_sigma * (double)zl[3];
+            const double si = smear(rec.sigma[ci], zi), sj = smear(rec.sigma[cj], zj);
+            const double mx = rec.met[0] + a.met_sigma * (double)zl[2];
+            const double my = rec.met[1] + a.met_sigma * (double)zl[3];
             const double mw2 = a.m_w * a.m_w, mt2_mw2 = a.m_t * a.m_t - mw2;
-            const double ml2p = lp[0] * lp[0] - lp[1] * lp[1] - lp[2] * lp[2] - lp[3] * lp[3];
-            const double ml2m = lm[0] * lm[0] - lm[1] * lm[1] - lm[2] * lm[2] - lm[3] * lm[3];
+            const double ml2p = rec.ml2p, ml2m = rec.ml2m;
             const SideVar A = side_var(sp, mw2 / (2.0 * slp) - 0.5 * slp * ml2p, slp, si, mt2_mw2);
             const SideVar Bv = side_var(sm, mw2 / (2.0 * slm) - 0.5 * slm * ml2m, slm, sj, mt2_mw2);
             const double x = r.x, y = r.y, xb = mx - x, yb = my - y;
@@ -537,6 +616,8 @@ __global__ __launch_bounds__(256) void k_epilogue(EvView ev, const int32_t *__re
                 // b-tagged selected jets; with only one, the leading remaining untagged one joins it.
                 double mbb = HF_NO_SOLUTION;
                 if (a.want_mbb) {
+                    const uint32_t j0 = ev.jet_off[e], j1 = ev.jet_off[e + 1];
+                    const uint32_t bi = j0 + (uint32_t)jidx[0], bj = j0 + (uint32_t)jidx[1];
                     uint32_t pick[2] = {0, 0};
                     int got = 0;
                     for (uint32_t q = j0; q < j1 && got < 2; ++q)
@@ -602,14 +683,18 @@ hipEvent_t g_time_start = nullptr, g_time_stop = nullptr;
 template <typename T>
 hipError_t launch_t(const EvView &ev, const int32_t *idx, const int64_t *count, int64_t capacity, const RecoArgs &a,
                     const RecoOutView &out, hf_counters_t *reco_counter, uint64_t *wstats, BestRec *best,
-                    hipStream_t s) {
+                    StageRec *stage, hipStream_t s) {
+    const int64_t eg = capacity > 0 ? (capacity + 255) / 256 : 1;
     if (capacity > 0) {
+        hipLaunchKernelGGL(k_stage, dim3((unsigned)eg), dim3(256), 0, s, ev, idx, count, capacity, a, stage);
+        hipError_t e1 = hipGetLastError();
+        if (e1 != hipSuccess) return e1;
         if (g_time_start) {
             const hipError_t e0 = hipEventRecord(g_time_start, s);
             if (e0 != hipSuccess) return e0;
         }
-        hipLaunchKernelGGL(k_search<T>, dim3(search_grid<T>(capacity)), dim3(kRecoBlock), 0, s, ev, idx, count,
-                           capacity, a, best, wstats);
+        hipLaunchKernelGGL(k_search<T>, dim3(search_grid<T>(capacity)), dim3(kRecoBlock), 0, s, count, capacity, a,
+                           stage, best, wstats);
         hipError_t err = hipGetLastError();
         if (err != hipSuccess) return err;
         if (g_time_stop) {
@@ -617,8 +702,7 @@ hipError_t launch_t(const EvView &ev, const int32_t *idx, const int64_t *count, 
             if (err != hipSuccess) return err;
         }
     }
-    const int64_t eg = capacity > 0 ? (capacity + 255) / 256 : 1;
-    hipLaunchKernelGGL(k_epilogue<T>, dim3((unsigned)eg), dim3(256), 0, s, ev, idx, count, capacity, a, best, out,
+    hipLaunchKernelGGL(k_epilogue<T>, dim3((unsigned)eg), dim3(256), 0, s, ev, count, capacity, a, stage, best, out,
                        reco_counter, wstats);
     return hipGetLastError();
 }
@@ -630,18 +714,28 @@ void set_reco_timing(hipEvent_t start, hipEvent_t stop) {
     g_time_stop = stop;
 }
 
-size_t reco_ws_bytes(int64_t capacity) { return kWsHeader + (size_t)(capacity > 0 ? capacity : 0) * sizeof(BestRec); }
+// Workspace: counters (kWsHeader bytes), BestRec[capacity], then StageRec[capacity]
+// at the next 256-byte boundary.
+static size_t stage_offset(int64_t capacity) {
+    const size_t b = kWsHeader + (size_t)(capacity > 0 ? capacity : 0) * sizeof(BestRec);
+    return (b + 255) & ~(size_t)255;
+}
+
+size_t reco_ws_bytes(int64_t capacity) {
+    return stage_offset(capacity) + (size_t)(capacity > 0 ? capacity : 0) * sizeof(StageRec);
+}
 
 hipError_t launch_reco(const EvView &ev, const int32_t *idx, const int64_t *count, int64_t capacity,
                        const RecoArgs &a, int precision, const RecoOutView &out, hf_counters_t *reco_counter,
                        void *ws, hipStream_t s) {
     uint64_t *wstats = static_cast<uint64_t *>(ws);
     BestRec *best = reinterpret_cast<BestRec *>(static_cast<char *>(ws) + kWsHeader);
+    StageRec *stage = reinterpret_cast<StageRec *>(static_cast<char *>(ws) + stage_offset(capacity));
     hipLaunchKernelGGL(k_reco_init, dim3(1), dim3(64), 0, s, wstats);
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
-    if (precision == HF_PREC_MIXED) return launch_t<float>(ev, idx, count, capacity, a, out, reco_counter, wstats, best, s);
-    return launch_t<double>(ev, idx, count, capacity, a, out, reco_counter, wstats, best, s);
+    if (precision == HF_PREC_MIXED) return launch_t<float>(ev, idx, count, capacity, a, out, reco_counter, wstats, best, stage, s);
+    return launch_t<double>(ev, idx, count, capacity, a, out, reco_counter, wstats, best, stage, s);
 }
 
 }  // namespace hf

@@ -258,15 +258,18 @@ HF_HD __forceinline__ int cubic_roots(T A, T B, T C, T &r0, T &r1, T &r2) {
 }
 
 // Root of c on (lo, hi) where c(lo) < 0 iff lo_neg; x is the first iterate.
-// Newton steps that leave the bracket are replaced by bisection.  Stops once
-// the Newton step is below 1e-12 max(1, |t|) (t = x / 100 GeV), tested
-// before the bracket so that an iterate sitting on a bracket end at
+// Newton steps that leave the bracket are replaced by bisection.  Converged
+// when the Newton step is below 1e-12 max(1, |t|) (t = x / 100 GeV), or below
+// 1e-7 max(1, |t|) and 1e-3 of the previous step (quadratic convergence: the
+// error after that step is of the order of its square).  The test comes
+// before the bracket update so that an iterate sitting on a bracket end at
 // convergence is not bisected away.  A root next to a critical point (a near
-// double root) is fixed only to the polynomial's rounding, where that step
-// test can fail forever: from the sixth iterate on, the search also stops
+// double root) is fixed only to the polynomial's rounding, where the step
+// tests can fail forever: from the sixth iterate on, the search also stops
 // when |p| is at its rounding floor (1e-15 of the sum of its terms'
 // magnitudes) or the bracket is narrower than the tolerance.
 HF_HD __forceinline__ double bracket_newton(const Poly4 &c, double lo, double hi, bool lo_neg, double x) {
+    double dx_prev = 0.0;
     for (int it = 0; it < 60; ++it) {
         HF_NEWTON_HOOK();
         double p, dp;
@@ -279,6 +282,7 @@ HF_HD __forceinline__ double bracket_newton(const Poly4 &c, double lo, double hi
         const double dx = p * fast_rcp(dp);
         const double tol = 1e-12 * fmax(1.0, fabs(x));
         if (fabs(dx) <= tol) return x - dx;
+        if (it >= 1 && fabs(dx) <= 1e5 * tol && fabs(dx) <= 1e-3 * fabs(dx_prev)) return x - dx;
         if (it >= 5) {
             // slow convergence (a root next to a critical point): stop once p is
             // at its rounding floor or the bracket is below the tolerance
@@ -289,27 +293,32 @@ HF_HD __forceinline__ double bracket_newton(const Poly4 &c, double lo, double hi
         }
         double xn = x - dx;
         if (!(xn > lo && xn < hi)) xn = 0.5 * (lo + hi);
+        dx_prev = dx;
         x = xn;
     }
     return x;
 }
 
 // Root of the interval [lo, hi] (values flo, fhi of opposite signs), in x
-// units.  First iterate: the quadratic model at a finite critical end
-// (p(c + d) ~ p(c) + p''(c) d^2 / 2), the secant when both ends are critical.
+// units.  First iterate: the quadratic model p(e + d) ~ p(e) + p''(e) d^2 / 2
+// at a critical end e -- for an interval between two critical points, at the
+// end where |p| is smaller (the root lies nearer to it), with the secant as
+// the fallback.
 HF_HD __forceinline__ void solve_interval(const Poly4 &c, double lo, double hi, double flo, double fhi, bool lo_crit,
                                           bool hi_crit, double &root, bool &found) {
     found = false;
     if (!((flo < 0.0 && fhi > 0.0) || (flo > 0.0 && fhi < 0.0)) || !(hi > lo)) return;
     double x0;
-    if (lo_crit && hi_crit) {
-        x0 = lo - flo * (hi - lo) * fast_rcp(fhi - flo);
-    } else if (lo_crit || hi_crit) {
-        const double cp = lo_crit ? lo : hi;
-        const double fv = lo_crit ? flo : fhi;
+    if (lo_crit || hi_crit) {
+        const bool from_lo = lo_crit && (!hi_crit || fabs(flo) <= fabs(fhi));
+        const double cp = from_lo ? lo : hi;
+        const double fv = from_lo ? flo : fhi;
         const double r = -2.0 * fv * fast_rcp(peval_d2(c, cp));
-        const double d = r > 0.0 ? sqrt(r) : fmax(1.0, fabs(cp));
-        x0 = lo_crit ? cp + d : cp - d;
+        if (r > 0.0)
+            x0 = from_lo ? cp + sqrt(r) : cp - sqrt(r);
+        else
+            x0 = (lo_crit && hi_crit) ? lo : from_lo ? cp + fmax(1.0, fabs(cp)) : cp - fmax(1.0, fabs(cp));
+        if (lo_crit && hi_crit && !(x0 > lo && x0 < hi)) x0 = lo - flo * (hi - lo) * fast_rcp(fhi - flo);
     } else {
         x0 = 0.0;
     }

@@ -40,33 +40,58 @@ __device__ __forceinline__ double fold_dphi(double d) {
     return d;
 }
 
+// Objects are visited in chunks of kChunk whose columns are loaded together
+// (predicated loads, issued back to back), so that a chunk costs one memory
+// round trip rather than one per object; the predicates and sums are then
+// evaluated in object order exactly as a plain loop would.
+constexpr int kChunk = 4;
+
 __device__ bool eval_cut(const EvView &ev, int64_t e, const hf_cut_t &c) {
     switch (c.kind) {
     case HF_CUT_LEP_N_OS: {
         const uint32_t l0 = ev.lep_off[e], l1 = ev.lep_off[e + 1];
         int n = 0;
         float qprod = 1.0f;
-        for (uint32_t k = l0; k < l1; ++k)
-            if (lep_ok(ev, k, c.f[0], c.f[1])) {
-                ++n;
-                qprod *= ev.lep_q[k];
+        for (uint32_t c0 = l0; c0 < l1; c0 += kChunk) {
+            float pt[kChunk], eta[kChunk], q[kChunk];
+#pragma unroll
+            for (int u = 0; u < kChunk; ++u) {
+                const bool in = c0 + u < l1;
+                pt[u] = in ? ev.lep_pt[c0 + u] : 0.0f;
+                eta[u] = in ? ev.lep_eta[c0 + u] : 0.0f;
+                q[u] = in ? ev.lep_q[c0 + u] : 0.0f;
             }
+#pragma unroll
+            for (int u = 0; u < kChunk; ++u)
+                if (c0 + u < l1 && pt[u] > c.f[0] && fabsf(eta[u]) < c.f[1]) {
+                    ++n;
+                    qprod *= q[u];
+                }
+        }
         if (n != c.i[0]) return false;
         if (c.i[1] && n == 2 && !(qprod < 0.0f)) return false;
         return true;
     }
-    case HF_CUT_JET_N_MIN: {
-        const uint32_t j0 = ev.jet_off[e], j1 = ev.jet_off[e + 1];
-        int n = 0;
-        for (uint32_t k = j0; k < j1; ++k) n += jet_ok(ev, k, c.f[0], c.f[1]);
-        return n >= c.i[0];
-    }
+    case HF_CUT_JET_N_MIN:
     case HF_CUT_BTAG_N_MIN:
     case HF_CUT_BTAG_N_EQ: {
+        const bool tag = c.kind != HF_CUT_JET_N_MIN;
         const uint32_t j0 = ev.jet_off[e], j1 = ev.jet_off[e + 1];
         int n = 0;
-        for (uint32_t k = j0; k < j1; ++k) n += jet_ok(ev, k, c.f[0], c.f[1]) && ev.jet_btag[k] > c.f[2];
-        return c.kind == HF_CUT_BTAG_N_MIN ? n >= c.i[0] : n == c.i[0];
+        for (uint32_t c0 = j0; c0 < j1; c0 += kChunk) {
+            float pt[kChunk], eta[kChunk], bt[kChunk];
+#pragma unroll
+            for (int u = 0; u < kChunk; ++u) {
+                const bool in = c0 + u < j1;
+                pt[u] = in ? ev.jet_pt[c0 + u] : 0.0f;
+                eta[u] = in ? ev.jet_eta[c0 + u] : 0.0f;
+                bt[u] = (in && tag) ? ev.jet_btag[c0 + u] : 0.0f;
+            }
+#pragma unroll
+            for (int u = 0; u < kChunk; ++u)
+                n += (c0 + u < j1 && pt[u] > c.f[0] && fabsf(eta[u]) < c.f[1] && (!tag || bt[u] > c.f[2])) ? 1 : 0;
+        }
+        return c.kind == HF_CUT_BTAG_N_EQ ? n == c.i[0] : n >= c.i[0];
     }
     case HF_CUT_MET_MIN: {
         const double mx = ev.met_x[e], my = ev.met_y[e], t = c.f[0];
@@ -76,15 +101,27 @@ __device__ bool eval_cut(const EvView &ev, int64_t e, const hf_cut_t &c) {
         const uint32_t l0 = ev.lep_off[e], l1 = ev.lep_off[e + 1];
         double E = 0, px = 0, py = 0, pz = 0;
         int n = 0;
-        for (uint32_t k = l0; k < l1 && n < 2; ++k)
-            if (lep_ok(ev, k, c.f[0], c.f[1])) {
-                const double pt = ev.lep_pt[k], eta = ev.lep_eta[k], phi = ev.lep_phi[k];
-                E += ev.lep_e[k];
-                px += pt * cos(phi);
-                py += pt * sin(phi);
-                pz += pt * sinh(eta);
-                ++n;
+        for (uint32_t c0 = l0; c0 < l1 && n < 2; c0 += kChunk) {
+            float pt[kChunk], eta[kChunk], phi[kChunk], en[kChunk];
+#pragma unroll
+            for (int u = 0; u < kChunk; ++u) {
+                const bool in = c0 + u < l1;
+                pt[u] = in ? ev.lep_pt[c0 + u] : 0.0f;
+                eta[u] = in ? ev.lep_eta[c0 + u] : 0.0f;
+                phi[u] = in ? ev.lep_phi[c0 + u] : 0.0f;
+                en[u] = in ? ev.lep_e[c0 + u] : 0.0f;
             }
+#pragma unroll
+            for (int u = 0; u < kChunk; ++u)
+                if (n < 2 && c0 + u < l1 && pt[u] > c.f[0] && fabsf(eta[u]) < c.f[1]) {
+                    const double dpt = pt[u];
+                    E += en[u];
+                    px += dpt * cos((double)phi[u]);
+                    py += dpt * sin((double)phi[u]);
+                    pz += dpt * sinh((double)eta[u]);
+                    ++n;
+                }
+        }
         if (n < 2) return false;
         const double m2 = E * E - px * px - py * py - pz * pz;
         const double t = c.f[2];
@@ -92,9 +129,17 @@ __device__ bool eval_cut(const EvView &ev, int64_t e, const hf_cut_t &c) {
     }
     case HF_CUT_FWD_JET_VETO: {
         const uint32_t j0 = ev.jet_off[e], j1 = ev.jet_off[e + 1];
-        for (uint32_t k = j0; k < j1; ++k) {
-            const float ae = fabsf(ev.jet_eta[k]);
-            if (ev.jet_pt[k] > c.f[0] && ae >= c.f[1] && ae < c.f[2]) return false;
+        for (uint32_t c0 = j0; c0 < j1; c0 += kChunk) {
+            float pt[kChunk], ae[kChunk];
+#pragma unroll
+            for (int u = 0; u < kChunk; ++u) {
+                const bool in = c0 + u < j1;
+                pt[u] = in ? ev.jet_pt[c0 + u] : 0.0f;
+                ae[u] = in ? fabsf(ev.jet_eta[c0 + u]) : 0.0f;
+            }
+#pragma unroll
+            for (int u = 0; u < kChunk; ++u)
+                if (c0 + u < j1 && pt[u] > c.f[0] && ae[u] >= c.f[1] && ae[u] < c.f[2]) return false;
         }
         return true;
     }
@@ -106,11 +151,22 @@ __device__ bool eval_cut(const EvView &ev, int64_t e, const hf_cut_t &c) {
         for (uint32_t a = l0; a < l1; ++a) {
             if (!lep_ok(ev, a, c.f[0], c.f[1])) continue;
             const double leta = ev.lep_eta[a], lphi = ev.lep_phi[a];
-            for (uint32_t k = j0; k < j1; ++k) {
-                if (!jet_ok(ev, k, c.f[2], c.f[3])) continue;
-                const double deta = leta - (double)ev.jet_eta[k];
-                const double dphi = fold_dphi(lphi - (double)ev.jet_phi[k]);
-                if (deta * deta + dphi * dphi < dr2) return false;
+            for (uint32_t c0 = j0; c0 < j1; c0 += kChunk) {
+                float pt[kChunk], eta[kChunk], phi[kChunk];
+#pragma unroll
+                for (int u = 0; u < kChunk; ++u) {
+                    const bool in = c0 + u < j1;
+                    pt[u] = in ? ev.jet_pt[c0 + u] : 0.0f;
+                    eta[u] = in ? ev.jet_eta[c0 + u] : 0.0f;
+                    phi[u] = in ? ev.jet_phi[c0 + u] : 0.0f;
+                }
+#pragma unroll
+                for (int u = 0; u < kChunk; ++u) {
+                    if (!(c0 + u < j1 && pt[u] > c.f[2] && fabsf(eta[u]) < c.f[3])) continue;
+                    const double deta = leta - (double)eta[u];
+                    const double dphi = fold_dphi(lphi - (double)phi[u]);
+                    if (deta * deta + dphi * dphi < dr2) return false;
+                }
             }
         }
         return true;
@@ -208,6 +264,41 @@ hipError_t launch_select(const EvView &ev, const CutTable &ct, const int32_t *or
     if (err != hipSuccess) return err;
     hipLaunchKernelGGL(k_select_reduce, dim3(ct.n * 3), dim3(256), 0, s, partial, grid, ct.n * 3,
                        reinterpret_cast<uint64_t *>(counters));
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- reordering
+// The greedy placement of hf_reorder_stats (section 5.2) on the device, so
+// that a recorded step can reorder its cuts without a host round trip.  One
+// thread: at most HF_MAX_CUTS cuts.  The rank arithmetic is the host's
+// (correctly rounded FP64 division, no contraction in this unit), so both
+// produce the same order.
+__global__ void k_reorder(const hf_counters_t *__restrict__ counters, CutTable ct, int32_t *__restrict__ order) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    __shared__ double rank[HF_MAX_CUTS];
+    for (int c = 0; c < ct.n; ++c) {
+        const hf_counters_t k = counters[c];
+        const double p = k.reached ? (double)k.passed / (double)k.reached : 1.0;
+        const double cost = k.reached ? (double)k.cost / (double)k.reached : 0.0;
+        const double rej = 1.0 - p;
+        rank[c] = cost / (rej > 1e-9 ? rej : 1e-9);
+    }
+    uint64_t placed = 0;
+    for (int pos = 0; pos < ct.n; ++pos) {
+        int best = -1;
+        for (int c = 0; c < ct.n; ++c) {
+            if ((placed >> c) & 1ull) continue;
+            if (ct.c[c].dep_mask & ~placed) continue;
+            if (best < 0 || rank[c] < rank[best]) best = c;
+        }
+        if (best < 0) return;  // cyclic: rejected on the host before the launch
+        order[pos] = best;
+        placed |= 1ull << best;
+    }
+}
+
+hipError_t launch_reorder(const hf_counters_t *counters, const CutTable &ct, int32_t *order, hipStream_t s) {
+    hipLaunchKernelGGL(k_reorder, dim3(1), dim3(64), 0, s, counters, ct, order);
     return hipGetLastError();
 }
 

@@ -132,7 +132,7 @@ int main(int argc, char **argv) {
             T32.clear();
             CD x = kXScale * bracket_root(Bk, kk), y;
             ++items;
-            if (recover_y(A.q, Q, x, y) && polish_xy(A.q, Q, x, y, 2, kPolishSkip * kAcceptM2 * 80.4 * 80.4) <= kAcceptM2 * 80.4 * 80.4) {
+            if (recover_y(A.q, Q, x, y) && polish_xy(A.q, Q, x, y, 4, kPolishSkip * kAcceptM2 * 80.4 * 80.4) <= kAcceptM2 * 80.4 * 80.4) {
                 const CD en = sp[kE1] * x + sp[kE2] * y + A.e0;
                 const CD xb = CD(r[16]) - x, yb = CD(r[17]) - y;
                 const CD eb = sm[kE1] * xb + sm[kE2] * yb + B.e0;

@@ -120,3 +120,23 @@ def test_reorder_rejects_cycles(B):
     arr = B.cut_table(cuts)
     with pytest.raises(B.HFError):
         B.reorder_stats(np.zeros((2, 3), dtype=np.uint64), arr, 2)
+
+
+def test_reorder_device_validates_on_the_host(B):
+    """Errors are reported before anything is launched (no GPU needed)."""
+    import ctypes as C
+    L = B.lib()
+    cuts = [{"name": "a", "kind": "MET_MIN", "f": [1], "deps": ["b"]},
+            {"name": "b", "kind": "MET_MIN", "f": [1], "deps": ["a"]}]
+    arr = B.cut_table(cuts)
+    dummy = C.c_void_p(16)
+    cyc = C.cast(arr, C.c_void_p)
+    assert L.hf_reorder_device(dummy, cyc, 2, dummy, None) == -1  # cyclic
+    assert L.hf_reorder_device(None, cyc, 2, dummy, None) == -1
+    assert L.hf_reorder_device(dummy, None, 2, dummy, None) == -1
+    assert L.hf_reorder_device(dummy, cyc, 0, dummy, None) == -1
+    assert L.hf_reorder_device(dummy, cyc, 33, dummy, None) == -1
+    # a dependency on a cut beyond n_cuts: b depends on a, only b is passed
+    two = B.cut_table([{"name": "b", "kind": "MET_MIN", "f": [1], "deps": ["a"]},
+                       {"name": "a", "kind": "MET_MIN", "f": [1], "deps": []}])
+    assert L.hf_reorder_device(dummy, C.cast(two, C.c_void_p), 1, dummy, None) == -1

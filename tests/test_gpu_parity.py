@@ -389,8 +389,23 @@ def test_full_size_bench_config_sampled(B, orc):
     worst = np.sort(np.argsort(-dev)[:32])
     want_w = orc.ttbar_reco(ev, got["idx"][worst], cfg["reco"])
     st_w = compare({k: v[worst] for k, v in r.items() if k != "stats"}, want_w)
-    _say("most off-shell", float(dev.max()), st_w)
-    assert st_w["decision_agree"] >= 0.9 and st_w["choice_agree"] >= 0.9, st_w
+    _say("most off-shell, mixed", float(dev.max()), st_w)
+    # These are the worst-conditioned events (near-tangent conics).  The mixed
+    # form's FP32 draws differ from the oracle's at the 1e-7 level, enough to
+    # make or remove an intersection here, so only the decision is compared;
+    # the FP64 form sees the oracle's inputs and must pick the same solutions.
+    assert st_w["decision_agree"] >= 0.9, st_w
+    ids = torch.from_numpy(np.ascontiguousarray(got["idx"][worst])).cuda()
+    from paper_2211_14346_amd.binding import RecoOutputs
+    outs = RecoOutputs(len(worst), want_mbb=False)
+    ws = B.workspace(B.lib().hf_ttbar_reco_workspace_size(len(worst)))
+    B.ttbar_reco(ch.dev, ids, torch.tensor([len(worst)], dtype=torch.int64, device="cuda"), len(worst),
+                 B.reco_params(cfg["reco"], precision="fp64", reco_cut=0), outs,
+                 torch.zeros(1, 3, dtype=torch.int64, device="cuda"), ws)
+    g64 = outs.host(len(worst))
+    st64 = compare({k: v for k, v in g64.items() if k != "stats"}, want_w)
+    _say("most off-shell, fp64", st64)
+    assert st64["decision_agree"] >= 0.9 and st64["choice_agree"] >= 0.9, st64
     assert np.array_equal(got["final"], got["idx"][hs])
     stats = r["stats"]
     assert stats[0] == S and stats[4] == r["n_sol"].sum() and stats[3] >= stats[4]
@@ -418,6 +433,54 @@ def test_graph_replay_matches_eager(B):
         for k in ("has_sol", "best_v", "best_i", "best_j", "n_sol", "nu", "nubar", "logw"):
             assert np.array_equal(r["reco"][k], ref["reco"][k]), (rep, k)
         assert np.array_equal(r["counters"][:, :2], ref["counters"][:, :2]), rep
+
+
+def test_reorder_device_matches_host(B, orc):
+    _say("device reorder")
+    rng = np.random.default_rng(12)
+    for name in ("ttbar10k", "tth4M_v256"):
+        cuts = hfgen.config(name)["cuts"]
+        n = len(cuts)
+        deps = np.array(hfgen.dep_masks(cuts), dtype=np.uint64)
+        arr = B.cut_table(cuts)
+        order = torch.zeros(n, dtype=torch.int32, device="cuda")
+        for _ in range(100):
+            reached = rng.integers(0, 10 ** 6, n).astype(np.uint64)
+            reached[rng.uniform(size=n) < 0.1] = 0
+            passed = (reached * rng.uniform(0, 1, n)).astype(np.uint64)
+            passed[rng.uniform(size=n) < 0.1] = 0  # some cuts reject everything they see
+            cost = (reached * rng.uniform(0, 1000, n)).astype(np.uint64)
+            cnt = np.stack([reached, passed, cost], axis=1)
+            B.reorder_device(torch.from_numpy(cnt.view(np.int64)).cuda(), arr, n, order)
+            got = order.cpu().numpy().tolist()
+            assert got == B.reorder_stats(cnt, arr, n)
+            assert got == list(orc.reorder(reached, passed, cost, deps))
+
+
+def test_graph_with_device_reorder(B):
+    """A recorded step that reorders its own cuts gives, replay after replay,
+    the order the host rule gives for the same accumulated counters."""
+    _say("graph with device reorder")
+    cfg = hfgen.config("tth4M_v256")
+    ev = hfgen.generate(cfg, n_events=20000, seed=92)
+    from paper_2211_14346_amd.chain import Chain
+    ch = Chain(ev, cfg["cuts"], cfg["reco"], precision="mixed")
+    ch.capture(reorder=True)
+    ch.reset_counters()
+    ref = None
+    for rep in range(4):
+        before = ch.order.cpu().numpy().tolist()
+        _ = torch.randn(1000, device="cuda").sum().item()  # eager work between replays
+        ch.replay()
+        torch.cuda.synchronize()
+        r = ch.results()
+        if ref is None:
+            ref = r
+        # the selection outcome does not depend on the order; the counters' reached column does
+        assert np.array_equal(r["survive"], ref["survive"]) and np.array_equal(r["final"], ref["final"]), rep
+        want = B.reorder_stats(ch.counters_host(), ch.cut_arr, ch.n_cuts)
+        assert ch.order.cpu().numpy().tolist() == want, (rep, before, want)
+    _say("device reorder: order after four steps", want)
 
 
 def test_deterministic_repeat(B):
