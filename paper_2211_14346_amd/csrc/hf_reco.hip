@@ -164,99 +164,119 @@ __global__ __launch_bounds__(256) void k_stage(EvView ev, const int32_t *__restr
         r.met[1] = (double)ev.met_y[e];
         const uint32_t l0 = ev.lep_off[e], l1 = ev.lep_off[e + 1];
         const uint32_t j0 = ev.jet_off[e], j1 = ev.jet_off[e + 1];
-        // ---- leptons
-        uint32_t ls0 = 0, ls1 = 0;
-        int nl = 0;
-        for (uint32_t c0 = l0; c0 < l1; c0 += kChunk) {
-            float pt[kChunk], eta[kChunk];
+        // The first chunk of each object list is loaded before anything is
+        // decided, so that leptons and jets share one memory round trip.
+        float lpt[kChunk], leta[kChunk], lq[kChunk], jpt[kChunk], jeta[kChunk], jbt[kChunk];
+        auto load_leps = [&](uint32_t c0) {
 #pragma unroll
             for (int u = 0; u < kChunk; ++u) {
                 const bool in = c0 + u < l1;
-                pt[u] = in ? ev.lep_pt[c0 + u] : 0.0f;
-                eta[u] = in ? ev.lep_eta[c0 + u] : 0.0f;
+                lpt[u] = in ? ev.lep_pt[c0 + u] : 0.0f;
+                leta[u] = in ? ev.lep_eta[c0 + u] : 0.0f;
+                lq[u] = in ? ev.lep_q[c0 + u] : 0.0f;
             }
+        };
+        auto load_jets = [&](uint32_t c0) {
+#pragma unroll
+            for (int u = 0; u < kChunk; ++u) {
+                const bool in = c0 + u < j1;
+                jpt[u] = in ? ev.jet_pt[c0 + u] : 0.0f;
+                jeta[u] = in ? ev.jet_eta[c0 + u] : 0.0f;
+                jbt[u] = in ? ev.jet_btag[c0 + u] : 0.0f;
+            }
+        };
+        load_leps(l0);
+        load_jets(j0);
+        // ---- leptons
+        uint32_t ls0 = 0, ls1 = 0;
+        float q0 = 0.0f, q1 = 0.0f;
+        int nl = 0;
+        for (uint32_t c0 = l0; c0 < l1; c0 += kChunk) {
+            if (c0 != l0) load_leps(c0);
 #pragma unroll
             for (int u = 0; u < kChunk; ++u)
-                if (c0 + u < l1 && pt[u] > a.lep_pt_min && fabsf(eta[u]) < a.lep_eta_max) {
-                    if (nl == 0) ls0 = c0 + u;
-                    if (nl == 1) ls1 = c0 + u;
+                if (c0 + u < l1 && lpt[u] > a.lep_pt_min && fabsf(leta[u]) < a.lep_eta_max) {
+                    if (nl == 0) {
+                        ls0 = c0 + u;
+                        q0 = lq[u];
+                    }
+                    if (nl == 1) {
+                        ls1 = c0 + u;
+                        q1 = lq[u];
+                    }
                     ++nl;
                 }
         }
-        const float q0 = nl == 2 ? ev.lep_q[ls0] : 0.0f, q1 = nl == 2 ? ev.lep_q[ls1] : 0.0f;
-        if (nl == 2 && q0 * q1 < 0.0f) {
-            const uint32_t kp = q0 > 0.0f ? ls0 : ls1, km = q0 > 0.0f ? ls1 : ls0;
-            // ---- b candidates: tagged selected jets in order (or all selected), then the fill
-            const int cap = a.max_cands < kMaxC ? a.max_cands : kMaxC;
-            const bool all = a.pair_mode == HF_PAIR_ALL_JETS;
-            uint32_t jl[kMaxC];
-            uint32_t f0 = 0, f1 = 0;
-            int nfill = 0;
+        // ---- b candidates: tagged selected jets in order (or all selected), then the fill
+        const int cap = a.max_cands < kMaxC ? a.max_cands : kMaxC;
+        const bool all = a.pair_mode == HF_PAIR_ALL_JETS;
+        uint32_t jl[kMaxC];
+        uint32_t f0 = 0, f1 = 0;
+        int nfill = 0;
 #pragma unroll
-            for (int c = 0; c < kMaxC; ++c) jl[c] = 0;
-            for (uint32_t c0 = j0; c0 < j1; c0 += kChunk) {
-                float pt[kChunk], eta[kChunk], bt[kChunk];
+        for (int c = 0; c < kMaxC; ++c) jl[c] = 0;
+        for (uint32_t c0 = j0; c0 < j1; c0 += kChunk) {
+            if (c0 != j0) load_jets(c0);
 #pragma unroll
-                for (int u = 0; u < kChunk; ++u) {
-                    const bool in = c0 + u < j1;
-                    pt[u] = in ? ev.jet_pt[c0 + u] : 0.0f;
-                    eta[u] = in ? ev.jet_eta[c0 + u] : 0.0f;
-                    bt[u] = in ? ev.jet_btag[c0 + u] : 0.0f;
-                }
+            for (int u = 0; u < kChunk; ++u) {
+                if (!(c0 + u < j1 && jpt[u] > a.jet_pt_min && fabsf(jeta[u]) < a.jet_eta_max)) continue;
+                if (all || jbt[u] > a.btag_min) {
+                    if (nc < cap) {
 #pragma unroll
-                for (int u = 0; u < kChunk; ++u) {
-                    if (!(c0 + u < j1 && pt[u] > a.jet_pt_min && fabsf(eta[u]) < a.jet_eta_max)) continue;
-                    if (all || bt[u] > a.btag_min) {
-                        if (nc < cap) {
-#pragma unroll
-                            for (int c = 0; c < kMaxC; ++c) jl[c] = c == nc ? c0 + u : jl[c];
-                            ++nc;
-                        }
-                    } else {
-                        if (nfill == 0) f0 = c0 + u;
-                        if (nfill == 1) f1 = c0 + u;
-                        ++nfill;
+                        for (int c = 0; c < kMaxC; ++c) jl[c] = c == nc ? c0 + u : jl[c];
+                        ++nc;
                     }
+                } else {
+                    if (nfill == 0) f0 = c0 + u;
+                    if (nfill == 1) f1 = c0 + u;
+                    ++nfill;
                 }
             }
-            if (!all) {
-                // leading untagged selected jets fill the list up to two
-                if (nc < 2 && nfill > 0) {
+        }
+        if (!all) {
+            // leading untagged selected jets fill the list up to two
+            if (nc < 2 && nfill > 0) {
 #pragma unroll
-                    for (int c = 0; c < 2; ++c) jl[c] = c == nc ? f0 : jl[c];
-                    ++nc;
-                }
-                if (nc < 2 && nfill > 1) {
-                    jl[1] = f1;
-                    ++nc;
-                }
+                for (int c = 0; c < 2; ++c) jl[c] = c == nc ? f0 : jl[c];
+                ++nc;
             }
-            // ---- columns of the selected objects, loaded together (leptons, then
-            // candidates four at a time), then FP64 Cartesian
-            double v[4];
-            {
-                const float pa = ev.lep_pt[kp], ea = ev.lep_eta[kp], fa = ev.lep_phi[kp], xa = ev.lep_e[kp];
-                const float pb = ev.lep_pt[km], eb = ev.lep_eta[km], fb = ev.lep_phi[km], xb = ev.lep_e[km];
-                polar_to_cart(pa, ea, fa, xa, v);
-                for (int q = 0; q < 4; ++q) r.lp[q] = v[q];
-                r.ml2p = v[0] * v[0] - v[1] * v[1] - v[2] * v[2] - v[3] * v[3];
-                polar_to_cart(pb, eb, fb, xb, v);
-                for (int q = 0; q < 4; ++q) r.lm[q] = v[q];
-                r.ml2m = v[0] * v[0] - v[1] * v[1] - v[2] * v[2] - v[3] * v[3];
+            if (nc < 2 && nfill > 1) {
+                jl[1] = f1;
+                ++nc;
             }
-#pragma unroll
-            for (int c0 = 0; c0 < kMaxC; c0 += 4) {
-                if (c0 >= nc) break;
-                float cpt[4], ceta[4], cphi[4], ce[4];
+        }
+        if (!(nl == 2 && q0 * q1 < 0.0f)) nc = 0;
+        if (nc > 0) {
+            const uint32_t kp = q0 > 0.0f ? ls0 : ls1, km = q0 > 0.0f ? ls1 : ls0;
+            // ---- columns of the selected objects, loaded together (the leptons with
+            // the first four candidates, then four at a time), then FP64 Cartesian;
+            // all loads of a round precede the stores, which may alias them
+            float cpt[4], ceta[4], cphi[4], ce[4];
+            auto load_cands = [&](int c0) {
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                     const bool in = c0 + u < nc;
-                    const uint32_t q = jl[c0 + u];
+                    const uint32_t q = in ? jl[c0 + u] : j0;
                     cpt[u] = in ? ev.jet_pt[q] : 0.0f;
                     ceta[u] = in ? ev.jet_eta[q] : 0.0f;
                     cphi[u] = in ? ev.jet_phi[q] : 0.0f;
                     ce[u] = in ? ev.jet_e[q] : 1.0f;
                 }
+            };
+            const float pa = ev.lep_pt[kp], ea = ev.lep_eta[kp], fa = ev.lep_phi[kp], xa = ev.lep_e[kp];
+            const float pb = ev.lep_pt[km], eb = ev.lep_eta[km], fb = ev.lep_phi[km], xb = ev.lep_e[km];
+            load_cands(0);
+            double v[4];
+            polar_to_cart(pa, ea, fa, xa, v);
+            for (int q = 0; q < 4; ++q) r.lp[q] = v[q];
+            r.ml2p = v[0] * v[0] - v[1] * v[1] - v[2] * v[2] - v[3] * v[3];
+            polar_to_cart(pb, eb, fb, xb, v);
+            for (int q = 0; q < 4; ++q) r.lm[q] = v[q];
+            r.ml2m = v[0] * v[0] - v[1] * v[1] - v[2] * v[2] - v[3] * v[3];
+#pragma unroll
+            for (int c0 = 0; c0 < kMaxC; c0 += 4) {
+                if (c0 >= nc) break;
+                if (c0 > 0) load_cands(c0);
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                     const int c = c0 + u;
@@ -370,8 +390,8 @@ __global__ __launch_bounds__(kRecoBlock, 2) void k_search(const int64_t *__restr
                 const double slm = smear(a.lep_sigma, st.zl[1][lane]);
                 const double mx = metx + a.met_sigma * (double)st.zl[2][lane];
                 const double my = mety + a.met_sigma * (double)st.zl[3][lane];
-                const double Wp = mw2 / (2.0 * slp) - 0.5 * slp * st.rec.ml2p;
-                const double Wm = mw2 / (2.0 * slm) - 0.5 * slm * st.rec.ml2m;
+                const double Wp = (0.5 * mw2) * fast_rcp(slp) - 0.5 * slp * st.rec.ml2p;
+                const double Wm = (0.5 * mw2) * fast_rcp(slm) - 0.5 * slm * st.rec.ml2m;
                 for (int i = 0; i < nc; ++i) {
                     if (!st.okp[i]) continue;
                     const double si = smear(st.rec.sigma[i], st.z[i][lane]);
@@ -462,7 +482,7 @@ __global__ __launch_bounds__(kRecoBlock, 2) void k_search(const int64_t *__restr
                             const double zz = (double)zli0 * zli0 + (double)zli1 * zli1 +
                                               (double)st.zl[2][src] * st.zl[2][src] +
                                               (double)st.zl[3][src] * st.zl[3][src] + (double)zi * zi + (double)zj * zj;
-                            const double w = -0.5 * zz - (sqrt(tx * tx + ty * ty) + sqrt(tbx * tbx + tby * tby)) *
+                            const double w = -0.5 * zz - (fast_sqrt(tx * tx + ty * ty) + fast_sqrt(tbx * tbx + tby * tby)) *
                                                              a.inv_lambda;
                             const int vs = vb + src;
                             if (better(w, vs, p, x, best_s, best_v, best_p, best_x)) {

@@ -44,6 +44,23 @@ HF_HD __forceinline__ double fast_rcp(double d) {
 #endif
 }
 
+// sqrt(v) for v >= 0 to about one ulp: the hardware reciprocal square root
+// and one Goldschmidt refinement (no IEEE correction sequence).
+HF_HD __forceinline__ double fast_sqrt(double v) {
+#ifdef __HIP_DEVICE_COMPILE__
+    if (!(v > 0.0)) return 0.0;
+    const double y = __builtin_amdgcn_rsq(v);
+    double s = v * y, h = 0.5 * y;
+    const double r = fma(-s, h, 0.5);
+    s = fma(s, r, s);
+    h = fma(h, r, h);
+    const double d = fma(-s, s, v);
+    return fma(d, h, s);
+#else
+    return sqrt(v);
+#endif
+}
+
 // constants of one (lepton, b candidate) side, nominal kinematics
 enum SideField { kE1 = 0, kE2, kZ1, kZ2, kAl, kBe, kGa, kDe, kQxx, kQxy, kQyy, kMb2, kBl, kSide };
 
@@ -102,7 +119,7 @@ struct SideVar {
 
 HF_HD __forceinline__ SideVar side_var(const double *s, double W, double s_l, double s_b, double mt2_mw2) {
     SideVar r;
-    const double U = mt2_mw2 / (2.0 * s_b) - 0.5 * s_b * s[kMb2] - s_l * s[kBl];
+    const double U = (0.5 * mt2_mw2) * fast_rcp(s_b) - 0.5 * s_b * s[kMb2] - s_l * s[kBl];
     r.e0 = s[kAl] * U - s[kBe] * W;
     r.z0 = s[kGa] * U - s[kDe] * W;
     r.q.xx = s[kQxx];
