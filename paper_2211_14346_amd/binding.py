@@ -47,7 +47,7 @@ class RecoParams(C.Structure):
                [(k, C.c_float) for k in ("lep_pt_min", "lep_eta_max", "jet_pt_min", "jet_eta_max", "btag_min")] + \
                [("reco_cut", C.c_int32), ("seed", C.c_uint64)] + \
                [(k, C.c_int32) for k in ("smear", "n_var_uniform", "precision", "pair_mode", "max_cands",
-                                         "want_mbb")]
+                                         "want_mbb", "schedule", "reserved")]
 
 
 class RecoOut(C.Structure):
@@ -55,7 +55,7 @@ class RecoOut(C.Structure):
                                           "m_tbar", "m_wp", "m_wm", "logw", "m_bb", "stats")]
 
 
-assert C.sizeof(Cut) == 64 and C.sizeof(RecoParams) == 112 and C.sizeof(Counters) == 24
+assert C.sizeof(Cut) == 64 and C.sizeof(RecoParams) == 120 and C.sizeof(Counters) == 24
 
 _lib = None
 
@@ -81,12 +81,14 @@ def lib():
                                     P, C.c_size_t, P]
         L.hf_reorder_stats.argtypes = [P, P, C.c_int, P]
         L.hf_reorder_device.argtypes = [P, P, C.c_int, P, P]
+        L.hf_ttbar_reco_autotune.argtypes = [C.POINTER(Events), P, P, C.c_int64, C.POINTER(RecoParams),
+                                             C.POINTER(RecoOut), P, C.c_size_t, P, P]
         L.hf_reco_timing_events.argtypes = [P, P]
         L.hf_reco_timing_events.restype = C.c_int
         L.hf_philox_blocks.argtypes = [P, C.c_uint64, P, C.c_int64, P]
         L.hf_gauss_draws.argtypes = [C.c_uint64, P, P, P, C.c_int64, C.c_int, P, P]
-        for f in ("hf_select", "hf_compact", "hf_ttbar_reco", "hf_reorder_stats", "hf_reorder_device",
-                  "hf_philox_blocks", "hf_gauss_draws"):
+        for f in ("hf_select", "hf_compact", "hf_ttbar_reco", "hf_ttbar_reco_autotune", "hf_reorder_stats",
+                  "hf_reorder_device", "hf_philox_blocks", "hf_gauss_draws"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -127,14 +129,18 @@ def cut_table(cuts):
     return arr
 
 
-def reco_params(reco, precision="mixed", reco_cut=-1):
+SCHED = {"auto": 0, "event": 1, "worklist": 2}
+
+
+def reco_params(reco, precision="mixed", reco_cut=-1, schedule="auto"):
     return RecoParams(
         m_t=reco["m_t"], m_w=reco["m_w"], lambda_pt=reco["lambda_pt"], jet_a=reco["jet_a"], jet_c=reco["jet_c"],
         lep_sigma=reco["lep_sigma"], met_sigma=reco["met_sigma"], lep_pt_min=reco["lep_pt_min"],
         lep_eta_max=reco["lep_eta_max"], jet_pt_min=reco["jet_pt_min"], jet_eta_max=reco["jet_eta_max"],
         btag_min=reco["btag_min"], reco_cut=int(reco_cut), seed=int(reco["seed"]), smear=int(reco["smear"]),
         n_var_uniform=int(reco["n_var"]) if reco["n_var"] else 1, precision=PREC[precision],
-        pair_mode=PAIR[reco["pair_mode"]], max_cands=int(reco["max_cands"]), want_mbb=int(reco["want_mbb"]))
+        pair_mode=PAIR[reco["pair_mode"]], max_cands=int(reco["max_cands"]), want_mbb=int(reco["want_mbb"]),
+        schedule=SCHED[schedule] if isinstance(schedule, str) else int(schedule))
 
 
 class DeviceEvents:
@@ -214,6 +220,16 @@ def reorder_stats(counters_host, cuts_arr, n_cuts):
                                 C.cast(order, C.c_void_p))
     _check(rc, "hf_reorder_stats")
     return list(order)
+
+
+def ttbar_reco_autotune(dev, idx, count, capacity, params, outs, ws, stream=None):
+    """Times the two schedules on this input, stores the faster one in params
+    (and in the HF_AUTOTUNE_CACHE file if set); returns (ms_event, ms_worklist)."""
+    ms = (C.c_double * 2)()
+    rc = lib().hf_ttbar_reco_autotune(dev.ptr, _p(idx), _p(count), int(capacity), C.byref(params), C.byref(outs.s),
+                                      _p(ws), ws.numel() * ws.element_size(), _stream(stream), ms)
+    _check(rc, "hf_ttbar_reco_autotune")
+    return ms[0], ms[1]
 
 
 def reorder_device(counters, cuts_arr, n_cuts, order, stream=None):

@@ -3,8 +3,11 @@
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
+#include <map>
+#include <mutex>
 #include <string>
 
 #include "../../include/hf.h"
@@ -59,6 +62,62 @@ int check_cuts(const hf_cut_t *h_cuts, int n_cuts, bool *need_phi_e) {
         if (k.kind == HF_CUT_MLL_MIN || k.kind == HF_CUT_LEP_ISO) *need_phi_e = true;
     }
     return HF_OK;
+}
+
+// ---- autotuner cache: one line per configuration, "key schedule ms_event ms_worklist";
+// the last line for a key wins.  Read once per process from HF_AUTOTUNE_CACHE.
+std::mutex g_tune_mu;
+bool g_tune_loaded = false;
+std::map<std::string, int> g_tune;
+
+std::string tune_key(const hf_events_t *ev, const hf_reco_params_t *p, int64_t capacity) {
+    int dev = 0;
+    char name[64] = "gpu";
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+        snprintf(name, sizeof name, "%s", prop.gcnArchName);
+    for (char *c = name; *c; ++c)
+        if (*c == ' ' || *c == ':') *c = '_';
+    int bucket = 0;
+    while (bucket < 62 && ((int64_t)1 << (bucket + 1)) <= capacity) ++bucket;
+    char key[256];
+    snprintf(key, sizeof key, "%s|prec=%d|pair=%d|cands=%d|nvar=%s%d|cap=2^%d", name, p->precision, p->pair_mode,
+             p->max_cands, ev->n_var ? "per_event" : "", ev->n_var ? 0 : p->n_var_uniform, bucket);
+    return key;
+}
+
+void load_tune_cache() {
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char *path = getenv("HF_AUTOTUNE_CACHE");
+    if (!path || !*path) return;
+    FILE *f = fopen(path, "r");
+    if (!f) return;
+    char key[256];
+    int sched;
+    double a, b;
+    while (fscanf(f, "%255s %d %lf %lf", key, &sched, &a, &b) == 4)
+        if (sched == HF_SCHED_EVENT || sched == HF_SCHED_WORKLIST) g_tune[key] = sched;
+    fclose(f);
+}
+
+int tuned_schedule(const std::string &key) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    load_tune_cache();
+    auto it = g_tune.find(key);
+    return it == g_tune.end() ? HF_SCHED_AUTO : it->second;
+}
+
+void store_schedule(const std::string &key, int sched, const double ms[2]) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    load_tune_cache();
+    g_tune[key] = sched;
+    const char *path = getenv("HF_AUTOTUNE_CACHE");
+    if (!path || !*path) return;
+    FILE *f = fopen(path, "a");
+    if (!f) return;
+    fprintf(f, "%s %d %.6f %.6f\n", key.c_str(), sched, ms[0], ms[1]);
+    fclose(f);
 }
 
 }  // namespace
@@ -149,6 +208,8 @@ int hf_ttbar_reco(const hf_events_t *ev, const int32_t *d_idx, const int64_t *d_
     if (!(p->jet_a >= 0.0) || !(p->jet_c >= 0.0) || !(p->lep_sigma >= 0.0) || !(p->met_sigma >= 0.0))
         return fail(HF_ERR_INVAL, "hf_ttbar_reco: resolutions must be finite and >= 0");
     if (p->smear != 0 && p->smear != 1) return fail(HF_ERR_INVAL, "hf_ttbar_reco: smear must be 0 or 1");
+    if (p->schedule != HF_SCHED_AUTO && p->schedule != HF_SCHED_EVENT && p->schedule != HF_SCHED_WORKLIST)
+        return fail(HF_ERR_INVAL, "hf_ttbar_reco: unknown schedule %d", p->schedule);
     const size_t need = hf::reco_ws_bytes(capacity);
     if (!d_ws || ws_bytes < need)
         return fail(HF_ERR_CAPACITY, "hf_ttbar_reco: workspace %zu bytes < %zu required", ws_bytes, need);
@@ -177,8 +238,55 @@ int hf_ttbar_reco(const hf_events_t *ev, const int32_t *d_idx, const int64_t *d_
     hf::RecoOutView o{out->has_sol, out->n_sol, out->best_v, out->best_i, out->best_j, out->nu, out->nubar,
                       out->m_t,     out->m_tbar, out->m_wp,  out->m_wm,   out->logw, out->m_bb, out->stats};
     hf_counters_t *rc = (d_counters && p->reco_cut >= 0) ? d_counters + p->reco_cut : nullptr;
-    hipError_t e = hf::launch_reco(hf::make_view(*ev), d_idx, d_count, capacity, a, p->precision, o, rc, d_ws, stream);
+    int sched = p->schedule;
+    if (sched == HF_SCHED_AUTO) sched = tuned_schedule(tune_key(ev, p, capacity));
+    if (sched == HF_SCHED_AUTO) sched = ev->n_var ? HF_SCHED_WORKLIST : HF_SCHED_EVENT;
+    hipError_t e = hf::launch_reco(hf::make_view(*ev), d_idx, d_count, capacity, a, p->precision, o, rc, d_ws,
+                                   sched == HF_SCHED_WORKLIST, stream);
     if (e != hipSuccess) return device_fail("hf_ttbar_reco launch", e);
+    return HF_OK;
+}
+
+int hf_ttbar_reco_autotune(const hf_events_t *ev, const int32_t *d_idx, const int64_t *d_count, int64_t capacity,
+                           hf_reco_params_t *h_params, const hf_reco_out_t *out, void *d_ws, size_t ws_bytes,
+                           hipStream_t stream, double *h_ms) {
+    if (!h_params || !out) return fail(HF_ERR_INVAL, "hf_ttbar_reco_autotune: params or out is NULL");
+    hf_reco_params_t p = *h_params;
+    hf_reco_out_t o = *out;
+    o.stats = nullptr;  // the trial calls leave no trace in the statistics or counters
+    const int cand[2] = {HF_SCHED_EVENT, HF_SCHED_WORKLIST};
+    double ms[2] = {0.0, 0.0};
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    if (hipEventCreate(&t0) != hipSuccess || hipEventCreate(&t1) != hipSuccess) {
+        if (t0) (void)hipEventDestroy(t0);
+        return fail(HF_ERR_DEVICE, "hf_ttbar_reco_autotune: hipEventCreate failed");
+    }
+    int rc = HF_OK;
+    constexpr int kReps = 3;
+    for (int c = 0; c < 2 && rc == HF_OK; ++c) {
+        p.schedule = cand[c];
+        rc = hf_ttbar_reco(ev, d_idx, d_count, capacity, &p, &o, nullptr, d_ws, ws_bytes, stream);  // warm-up
+        if (rc != HF_OK) break;
+        if (hipEventRecord(t0, stream) != hipSuccess) rc = fail(HF_ERR_DEVICE, "hf_ttbar_reco_autotune: record");
+        for (int r = 0; r < kReps && rc == HF_OK; ++r)
+            rc = hf_ttbar_reco(ev, d_idx, d_count, capacity, &p, &o, nullptr, d_ws, ws_bytes, stream);
+        if (rc != HF_OK) break;
+        float el = 0.0f;
+        if (hipEventRecord(t1, stream) != hipSuccess || hipEventSynchronize(t1) != hipSuccess ||
+            hipEventElapsedTime(&el, t0, t1) != hipSuccess)
+            rc = fail(HF_ERR_DEVICE, "hf_ttbar_reco_autotune: timing failed");
+        ms[c] = (double)el / kReps;
+    }
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    if (rc != HF_OK) return rc;
+    const int best = ms[1] < ms[0] ? HF_SCHED_WORKLIST : HF_SCHED_EVENT;
+    h_params->schedule = best;
+    if (h_ms) {
+        h_ms[0] = ms[0];
+        h_ms[1] = ms[1];
+    }
+    store_schedule(tune_key(ev, h_params, capacity), best, ms);
     return HF_OK;
 }
 

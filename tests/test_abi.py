@@ -40,7 +40,7 @@ def test_exports_every_declared_symbol(B):
 def test_struct_layouts(B):
     assert C.sizeof(B.Cut) == 64
     assert C.sizeof(B.Counters) == 24
-    assert C.sizeof(B.RecoParams) == 112
+    assert C.sizeof(B.RecoParams) == 120
     assert C.sizeof(B.Events) == 16 + 8 * 15
     assert C.sizeof(B.RecoOut) == 8 * 14
 

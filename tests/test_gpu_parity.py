@@ -246,6 +246,81 @@ def test_reco_heavy_tailed_variations(B, orc, precision):
     _full_chain_check(B, orc, "stress2M_heavytail", 1500, precision, seed=79)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_reco_worklist_packs_and_splits(B, orc, precision):
+    """Variation counts chosen to exercise the worklist: several small events
+    packed into one 64-lane block, events split over many blocks, blocks
+    split over wavefronts (few events, far more blocks than for one per
+    event), counts of exactly 16, 64 and one more."""
+    _say("worklist pack/split", precision)
+    cfg = hfgen.config("ttbar1M_v64")
+    ev = hfgen.generate(cfg, n_events=400, seed=93)
+    rng = np.random.default_rng(93)
+    fixed = [1024, 1, 2, 3, 700, 17, 64, 65, 128, 5, 16, 15, 33, 1000, 1, 1, 1, 1, 1, 1, 63, 900]
+    nv = np.concatenate([fixed, rng.integers(1, 40, ev["n"] - len(fixed))]).astype(np.uint16)
+    ev["n_var"] = nv
+    reco = dict(cfg["reco"])
+    ch, got = _chain(ev, cfg["cuts"], reco, precision)
+    want = orc.run_chain(ev, cfg["cuts"], reco)
+    _check_selection(got, want, cfg["cuts"])
+    st = compare(got["reco"], want["reco"])
+    _say(st)
+    assert_agree(st, min_agree=0.99 if precision == "mixed" else 0.999)
+    stats = got["reco"]["stats"]
+    assert stats[0] == got["count"] and stats[4] == got["reco"]["n_sol"].sum()
+
+
+def _reco_direct(B, ev, ids, reco, precision, schedule, index_base=0):
+    from paper_2211_14346_amd.binding import DeviceEvents, RecoOutputs
+    dev = DeviceEvents(ev, index_base=index_base)
+    S = len(ids)
+    outs = RecoOutputs(S)
+    p = B.reco_params(reco, precision=precision, reco_cut=0, schedule=schedule)
+    ws = B.workspace(B.lib().hf_ttbar_reco_workspace_size(S))
+    idx = torch.from_numpy(np.ascontiguousarray(ids, dtype=np.int32)).cuda()
+    cnt = torch.tensor([S], dtype=torch.int64, device="cuda")
+    B.ttbar_reco(dev, idx, cnt, S, p, outs, torch.zeros(1, 3, dtype=torch.int64, device="cuda"), ws)
+    return outs.host(S), (dev, idx, cnt, S, p, outs, ws)
+
+
+@pytest.mark.parametrize("name,n", [("stress2M_heavytail", 2000), ("ttbar1M_v64", 2000)])
+def test_schedules_give_identical_results(B, orc, name, n):
+    """The two schedules assign the same arithmetic to different lanes and
+    wavefronts; every output must be bit-identical."""
+    _say("schedules", name)
+    cfg = hfgen.config(name)
+    ev = hfgen.generate(cfg, n_events=n, seed=94)
+    s_w, _, _ = orc.select(ev, cfg["cuts"], list(range(len(cfg["cuts"]))))
+    ids = np.flatnonzero(s_w)
+    a, _ = _reco_direct(B, ev, ids, cfg["reco"], "mixed", "event")
+    b, _ = _reco_direct(B, ev, ids, cfg["reco"], "mixed", "worklist")
+    for k in ("has_sol", "n_sol", "best_v", "best_i", "best_j", "nu", "nubar", "m_t", "m_tbar", "m_wp", "m_wm",
+              "logw"):
+        assert np.array_equal(a[k], b[k]), k
+    assert np.array_equal(a["stats"][[0, 3, 4]], b["stats"][[0, 3, 4]])
+
+
+def test_autotune_picks_a_schedule_and_caches_it(B, tmp_path, monkeypatch):
+    _say("autotune")
+    cache = tmp_path / "hf_tune.txt"
+    monkeypatch.setenv("HF_AUTOTUNE_CACHE", str(cache))
+    cfg = hfgen.config("stress2M_heavytail")
+    ev = hfgen.generate(cfg, n_events=3000, seed=95)
+    ids = np.arange(ev["n"], dtype=np.int32)
+    ref, args = _reco_direct(B, ev, ids, cfg["reco"], "mixed", "event")
+    dev, idx, cnt, S, p, outs, ws = args
+    outs.t["has_sol"].fill_(7)
+    ms_ev, ms_wl = B.ttbar_reco_autotune(dev, idx, cnt, S, p, outs, ws)
+    _say("autotune ms", ms_ev, ms_wl, "->", p.schedule)
+    assert ms_ev > 0 and ms_wl > 0
+    assert p.schedule == (2 if ms_wl < ms_ev else 1)
+    got = outs.host(S)
+    for k in ("has_sol", "best_v", "nu", "logw"):
+        assert np.array_equal(got[k], ref[k]), k
+    line = cache.read_text().strip().splitlines()[-1].split()
+    assert int(line[1]) == p.schedule and "per_event" in line[0]
+
+
 def test_reco_all_jets_mode(B, orc):
     _full_chain_check(B, orc, "ttbar1M_v64", 1500, "mixed", reco_over={"pair_mode": "ALL_JETS", "n_var": 16},
                       seed=80)
