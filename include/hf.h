@@ -192,8 +192,7 @@ int hf_compact(const uint8_t *d_mask, int64_t capacity, const int64_t *d_n, int6
  * variations share a block, events with many are split over blocks and
  * wavefronts).  HF_SCHED_AUTO takes the choice that hf_ttbar_reco_autotune
  * stored for this configuration in the file named by HF_AUTOTUNE_CACHE, if
- * any, else the worklist when n_var is given per event and one wavefront
- * per event otherwise. */
+ * any, else one wavefront per event. */
 #define HF_SCHED_AUTO 0
 #define HF_SCHED_EVENT 1
 #define HF_SCHED_WORKLIST 2

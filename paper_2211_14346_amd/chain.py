@@ -13,7 +13,8 @@ from . import binding as B
 
 
 class Chain:
-    def __init__(self, ev, cuts, reco, precision="mixed", device="cuda", index_base=0, order=None):
+    def __init__(self, ev, cuts, reco, precision="mixed", device="cuda", index_base=0, order=None,
+                 schedule="auto"):
         self.device = device
         self.cuts = cuts
         self.n_cuts = len(cuts)
@@ -23,7 +24,7 @@ class Chain:
         self.dev = B.DeviceEvents(ev, device=device, index_base=index_base)
         n = self.dev.n
         self.n = n
-        self.params = B.reco_params(reco, precision=precision, reco_cut=self.reco_id)
+        self.params = B.reco_params(reco, precision=precision, reco_cut=self.reco_id, schedule=schedule)
         self.want_mbb = bool(reco.get("want_mbb", 0))
         if self.want_mbb:
             self.params.want_mbb = 1

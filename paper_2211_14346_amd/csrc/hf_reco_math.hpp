@@ -594,9 +594,9 @@ HF_HD __forceinline__ bool recover_y(const Conic &P, const Conic &Q, double x, d
 // mass constraint then holds to 1e-6 relative.
 constexpr double kAcceptM2 = 2e-6;
 
-// Points whose squared masses are already 1e4 times inside the acceptance
-// bound are not polished.
-constexpr double kPolishSkip = 1e-4;
+// Points whose squared masses are already 100 times inside the acceptance
+// bound (every mass within 1e-8 relative) are not polished.
+constexpr double kPolishSkip = 1e-2;
 
 // Newton's method on the two conics for (x, y), each step kept only while it
 // lowers the larger relative residual (|value| over the sum of the magnitudes

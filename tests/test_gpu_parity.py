@@ -35,9 +35,9 @@ def B():
     return binding
 
 
-def _chain(ev, cuts, reco, precision, order=None):
+def _chain(ev, cuts, reco, precision, order=None, schedule="auto"):
     from paper_2211_14346_amd.chain import Chain
-    ch = Chain(ev, cuts, reco, precision=precision, order=order)
+    ch = Chain(ev, cuts, reco, precision=precision, order=order, schedule=schedule)
     ch.step()
     return ch, ch.results()
 
@@ -204,14 +204,14 @@ def test_compact_adversarial(B, n):
 
 # ---------------------------------------------------------- reconstruction
 
-def _full_chain_check(B, orc, name, n, precision, reco_over=None, min_within=1.0, seed=None):
+def _full_chain_check(B, orc, name, n, precision, reco_over=None, min_within=1.0, seed=None, schedule="auto"):
     cfg = hfgen.config(name)
     ev = hfgen.generate(cfg, n_events=n, seed=seed)
     reco = dict(cfg["reco"])
     if reco_over:
         reco.update(reco_over)
-    _say("chain", name, n, precision, reco_over)
-    ch, got = _chain(ev, cfg["cuts"], reco, precision)
+    _say("chain", name, n, precision, reco_over, schedule)
+    ch, got = _chain(ev, cfg["cuts"], reco, precision, schedule=schedule)
     want = orc.run_chain(ev, cfg["cuts"], reco)
     _check_selection(got, want, cfg["cuts"])
     st = compare(got["reco"], want["reco"])
@@ -241,18 +241,18 @@ def test_reco_tth_v256_mbb(B, orc, precision):
     assert st.get("max_rel_m_bb", 0.0) <= 1e-9
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_reco_heavy_tailed_variations(B, orc, precision):
-    _full_chain_check(B, orc, "stress2M_heavytail", 1500, precision, seed=79)
+@pytest.mark.parametrize("precision,schedule", [("fp64", "event"), ("mixed", "event"), ("mixed", "worklist")])
+def test_reco_heavy_tailed_variations(B, orc, precision, schedule):
+    _full_chain_check(B, orc, "stress2M_heavytail", 1500, precision, seed=79, schedule=schedule)
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_reco_worklist_packs_and_splits(B, orc, precision):
+@pytest.mark.parametrize("precision,schedule", [("fp64", "worklist"), ("mixed", "worklist"), ("mixed", "event")])
+def test_reco_worklist_packs_and_splits(B, orc, precision, schedule):
     """Variation counts chosen to exercise the worklist: several small events
     packed into one 64-lane block, events split over many blocks, blocks
     split over wavefronts (few events, far more blocks than for one per
     event), counts of exactly 16, 64 and one more."""
-    _say("worklist pack/split", precision)
+    _say("worklist pack/split", precision, schedule)
     cfg = hfgen.config("ttbar1M_v64")
     ev = hfgen.generate(cfg, n_events=400, seed=93)
     rng = np.random.default_rng(93)
@@ -260,11 +260,11 @@ def test_reco_worklist_packs_and_splits(B, orc, precision):
     nv = np.concatenate([fixed, rng.integers(1, 40, ev["n"] - len(fixed))]).astype(np.uint16)
     ev["n_var"] = nv
     reco = dict(cfg["reco"])
-    ch, got = _chain(ev, cfg["cuts"], reco, precision)
+    ch, got = _chain(ev, cfg["cuts"], reco, precision, schedule=schedule)
     want = orc.run_chain(ev, cfg["cuts"], reco)
     _check_selection(got, want, cfg["cuts"])
     st = compare(got["reco"], want["reco"])
-    _say(st)
+    _say(schedule, st)
     assert_agree(st, min_agree=0.99 if precision == "mixed" else 0.999)
     stats = got["reco"]["stats"]
     assert stats[0] == got["count"] and stats[4] == got["reco"]["n_sol"].sum()
