@@ -124,7 +124,7 @@ def main():
     kernel_ms = float(np.mean(kms))
     flops = FLOP_PER_VARIATION * per[1] + FLOP_PER_PAIRING * per[2] + FLOP_PER_INTERVAL * per[3]
     achieved = flops / (kernel_ms * 1e-3) / 1e12
-    kname = "k_search<float>" if args.precision == "mixed" else "k_search<double>"
+    kname = "k_search_ev<float>" if args.precision == "mixed" else "k_search_ev<double>"
     roofline = {"bound": "alu", "kernel": kname,
                 "achieved": round(achieved, 3), "peak": PEAK_ALU_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_ALU_TFLOPS, 4), "traffic": measured_traffic(kname),

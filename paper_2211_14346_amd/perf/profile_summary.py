@@ -21,7 +21,7 @@ import collections
 import csv
 import os
 
-SEARCH = "k_search<float>"
+SEARCH = "k_search_ev<float>"
 TRACE_CMD = ("rocprofv3 --kernel-trace --stats -d <dir> -o run --output-format csv -- "
              "python3 bench.py --profile-only --steps 5 --warmup 1")
 PMC_CMD = ("rocprofv3 --pmc <counters> -d <dir> -o run --output-format csv -- "
