@@ -58,6 +58,13 @@ def chain_tth8():
     ]
 
 
+# Single-neutrino reconstruction (section 6.2): chi^2 of the top and W
+# masses with the widths the paper uses.
+SEMILEP_DEFAULTS = {
+    "m_t": 172.5, "m_w": 80.4, "sigma_t": 11.5, "sigma_w": 7.5,
+    "lep_pt_min": 20.0, "lep_eta_max": 2.5, "jet_pt_min": 25.0, "jet_eta_max": 2.5, "max_cands": 12,
+}
+
 RECO_DEFAULTS = {
     "m_t": 172.5, "m_w": 80.4, "lambda_pt": 100.0,
     "jet_a": 1.0, "jet_c": 0.05, "lep_sigma": 0.02, "met_sigma": 10.0,
@@ -89,6 +96,12 @@ CONFIGS = {
         "reco": {"smear": 1, "n_var": 256, "want_mbb": 1},
         "desc": "4M ttH-like events, 4-10 jets, >=3 b-tags, 256 variations, 8 cuts",
     },
+    "tchan1M": {
+        "index": 5, "n_events": 1_000_000, "kind": "tchan", "n_extra_max": 4,
+        "bkg_frac": 0.3, "bkg_jet_max": 6, "chain": "semilep",
+        "reco": {"smear": 0, "n_var": 1},
+        "desc": "1M single-top t-channel-like events (one lepton), 2-6 jets, 30% W+jets-like background",
+    },
     "stress2M_heavytail": {
         "index": 3, "n_events": 2_000_000, "kind": "ttbar", "n_extra_max": 10,
         "bkg_frac": 0.2, "bkg_jet_max": 12, "chain": "dilepton",
@@ -99,6 +112,17 @@ CONFIGS = {
 }
 
 
+def chain_semilep():
+    """Single-lepton chain plus the single-neutrino reconstruction."""
+    return [
+        _cut("LEP1", "LEP_N_OS", [20.0, 2.5], [1, 0]),
+        _cut("JETS2", "JET_N_MIN", [25.0, 2.5], [2]),
+        _cut("BTAG1", "BTAG_N_MIN", [25.0, 2.5, 0.5], [1]),
+        _cut("MET30", "MET_MIN", [30.0]),
+        _cut("RECO", "RECO", deps=["LEP1", "JETS2", "BTAG1", "MET30"]),
+    ]
+
+
 def config(name):
     c = copy.deepcopy(CONFIGS[name])
     c["name"] = name
@@ -107,7 +131,8 @@ def config(name):
     reco.update(c["reco"])
     reco["seed"] = c["seed"]
     c["reco"] = reco
-    c["cuts"] = {"dilepton": chain_dilepton, "tth8": chain_tth8}[c["chain"]]()
+    c["semilep"] = dict(SEMILEP_DEFAULTS)
+    c["cuts"] = {"dilepton": chain_dilepton, "tth8": chain_tth8, "semilep": chain_semilep}[c["chain"]]()
     return c
 
 

@@ -21,7 +21,15 @@ Recipe (all energies in GeV):
     the four true b jets are tagged at 0.70 and re-drawn until at least three
     are tagged; 0..n_extra_max extra jets;
   * per-event variation counts for the heavy-tailed stress sample:
-    V = clamp(floor(2^(10u)), 1, 1024) with u ~ U(0, 1).
+    V = clamp(floor(2^(10u)), 1, 1024) with u ~ U(0, 1);
+  * one-lepton samples (for the single-neutrino reconstruction): t or tbar
+    (equal odds) with the top recipe above, t -> b W, W -> l nu, MET = the
+    neutrino's pT, plus: one light jet pT ~ Exp(50), eta ~ U(-4, 4)
+    (t-channel-like); or a W (pT ~ Exp(100), |y| < 2.5) decaying to two
+    massless quarks (Wt-like); or a second top decaying hadronically
+    (semileptonic ttbar); b jets tagged at 0.70, other jets at 0.01, extra
+    jets as above; background (W+jets-like): 0..2 leptons pT ~ Exp(40), jets
+    as above tagged at 0.10, MET x, y ~ N(0, 30^2).
 Objects are sorted by descending pT within each event.
 
 This module holds no arithmetic of the method under test (selection,
@@ -237,6 +245,115 @@ def _chunk(rng, cfg, n):
     return ev64, loff, joff, nvar, truth
 
 
+def _chunk_single(rng, cfg, n):
+    """One-lepton samples.  Every kind has t -> b W+, W+ -> l+ nu (or the
+    charge conjugate, equal odds); the other truth jets are
+      tchan:  one light jet, pT ~ Exp(50), eta ~ U(-4, 4);
+      wt:     the two quarks of a W (pT ~ Exp(100), |y| < 2.5) decaying
+              isotropically to massless quarks;
+      ttsemi: the b and the two quarks of a hadronically decaying top drawn
+              with the top recipe.
+    Background: 0..2 random leptons, random jets, Gaussian MET."""
+    kind = cfg["kind"]
+    kx = cfg["n_extra_max"]
+    is_sig = rng.uniform(0.0, 1.0, n) >= cfg.get("bkg_frac", 0.0)
+    top, b, lep, nu = _top_decay(rng, n)
+    q = np.where(rng.uniform(0.0, 1.0, n) < 0.5, 1.0, -1.0)
+    truth = {"top": top, "b": b, "lep": lep, "nu": nu}
+    if kind == "tchan":
+        pt, eta, phi, e = _random_objects(rng, n, (n,), 50.0, -4.0, 4.0)
+        light = np.stack([e, pt * np.cos(phi), pt * np.sin(phi), pt * np.sinh(eta)], axis=-1)
+        others = [light]
+    elif kind == "wt":
+        w = _p4_pt_y_phi_m(rng.exponential(100.0, n), rng.uniform(-2.5, 2.5, n), rng.uniform(-np.pi, np.pi, n),
+                           M_W)
+        q1, q2 = _two_body(rng, w, M_W, 0.0, 0.0)
+        truth["q1"], truth["q2"] = q1, q2
+        others = [q1, q2]
+    elif kind == "ttsemi":
+        top2 = _p4_pt_y_phi_m(rng.exponential(100.0, n), rng.uniform(-2.5, 2.5, n),
+                              rng.uniform(-np.pi, np.pi, n), M_TOP)
+        bh, w2 = _two_body(rng, top2, M_TOP, M_B, M_W)
+        q1, q2 = _two_body(rng, w2, M_W, 0.0, 0.0)
+        truth["bh"], truth["q1"], truth["q2"] = bh, q1, q2
+        others = [bh, q1, q2]
+    else:
+        raise ValueError(f"unknown one-lepton kind {kind!r}")
+    nt = 1 + len(others)
+    nl_max = 2
+    lpt = np.zeros((n, nl_max)); leta = np.zeros((n, nl_max)); lphi = np.zeros((n, nl_max))
+    le = np.zeros((n, nl_max)); lq = np.zeros((n, nl_max)); lorig = np.full((n, nl_max), -1)
+    lval = np.zeros((n, nl_max), dtype=bool)
+    pt, eta, phi, e = _polar(lep)
+    lpt[:, 0], leta[:, 0], lphi[:, 0], le[:, 0], lq[:, 0] = pt, eta, phi, e, q
+    lorig[:, 0] = 0
+    lval[:, 0] = True
+    bk = ~is_sig
+    nbk = int(bk.sum())
+    if nbk:
+        cnt = rng.integers(0, nl_max + 1, nbk)
+        pt, eta, phi, e = _random_objects(rng, nbk, (nbk, nl_max), 40.0, -2.5, 2.5)
+        lpt[bk], leta[bk], lphi[bk], le[bk] = pt, eta, phi, e
+        lq[bk] = np.where(rng.uniform(0, 1, (nbk, nl_max)) < 0.5, -1.0, 1.0)
+        lorig[bk] = -1
+        lval[bk] = np.arange(nl_max)[None, :] < cnt[:, None]
+    nj_max = max(nt + kx, cfg.get("bkg_jet_max", 0))
+    jpt = np.zeros((n, nj_max)); jeta = np.zeros((n, nj_max)); jphi = np.zeros((n, nj_max))
+    je = np.zeros((n, nj_max)); jtag = np.zeros((n, nj_max)); jorig = np.full((n, nj_max), -1)
+    jval = np.zeros((n, nj_max), dtype=bool)
+    for c, p4 in enumerate([b] + others):
+        pt, eta, phi, e = _polar(p4)
+        jpt[:, c], jeta[:, c], jphi[:, c], je[:, c] = pt, eta, phi, e
+        is_b = c == 0 or (kind == "ttsemi" and c == 1)
+        jtag[:, c] = rng.uniform(0, 1, n) < (0.70 if is_b else 0.01)
+        jorig[:, c] = c
+        jval[:, c] = True
+    nextra = rng.integers(0, kx + 1, n)
+    pt, eta, phi, e = _random_objects(rng, n, (n, kx), 40.0, -3.5, 3.5)
+    jpt[:, nt:nt + kx], jeta[:, nt:nt + kx], jphi[:, nt:nt + kx], je[:, nt:nt + kx] = pt, eta, phi, e
+    jtag[:, nt:nt + kx] = rng.uniform(0, 1, (n, kx)) < 0.01
+    jval[:, nt:nt + kx] = np.arange(kx)[None, :] < nextra[:, None]
+    if nbk:
+        jm = cfg["bkg_jet_max"]
+        cnt = rng.integers(2, jm + 1, nbk)
+        pt, eta, phi, e = _random_objects(rng, nbk, (nbk, nj_max), 40.0, -3.5, 3.5)
+        jpt[bk], jeta[bk], jphi[bk], je[bk] = pt, eta, phi, e
+        jtag[bk] = rng.uniform(0, 1, (nbk, nj_max)) < 0.10
+        jorig[bk] = -1
+        jval[bk] = np.arange(nj_max)[None, :] < cnt[:, None]
+    metx = nu[:, 1].copy()
+    mety = nu[:, 2].copy()
+    if nbk:
+        metx[bk] = rng.normal(0.0, 30.0, nbk)
+        mety[bk] = rng.normal(0.0, 30.0, nbk)
+    lp_, loff, _, _ = _pack({"pt": lpt, "eta": leta, "phi": lphi, "e": le, "q": lq, "orig": lorig}, lval)
+    jt_, joff, _, _ = _pack({"pt": jpt, "eta": jeta, "phi": jphi, "e": je, "btag": jtag, "orig": jorig}, jval)
+
+    def _pos(orig_sorted_flat, off, code):
+        out = np.full(n, -1, dtype=np.int32)
+        ev = np.repeat(np.arange(n), np.diff(off))
+        local = np.arange(orig_sorted_flat.size) - off[ev]
+        hit = orig_sorted_flat == code
+        out[ev[hit]] = local[hit]
+        return out
+
+    truth["is_signal"] = is_sig
+    truth["lep_idx"] = _pos(lp_["orig"], loff, 0)
+    names = ["b_idx"] + {"tchan": ["light_idx"], "wt": ["q1_idx", "q2_idx"],
+                         "ttsemi": ["bh_idx", "q1_idx", "q2_idx"]}[kind]
+    for c, k in enumerate(names):
+        truth[k] = _pos(jt_["orig"], joff, c)
+    for k in list(truth):
+        if truth[k].dtype == np.float64 and truth[k].ndim == 2:
+            truth[k][~is_sig] = np.nan
+    ev64 = {
+        "lep_pt": lp_["pt"], "lep_eta": lp_["eta"], "lep_phi": lp_["phi"], "lep_e": lp_["e"],
+        "lep_q": lp_["q"], "jet_pt": jt_["pt"], "jet_eta": jt_["eta"], "jet_phi": jt_["phi"],
+        "jet_e": jt_["e"], "jet_btag": jt_["btag"], "met_x": metx, "met_y": mety,
+    }
+    return ev64, loff, joff, None, truth
+
+
 def _concat(parts):
     ev = {k: np.concatenate([p[0][k] for p in parts]) for k in parts[0][0]}
     offs = []
@@ -271,7 +388,8 @@ def generate(cfg, n_events=None, seed=None, keep_fp64=False):
     parts = []
     for c in range(nchunks):
         m = min(CHUNK, n - c * CHUNK)
-        parts.append(_chunk(np.random.Generator(np.random.PCG64(children[c])), cfg, m))
+        gen = _chunk_single if cfg["kind"] in ("tchan", "wt", "ttsemi") else _chunk
+        parts.append(gen(np.random.Generator(np.random.PCG64(children[c])), cfg, m))
     ev64, loff, joff, nvar, truth = parts[0] if len(parts) == 1 else _concat(parts)
     if loff[-1] >= 2 ** 32 or joff[-1] >= 2 ** 32:
         raise ValueError("sample too large for 32-bit object offsets")

@@ -62,6 +62,20 @@ class RecoOut(C.Structure):
                                           "nubar", "m_t", "m_tbar", "m_wp", "m_wm", "logw", "m_bb")]
 
 
+TOPOLOGY = {"TCHAN": 0, "WT": 1, "TTSEMI": 2}
+
+
+class SemilepParams(C.Structure):
+    _fields_ = [(k, C.c_double) for k in ("m_t", "m_w", "sigma_t", "sigma_w", "lep_pt_min", "lep_eta_max",
+                                          "jet_pt_min", "jet_eta_max")] + \
+               [("topology", C.c_int32), ("max_cands", C.c_int32)]
+
+
+class SemilepOut(C.Structure):
+    _fields_ = [(k, C.c_void_p) for k in ("has_sol", "root", "best_j", "best_h", "best_p", "best_q", "nu",
+                                          "m_tl", "m_wl", "m_th", "m_wh", "chi2")]
+
+
 _lib = None
 
 
@@ -85,6 +99,10 @@ def lib():
         L.orc_ttbar_reco.argtypes = [C.POINTER(Events), P, C.c_int64, C.POINTER(RecoParams),
                                      C.POINTER(RecoOut), C.c_int]
         L.orc_ttbar_reco.restype = C.c_int64
+        L.orc_nu_pz.argtypes = [P, C.c_double, C.c_double, C.c_double, P, P]
+        L.orc_semilep_reco.argtypes = [C.POINTER(Events), P, C.c_int64, C.POINTER(SemilepParams),
+                                       C.POINTER(SemilepOut), C.c_int]
+        L.orc_semilep_reco.restype = C.c_int64
         _lib = L
     return _lib
 
@@ -225,6 +243,41 @@ def ttbar_reco(ev, idx, reco, index_base=0, n_threads=0, fp64=False):
     ro = RecoOut(**{k: _ptr(v) for k, v in o.items()})
     prm = reco_params(reco)
     npass = lib().orc_ttbar_reco(C.byref(h.s), _ptr(idx), S, C.byref(prm), C.byref(ro), int(n_threads))
+    res = {k: v[:S].copy() for k, v in o.items()}
+    res["n_pass"] = int(npass)
+    return res
+
+
+def nu_pz(lep, metx, mety, mw=80.4):
+    """Neutrino p_z candidates from the W mass; lep = (E, px, py, pz).
+    Returns (pz array, kind array): kind 0/1 minus/plus root, 2 real part."""
+    pz = np.zeros(2)
+    kind = np.zeros(2, dtype=np.int32)
+    n = lib().orc_nu_pz(_ptr(_v4(lep)), float(metx), float(mety), float(mw), _ptr(pz), _ptr(kind))
+    return pz[:n].copy(), kind[:n].copy()
+
+
+def semilep_params(sl, topology="TCHAN"):
+    return SemilepParams(
+        m_t=sl["m_t"], m_w=sl["m_w"], sigma_t=sl["sigma_t"], sigma_w=sl["sigma_w"],
+        lep_pt_min=float(np.float32(sl["lep_pt_min"])), lep_eta_max=float(np.float32(sl["lep_eta_max"])),
+        jet_pt_min=float(np.float32(sl["jet_pt_min"])), jet_eta_max=float(np.float32(sl["jet_eta_max"])),
+        topology=TOPOLOGY[topology], max_cands=int(sl["max_cands"]))
+
+
+def semilep_reco(ev, idx, sl, topology="TCHAN", index_base=0, n_threads=0, fp64=False):
+    """Single-neutrino chi^2 reconstruction of events idx (global ids)."""
+    h = _EventsHolder(ev, index_base, fp64=fp64)
+    idx = np.ascontiguousarray(idx, dtype=np.int32)
+    S = idx.size
+    m = max(S, 1)
+    o = {"has_sol": np.zeros(m, np.uint8), "root": np.zeros(m, np.int8), "best_j": np.zeros(m, np.int16),
+         "best_h": np.zeros(m, np.int16), "best_p": np.zeros(m, np.int16), "best_q": np.zeros(m, np.int16),
+         "nu": np.zeros((m, 3)), "m_tl": np.zeros(m), "m_wl": np.zeros(m), "m_th": np.zeros(m),
+         "m_wh": np.zeros(m), "chi2": np.zeros(m)}
+    so = SemilepOut(**{k: _ptr(v) for k, v in o.items()})
+    prm = semilep_params(sl, topology)
+    npass = lib().orc_semilep_reco(C.byref(h.s), _ptr(idx), S, C.byref(prm), C.byref(so), int(n_threads))
     res = {k: v[:S].copy() for k, v in o.items()}
     res["n_pass"] = int(npass)
     return res

@@ -1,6 +1,7 @@
 /*
  * hf_oracle.c -- plain FP64 CPU oracle for the cut chain, survivor
- * compaction, adaptive cut ordering and dileptonic ttbar reconstruction.
+ * compaction, adaptive cut ordering, dileptonic ttbar reconstruction and
+ * the single-neutrino chi^2 reconstruction.
  *
  * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
  * benchmark's CPU-baseline leg may load this library.  It shares no code,
@@ -19,6 +20,10 @@
  *     the most probable solution (section 4);
  *   - pseudo-experiments: energies and momenta varied within a resolution,
  *     keeping the most probable solution (section 4, ttH_sci);
+ *   - one-lepton final states: E_T^miss as the neutrino's transverse
+ *     momentum, its p_z from the W mass, and the jet assignment that
+ *     minimises the chi^2 of Eq. (chi2) with the section 6.2 masses and
+ *     widths;
  *   - eta = -ln tan(theta/2) and Delta R = sqrt(Delta eta^2 + Delta phi^2)
  *     (section 6.1 footnote); E_T^miss > 30 GeV, M_ll > 40 GeV, eta regions
  *     (section 6.1); unset variables default to -9999 (section 6.1 example).
@@ -919,6 +924,181 @@ int64_t orc_ttbar_reco(const orc_events *ev, const int32_t *idx, int64_t S, cons
             }
             out->m_bb[s] = mbb;
         }
+    }
+    return npass;
+}
+
+/* ----------------------------------------- single-neutrino reconstruction
+ * Section 6.2, Eq. (chi2).  One-lepton final states: the missing transverse
+ * momentum is the neutrino's transverse momentum and only the neutrino's
+ * p_z is unknown; it follows from the W mass.  Among every assignment of the
+ * selected jets to the expected top quarks and W bosons, the one with the
+ * smallest
+ *   chi^2 = sum_k (m_top_k - m_t)^2 / sigma_t^2 + sum_m (m_W_m - m_W)^2 / sigma_W^2
+ * is kept.  Topologies (the k and m counts of Eq. (chi2)):
+ *   TCHAN  (t-channel single top): one top (j l nu), one W (l nu);
+ *   WT     (Wt, semileptonic):     one top (j l nu), two W: (l nu) and the
+ *                                  two-jet W (p q) (reading: the hadronic W's
+ *                                  mass is that of two further jets);
+ *   TTSEMI (semileptonic ttbar):   two tops (j l nu) and (h p q), two W:
+ *                                  (l nu) and (p q).
+ * Jets j, h, p, q are distinct; p < q.                                     */
+
+enum { ORC_TOPO_TCHAN = 0, ORC_TOPO_WT = 1, ORC_TOPO_TTSEMI = 2 };
+
+typedef struct {
+    double m_t, m_w, sigma_t, sigma_w;
+    double lep_pt_min, lep_eta_max, jet_pt_min, jet_eta_max;
+    int32_t topology, max_cands;
+} orc_semilep_params;
+
+typedef struct {
+    uint8_t *has_sol;
+    int8_t *root;                       /* 0: minus sign, 1: plus sign, 2: real part */
+    int16_t *best_j, *best_h, *best_p, *best_q;
+    double *nu;                         /* [S][3] */
+    double *m_tl, *m_wl, *m_th, *m_wh, *chi2;
+} orc_semilep_out;
+
+/* Neutrino p_z from (l + nu)^2 = m_W^2 with nu = (|nu|, metx, mety, p_z)
+ * massless.  Writing mu = (m_W^2 - m_l^2)/2 + px_l metx + py_l mety, the
+ * constraint reads E_l sqrt(pT^2 + p_z^2) = mu + pz_l p_z; squared it is the
+ * quadratic  a p_z^2 - 2 mu pz_l p_z + (E_l^2 pT^2 - mu^2) = 0  with
+ * a = E_l^2 - pz_l^2, whose reduced discriminant is E_l^2 (mu^2 - a pT^2).
+ * Roots (mu pz_l -/+ E_l sqrt(mu^2 - a pT^2)) / a; with a negative
+ * discriminant the real part mu pz_l / a is the single candidate (reading).
+ * Returns the candidate count (0 if a <= 0); kind[r] is 0/1 for the
+ * minus/plus root, 2 for the real part.                                     */
+int orc_nu_pz(const double l[4], double metx, double mety, double mw, double pz[2], int kind[2])
+{
+    double El = l[0], px = l[1], py = l[2], plz = l[3];
+    double ml2 = El * El - px * px - py * py - plz * plz;
+    double a = El * El - plz * plz;
+    if (!(a > 0.0)) return 0;
+    double pt2 = metx * metx + mety * mety;
+    double mu = 0.5 * (mw * mw - ml2) + px * metx + py * mety;
+    double d = mu * mu - a * pt2;
+    if (d < 0.0) {
+        pz[0] = mu * plz / a;
+        kind[0] = 2;
+        return 1;
+    }
+    double sq = El * sqrt(d);
+    pz[0] = (mu * plz - sq) / a;
+    pz[1] = (mu * plz + sq) / a;
+    kind[0] = 0;
+    kind[1] = 1;
+    return 2;
+}
+
+static double orc_sq(double x) { return x * x; }
+
+int64_t orc_semilep_reco(const orc_events *ev, const int32_t *idx, int64_t S, const orc_semilep_params *p,
+                         const orc_semilep_out *out, int n_threads)
+{
+    int64_t npass = 0;
+#ifdef _OPENMP
+    if (n_threads > 0) omp_set_num_threads(n_threads);
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : npass)
+#endif
+    for (int64_t s = 0; s < S; ++s) {
+        int64_t e = (int64_t)idx[s] - ev->index_base;
+        uint32_t l0 = ev->lep_off[e], l1 = ev->lep_off[e + 1];
+        uint32_t j0 = ev->jet_off[e], j1 = ev->jet_off[e + 1];
+        /* the lepton: the leading selected one (reading) */
+        int64_t kl = -1;
+        for (uint32_t k = l0; k < l1; ++k)
+            if (orc_lep_sel(ev, k, p->lep_pt_min, p->lep_eta_max)) { kl = k; break; }
+        /* jets: the selected ones in pT order, at most max_cands (reading) */
+        int cap = p->max_cands < ORC_MAX_CANDS ? p->max_cands : ORC_MAX_CANDS;
+        int cand[ORC_MAX_CANDS];
+        vec4 cj[ORC_MAX_CANDS];
+        int nc = 0;
+        for (uint32_t k = j0; k < j1 && nc < cap; ++k)
+            if (orc_jet_sel(ev, k, p->jet_pt_min, p->jet_eta_max)) {
+                cand[nc] = (int)(k - j0);
+                cj[nc] = orc_from_polar(ev->jet_pt[k], ev->jet_eta[k], ev->jet_phi[k], ev->jet_e[k]);
+                ++nc;
+            }
+        int need = p->topology == ORC_TOPO_TCHAN ? 1 : p->topology == ORC_TOPO_WT ? 3 : 4;
+        double pz[2];
+        int kind[2];
+        int nr = 0;
+        vec4 lep = {0, 0, 0, 0};
+        double mx = ev->met_x[e], my = ev->met_y[e];
+        if (kl >= 0 && nc >= need) {
+            lep = orc_from_polar(ev->lep_pt[kl], ev->lep_eta[kl], ev->lep_phi[kl], ev->lep_e[kl]);
+            double l4[4] = {lep.e, lep.x, lep.y, lep.z};
+            nr = orc_nu_pz(l4, mx, my, p->m_w, pz, kind);
+        }
+        int have = 0;
+        double best = 0.0;
+        int bj = -1, bh = -1, bp = -1, bq = -1, br = -1;
+        double b_mtl = 0, b_mwl = 0, b_mth = ORC_NOSOL, b_mwh = ORC_NOSOL;
+        vec4 b_nu = {0, 0, 0, 0};
+        for (int r = 0; r < nr; ++r) {
+            vec4 nu = {sqrt(mx * mx + my * my + pz[r] * pz[r]), mx, my, pz[r]};
+            vec4 w = orc_add(lep, nu);
+            double mwl = orc_mass(w);
+            double c_w = orc_sq(mwl - p->m_w) / orc_sq(p->sigma_w);
+            for (int j = 0; j < nc; ++j) {
+                double mtl = orc_mass(orc_add(w, cj[j]));
+                double c_t = orc_sq(mtl - p->m_t) / orc_sq(p->sigma_t);
+                if (p->topology == ORC_TOPO_TCHAN) {
+                    double chi2 = c_t + c_w;
+                    if (!have || chi2 < best) {
+                        have = 1; best = chi2; bj = j; br = r; b_mtl = mtl; b_mwl = mwl; b_nu = nu;
+                    }
+                    continue;
+                }
+                /* TTSEMI: every h; WT: no hadronic top (h = -1) */
+                int nh = p->topology == ORC_TOPO_TTSEMI ? nc : 1;
+                for (int hi = 0; hi < nh; ++hi) {
+                    int h = p->topology == ORC_TOPO_TTSEMI ? hi : -1;
+                    if (h == j) continue;
+                    for (int a = 0; a < nc; ++a) {
+                        if (a == j || a == h) continue;
+                        for (int b = a + 1; b < nc; ++b) {
+                            if (b == j || b == h) continue;
+                            vec4 wh = orc_add(cj[a], cj[b]);
+                            double mwh = orc_mass(wh);
+                            double chi2 = c_t + c_w + orc_sq(mwh - p->m_w) / orc_sq(p->sigma_w);
+                            double mth = ORC_NOSOL;
+                            if (h >= 0) {
+                                mth = orc_mass(orc_add(wh, cj[h]));
+                                chi2 += orc_sq(mth - p->m_t) / orc_sq(p->sigma_t);
+                            }
+                            if (!have || chi2 < best) {
+                                have = 1; best = chi2; bj = j; bh = h; bp = a; bq = b; br = r;
+                                b_mtl = mtl; b_mwl = mwl; b_mth = mth; b_mwh = mwh; b_nu = nu;
+                            }
+                        }
+                    }
+                }
+            }
+        }
+        out->has_sol[s] = (uint8_t)have;
+        if (!have) {
+            out->root[s] = -1;
+            out->best_j[s] = out->best_h[s] = out->best_p[s] = out->best_q[s] = -1;
+            for (int k = 0; k < 3; ++k) out->nu[3 * s + k] = ORC_NOSOL;
+            out->m_tl[s] = out->m_wl[s] = out->m_th[s] = out->m_wh[s] = out->chi2[s] = ORC_NOSOL;
+            continue;
+        }
+        ++npass;
+        out->root[s] = (int8_t)kind[br];
+        out->best_j[s] = (int16_t)cand[bj];
+        out->best_h[s] = (int16_t)(bh >= 0 ? cand[bh] : -1);
+        out->best_p[s] = (int16_t)(bp >= 0 ? cand[bp] : -1);
+        out->best_q[s] = (int16_t)(bq >= 0 ? cand[bq] : -1);
+        out->nu[3 * s + 0] = b_nu.x;
+        out->nu[3 * s + 1] = b_nu.y;
+        out->nu[3 * s + 2] = b_nu.z;
+        out->m_tl[s] = b_mtl;
+        out->m_wl[s] = b_mwl;
+        out->m_th[s] = b_mth;
+        out->m_wh[s] = b_mwh;
+        out->chi2[s] = best;
     }
     return npass;
 }
