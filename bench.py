@@ -7,6 +7,10 @@ batch: hf_select -> hf_compact -> hf_ttbar_reco -> hf_compact -> the cut
 reordering from the accumulated counters (hf_reorder_device), recorded as one
 HIP graph.  Inputs are resident in HBM before timing starts.
 
+A second leg measures the single-neutrino chi^2 reconstruction the same way
+(1M one-lepton t-channel-like events, four cuts plus hf_semilep_reco, one HIP
+graph per step) and reports it under "semilep" in the same line.
+
 Prints one JSON line.  --gpus above 1 is refused: this build runs on one GPU.
 """
 
@@ -22,6 +26,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 WORKLOAD = "ttbar1M_v64"
+SEMILEP_WORKLOAD = "tchan1M"
 
 # Algorithmic FP operations of the reconstruction search kernel per unit of
 # work (one each for add, mul, div, sqrt, transcendental; two for FMA),
@@ -53,6 +58,7 @@ def _parse():
     ap.add_argument("--no-fp64-form", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=200_000)
     ap.add_argument("--profile-only", action="store_true", help="few steps, no CPU baseline (for profilers)")
+    ap.add_argument("--no-semilep", action="store_true", help="skip the single-neutrino reconstruction leg")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB a few times (to scale the "
                          "FETCH_SIZE / WRITE_SIZE counters into bytes) and exit")
@@ -155,19 +161,113 @@ def main():
     if not args.profile_only and not args.no_cpu_baseline:
         out["cpu_baseline"], acc = cpu_baseline(ev, cfg, args, torch)
         out["accuracy_vs_oracle"] = acc
+    if not args.no_semilep:
+        del ch
+        torch.cuda.empty_cache()
+        out["semilep"] = semilep_leg(args, torch)
     print(json.dumps(out))
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of the search kernel from the committed rocprofv3
+# Algorithmic HBM bytes of hf_semilep_reco per unit: per compacted event the
+# index (4), the two offsets of each object list (16), MET (8) and the outputs
+# (has_sol 1, root 1, four jet indices 8, nu 24, five masses/chi^2 40); per
+# lepton of the event pT and eta (8) and for the chosen one phi and E (8); per
+# jet pT and eta (8) and for each candidate jet phi and E (8).
+SL_BYTES_EVENT = 4 + 16 + 8 + (1 + 1 + 8 + 24 + 40)
+SL_BYTES_OBJ = 8
+SL_BYTES_PICKED = 8
+
+
+def semilep_bytes(ev, idx, sl):
+    """Algorithmic bytes of one hf_semilep_reco launch over the compacted ids."""
+    e = np.asarray(idx, dtype=np.int64)
+    lo, jo = ev["lep_off"].astype(np.int64), ev["jet_off"].astype(np.int64)
+    n_lep = int((lo[e + 1] - lo[e]).sum())
+    n_jet = int((jo[e + 1] - jo[e]).sum())
+    sel = (ev["jet_pt"] > np.float32(sl["jet_pt_min"])) & (np.abs(ev["jet_eta"]) < np.float32(sl["jet_eta_max"]))
+    csel = np.concatenate([[0], np.cumsum(sel, dtype=np.int64)])
+    n_cand = int(np.minimum(csel[jo[e + 1]] - csel[jo[e]], sl["max_cands"]).sum())
+    return e.size * (SL_BYTES_EVENT + SL_BYTES_PICKED) + (n_lep + n_jet) * SL_BYTES_OBJ + n_cand * SL_BYTES_PICKED
+
+
+def semilep_leg(args, torch):
+    """select -> compact -> hf_semilep_reco (t-channel) -> compact -> reorder,
+    one HIP graph per step over 1M one-lepton events; the reconstruction
+    kernel timed alone with HIP events on its stream; the oracle beside it."""
+    import hfgen
+    from paper_2211_14346_amd.chain import Chain
+
+    cfg = hfgen.config(SEMILEP_WORKLOAD)
+    ev = hfgen.generate(cfg)
+    n = ev["n"]
+    ch = Chain(ev, cfg["cuts"], None, semilep=cfg["semilep"], topology="TCHAN")
+    for _ in range(max(1, args.warmup)):
+        ch.step()
+    torch.cuda.synchronize()
+    ch.capture(reorder=True)
+    ch.reset_counters()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ch.replay()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    res = ch.results()
+    # the reconstruction kernel alone (one launch per call, on torch's current stream)
+    s = torch.cuda.current_stream()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(max(3, min(10, args.steps)))]
+    for a, b in evs:
+        a.record(s)
+        ch.run_reco()
+        b.record(s)
+    torch.cuda.synchronize()
+    kernel_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    nbytes = semilep_bytes(ev, res["idx"], cfg["semilep"])
+    gbs = nbytes / (kernel_ms * 1e-3) / 1e9
+    leg = {"metric": "events/s through cut chain + single-neutrino chi^2 reco (t-channel)",
+           "value": round(n * args.steps / dt, 1), "unit": "events/s",
+           "ms_per_step": round(1e3 * dt / args.steps, 4), "dtype": "f64",
+           "config": {"workload": SEMILEP_WORKLOAD, "events": n, "topology": "TCHAN",
+                      "cuts": [c["name"] for c in cfg["cuts"]], "survivors": int(res["count"]),
+                      "reconstructed": int(len(res["final"]))},
+           "roofline": {"bound": "hbm", "kernel": "k_semilep_tchan", "achieved": round(gbs, 1),
+                        "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4),
+                        "traffic": measured_traffic("k_semilep_tchan", "semilep"), "kernel_ms": round(kernel_ms, 4),
+                        "bytes_per_launch": int(nbytes)}}
+    print(f"[bench] semilep: {leg['ms_per_step']} ms/step, kernel {kernel_ms:.4f} ms, {gbs:.0f} GB/s",
+          file=sys.stderr, flush=True)
+    if not args.profile_only and not args.no_cpu_baseline:
+        import oracle
+        from tests.gpu_compare import compare_semilep
+        threads = min(os.cpu_count() or 1, 16)
+        oracle.lib()
+        t0 = time.perf_counter()
+        surv, _, _ = oracle.select(ev, cfg["cuts"], list(range(len(cfg["cuts"]))))
+        idx = oracle.compact(surv)
+        rec = oracle.semilep_reco(ev, idx, cfg["semilep"], "TCHAN", n_threads=threads)
+        oracle.compact(rec["has_sol"], 0, idx)
+        dtc = time.perf_counter() - t0
+        leg["cpu_baseline"] = {"value": round(n / dtc, 1), "unit": "events/s", "cores": threads, "kind": "oracle",
+                               "sample": f"all {n} events of the {SEMILEP_WORKLOAD} batch, "
+                                         f"select+compact+reco+compact, {dtc:.1f} s wall on {threads} threads"}
+        st = compare_semilep(res["reco"], rec)
+        leg["accuracy_vs_oracle"] = {k: (round(v, 12) if isinstance(v, float) else v) for k, v in st.items()}
+    return leg
+
+
+def measured_traffic(kernel, kind="search"):
+    """HBM bytes per launch of a profiled kernel (the search kernel, or the
+    single-neutrino kernel with kind="semilep") from the committed rocprofv3
     counter summary (FETCH_SIZE + WRITE_SIZE scaled by a device-copy
     calibration), or None when the summary is for another kernel or for
     different kernel sources than the ones built here."""
-    from paper_2211_14346_amd.perf import built_source_hash, search_source_hash
-    built = built_source_hash()
-    if built is None or built != search_source_hash():
+    from paper_2211_14346_amd.perf import built_source_hash, source_hash
+    built = built_source_hash(kind)
+    if built is None or built != source_hash(kind):
         return None  # library and sources differ: the counters cannot be attributed
-    path = os.path.join(ROOT, "profiles", "k_search_ttbar1M_v64_counters.txt")
+    name = {"search": "k_search_ttbar1M_v64_counters.txt", "semilep": "k_semilep_tchan1M.txt"}[kind]
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     kv = {}
@@ -175,9 +275,9 @@ def measured_traffic(kernel):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
-    if kv.get("search_kernel") != kernel or kv.get("search_source_hash") != built:
+    if kv.get(f"{kind}_kernel") != kernel or kv.get(f"{kind}_source_hash") != built:
         return None
-    return int(kv["search_traffic_bytes_per_launch"])
+    return int(kv[f"{kind}_traffic_bytes_per_launch"])
 
 
 def cfg_metric():

@@ -268,6 +268,63 @@ int hf_ttbar_reco_autotune(const hf_events_t *ev, const int32_t *d_idx, const in
  * Errors: HF_ERR_INVAL if exactly one of the two is NULL. */
 int hf_reco_timing_events(hipEvent_t start, hipEvent_t stop);
 
+/* ------------------------------------- single-neutrino reconstruction */
+
+#define HF_TOPO_TCHAN 0  /* t-channel single top: one top (j l nu), one W (l nu) */
+#define HF_TOPO_WT 1     /* Wt, semileptonic: one top (j l nu), W (l nu) and W (p q) */
+#define HF_TOPO_TTSEMI 2 /* semileptonic ttbar: tops (j l nu) and (h p q), W (l nu) and W (p q) */
+
+/* Parameters of the chi^2 reconstruction (section 6.2, Eq. (chi2)): m_t and
+ * m_w are the central masses (172.5 and 80.4 GeV in the paper), sigma_t and
+ * sigma_w the widths (11.5 and 7.5 GeV).  The lepton is the leading one with
+ * pT > lep_pt_min and |eta| < lep_eta_max; the candidate jets are the jets
+ * with pT > jet_pt_min and |eta| < jet_eta_max, in input (pT) order, at most
+ * max_cands (1..HF_MAX_CANDS).  reco_cut is the id of the RECO cut whose
+ * counters the call updates (-1: none); reserved must be 0. */
+typedef struct hf_semilep_params {
+    double m_t, m_w, sigma_t, sigma_w;
+    float lep_pt_min, lep_eta_max, jet_pt_min, jet_eta_max;
+    int32_t topology, max_cands, reco_cut, reserved;
+} hf_semilep_params_t;
+
+/* Outputs, structure of arrays over the compacted positions [0, capacity);
+ * positions >= *d_count are left untouched.  root: 0 (minus sign) or 1 (plus
+ * sign) root of the neutrino p_z quadratic, 2 when its discriminant is
+ * negative and the real part was taken.  best_j: the jet of the leptonic top;
+ * best_h: the b jet of the hadronic top (semileptonic ttbar); best_p < best_q:
+ * the jets of the two-jet W (Wt, semileptonic ttbar); -1 where the topology
+ * has no such jet.  Jet indices are within the event.  nu: (px, py, pz) of the
+ * neutrino ([capacity][3]).  m_tl, m_wl: leptonic top and W masses; m_th,
+ * m_wh: hadronic top and W masses (HF_NO_SOLUTION where absent); chi2: the
+ * minimum.  Positions without a solution (no selected lepton, fewer jets than
+ * the topology needs, an id outside the chunk) get has_sol = 0, -1 indices
+ * and HF_NO_SOLUTION in every float output. */
+typedef struct hf_semilep_out {
+    uint8_t *has_sol;
+    int8_t *root;
+    int16_t *best_j, *best_h, *best_p, *best_q;
+    double *nu;
+    double *m_tl, *m_wl, *m_th, *m_wh, *chi2;
+} hf_semilep_out_t;
+
+/* Single-neutrino kinematic reconstruction of the compacted events
+ * (section 6.2): for each event d_idx[k] (global id, k < *d_count <=
+ * capacity), the missing transverse momentum is the neutrino's transverse
+ * momentum and its p_z solves (l + nu)^2 = m_W^2 for a massless neutrino:
+ *   p_z = (mu pz_l -/+ E_l sqrt(mu^2 - a pT^2)) / a,
+ *   mu = (m_W^2 - m_l^2)/2 + px_l px + py_l py,  a = E_l^2 - pz_l^2,
+ * or mu pz_l / a when the discriminant is negative.  Every assignment of
+ * distinct candidate jets to the topology's tops and W bosons, with every p_z
+ * candidate, is scored by Eq. (chi2) and the smallest chi^2 is kept (ties:
+ * the first in the order root, j, h, p, q).  Every step runs in FP64 on the
+ * device.  Updates d_counters[reco_cut] (reached += count, passed += events
+ * with a solution).  Allocates nothing; no workspace.  Errors: HF_ERR_INVAL
+ * for null pointers, an unknown topology, max_cands outside
+ * [1, HF_MAX_CANDS], non-positive widths or masses with m_t <= m_w. */
+int hf_semilep_reco(const hf_events_t *ev, const int32_t *d_idx, const int64_t *d_count, int64_t capacity,
+                    const hf_semilep_params_t *h_params, const hf_semilep_out_t *out, hf_counters_t *d_counters,
+                    hipStream_t stream);
+
 /* -------------------------------------------------------- random draws */
 
 /* The variation draws the reconstruction uses (paper section 5.3 draws its

@@ -55,7 +55,22 @@ class RecoOut(C.Structure):
                                           "m_tbar", "m_wp", "m_wm", "logw", "m_bb", "stats")]
 
 
+TOPO = {"TCHAN": 0, "WT": 1, "TTSEMI": 2}
+
+
+class SemilepParams(C.Structure):
+    _fields_ = [(k, C.c_double) for k in ("m_t", "m_w", "sigma_t", "sigma_w")] + \
+               [(k, C.c_float) for k in ("lep_pt_min", "lep_eta_max", "jet_pt_min", "jet_eta_max")] + \
+               [(k, C.c_int32) for k in ("topology", "max_cands", "reco_cut", "reserved")]
+
+
+class SemilepOut(C.Structure):
+    _fields_ = [(k, C.c_void_p) for k in ("has_sol", "root", "best_j", "best_h", "best_p", "best_q", "nu", "m_tl",
+                                          "m_wl", "m_th", "m_wh", "chi2")]
+
+
 assert C.sizeof(Cut) == 64 and C.sizeof(RecoParams) == 120 and C.sizeof(Counters) == 24
+assert C.sizeof(SemilepParams) == 64
 
 _lib = None
 
@@ -87,8 +102,10 @@ def lib():
         L.hf_reco_timing_events.restype = C.c_int
         L.hf_philox_blocks.argtypes = [P, C.c_uint64, P, C.c_int64, P]
         L.hf_gauss_draws.argtypes = [C.c_uint64, P, P, P, C.c_int64, C.c_int, P, P]
+        L.hf_semilep_reco.argtypes = [C.POINTER(Events), P, P, C.c_int64, C.POINTER(SemilepParams),
+                                      C.POINTER(SemilepOut), P, P]
         for f in ("hf_select", "hf_compact", "hf_ttbar_reco", "hf_ttbar_reco_autotune", "hf_reorder_stats",
-                  "hf_reorder_device", "hf_philox_blocks", "hf_gauss_draws"):
+                  "hf_reorder_device", "hf_philox_blocks", "hf_gauss_draws", "hf_semilep_reco"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -209,6 +226,40 @@ def ttbar_reco(dev, idx, count, capacity, params, outs, counters, ws, stream=Non
     rc = lib().hf_ttbar_reco(dev.ptr, _p(idx), _p(count), int(capacity), C.byref(params), C.byref(outs.s),
                              _p(counters), _p(ws), ws.numel() * ws.element_size(), _stream(stream))
     _check(rc, "hf_ttbar_reco")
+
+
+def semilep_params(sl, topology="TCHAN", reco_cut=-1):
+    return SemilepParams(m_t=sl["m_t"], m_w=sl["m_w"], sigma_t=sl["sigma_t"], sigma_w=sl["sigma_w"],
+                         lep_pt_min=sl["lep_pt_min"], lep_eta_max=sl["lep_eta_max"], jet_pt_min=sl["jet_pt_min"],
+                         jet_eta_max=sl["jet_eta_max"], topology=TOPO[topology], max_cands=int(sl["max_cands"]),
+                         reco_cut=int(reco_cut), reserved=0)
+
+
+class SemilepOutputs:
+    """Device output arrays of hf_semilep_reco for `capacity` positions."""
+
+    def __init__(self, capacity, device="cuda"):
+        cap = max(1, int(capacity))
+        f64 = dict(dtype=torch.float64, device=device)
+        i16 = dict(dtype=torch.int16, device=device)
+        self.t = {
+            "has_sol": torch.zeros(cap, dtype=torch.uint8, device=device),
+            "root": torch.zeros(cap, dtype=torch.int8, device=device),
+            "best_j": torch.zeros(cap, **i16), "best_h": torch.zeros(cap, **i16),
+            "best_p": torch.zeros(cap, **i16), "best_q": torch.zeros(cap, **i16),
+            "nu": torch.zeros(cap, 3, **f64), "m_tl": torch.zeros(cap, **f64), "m_wl": torch.zeros(cap, **f64),
+            "m_th": torch.zeros(cap, **f64), "m_wh": torch.zeros(cap, **f64), "chi2": torch.zeros(cap, **f64),
+        }
+        self.s = SemilepOut(**{k: v.data_ptr() for k, v in self.t.items()})
+
+    def host(self, n):
+        return {k: v[:n].cpu().numpy() for k, v in self.t.items()}
+
+
+def semilep_reco(dev, idx, count, capacity, params, outs, counters=None, stream=None):
+    rc = lib().hf_semilep_reco(dev.ptr, _p(idx), _p(count), int(capacity), C.byref(params), C.byref(outs.s),
+                               _p(counters), _stream(stream))
+    _check(rc, "hf_semilep_reco")
 
 
 def reorder_stats(counters_host, cuts_arr, n_cuts):

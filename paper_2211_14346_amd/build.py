@@ -25,6 +25,7 @@ UNITS = {
     "hf_compact.hip": [],
     "hf_reco.hip": [],
     "hf_rng.hip": [],
+    "hf_semilep.hip": [],
     "hf_api.cpp": [],
 }
 
@@ -56,9 +57,10 @@ def build(verbose=False):
     os.replace(tmp, LIB)
     # identity of the search kernel's sources this library was built from
     sys.path.insert(0, os.path.dirname(HERE))
-    from paper_2211_14346_amd.perf import search_source_hash
+    from paper_2211_14346_amd.perf import SOURCES, source_hash
     with open(LIB + ".srchash", "w") as f:
-        f.write(search_source_hash() + "\n")
+        for kind in SOURCES:
+            f.write(f"{kind} {source_hash(kind)}\n")
     return LIB
 
 

@@ -1,4 +1,5 @@
-"""One chunk of the hot path: select -> compact -> ttbar reconstruction ->
+"""One chunk of the hot path: select -> compact -> kinematic reconstruction
+(dileptonic ttbar, or the single-neutrino chi^2 fit of one-lepton events) ->
 compact, with per-cut counters, adaptive reordering between steps and an
 optional HIP-graph recording of the four calls.
 
@@ -14,7 +15,10 @@ from . import binding as B
 
 class Chain:
     def __init__(self, ev, cuts, reco, precision="mixed", device="cuda", index_base=0, order=None,
-                 schedule="auto"):
+                 schedule="auto", semilep=None, topology="TCHAN"):
+        """reco: dileptonic reconstruction parameters (hfgen reco dict), or
+        None with semilep (hfgen semilep dict) and topology for the
+        single-neutrino reconstruction."""
         self.device = device
         self.cuts = cuts
         self.n_cuts = len(cuts)
@@ -24,10 +28,15 @@ class Chain:
         self.dev = B.DeviceEvents(ev, device=device, index_base=index_base)
         n = self.dev.n
         self.n = n
-        self.params = B.reco_params(reco, precision=precision, reco_cut=self.reco_id, schedule=schedule)
-        self.want_mbb = bool(reco.get("want_mbb", 0))
-        if self.want_mbb:
-            self.params.want_mbb = 1
+        self.semilep = semilep is not None
+        if self.semilep:
+            self.params = B.semilep_params(semilep, topology, reco_cut=self.reco_id)
+            self.want_mbb = False
+        else:
+            self.params = B.reco_params(reco, precision=precision, reco_cut=self.reco_id, schedule=schedule)
+            self.want_mbb = bool(reco.get("want_mbb", 0))
+            if self.want_mbb:
+                self.params.want_mbb = 1
         self.order_host = list(range(self.n_cuts)) if order is None else list(order)
         self.order = torch.tensor(self.order_host, dtype=torch.int32, device=device)
         self.counters = torch.zeros(self.n_cuts, 3, dtype=torch.int64, device=device)
@@ -36,11 +45,15 @@ class Chain:
         self.count = torch.zeros(1, dtype=torch.int64, device=device)
         self.final_idx = torch.zeros(max(n, 1), dtype=torch.int32, device=device)
         self.final_count = torch.zeros(1, dtype=torch.int64, device=device)
-        self.out = B.RecoOutputs(n, device=device, want_mbb=self.want_mbb)
+        if self.semilep:
+            self.out = B.SemilepOutputs(n, device=device)
+            self.ws_reco = None
+        else:
+            self.out = B.RecoOutputs(n, device=device, want_mbb=self.want_mbb)
+            self.ws_reco = B.workspace(B.lib().hf_ttbar_reco_workspace_size(n), device)
         self.ws_sel = B.workspace(B.lib().hf_select_workspace_size(n, self.n_cuts), device)
         self.ws_cmp = B.workspace(B.lib().hf_compact_workspace_size(n), device)
         self.ws_cmp2 = B.workspace(B.lib().hf_compact_workspace_size(n), device)
-        self.ws_reco = B.workspace(B.lib().hf_ttbar_reco_workspace_size(n), device)
         self.graph = None
 
     # -------------------------------------------------------------- stages
@@ -52,8 +65,11 @@ class Chain:
                   stream=stream)
 
     def run_reco(self, stream=None):
-        B.ttbar_reco(self.dev, self.idx, self.count, self.n, self.params, self.out, self.counters, self.ws_reco,
-                     stream)
+        if self.semilep:
+            B.semilep_reco(self.dev, self.idx, self.count, self.n, self.params, self.out, self.counters, stream)
+        else:
+            B.ttbar_reco(self.dev, self.idx, self.count, self.n, self.params, self.out, self.counters,
+                         self.ws_reco, stream)
 
     def run_final(self, stream=None):
         B.compact(self.out.t["has_sol"], self.n, self.final_idx, self.final_count, self.ws_cmp2, d_n=self.count,

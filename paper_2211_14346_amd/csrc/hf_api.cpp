@@ -290,6 +290,47 @@ int hf_ttbar_reco_autotune(const hf_events_t *ev, const int32_t *d_idx, const in
     return HF_OK;
 }
 
+int hf_semilep_reco(const hf_events_t *ev, const int32_t *d_idx, const int64_t *d_count, int64_t capacity,
+                    const hf_semilep_params_t *p, const hf_semilep_out_t *out, hf_counters_t *d_counters,
+                    hipStream_t stream) {
+    const char *why = nullptr;
+    if (!events_ok(ev, true, &why)) return fail(HF_ERR_INVAL, "hf_semilep_reco: %s", why);
+    if (!p || !out) return fail(HF_ERR_INVAL, "hf_semilep_reco: params or out is NULL");
+    if (capacity < 0 || capacity >= ((int64_t)1 << 31))
+        return fail(HF_ERR_INVAL, "hf_semilep_reco: capacity out of range");
+    if (!d_count) return fail(HF_ERR_INVAL, "hf_semilep_reco: count is NULL");
+    if (capacity > 0 && (!d_idx || !out->has_sol || !out->root || !out->best_j || !out->best_h || !out->best_p ||
+                         !out->best_q || !out->nu || !out->m_tl || !out->m_wl || !out->m_th || !out->m_wh ||
+                         !out->chi2))
+        return fail(HF_ERR_INVAL, "hf_semilep_reco: an index or output array is NULL");
+    if (p->topology != HF_TOPO_TCHAN && p->topology != HF_TOPO_WT && p->topology != HF_TOPO_TTSEMI)
+        return fail(HF_ERR_INVAL, "hf_semilep_reco: unknown topology %d", p->topology);
+    if (p->max_cands < 1 || p->max_cands > HF_MAX_CANDS)
+        return fail(HF_ERR_INVAL, "hf_semilep_reco: max_cands %d outside [1, %d]", p->max_cands, HF_MAX_CANDS);
+    if (!(p->m_t > p->m_w && p->m_w > 0.0) || !isfinite(p->m_t))
+        return fail(HF_ERR_INVAL, "hf_semilep_reco: masses invalid");
+    if (!(p->sigma_t > 0.0) || !(p->sigma_w > 0.0) || !isfinite(p->sigma_t) || !isfinite(p->sigma_w))
+        return fail(HF_ERR_INVAL, "hf_semilep_reco: widths must be finite and > 0");
+    if (p->reserved != 0) return fail(HF_ERR_INVAL, "hf_semilep_reco: reserved field must be 0");
+    hf::SemilepArgs a;
+    a.m_t = p->m_t;
+    a.m_w = p->m_w;
+    a.inv_st2 = 1.0 / (p->sigma_t * p->sigma_t);
+    a.inv_sw2 = 1.0 / (p->sigma_w * p->sigma_w);
+    a.lep_pt_min = p->lep_pt_min;
+    a.lep_eta_max = p->lep_eta_max;
+    a.jet_pt_min = p->jet_pt_min;
+    a.jet_eta_max = p->jet_eta_max;
+    a.topology = p->topology;
+    a.max_cands = p->max_cands;
+    hf::SemilepOutView o{out->has_sol, out->root, out->best_j, out->best_h, out->best_p, out->best_q, out->nu,
+                         out->m_tl,    out->m_wl, out->m_th,   out->m_wh,   out->chi2};
+    hf_counters_t *rc = (d_counters && p->reco_cut >= 0) ? d_counters + p->reco_cut : nullptr;
+    hipError_t e = hf::launch_semilep(hf::make_view(*ev), d_idx, d_count, capacity, a, o, rc, stream);
+    if (e != hipSuccess) return device_fail("hf_semilep_reco launch", e);
+    return HF_OK;
+}
+
 int hf_reco_timing_events(hipEvent_t start, hipEvent_t stop) {
     if ((start == nullptr) != (stop == nullptr)) return fail(HF_ERR_INVAL, "hf_reco_timing_events: one event is NULL");
     hf::set_reco_timing(start, stop);

@@ -70,6 +70,23 @@ hipError_t launch_reco(const EvView &ev, const int32_t *idx, const int64_t *coun
                        const RecoArgs &a, int precision, const RecoOutView &out, hf_counters_t *reco_counter,
                        void *ws, bool worklist, hipStream_t s);
 
+// ---- single-neutrino reconstruction (hf_semilep.hip)
+struct SemilepArgs {
+    double m_t, m_w, inv_st2, inv_sw2;  // 1 / sigma_t^2, 1 / sigma_W^2
+    float lep_pt_min, lep_eta_max, jet_pt_min, jet_eta_max;
+    int topology, max_cands;
+};
+
+struct SemilepOutView {
+    uint8_t *has_sol;
+    int8_t *root;
+    int16_t *best_j, *best_h, *best_p, *best_q;
+    double *nu, *m_tl, *m_wl, *m_th, *m_wh, *chi2;
+};
+
+hipError_t launch_semilep(const EvView &ev, const int32_t *idx, const int64_t *count, int64_t capacity,
+                          const SemilepArgs &a, const SemilepOutView &out, hf_counters_t *counter, hipStream_t s);
+
 // ---- random draws (hf_rng.hip)
 hipError_t launch_philox(const uint32_t *ctr, uint64_t seed, uint32_t *out, int64_t n, hipStream_t s);
 hipError_t launch_gauss(uint64_t seed, const int64_t *g, const int32_t *v, const int32_t *slot, int64_t n,

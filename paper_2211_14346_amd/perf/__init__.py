@@ -7,25 +7,38 @@ import os
 
 _CSRC = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "csrc")
 
-# Sources that determine the reconstruction search kernel's code.
-SEARCH_SOURCES = ("hf_reco.hip", "hf_reco_math.hpp", "hf_device.hpp", "hf_internal.hpp")
+# Sources that determine each profiled kernel's code: the dileptonic
+# reconstruction search and the single-neutrino reconstruction.
+SOURCES = {
+    "search": ("hf_reco.hip", "hf_reco_math.hpp", "hf_device.hpp", "hf_internal.hpp"),
+    "semilep": ("hf_semilep.hip", "hf_device.hpp", "hf_internal.hpp"),
+}
+SEARCH_SOURCES = SOURCES["search"]
 
 
-def search_source_hash():
-    """sha256 (first 16 hex digits) over the search kernel's sources."""
+def source_hash(kind="search"):
+    """sha256 (first 16 hex digits) over one kernel's sources."""
     h = hashlib.sha256()
-    for name in SEARCH_SOURCES:
+    for name in SOURCES[kind]:
         with open(os.path.join(_CSRC, name), "rb") as f:
             h.update(name.encode())
             h.update(f.read())
     return h.hexdigest()[:16]
 
 
-def built_source_hash():
-    """The search_source_hash() of the sources libhf.so was built from, or
-    None when the build recorded none."""
+def search_source_hash():
+    return source_hash("search")
+
+
+def built_source_hash(kind="search"):
+    """The source_hash(kind) of the sources libhf.so was built from, or None
+    when the build recorded none."""
     path = os.path.join(os.path.dirname(_CSRC), "libhf.so.srchash")
     if not os.path.exists(path):
         return None
     with open(path) as f:
-        return f.read().strip()
+        for line in f:
+            parts = line.split()
+            if len(parts) == 2 and parts[0] == kind:
+                return parts[1]
+    return None

@@ -11,6 +11,9 @@ Writes
   k_search_ttbar1M_v64_kernel_stats.txt   per-kernel calls and durations
   k_search_ttbar1M_v64_counters.txt       per-dispatch counters of each kernel,
                                           HBM traffic of the search kernel
+  k_semilep_tchan1M.txt                   duration, counters and HBM traffic of
+                                          the single-neutrino kernel (bench's
+                                          second leg), with --semilep-hash
 FETCH_SIZE and WRITE_SIZE (KiB per dispatch) are scaled into bytes by what
 each reads for a plain device copy of known size (--cal-bytes read and
 written once per copy): factor = copy bytes / (counter KiB * 1024).
@@ -22,6 +25,7 @@ import csv
 import os
 
 SEARCH = "k_search_ev<float>"
+SEMILEP = "k_semilep_tchan"
 TRACE_CMD = ("rocprofv3 --kernel-trace --stats -d <dir> -o run --output-format csv -- "
              "python3 bench.py --profile-only --steps 5 --warmup 1")
 PMC_CMD = ("rocprofv3 --pmc <counters> -d <dir> -o run --output-format csv -- "
@@ -65,6 +69,7 @@ def main():
     ap.add_argument("--cal-write", required=True)
     ap.add_argument("--cal-bytes", type=int, default=256 << 20)
     ap.add_argument("--hash", required=True, help="search kernel source hash of the profiled tree")
+    ap.add_argument("--semilep-hash", default=None, help="single-neutrino kernel source hash of the profiled tree")
     ap.add_argument("--out", default="profiles")
     a = ap.parse_args()
     os.makedirs(a.out, exist_ok=True)
@@ -106,6 +111,28 @@ def main():
                   f"search_source_hash: {a.hash}"]
     with open(os.path.join(a.out, "k_search_ttbar1M_v64_counters.txt"), "w") as f:
         f.write("\n".join(lines) + "\n")
+
+    lf, lw = merged.get((SEMILEP, "FETCH_SIZE")), merged.get((SEMILEP, "WRITE_SIZE"))
+    row = [r for r in ks if r[0] == SEMILEP]
+    if a.semilep_hash and lf and lw and row:
+        name, calls, avg, mn, mx, pct = row[0]
+        fb, wb = lf[0] * 1024.0 * fetch_f, lw[0] * 1024.0 * write_f
+        lines = ["# Single-neutrino chi^2 reconstruction (t-channel), bench workload tchan1M "
+                 "(1M one-lepton events, 4 cuts + hf_semilep_reco)",
+                 f"# trace command: {TRACE_CMD}",
+                 f"# counter command (one run per counter): {PMC_CMD}",
+                 f"# calibration: {CAL_CMD}",
+                 f"# calibration on a {a.cal_bytes} B device copy: bytes = FETCH_SIZE * 1024 * {fetch_f:.4f}, "
+                 f"bytes = WRITE_SIZE * 1024 * {write_f:.4f}", "",
+                 f"{'kernel':40s} {'calls':>6s} {'avg_us':>10s} {'min_us':>10s} {'max_us':>10s}",
+                 f"{name[:40]:40s} {calls:6d} {avg / 1e3:10.2f} {mn / 1e3:10.2f} {mx / 1e3:10.2f}", "",
+                 f"FETCH_SIZE KiB per dispatch  {lf[0]:12.1f}   ({lf[1]} dispatches)",
+                 f"WRITE_SIZE KiB per dispatch  {lw[0]:12.1f}   ({lw[1]} dispatches)", "",
+                 f"semilep_kernel: {SEMILEP}", f"semilep_avg_us: {avg / 1e3:.2f}",
+                 f"semilep_fetch_bytes_per_launch: {fb:.0f}", f"semilep_write_bytes_per_launch: {wb:.0f}",
+                 f"semilep_traffic_bytes_per_launch: {fb + wb:.0f}", f"semilep_source_hash: {a.semilep_hash}"]
+        with open(os.path.join(a.out, "k_semilep_tchan1M.txt"), "w") as f:
+            f.write("\n".join(lines) + "\n")
 
 
 if __name__ == "__main__":

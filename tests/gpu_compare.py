@@ -61,3 +61,41 @@ def assert_agree(st, min_agree=0.999, tol=1e-4, min_within=1.0):
     assert st["frac_within_1e-4"] >= min_within, st
     if min_within >= 1.0:
         assert st["max_rel_any"] <= tol, st
+
+
+SEMILEP_FLOATS = ("m_tl", "m_wl", "m_th", "m_wh", "chi2")
+
+
+def compare_semilep(g, w):
+    """Single-neutrino reconstruction: the decision (a lepton and enough jets)
+    is integer logic and must be identical; the choice (root, j, h, p, q) must
+    agree in >= 99.9 % of events; where it agrees, the neutrino momentum is
+    compared as |dp| / max(|p_ref|, 1 GeV) and masses and chi^2 as
+    |d| / max(|ref|, 1)."""
+    S = len(w["has_sol"])
+    hs_g, hs_w = g["has_sol"][:S].astype(bool), w["has_sol"][:S].astype(bool)
+    both = hs_g & hs_w
+    same = both.copy()
+    for k in ("root", "best_j", "best_h", "best_p", "best_q"):
+        same &= g[k][:S] == w[k][:S]
+    st = {"S": int(S), "decision_equal": bool(np.array_equal(hs_g, hs_w)), "n_both": int(both.sum()),
+          "choice_agree": float(same.sum() / both.sum()) if both.sum() else 1.0}
+    d = np.linalg.norm(g["nu"][:S][same] - w["nu"][:S][same], axis=1)
+    rels = [d / np.maximum(np.linalg.norm(w["nu"][:S][same], axis=1), 1.0)]
+    st["max_rel_nu"] = float(rels[0].max()) if rels[0].size else 0.0
+    for k in SEMILEP_FLOATS:
+        r = np.abs(g[k][:S][same] - w[k][:S][same]) / np.maximum(np.abs(w[k][:S][same]), 1.0)
+        st["max_rel_" + k] = float(r.max()) if r.size else 0.0
+        rels.append(r)
+    st["max_rel_any"] = float(np.max([r.max() for r in rels if r.size])) if same.any() else 0.0
+    nos = ~hs_g
+    st["sentinel_ok"] = bool(np.all(g["chi2"][:S][nos] == -9999.0) and np.all(g["nu"][:S][nos] == -9999.0)
+                             and np.all(g["best_j"][:S][nos] == -1) and np.all(g["root"][:S][nos] == -1))
+    return st
+
+
+def assert_agree_semilep(st, min_agree=0.999, tol=1e-4):
+    assert st["sentinel_ok"], st
+    assert st["decision_equal"], st
+    assert st["choice_agree"] >= min_agree, st
+    assert st["max_rel_any"] <= tol, st

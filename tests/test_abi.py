@@ -140,3 +140,31 @@ def test_reorder_device_validates_on_the_host(B):
     two = B.cut_table([{"name": "b", "kind": "MET_MIN", "f": [1], "deps": ["a"]},
                        {"name": "a", "kind": "MET_MIN", "f": [1], "deps": []}])
     assert L.hf_reorder_device(dummy, C.cast(two, C.c_void_p), 1, dummy, None) == -1
+
+
+def test_semilep_validation(B):
+    L = B.lib()
+    full = B.Events(n=10, index_base=0, **{k: 16 for k in ("lep_off", "jet_off", "lep_pt", "lep_eta", "lep_phi",
+                                                           "lep_e", "lep_q", "jet_pt", "jet_eta", "jet_phi",
+                                                           "jet_e", "jet_btag", "met_x", "met_y")})
+    dummy = C.c_void_p(16)
+    sl = hfgen.config("tchan1M")["semilep"]
+    out = B.SemilepOut(**{k: 16 for k, _ in B.SemilepOut._fields_})
+
+    def call(p, o=out, ev=full, count=dummy):
+        return L.hf_semilep_reco(C.byref(ev), dummy, count, 10, C.byref(p), C.byref(o), None, None)
+
+    assert C.sizeof(B.SemilepParams) == 64 and C.sizeof(B.SemilepOut) == 8 * 12
+    for field, val, word in (("topology", 3, b"topology"), ("max_cands", 0, b"max_cands"),
+                             ("max_cands", 13, b"max_cands"), ("sigma_t", 0.0, b"widths"),
+                             ("sigma_w", float("nan"), b"widths"), ("m_w", 200.0, b"masses"),
+                             ("reserved", 1, b"reserved")):
+        p = B.semilep_params(sl)
+        setattr(p, field, val)
+        assert call(p) == -1 and word in L.hf_last_error(), field
+    p = B.semilep_params(sl)
+    assert call(p, count=None) == -1
+    bad = B.SemilepOut(**{k: 16 for k, _ in B.SemilepOut._fields_})
+    bad.chi2 = None
+    assert call(p, o=bad) == -1 and b"NULL" in L.hf_last_error()
+    assert call(p, ev=B.Events(n=10, index_base=0)) == -1
