@@ -9,7 +9,10 @@ HIP graph.  Inputs are resident in HBM before timing starts.
 
 A second leg measures the single-neutrino chi^2 reconstruction the same way
 (1M one-lepton t-channel-like events, four cuts plus hf_semilep_reco, one HIP
-graph per step) and reports it under "semilep" in the same line.
+graph per step) and reports it under "semilep" in the same line.  A third
+leg streams 50 chunks of 1M mixed events from pinned host memory through a
+dileptonic and a one-lepton channel (12 cuts, copies overlapped with
+compute) and reports the end-to-end rate under "stream".
 
 Prints one JSON line.  --gpus above 1 is refused: this build runs on one GPU.
 """
@@ -27,6 +30,7 @@ sys.path.insert(0, ROOT)
 
 WORKLOAD = "ttbar1M_v64"
 SEMILEP_WORKLOAD = "tchan1M"
+STREAM_WORKLOAD = "hlhc50M"
 
 # Algorithmic FP operations of the reconstruction search kernel per unit of
 # work (one each for add, mul, div, sqrt, transcendental; two for FMA),
@@ -59,6 +63,12 @@ def _parse():
     ap.add_argument("--cpu-sample", type=int, default=200_000)
     ap.add_argument("--profile-only", action="store_true", help="few steps, no CPU baseline (for profilers)")
     ap.add_argument("--no-semilep", action="store_true", help="skip the single-neutrino reconstruction leg")
+    ap.add_argument("--no-stream", action="store_true", help="skip the chunked-stream leg")
+    ap.add_argument("--stream-only", action="store_true",
+                    help="run only the chunked-stream leg and print its JSON object (for profilers)")
+    ap.add_argument("--stream-chunks", type=int, default=50)
+    ap.add_argument("--stream-pool", type=int, default=4,
+                    help="distinct generated chunks the stream cycles through (each pass gets new event ids)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB a few times (to scale the "
                          "FETCH_SIZE / WRITE_SIZE counters into bytes) and exit")
@@ -88,6 +98,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes": nbytes, "copies": 5}))
+        return
+    if args.stream_only:
+        print(json.dumps({"stream": stream_leg(args, torch)}))
         return
     cfg = hfgen.config(WORKLOAD)
     t0 = time.time()
@@ -165,7 +178,89 @@ def main():
         del ch
         torch.cuda.empty_cache()
         out["semilep"] = semilep_leg(args, torch)
+    if not args.no_stream:
+        torch.cuda.empty_cache()
+        out["stream"] = stream_leg(args, torch)
     print(json.dumps(out))
+
+
+def stream_leg(args, torch):
+    """50 chunks of 1M mixed events (dileptonic ttbar, t-channel, Wt,
+    background) streamed from pinned host memory through the dileptonic
+    channel (6 cuts, quartic at 64 variations) and the one-lepton channel
+    (6 cuts, single-neutrino chi^2): two device slots, copies on their own
+    stream overlapped with compute.  Also the copy-only and compute-only
+    rates of the same chunks, to show which one bounds the stream."""
+    import hfgen
+    from paper_2211_14346_amd.stream import Channel, EventStream, HostChunk
+
+    cfg = hfgen.config(STREAM_WORKLOAD)
+    m = cfg["chunk"]
+    n_chunks = max(2, 10 if args.profile_only else args.stream_chunks)
+    t0 = time.time()
+    pool = [hfgen.stream_chunk(cfg, i)[0] for i in range(max(1, args.stream_pool))]
+    print(f"[bench] stream: generated {len(pool)} chunks in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    # chunk i reuses pool[i % P]'s kinematics with its own event ids (and so its own variation draws)
+    host = [HostChunk(ev, 0) for ev in pool]
+    chunks = []
+    for i in range(n_chunks):
+        hc = host[i % len(host)]
+        view = object.__new__(HostChunk)
+        view.__dict__.update(hc.__dict__)
+        view.index_base = i * m
+        chunks.append(view)
+    lep_cap = max(c.n_lep for c in host)
+    jet_cap = max(c.n_jet for c in host)
+    chans = [Channel("dilepton", cfg["chains"]["dilepton"], m, reco=cfg["reco"]),
+             Channel("single", cfg["chains"]["single"], m, semilep=cfg["semilep"], topology="TCHAN")]
+    es = EventStream(chans, m, lep_cap, jet_cap)
+    # warm-up: one untimed pass over the whole stream (the first pass pays
+    # one-time host costs of the copies and launches, about 0.5 ms a chunk)
+    es.run(chunks)
+    torch.cuda.synchronize()
+    es.reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    es.run(chunks)
+    t_issue = time.perf_counter() - t0
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    cnt = {ch.name: ch.counters.cpu().numpy() for ch in chans}
+    # copy only: the same H2D copies, alternating slots, no compute
+    t1 = time.perf_counter()
+    for i, hc in enumerate(chunks):
+        es.slots[i % 2].load(hc, es.copy_stream)
+    es.copy_stream.synchronize()
+    dt_copy = time.perf_counter() - t1
+    # compute only: the channels on a resident chunk
+    es.slots[0].load(chunks[0], es.copy_stream)
+    es.copy_stream.synchronize()
+    reps = min(10, n_chunks)
+    t2 = time.perf_counter()
+    for _ in range(reps):
+        for ch in chans:
+            ch.run(es.slots[0], es.compute_stream)
+    es.compute_stream.synchronize()
+    dt_comp = (time.perf_counter() - t2) / reps
+    nbytes = sum(c.nbytes for c in chunks)
+    n = m * n_chunks
+    leg = {"metric": "events/s end to end, pinned host chunks -> 2 channels (12 cuts, dileptonic quartic @64 "
+                     "variations + single-neutrino chi^2)",
+           "value": round(n / dt, 1), "unit": "events/s", "dtype": "f32+f64",
+           "ms_per_chunk": round(1e3 * dt / n_chunks, 4),
+           "config": {"workload": STREAM_WORKLOAD, "events": n, "chunk": m, "chunks": n_chunks,
+                      "distinct_chunks": len(pool), "cuts": len(cfg["cuts"]),
+                      "fractions": cfg["fractions"], "variations": cfg["reco"]["n_var"],
+                      "reconstructed": {k: int(v[chans[j].reco_id, 1]) for j, (k, v) in enumerate(cnt.items())},
+                      "input_bytes": int(nbytes)},
+           "h2d_only": {"GB_per_s": round(nbytes / dt_copy / 1e9, 2), "ms_per_chunk": round(1e3 * dt_copy / n_chunks, 4)},
+           "compute_only": {"events_per_s": round(m / dt_comp, 1), "ms_per_chunk": round(1e3 * dt_comp, 4)},
+           "overlap": round(max(dt_copy / n_chunks, dt_comp) / (dt / n_chunks), 3),
+           "host_issue_ms_per_chunk": round(1e3 * t_issue / n_chunks, 4),
+           "h2d_GB_per_s_in_stream": round(nbytes / dt / 1e9, 2)}
+    print(f"[bench] stream: {leg['ms_per_chunk']} ms/chunk, copy {leg['h2d_only']['ms_per_chunk']} ms, "
+          f"compute {leg['compute_only']['ms_per_chunk']} ms", file=sys.stderr, flush=True)
+    return leg
 
 
 # Algorithmic HBM bytes of hf_semilep_reco per unit: per compacted event the

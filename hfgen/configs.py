@@ -24,8 +24,9 @@ import copy
 #   FWD_JET_VETO  f=[pt_min, abs_eta_lo, abs_eta_hi]    (fails on any jet in [lo, hi))
 #   LEP_ISO       f=[lep_pt_min, lep_abs_eta_max, jet_pt_min, jet_abs_eta_max, dr_min]
 #   RECO          marker for the kinematic reconstruction (last cut)
+#   MTW_MIN       f=[lep_pt_min, lep_abs_eta_max, mtw_min]  (W transverse mass of the leading lepton)
 CUT_KINDS = ("LEP_N_OS", "JET_N_MIN", "BTAG_N_MIN", "BTAG_N_EQ", "MET_MIN",
-             "MLL_MIN", "FWD_JET_VETO", "LEP_ISO", "RECO")
+             "MLL_MIN", "FWD_JET_VETO", "LEP_ISO", "RECO", "MTW_MIN")
 
 
 def _cut(name, kind, f=(), i=(), deps=()):
@@ -102,6 +103,14 @@ CONFIGS = {
         "reco": {"smear": 0, "n_var": 1},
         "desc": "1M single-top t-channel-like events (one lepton), 2-6 jets, 30% W+jets-like background",
     },
+    "hlhc50M": {
+        "index": 4, "n_events": 50_000_000, "chunk": 1_000_000, "kind": "hlhc", "n_extra_max": 4,
+        "bkg_jet_max": 8, "chain": "hlhc",
+        "fractions": {"ttbar": 0.35, "tchan": 0.20, "wt": 0.15, "bkg": 0.30},
+        "reco": {"smear": 1, "n_var": 64},
+        "desc": "50M mixed events in 1M chunks (35% dileptonic ttbar, 20% t-channel, 15% Wt, 30% background), "
+                "dileptonic (6 cuts, quartic at 64 variations) and one-lepton (6 cuts, chi^2) channels",
+    },
     "stress2M_heavytail": {
         "index": 3, "n_events": 2_000_000, "kind": "ttbar", "n_extra_max": 10,
         "bkg_frac": 0.2, "bkg_jet_max": 12, "chain": "dilepton",
@@ -110,6 +119,34 @@ CONFIGS = {
         "desc": "2M events, 2-12 jets, variations log-uniform in 1..1024",
     },
 }
+
+
+def chain_hlhc_dilepton():
+    """HL-LHC dileptonic channel (section 6.1): two isolated opposite-sign
+    leptons, jets, a b tag, E_T^miss > 30, M_ll > 40, then the two-neutrino
+    reconstruction."""
+    return [
+        _cut("D_LEP2OS", "LEP_N_OS", [20.0, 2.5], [2, 1]),
+        _cut("D_JETS2", "JET_N_MIN", [25.0, 2.5], [2]),
+        _cut("D_BTAG1", "BTAG_N_MIN", [25.0, 2.5, 0.5], [1]),
+        _cut("D_MET30", "MET_MIN", [30.0]),
+        _cut("D_MLL40", "MLL_MIN", [20.0, 2.5, 40.0], deps=["D_LEP2OS"]),
+        _cut("D_RECO", "RECO", deps=["D_LEP2OS", "D_JETS2", "D_BTAG1", "D_MET30", "D_MLL40"]),
+    ]
+
+
+def chain_hlhc_single():
+    """HL-LHC one-lepton single-top channel (section 6.1): exactly one
+    lepton, jets, exactly one b tag, E_T^miss > 30, M_T^W > 50, then the
+    single-neutrino chi^2 reconstruction."""
+    return [
+        _cut("S_LEP1", "LEP_N_OS", [20.0, 2.5], [1, 0]),
+        _cut("S_JETS2", "JET_N_MIN", [25.0, 2.5], [2]),
+        _cut("S_BTAG1", "BTAG_N_EQ", [25.0, 2.5, 0.5], [1]),
+        _cut("S_MET30", "MET_MIN", [30.0]),
+        _cut("S_MTW50", "MTW_MIN", [20.0, 2.5, 50.0], deps=["S_LEP1"]),
+        _cut("S_RECO", "RECO", deps=["S_LEP1", "S_JETS2", "S_BTAG1", "S_MET30", "S_MTW50"]),
+    ]
 
 
 def chain_semilep():
@@ -132,7 +169,11 @@ def config(name):
     reco["seed"] = c["seed"]
     c["reco"] = reco
     c["semilep"] = dict(SEMILEP_DEFAULTS)
-    c["cuts"] = {"dilepton": chain_dilepton, "tth8": chain_tth8, "semilep": chain_semilep}[c["chain"]]()
+    if c["chain"] == "hlhc":
+        c["chains"] = {"dilepton": chain_hlhc_dilepton(), "single": chain_hlhc_single()}
+        c["cuts"] = c["chains"]["dilepton"] + c["chains"]["single"]
+    else:
+        c["cuts"] = {"dilepton": chain_dilepton, "tth8": chain_tth8, "semilep": chain_semilep}[c["chain"]]()
     return c
 
 

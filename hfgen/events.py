@@ -29,7 +29,11 @@ Recipe (all energies in GeV):
     massless quarks (Wt-like); or a second top decaying hadronically
     (semileptonic ttbar); b jets tagged at 0.70, other jets at 0.01, extra
     jets as above; background (W+jets-like): 0..2 leptons pT ~ Exp(40), jets
-    as above tagged at 0.10, MET x, y ~ N(0, 30^2).
+    as above tagged at 0.10, MET x, y ~ N(0, 30^2);
+  * HL-LHC mixture: per chunk, process counts drawn multinomially from the
+    fractions (dileptonic ttbar, t-channel, Wt, background), each generated
+    with its recipe above (the background with the dileptonic sample's
+    background recipe), then shuffled.
 Objects are sorted by descending pT within each event.
 
 This module holds no arithmetic of the method under test (selection,
@@ -354,6 +358,39 @@ def _chunk_single(rng, cfg, n):
     return ev64, loff, joff, None, truth
 
 
+HLHC_PROCESSES = ("ttbar", "tchan", "wt", "bkg")
+
+
+def _chunk_hlhc(rng, cfg, n):
+    """Mixed HL-LHC-like chunk: dileptonic ttbar, t-channel and Wt single
+    top (one lepton) and background in the fractions cfg["fractions"],
+    generated per process and shuffled.  Truth keeps the process code
+    (index into HLHC_PROCESSES) only."""
+    fr = cfg["fractions"]
+    counts = rng.multinomial(n, [fr[p] for p in HLHC_PROCESSES])
+    parts = []
+    for code, (proc, m) in enumerate(zip(HLHC_PROCESSES, counts)):
+        m = int(m)
+        if m == 0:
+            continue
+        sub = {"n_extra_max": cfg["n_extra_max"], "bkg_jet_max": cfg["bkg_jet_max"]}
+        if proc == "ttbar":
+            sub.update(kind="ttbar", bkg_frac=0.0)
+            part = _chunk(rng, sub, m)
+        elif proc == "bkg":
+            sub.update(kind="ttbar", bkg_frac=1.0)
+            part = _chunk(rng, sub, m)
+        else:
+            sub.update(kind=proc, bkg_frac=0.0)
+            part = _chunk_single(rng, sub, m)
+        parts.append((part[0], part[1], part[2], None, {"process": np.full(m, code, dtype=np.int8)}))
+    ev64, loff, joff, _, truth = parts[0] if len(parts) == 1 else _concat(parts)
+    tmp = dict(ev64, n=n, lep_off=loff, jet_off=joff, n_var=None, truth=truth)
+    out = subset(tmp, rng.permutation(n))
+    ev64 = {k: v for k, v in out.items() if k not in ("n", "lep_off", "jet_off", "n_var", "truth")}
+    return ev64, out["lep_off"].astype(np.int64), out["jet_off"].astype(np.int64), None, out["truth"]
+
+
 def _concat(parts):
     ev = {k: np.concatenate([p[0][k] for p in parts]) for k in parts[0][0]}
     offs = []
@@ -388,7 +425,8 @@ def generate(cfg, n_events=None, seed=None, keep_fp64=False):
     parts = []
     for c in range(nchunks):
         m = min(CHUNK, n - c * CHUNK)
-        gen = _chunk_single if cfg["kind"] in ("tchan", "wt", "ttsemi") else _chunk
+        gen = _chunk_single if cfg["kind"] in ("tchan", "wt", "ttsemi") else \
+            _chunk_hlhc if cfg["kind"] == "hlhc" else _chunk
         parts.append(gen(np.random.Generator(np.random.PCG64(children[c])), cfg, m))
     ev64, loff, joff, nvar, truth = parts[0] if len(parts) == 1 else _concat(parts)
     if loff[-1] >= 2 ** 32 or joff[-1] >= 2 ** 32:
@@ -435,3 +473,14 @@ def subset(ev, sel):
         f["met_y"] = ev["fp64"]["met_y"][sel]
         out["fp64"] = f
     return out
+
+
+def stream_chunk(cfg, i, n=None):
+    """Chunk i of a streamed sample (a config with a "chunk" size): generated
+    with its own seed; its events take the global ids i*n .. i*n + n - 1.
+    Returns (sample, index_base)."""
+    if isinstance(cfg, str):
+        cfg = _cfgs.config(cfg)
+    m = int(cfg["chunk"] if n is None else n)
+    ev = generate(cfg, n_events=m, seed=int(cfg["seed"]) * 100003 + int(i))
+    return ev, int(i) * m

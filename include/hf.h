@@ -82,7 +82,13 @@ typedef struct hf_events {
  *                       (every selected lepton at Delta R >= dr_min from every
  *                        selected jet; Delta R = sqrt(Delta eta^2 + Delta phi^2))
  *   HF_CUT_RECO         the kinematic reconstruction (section 4: last cut);
- *                       hf_select skips it, hf_ttbar_reco fills its counters. */
+ *                       hf_select skips it, hf_ttbar_reco or hf_semilep_reco
+ *                       fills its counters.
+ *   HF_CUT_MTW_MIN      f = {lep_pt_min, lep_eta_max, mtw_min}
+ *                       (W transverse mass of the leading selected lepton and
+ *                        the missing momentum, M_T^2 = 2 (pT_l MET - pT_l . MET),
+ *                        above mtw_min; fails without a selected lepton;
+ *                        section 6.1) */
 enum {
     HF_CUT_LEP_N_OS = 0,
     HF_CUT_JET_N_MIN = 1,
@@ -92,7 +98,8 @@ enum {
     HF_CUT_MLL_MIN = 5,
     HF_CUT_FWD_JET_VETO = 6,
     HF_CUT_LEP_ISO = 7,
-    HF_CUT_RECO = 8
+    HF_CUT_RECO = 8,
+    HF_CUT_MTW_MIN = 9
 };
 
 /* A cut of the chain.  Its id is its index in the cut table.  Bit j of

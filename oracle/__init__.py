@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libhf_oracle.so")
 SRC_PATH = os.path.join(_HERE, "hf_oracle.c")
 
 KIND = {"LEP_N_OS": 0, "JET_N_MIN": 1, "BTAG_N_MIN": 2, "BTAG_N_EQ": 3, "MET_MIN": 4,
-        "MLL_MIN": 5, "FWD_JET_VETO": 6, "LEP_ISO": 7, "RECO": 8}
+        "MLL_MIN": 5, "FWD_JET_VETO": 6, "LEP_ISO": 7, "RECO": 8, "MTW_MIN": 9}
 PAIR_MODE = {"BTAG_FILL": 0, "ALL_JETS": 1}
 NOSOL = -9999.0
 

@@ -58,7 +58,7 @@ typedef struct {
 enum {
     ORC_LEP_N_OS = 0, ORC_JET_N_MIN = 1, ORC_BTAG_N_MIN = 2, ORC_BTAG_N_EQ = 3,
     ORC_MET_MIN = 4, ORC_MLL_MIN = 5, ORC_FWD_JET_VETO = 6, ORC_LEP_ISO = 7,
-    ORC_RECO = 8
+    ORC_RECO = 8, ORC_MTW_MIN = 9
 };
 
 typedef struct {
@@ -271,6 +271,21 @@ static int orc_eval_cut(const orc_events *ev, int64_t e, const orc_cut *c)
             }
         }
         return 1;
+    }
+    case ORC_MTW_MIN: {
+        /* W transverse mass of the leading selected lepton and the missing
+         * transverse momentum (section 6.1: M_T^W above 50 GeV in the Wt
+         * semileptonic bins): M_T^2 = 2 (pT_l E_T^miss - pT_l . MET) */
+        for (uint32_t a = l0; a < l1; ++a) {
+            if (!orc_lep_sel(ev, a, c->f[0], c->f[1])) continue;
+            double pt = ev->lep_pt[a];
+            double px = pt * cos(ev->lep_phi[a]), py = pt * sin(ev->lep_phi[a]);
+            double mx = ev->met_x[e], my = ev->met_y[e];
+            double met = sqrt(mx * mx + my * my);
+            double mt2 = 2.0 * (pt * met - (px * mx + py * my));
+            return mt2 > c->f[2] * c->f[2];
+        }
+        return 0;
     }
     default:
         return 1; /* RECO is evaluated by the reconstruction itself */

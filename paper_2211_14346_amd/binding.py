@@ -17,7 +17,7 @@ HF_MAX_CUTS = 32
 HF_MAX_CANDS = 12
 HF_NO_SOLUTION = -9999.0
 CUT_KIND = {"LEP_N_OS": 0, "JET_N_MIN": 1, "BTAG_N_MIN": 2, "BTAG_N_EQ": 3, "MET_MIN": 4, "MLL_MIN": 5,
-            "FWD_JET_VETO": 6, "LEP_ISO": 7, "RECO": 8}
+            "FWD_JET_VETO": 6, "LEP_ISO": 7, "RECO": 8, "MTW_MIN": 9}
 PREC = {"fp64": 0, "mixed": 1}
 PAIR = {"BTAG_FILL": 0, "ALL_JETS": 1}
 

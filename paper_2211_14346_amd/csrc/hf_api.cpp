@@ -52,14 +52,14 @@ int check_cuts(const hf_cut_t *h_cuts, int n_cuts, bool *need_phi_e) {
     *need_phi_e = false;
     for (int c = 0; c < n_cuts; ++c) {
         const hf_cut_t &k = h_cuts[c];
-        if (k.kind < HF_CUT_LEP_N_OS || k.kind > HF_CUT_RECO)
+        if (k.kind < HF_CUT_LEP_N_OS || k.kind > HF_CUT_MTW_MIN)
             return fail(HF_ERR_INVAL, "cut %d: unknown kind %d", c, k.kind);
         if (k.reserved != 0) return fail(HF_ERR_INVAL, "cut %d: reserved field must be 0", c);
         if (k.dep_mask >> n_cuts) return fail(HF_ERR_INVAL, "cut %d: dependency on a cut id >= n_cuts", c);
         if (k.dep_mask & (1ull << c)) return fail(HF_ERR_INVAL, "cut %d depends on itself", c);
         for (int q = 0; q < 8; ++q)
             if (!isfinite(k.f[q])) return fail(HF_ERR_INVAL, "cut %d: non-finite parameter f[%d]", c, q);
-        if (k.kind == HF_CUT_MLL_MIN || k.kind == HF_CUT_LEP_ISO) *need_phi_e = true;
+        if (k.kind == HF_CUT_MLL_MIN || k.kind == HF_CUT_LEP_ISO || k.kind == HF_CUT_MTW_MIN) *need_phi_e = true;
     }
     return HF_OK;
 }

@@ -171,6 +171,32 @@ __device__ bool eval_cut(const EvView &ev, int64_t e, const hf_cut_t &c) {
         }
         return true;
     }
+    case HF_CUT_MTW_MIN: {
+        // leading selected lepton; M_T^2 = 2 (pT_l MET - pT_l . MET)
+        const uint32_t l0 = ev.lep_off[e], l1 = ev.lep_off[e + 1];
+        for (uint32_t c0 = l0; c0 < l1; c0 += kChunk) {
+            float pt[kChunk], eta[kChunk], phi[kChunk];
+#pragma unroll
+            for (int u = 0; u < kChunk; ++u) {
+                const bool in = c0 + u < l1;
+                pt[u] = in ? ev.lep_pt[c0 + u] : 0.0f;
+                eta[u] = in ? ev.lep_eta[c0 + u] : 0.0f;
+                phi[u] = in ? ev.lep_phi[c0 + u] : 0.0f;
+            }
+#pragma unroll
+            for (int u = 0; u < kChunk; ++u)
+                if (c0 + u < l1 && pt[u] > c.f[0] && fabsf(eta[u]) < c.f[1]) {
+                    const double dpt = pt[u];
+                    const double px = dpt * cos((double)phi[u]), py = dpt * sin((double)phi[u]);
+                    const double mx = ev.met_x[e], my = ev.met_y[e];
+                    const double met = sqrt(mx * mx + my * my);
+                    const double mt2 = 2.0 * (dpt * met - (px * mx + py * my));
+                    const double t = c.f[2];
+                    return mt2 > t * t;
+                }
+        }
+        return false;
+    }
     default:
         return true;
     }

@@ -14,6 +14,8 @@ Writes
   k_semilep_tchan1M.txt                   duration, counters and HBM traffic of
                                           the single-neutrino kernel (bench's
                                           second leg), with --semilep-hash
+  stream_hlhc50M_kernel_stats.txt         per-kernel durations of the chunked
+                                          stream, with --stream-trace
 FETCH_SIZE and WRITE_SIZE (KiB per dispatch) are scaled into bytes by what
 each reads for a plain device copy of known size (--cal-bytes read and
 written once per copy): factor = copy bytes / (counter KiB * 1024).
@@ -27,9 +29,11 @@ import os
 SEARCH = "k_search_ev<float>"
 SEMILEP = "k_semilep_tchan"
 TRACE_CMD = ("rocprofv3 --kernel-trace --stats -d <dir> -o run --output-format csv -- "
-             "python3 bench.py --profile-only --steps 5 --warmup 1")
+             "python3 bench.py --profile-only --steps 5 --warmup 1 --no-stream")
 PMC_CMD = ("rocprofv3 --pmc <counters> -d <dir> -o run --output-format csv -- "
-           "python3 bench.py --profile-only --steps 2 --warmup 1")
+           "python3 bench.py --profile-only --steps 2 --warmup 1 --no-stream")
+STREAM_TRACE_CMD = ("rocprofv3 --kernel-trace --stats -d <dir> -o run --output-format csv -- "
+                    "python3 bench.py --stream-only --profile-only")
 CAL_CMD = ("rocprofv3 --pmc <FETCH_SIZE|WRITE_SIZE> -d <dir> -o run --output-format csv -- "
            "python3 bench.py --copy-calibration 256")
 
@@ -64,6 +68,7 @@ def copy_factor(d, counter, nbytes):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--trace", required=True)
+    ap.add_argument("--stream-trace", default=None, help="trace of the chunked-stream leg alone")
     ap.add_argument("--pmc", nargs="+", required=True)
     ap.add_argument("--cal-fetch", required=True)
     ap.add_argument("--cal-write", required=True)
@@ -111,6 +116,17 @@ def main():
                   f"search_source_hash: {a.hash}"]
     with open(os.path.join(a.out, "k_search_ttbar1M_v64_counters.txt"), "w") as f:
         f.write("\n".join(lines) + "\n")
+
+    if a.stream_trace:
+        lines = ["# Kernel durations of the chunked stream, workload hlhc50M (1M-event chunks of mixed events "
+                 "from pinned host memory; dileptonic channel 6 cuts + quartic at 64 variations, one-lepton "
+                 "channel 6 cuts + single-neutrino chi^2; 10 chunks after a full warm-up pass)",
+                 f"# command: {STREAM_TRACE_CMD}", "",
+                 f"{'kernel':40s} {'calls':>6s} {'avg_us':>10s} {'min_us':>10s} {'max_us':>10s} {'pct':>7s}"]
+        for name, calls, avg, mn, mx, pct in kernel_stats(a.stream_trace):
+            lines.append(f"{name[:40]:40s} {calls:6d} {avg / 1e3:10.2f} {mn / 1e3:10.2f} {mx / 1e3:10.2f} {pct:7.2f}")
+        with open(os.path.join(a.out, "stream_hlhc50M_kernel_stats.txt"), "w") as f:
+            f.write("\n".join(lines) + "\n")
 
     lf, lw = merged.get((SEMILEP, "FETCH_SIZE")), merged.get((SEMILEP, "WRITE_SIZE"))
     row = [r for r in ks if r[0] == SEMILEP]

@@ -12,6 +12,8 @@ GOLD = os.path.join(os.path.dirname(__file__), "golden", "cut_cases.json")
 CUT_DEFS = {c["name"]: c for c in hfgen.configs.chain_dilepton() + hfgen.configs.chain_tth8()}
 CUT_DEFS["JETS4"] = [c for c in hfgen.configs.chain_tth8() if c["name"] == "JETS4"][0]
 CUT_DEFS["BTAG3"] = [c for c in hfgen.configs.chain_tth8() if c["name"] == "BTAG3"][0]
+CUT_DEFS["MTW50"] = dict([c for c in hfgen.configs.chain_hlhc_single() if c["name"] == "S_MTW50"][0],
+                         name="MTW50")
 
 
 def load():

@@ -1,0 +1,127 @@
+"""GPU parity of the chunked stream (two device slots filled from pinned
+host memory on a copy stream while the compute stream runs the channels):
+every chunk of a mixed HL-LHC-like sample, through the dileptonic channel
+(quartic at 64 variations) and the one-lepton channel (single-neutrino
+chi^2), against the FP64 oracle under the cut order the GPU ran it with;
+counters accumulated over the stream against the oracle's sums."""
+
+import sys
+
+import numpy as np
+import pytest
+
+import hfgen
+
+from .gpu_compare import assert_agree, assert_agree_semilep, compare, compare_semilep
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(*a):
+    print("[gpu]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2211_14346_amd import binding
+    binding.lib()
+    return binding
+
+
+def _setup(n_chunk, n_chunks):
+    from paper_2211_14346_amd.stream import Channel, EventStream, HostChunk
+    cfg = hfgen.config("hlhc50M")
+    samples = [hfgen.stream_chunk(cfg, i, n=n_chunk) for i in range(n_chunks)]
+    chunks = [HostChunk(ev, base) for ev, base in samples]
+    lep_cap = max(c.n_lep for c in chunks)
+    jet_cap = max(c.n_jet for c in chunks) + 3  # ragged: slots larger than any chunk
+    chans = [Channel("dilepton", cfg["chains"]["dilepton"], n_chunk, reco=cfg["reco"]),
+             Channel("single", cfg["chains"]["single"], n_chunk, semilep=cfg["semilep"], topology="TCHAN")]
+    es = EventStream(chans, n_chunk, lep_cap, jet_cap)
+    return cfg, samples, chunks, chans, es
+
+
+def test_stream_chunks_match_oracle(B, orc):
+    cfg, samples, chunks, chans, es = _setup(20000, 3)
+    sums = [np.zeros((ch.n_cuts, 2), dtype=np.uint64) for ch in chans]
+    seen = []
+
+    def check(i, hc, orders):
+        ev, base = samples[i]
+        _say("stream chunk", i, "orders", [list(o) for o in orders])
+        for c, (ch, order) in enumerate(zip(chans, orders)):
+            got = ch.results(hc.n)
+            surv, reached, passed = orc.select(ev, ch.cuts, list(order), index_base=base)
+            assert np.array_equal(got["survive"], surv), (ch.name, i)
+            idx = orc.compact(surv, base)
+            assert np.array_equal(got["idx"], idx), (ch.name, i)
+            if ch.semilep:
+                want = orc.semilep_reco(ev, idx, cfg["semilep"], "TCHAN", index_base=base)
+                st = compare_semilep(got["reco"], want)
+                _say(ch.name, st)
+                assert_agree_semilep(st)
+            else:
+                want = orc.ttbar_reco(ev, idx, cfg["reco"], index_base=base)
+                st = compare(got["reco"], want)
+                _say(ch.name, st)
+                assert_agree(st)
+            # the final compaction keeps the GPU's own decisions (agreement checked above)
+            assert np.array_equal(got["final"], idx[got["reco"]["has_sol"].astype(bool)]), (ch.name, i)
+            r = ch.reco_id
+            reached[r] += np.uint64(idx.size)
+            passed[r] += np.uint64(got["reco"]["has_sol"].sum())
+            sums[c][:, 0] += reached
+            sums[c][:, 1] += passed
+        seen.append(i)
+
+    es.run(chunks, on_chunk=check)
+    assert seen == [0, 1, 2]
+    for c, ch in enumerate(chans):
+        cnt = ch.counters.cpu().numpy().astype(np.uint64)
+        assert np.array_equal(cnt[:, :2], sums[c]), ch.name
+
+
+def test_stream_overlapped_matches_oracle(B, orc):
+    """The same chunks with no host synchronisation between them (copies of
+    one slot overlapping compute on the other).  The measured costs, and so
+    the cut orders, vary from run to run; the orders each chunk ran under are
+    logged on the device, and the counters accumulated over the stream must
+    equal the oracle's under those orders.  The last chunk's results must
+    equal the oracle's."""
+    cfg, samples, chunks, chans, es = _setup(20000, 4)
+    log = []
+    es.run(chunks, order_log=log)
+    torch.cuda.synchronize()
+    assert len(log) == len(chunks)
+    for c, ch in enumerate(chans):
+        want = np.zeros((ch.n_cuts, 2), dtype=np.uint64)
+        for i, (ev, base) in enumerate(samples):
+            order = log[i][c].cpu().numpy()
+            surv, reached, passed = orc.select(ev, ch.cuts, list(order), index_base=base)
+            idx = orc.compact(surv, base)
+            if ch.semilep:
+                rec = orc.semilep_reco(ev, idx, cfg["semilep"], "TCHAN", index_base=base)
+            else:
+                rec = orc.ttbar_reco(ev, idx, cfg["reco"], index_base=base)
+            reached[ch.reco_id] += np.uint64(idx.size)
+            passed[ch.reco_id] += np.uint64(rec["has_sol"].sum())
+            want[:, 0] += reached
+            want[:, 1] += passed
+        got = ch.counters.cpu().numpy().astype(np.uint64)[:, :2]
+        _say(ch.name, "orders", [list(o[c].cpu().numpy()) for o in log])
+        if ch.semilep:
+            assert np.array_equal(got, want), ch.name
+        else:
+            # the dileptonic RECO decision is floating point (>= 99.9 % agreement)
+            assert np.array_equal(np.delete(got, ch.reco_id, 0), np.delete(want, ch.reco_id, 0)), ch.name
+            assert got[ch.reco_id, 0] == want[ch.reco_id, 0]
+            assert abs(int(got[ch.reco_id, 1]) - int(want[ch.reco_id, 1])) <= 1e-3 * want[ch.reco_id, 0]
+        last = ch.results(chunks[-1].n)
+        ev, base = samples[-1]
+        surv, _, _ = orc.select(ev, ch.cuts, list(range(ch.n_cuts)), index_base=base)
+        assert np.array_equal(last["survive"], surv), ch.name
