@@ -25,8 +25,9 @@ import copy
 #   LEP_ISO       f=[lep_pt_min, lep_abs_eta_max, jet_pt_min, jet_abs_eta_max, dr_min]
 #   RECO          marker for the kinematic reconstruction (last cut)
 #   MTW_MIN       f=[lep_pt_min, lep_abs_eta_max, mtw_min]  (W transverse mass of the leading lepton)
+#   USER          a user predicate: "src" holds the body of a C function of one event
 CUT_KINDS = ("LEP_N_OS", "JET_N_MIN", "BTAG_N_MIN", "BTAG_N_EQ", "MET_MIN",
-             "MLL_MIN", "FWD_JET_VETO", "LEP_ISO", "RECO", "MTW_MIN")
+             "MLL_MIN", "FWD_JET_VETO", "LEP_ISO", "RECO", "MTW_MIN", "USER")
 
 
 def _cut(name, kind, f=(), i=(), deps=()):
@@ -146,6 +147,45 @@ def chain_hlhc_single():
         _cut("S_MET30", "MET_MIN", [30.0]),
         _cut("S_MTW50", "MTW_MIN", [20.0, 2.5, 50.0], deps=["S_LEP1"]),
         _cut("S_RECO", "RECO", deps=["S_LEP1", "S_JETS2", "S_BTAG1", "S_MET30", "S_MTW50"]),
+    ]
+
+
+def _user(name, src, deps=()):
+    """A user predicate (section 3: the user's own cut, a boolean function of
+    one event): the body of a C function over the accessors n_lep(),
+    n_jet(), lep_pt(i) ... jet_btag(i), met_x(), met_y()."""
+    return {"name": name, "kind": "USER", "f": [], "i": [], "deps": list(deps), "src": src}
+
+
+# User predicates, some restating built-in cuts (so that the two paths can be
+# checked against each other), some new: a forward jet in the paper's
+# Regions II/III (section 6.1), a scalar pT sum, a leading-lepton cut.
+USER_CUTS = {
+    "U_MET30": "double mx = met_x(), my = met_y(); return mx * mx + my * my > 30.0 * 30.0;",
+    "U_JETS2": ("int n = 0;\nfor (int k = 0; k < n_jet(); ++k)\n"
+                "    if (jet_pt(k) > 25.0f && fabsf(jet_eta(k)) < 2.5f) ++n;\nreturn n >= 2;"),
+    "U_LEP2OS": ("int n = 0; float q = 1.0f;\nfor (int k = 0; k < n_lep(); ++k)\n"
+                 "    if (lep_pt(k) > 20.0f && fabsf(lep_eta(k)) < 2.5f) { ++n; q *= lep_q(k); }\n"
+                 "return n == 2 && q < 0.0f;"),
+    "U_FWDJET": ("for (int k = 0; k < n_jet(); ++k) {\n    float a = fabsf(jet_eta(k));\n"
+                 "    if (jet_pt(k) > 25.0f && a >= 2.5f && a < 4.5f) return 1;\n}\nreturn 0;"),
+    "U_HT150": ("float ht = 0.0f;\nfor (int k = 0; k < n_jet(); ++k)\n"
+                "    if (jet_pt(k) > 25.0f && fabsf(jet_eta(k)) < 2.5f) ht += jet_pt(k);\nreturn ht > 150.0f;"),
+    "U_LEAD40": "return n_lep() > 0 && lep_pt(0) > 40.0f && lep_pt(n_lep()) == 0.0f && jet_eta(-1) == 0.0f;",
+}
+
+
+def chain_user_mix():
+    """Built-in and user cuts mixed (eight cuts, no reconstruction)."""
+    return [
+        _user("U_LEP2OS", USER_CUTS["U_LEP2OS"]),
+        _cut("JETS2", "JET_N_MIN", [25.0, 2.5], [2]),
+        _user("U_HT150", USER_CUTS["U_HT150"]),
+        _cut("MET30", "MET_MIN", [30.0]),
+        _user("U_FWDJET", USER_CUTS["U_FWDJET"]),
+        _user("U_LEAD40", USER_CUTS["U_LEAD40"], deps=["U_LEP2OS"]),
+        _cut("MLL40", "MLL_MIN", [20.0, 2.5, 40.0], deps=["U_LEP2OS"]),
+        _user("U_MET30", USER_CUTS["U_MET30"]),
     ]
 
 

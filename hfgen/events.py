@@ -368,6 +368,10 @@ def _chunk_hlhc(rng, cfg, n):
     (index into HLHC_PROCESSES) only."""
     fr = cfg["fractions"]
     counts = rng.multinomial(n, [fr[p] for p in HLHC_PROCESSES])
+    if n == 0:  # an empty chunk: the dileptonic generator's empty layout
+        part = _chunk(rng, {"kind": "ttbar", "n_extra_max": cfg["n_extra_max"], "bkg_jet_max": cfg["bkg_jet_max"],
+                            "bkg_frac": 0.0}, 0)
+        return part[0], part[1], part[2], None, {"process": np.zeros(0, dtype=np.int8)}
     parts = []
     for code, (proc, m) in enumerate(zip(HLHC_PROCESSES, counts)):
         m = int(m)

@@ -88,7 +88,9 @@ typedef struct hf_events {
  *                       (W transverse mass of the leading selected lepton and
  *                        the missing momentum, M_T^2 = 2 (pT_l MET - pT_l . MET),
  *                        above mtw_min; fails without a selected lepton;
- *                        section 6.1) */
+ *                        section 6.1)
+ *   HF_CUT_USER         a user predicate compiled at run time by
+ *                       hf_chain_compile; i = {index of its source} */
 enum {
     HF_CUT_LEP_N_OS = 0,
     HF_CUT_JET_N_MIN = 1,
@@ -99,7 +101,8 @@ enum {
     HF_CUT_FWD_JET_VETO = 6,
     HF_CUT_LEP_ISO = 7,
     HF_CUT_RECO = 8,
-    HF_CUT_MTW_MIN = 9
+    HF_CUT_MTW_MIN = 9,
+    HF_CUT_USER = 10
 };
 
 /* A cut of the chain.  Its id is its index in the cut table.  Bit j of
@@ -274,6 +277,52 @@ int hf_ttbar_reco_autotune(const hf_events_t *ev, const int32_t *d_idx, const in
  * record them.  Process-wide setting; calls from several threads race.
  * Errors: HF_ERR_INVAL if exactly one of the two is NULL. */
 int hf_reco_timing_events(hipEvent_t start, hipEvent_t stop);
+
+/* ------------------------------------------------ user-defined cuts */
+
+/* A cut chain with user predicates (section 3: the user registers each cut
+ * of the pipeline as a function of one event that returns a boolean).  Each
+ * HF_CUT_USER cut names one source h_user_src[i[0]]: the body of a C function
+ * of one event that returns nonzero when the event passes, written against
+ * these accessors (float values of the event's columns; an index outside
+ * the event's list reads 0):
+ *   n_lep(), n_jet()                      object counts (int)
+ *   lep_pt(i) lep_eta(i) lep_phi(i) lep_e(i) lep_q(i)
+ *   jet_pt(i) jet_eta(i) jet_phi(i) jet_e(i) jet_btag(i)
+ *   met_x(), met_y()
+ * plus the C math functions and local variables, loops and conditionals,
+ * e.g. "int n = 0; for (int k = 0; k < n_jet(); ++k) n += fabsf(jet_eta(k))
+ * >= 2.5f; return n >= 1;".  Arithmetic is compiled without contraction
+ * (-ffp-contract=off).  A predicate must terminate; one that does not hangs
+ * the kernel.
+ *
+ * hf_chain_compile generates the chain kernel with the user predicates
+ * inlined, compiles it for the current device with hipRTC and loads it
+ * (this call allocates: the code object; it is a set-up call, not one to
+ * record into a graph).  h_cuts[n_cuts] may mix built-in kinds and
+ * HF_CUT_USER; n_user sources are given.  *out receives the chain, owned by
+ * the caller (hf_chain_destroy); on failure *out is NULL and the compiler's
+ * messages are in hf_last_error().
+ * Errors: HF_ERR_INVAL for malformed cut tables, a user index outside
+ * [0, n_user), a NULL source or a source that does not compile;
+ * HF_ERR_DEVICE if loading the code fails. */
+typedef struct hf_chain hf_chain_t;
+
+int hf_chain_compile(const hf_cut_t *h_cuts, int n_cuts, const char *const *h_user_src, int n_user,
+                     hf_chain_t **out);
+
+/* hf_select for a compiled chain: the same kernel structure, order,
+ * counters, survive mask and workspace (hf_select_workspace_size(n, n_cuts));
+ * every event column must be present.  Asynchronous, allocates nothing, may
+ * be recorded into a HIP graph.  Errors: those of hf_select. */
+int hf_chain_select(const hf_chain_t *chain, const hf_events_t *ev, const int32_t *d_order, uint8_t *d_survive,
+                    hf_counters_t *d_counters, void *d_ws, size_t ws_bytes, hipStream_t stream);
+
+/* The compiler's messages for the chain ("" if none). */
+const char *hf_chain_log(const hf_chain_t *chain);
+
+/* Releases the chain's code object.  NULL is ignored. */
+void hf_chain_destroy(hf_chain_t *chain);
 
 /* ------------------------------------- single-neutrino reconstruction */
 

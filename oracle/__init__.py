@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libhf_oracle.so")
 SRC_PATH = os.path.join(_HERE, "hf_oracle.c")
 
 KIND = {"LEP_N_OS": 0, "JET_N_MIN": 1, "BTAG_N_MIN": 2, "BTAG_N_EQ": 3, "MET_MIN": 4,
-        "MLL_MIN": 5, "FWD_JET_VETO": 6, "LEP_ISO": 7, "RECO": 8, "MTW_MIN": 9}
+        "MLL_MIN": 5, "FWD_JET_VETO": 6, "LEP_ISO": 7, "RECO": 8, "MTW_MIN": 9, "USER": 10}
 PAIR_MODE = {"BTAG_FILL": 0, "ALL_JETS": 1}
 NOSOL = -9999.0
 
@@ -29,7 +29,7 @@ def build(force=True):
         return LIB_PATH
     tmp = LIB_PATH + ".tmp"
     cmd = ["gcc", "-O2", "-std=c11", "-D_DEFAULT_SOURCE", "-fno-fast-math", "-ffp-contract=off",
-           "-fopenmp", "-fPIC", "-shared", "-Wall", "-o", tmp, SRC_PATH, "-lm"]
+           "-fopenmp", "-fPIC", "-shared", "-Wall", "-I", _HERE, "-o", tmp, SRC_PATH, "-lm"]
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB_PATH)
     return LIB_PATH
@@ -90,6 +90,7 @@ def lib():
         L.orc_gauss.argtypes = [C.c_uint64, C.c_uint64, C.c_uint32, C.c_uint32]
         L.orc_gauss.restype = C.c_double
         L.orc_select.argtypes = [C.POINTER(Events), P, C.c_int, P, P, P, P]
+        L.orc_select_user.argtypes = [C.POINTER(Events), P, C.c_int, P, P, P, P, P]
         L.orc_compact.argtypes = [P, C.c_int64, C.c_int64, P, P]
         L.orc_compact.restype = C.c_int64
         L.orc_reorder.argtypes = [P, P, P, P, C.c_int, P]
@@ -132,6 +133,7 @@ def _cut_array(cuts):
     from hfgen.configs import dep_masks
     deps = dep_masks(cuts)
     arr = (Cut * len(cuts))()
+    u = 0
     for k, c in enumerate(cuts):
         arr[k].kind = KIND[c["kind"]]
         for j, v in enumerate(c["f"]):
@@ -139,8 +141,69 @@ def _cut_array(cuts):
             arr[k].f[j] = float(np.float32(v))
         for j, v in enumerate(c["i"]):
             arr[k].i[j] = int(v)
+        if c["kind"] == "USER":
+            arr[k].i[0] = u  # index of its predicate in the compiled user library
+            u += 1
         arr[k].dep_mask = deps[k]
     return arr
+
+
+# The accessors a user predicate is written against (section 3: a cut is a
+# boolean function of one event): float values of the event's columns, 0
+# for an index outside the event's list.
+_USER_PRELUDE = """#include <math.h>
+#include "orc_events.h"
+static float orc_col(const double *col, uint32_t base, uint32_t n, int i)
+{
+    return (i >= 0 && (uint32_t)i < n) ? (float)col[base + (uint32_t)i] : 0.0f;
+}
+#define n_lep() ((int)nl_)
+#define n_jet() ((int)nj_)
+#define lep_pt(i) orc_col(ev_->lep_pt, l0_, nl_, (i))
+#define lep_eta(i) orc_col(ev_->lep_eta, l0_, nl_, (i))
+#define lep_phi(i) orc_col(ev_->lep_phi, l0_, nl_, (i))
+#define lep_e(i) orc_col(ev_->lep_e, l0_, nl_, (i))
+#define lep_q(i) orc_col(ev_->lep_q, l0_, nl_, (i))
+#define jet_pt(i) orc_col(ev_->jet_pt, j0_, nj_, (i))
+#define jet_eta(i) orc_col(ev_->jet_eta, j0_, nj_, (i))
+#define jet_phi(i) orc_col(ev_->jet_phi, j0_, nj_, (i))
+#define jet_e(i) orc_col(ev_->jet_e, j0_, nj_, (i))
+#define jet_btag(i) orc_col(ev_->jet_btag, j0_, nj_, (i))
+#define met_x() ((float)ev_->met_x[e_])
+#define met_y() ((float)ev_->met_y[e_])
+"""
+
+_user_libs = {}
+
+
+def _user_fns(cuts):
+    """Compiles the USER cuts' predicate bodies with gcc (IEEE single
+    precision, no contraction) into a library of the oracle's own and returns
+    (library, array of function pointers), cached by source."""
+    import hashlib
+    import tempfile
+    srcs = [c["src"] for c in cuts if c["kind"] == "USER"]
+    if not srcs:
+        return None, None
+    key = hashlib.sha256("\0".join(srcs).encode()).hexdigest()[:16]
+    if key not in _user_libs:
+        body = [_USER_PRELUDE]
+        for u, src in enumerate(srcs):
+            body.append(f"int orc_user_cut_{u}(const orc_events *ev_, int64_t e_)\n{{\n"
+                        f"    const uint32_t l0_ = ev_->lep_off[e_], nl_ = ev_->lep_off[e_ + 1] - l0_;\n"
+                        f"    const uint32_t j0_ = ev_->jet_off[e_], nj_ = ev_->jet_off[e_ + 1] - j0_;\n"
+                        f"    (void)nl_;\n    (void)nj_;\n#line 1 \"user_cut_{u}\"\n{src}\n}}\n")
+        d = tempfile.mkdtemp(prefix="orc_user_")
+        c_path, so_path = os.path.join(d, "user.c"), os.path.join(d, "user.so")
+        with open(c_path, "w") as f:
+            f.write("\n".join(body))
+        subprocess.run(["gcc", "-O2", "-std=c11", "-fno-fast-math", "-ffp-contract=off", "-fPIC", "-shared",
+                        "-Werror=return-type", "-I", _HERE, "-o", so_path, c_path, "-lm"], check=True)
+        ul = C.CDLL(so_path)
+        fns = (C.c_void_p * len(srcs))(*[C.cast(getattr(ul, f"orc_user_cut_{u}"), C.c_void_p).value
+                                          for u in range(len(srcs))])
+        _user_libs[key] = (ul, fns)
+    return _user_libs[key]
 
 
 def select(ev, cuts, order, index_base=0):
@@ -152,8 +215,9 @@ def select(ev, cuts, order, index_base=0):
     passed = np.zeros(len(cuts), dtype=np.uint64)
     order = np.ascontiguousarray(order, dtype=np.int32)
     arr = _cut_array(cuts)
-    lib().orc_select(C.byref(h.s), C.cast(arr, C.c_void_p), len(cuts), _ptr(order), _ptr(surv),
-                     _ptr(reached), _ptr(passed))
+    _, fns = _user_fns(cuts)
+    lib().orc_select_user(C.byref(h.s), C.cast(arr, C.c_void_p), len(cuts), _ptr(order),
+                          None if fns is None else C.cast(fns, C.c_void_p), _ptr(surv), _ptr(reached), _ptr(passed))
     return surv, reached, passed
 
 

@@ -45,20 +45,12 @@
 
 /* ------------------------------------------------------------------ types */
 
-typedef struct {
-    int64_t n;
-    int64_t index_base;
-    const uint32_t *lep_off, *jet_off;
-    const double *lep_pt, *lep_eta, *lep_phi, *lep_e, *lep_q;
-    const double *jet_pt, *jet_eta, *jet_phi, *jet_e, *jet_btag;
-    const double *met_x, *met_y;
-    const int32_t *n_var; /* per event, or NULL */
-} orc_events;
+#include "orc_events.h"
 
 enum {
     ORC_LEP_N_OS = 0, ORC_JET_N_MIN = 1, ORC_BTAG_N_MIN = 2, ORC_BTAG_N_EQ = 3,
     ORC_MET_MIN = 4, ORC_MLL_MIN = 5, ORC_FWD_JET_VETO = 6, ORC_LEP_ISO = 7,
-    ORC_RECO = 8, ORC_MTW_MIN = 9
+    ORC_RECO = 8, ORC_MTW_MIN = 9, ORC_USER = 10
 };
 
 typedef struct {
@@ -205,8 +197,10 @@ static int orc_jet_sel(const orc_events *ev, uint32_t k, double ptmin, double et
     return ev->jet_pt[k] > ptmin && fabs(ev->jet_eta[k]) < etamax;
 }
 
-static int orc_eval_cut(const orc_events *ev, int64_t e, const orc_cut *c)
+static int orc_eval_cut(const orc_events *ev, int64_t e, const orc_cut *c, const orc_user_fn *user)
 {
+    if (c->kind == ORC_USER) /* a user predicate (section 3: a cut is a boolean function of one event) */
+        return user && user[c->i[0]] ? user[c->i[0]](ev, e) != 0 : 0;
     uint32_t l0 = ev->lep_off[e], l1 = ev->lep_off[e + 1];
     uint32_t j0 = ev->jet_off[e], j1 = ev->jet_off[e + 1];
     switch (c->kind) {
@@ -296,8 +290,8 @@ static int orc_eval_cut(const orc_events *ev, int64_t e, const orc_cut *c)
  * position k: reached counts events that survived positions 0..k-1, passed
  * counts those that also survive position k (indexed by cut id, added to
  * the caller's totals).  survive[e] is the AND over all non-RECO cuts.    */
-int orc_select(const orc_events *ev, const orc_cut *cuts, int n_cuts, const int32_t *order,
-               uint8_t *survive, uint64_t *reached, uint64_t *passed)
+int orc_select_user(const orc_events *ev, const orc_cut *cuts, int n_cuts, const int32_t *order,
+                    const orc_user_fn *user, uint8_t *survive, uint64_t *reached, uint64_t *passed)
 {
     for (int64_t e = 0; e < ev->n; ++e) {
         int alive = 1;
@@ -305,12 +299,18 @@ int orc_select(const orc_events *ev, const orc_cut *cuts, int n_cuts, const int3
             int c = order[k];
             if (cuts[c].kind == ORC_RECO) continue;
             reached[c] += 1;
-            alive = orc_eval_cut(ev, e, &cuts[c]);
+            alive = orc_eval_cut(ev, e, &cuts[c], user);
             passed[c] += alive ? 1 : 0;
         }
         survive[e] = (uint8_t)alive;
     }
     return 0;
+}
+
+int orc_select(const orc_events *ev, const orc_cut *cuts, int n_cuts, const int32_t *order,
+               uint8_t *survive, uint64_t *reached, uint64_t *passed)
+{
+    return orc_select_user(ev, cuts, n_cuts, order, NULL, survive, reached, passed);
 }
 
 /* Survivors in ascending order: idx[s] = map ? map[e] : index_base + e. */

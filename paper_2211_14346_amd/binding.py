@@ -17,7 +17,7 @@ HF_MAX_CUTS = 32
 HF_MAX_CANDS = 12
 HF_NO_SOLUTION = -9999.0
 CUT_KIND = {"LEP_N_OS": 0, "JET_N_MIN": 1, "BTAG_N_MIN": 2, "BTAG_N_EQ": 3, "MET_MIN": 4, "MLL_MIN": 5,
-            "FWD_JET_VETO": 6, "LEP_ISO": 7, "RECO": 8, "MTW_MIN": 9}
+            "FWD_JET_VETO": 6, "LEP_ISO": 7, "RECO": 8, "MTW_MIN": 9, "USER": 10}
 PREC = {"fp64": 0, "mixed": 1}
 PAIR = {"BTAG_FILL": 0, "ALL_JETS": 1}
 
@@ -102,10 +102,17 @@ def lib():
         L.hf_reco_timing_events.restype = C.c_int
         L.hf_philox_blocks.argtypes = [P, C.c_uint64, P, C.c_int64, P]
         L.hf_gauss_draws.argtypes = [C.c_uint64, P, P, P, C.c_int64, C.c_int, P, P]
+        L.hf_chain_compile.argtypes = [P, C.c_int, P, C.c_int, C.POINTER(C.c_void_p)]
+        L.hf_chain_select.argtypes = [P, C.POINTER(Events), P, P, P, P, C.c_size_t, P]
+        L.hf_chain_log.argtypes = [P]
+        L.hf_chain_log.restype = C.c_char_p
+        L.hf_chain_destroy.argtypes = [P]
+        L.hf_chain_destroy.restype = None
         L.hf_semilep_reco.argtypes = [C.POINTER(Events), P, P, C.c_int64, C.POINTER(SemilepParams),
                                       C.POINTER(SemilepOut), P, P]
         for f in ("hf_select", "hf_compact", "hf_ttbar_reco", "hf_ttbar_reco_autotune", "hf_reorder_stats",
-                  "hf_reorder_device", "hf_philox_blocks", "hf_gauss_draws", "hf_semilep_reco"):
+                  "hf_reorder_device", "hf_philox_blocks", "hf_gauss_draws", "hf_semilep_reco", "hf_chain_compile",
+                  "hf_chain_select"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -129,9 +136,12 @@ def _stream(stream):
 # ----------------------------------------------------------------- structures
 
 def cut_table(cuts):
-    """hfgen-style cut descriptions -> (ctypes array of Cut, n)."""
+    """hfgen-style cut descriptions -> ctypes array of Cut.  A USER cut
+    carries its predicate body in "src"; its i[0] becomes the index of that
+    source in user_sources(cuts)."""
     names = {c["name"]: k for k, c in enumerate(cuts)}
     arr = (Cut * len(cuts))()
+    u = 0
     for k, c in enumerate(cuts):
         arr[k].kind = CUT_KIND[c["kind"]]
         arr[k].reserved = 0
@@ -143,7 +153,44 @@ def cut_table(cuts):
             arr[k].f[j] = float(v)
         for j, v in enumerate(c.get("i", [])):
             arr[k].i[j] = int(v)
+        if c["kind"] == "USER":
+            arr[k].i[0] = u
+            u += 1
     return arr
+
+
+def user_sources(cuts):
+    """Predicate bodies of the USER cuts, in cut-table order."""
+    return [c["src"] for c in cuts if c["kind"] == "USER"]
+
+
+class CompiledChain:
+    """A cut chain with user predicates compiled for the device
+    (hf_chain_compile); released with the object."""
+
+    def __init__(self, cuts):
+        self.cut_arr = cut_table(cuts)
+        self.n_cuts = len(cuts)
+        srcs = [s.encode() for s in user_sources(cuts)]
+        self._srcs = (C.c_char_p * max(1, len(srcs)))(*srcs)
+        self.h = C.c_void_p()
+        _check(lib().hf_chain_compile(C.cast(self.cut_arr, C.c_void_p), self.n_cuts, C.cast(self._srcs, C.c_void_p),
+                                      len(srcs), C.byref(self.h)), "hf_chain_compile")
+
+    @property
+    def log(self):
+        return lib().hf_chain_log(self.h).decode()
+
+    def __del__(self):
+        if getattr(self, "h", None) and self.h.value and _lib is not None:
+            _lib.hf_chain_destroy(self.h)
+            self.h = C.c_void_p()
+
+
+def chain_select(chain, dev, order, survive, counters, ws, stream=None):
+    rc = lib().hf_chain_select(chain.h, dev.ptr, _p(order), _p(survive), _p(counters), _p(ws),
+                               ws.numel() * ws.element_size(), _stream(stream))
+    _check(rc, "hf_chain_select")
 
 
 SCHED = {"auto": 0, "event": 1, "worklist": 2}

@@ -23,6 +23,8 @@ class Chain:
         self.cuts = cuts
         self.n_cuts = len(cuts)
         self.cut_arr = B.cut_table(cuts)
+        # user predicates (USER cuts) need the chain kernel compiled at run time
+        self.compiled = B.CompiledChain(cuts) if any(c["kind"] == "USER" for c in cuts) else None
         kinds = [c["kind"] for c in cuts]
         self.reco_id = kinds.index("RECO") if "RECO" in kinds else -1
         self.dev = B.DeviceEvents(ev, device=device, index_base=index_base)
@@ -58,7 +60,11 @@ class Chain:
 
     # -------------------------------------------------------------- stages
     def run_select(self, stream=None):
-        B.select(self.dev, self.cut_arr, self.n_cuts, self.order, self.survive, self.counters, self.ws_sel, stream)
+        if self.compiled is not None:
+            B.chain_select(self.compiled, self.dev, self.order, self.survive, self.counters, self.ws_sel, stream)
+        else:
+            B.select(self.dev, self.cut_arr, self.n_cuts, self.order, self.survive, self.counters, self.ws_sel,
+                     stream)
 
     def run_compact(self, stream=None):
         B.compact(self.survive, self.n, self.idx, self.count, self.ws_cmp, index_base=self.dev.index_base,

@@ -9,10 +9,12 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <vector>
 
 #include "../../include/hf.h"
 #include "hf_internal.hpp"
 #include "hf_reco_math.hpp"
+#include "hf_rtc.hpp"
 
 namespace {
 
@@ -52,7 +54,7 @@ int check_cuts(const hf_cut_t *h_cuts, int n_cuts, bool *need_phi_e) {
     *need_phi_e = false;
     for (int c = 0; c < n_cuts; ++c) {
         const hf_cut_t &k = h_cuts[c];
-        if (k.kind < HF_CUT_LEP_N_OS || k.kind > HF_CUT_MTW_MIN)
+        if (k.kind < HF_CUT_LEP_N_OS || k.kind > HF_CUT_USER)
             return fail(HF_ERR_INVAL, "cut %d: unknown kind %d", c, k.kind);
         if (k.reserved != 0) return fail(HF_ERR_INVAL, "cut %d: reserved field must be 0", c);
         if (k.dep_mask >> n_cuts) return fail(HF_ERR_INVAL, "cut %d: dependency on a cut id >= n_cuts", c);
@@ -138,6 +140,10 @@ int hf_select(const hf_events_t *ev, const hf_cut_t *h_cuts, int n_cuts, const i
     bool need_pe = false;
     int rc = check_cuts(h_cuts, n_cuts, &need_pe);
     if (rc != HF_OK) return rc;
+    for (int c = 0; c < n_cuts; ++c)
+        if (h_cuts[c].kind == HF_CUT_USER)
+            return fail(HF_ERR_INVAL, "hf_select: cut %d is a user predicate; compile the chain with "
+                                      "hf_chain_compile and run it with hf_chain_select", c);
     const char *why = nullptr;
     if (!events_ok(ev, need_pe, &why)) return fail(HF_ERR_INVAL, "hf_select: %s", why);
     if (!d_order || !d_counters) return fail(HF_ERR_INVAL, "hf_select: order or counters is NULL");
@@ -288,6 +294,80 @@ int hf_ttbar_reco_autotune(const hf_events_t *ev, const int32_t *d_idx, const in
     }
     store_schedule(tune_key(ev, h_params, capacity), best, ms);
     return HF_OK;
+}
+
+int hf_chain_compile(const hf_cut_t *h_cuts, int n_cuts, const char *const *h_user_src, int n_user,
+                     hf_chain_t **out) {
+    if (!out) return fail(HF_ERR_INVAL, "hf_chain_compile: out is NULL");
+    *out = nullptr;
+    bool need_pe = false;
+    int rc = check_cuts(h_cuts, n_cuts, &need_pe);
+    if (rc != HF_OK) return rc;
+    if (n_user < 0 || n_user > HF_MAX_CUTS)
+        return fail(HF_ERR_INVAL, "hf_chain_compile: n_user %d outside [0, %d]", n_user, HF_MAX_CUTS);
+    if (n_user > 0 && !h_user_src) return fail(HF_ERR_INVAL, "hf_chain_compile: user sources are NULL");
+    std::vector<std::string> src;
+    for (int u = 0; u < n_user; ++u) {
+        if (!h_user_src[u]) return fail(HF_ERR_INVAL, "hf_chain_compile: user source %d is NULL", u);
+        src.emplace_back(h_user_src[u]);
+    }
+    for (int c = 0; c < n_cuts; ++c)
+        if (h_cuts[c].kind == HF_CUT_USER && (h_cuts[c].i[0] < 0 || h_cuts[c].i[0] >= n_user))
+            return fail(HF_ERR_INVAL, "hf_chain_compile: cut %d names user source %d outside [0, %d)", c,
+                        h_cuts[c].i[0], n_user);
+    std::vector<char> code;
+    std::string lowered, log;
+    if (!hf::rtc_compile(hf::chain_source(src), code, lowered, log)) {
+        g_err = "hf_chain_compile: the user predicates do not compile:\n" + log;
+        return HF_ERR_INVAL;
+    }
+    hf_chain *ch = new hf_chain;
+    ch->cuts.assign(h_cuts, h_cuts + n_cuts);
+    ch->n_user = n_user;
+    ch->log = log;
+    hipError_t e = hipModuleLoadData(&ch->module, code.data());
+    if (e == hipSuccess) e = hipModuleGetFunction(&ch->fn, ch->module, lowered.c_str());
+    if (e != hipSuccess) {
+        if (ch->module) (void)hipModuleUnload(ch->module);
+        delete ch;
+        return device_fail("hf_chain_compile: loading the chain kernel", e);
+    }
+    *out = ch;
+    return HF_OK;
+}
+
+int hf_chain_select(const hf_chain_t *ch, const hf_events_t *ev, const int32_t *d_order, uint8_t *d_survive,
+                    hf_counters_t *d_counters, void *d_ws, size_t ws_bytes, hipStream_t stream) {
+    if (!ch || !ch->fn) return fail(HF_ERR_INVAL, "hf_chain_select: chain is NULL");
+    const char *why = nullptr;
+    if (!events_ok(ev, true, &why)) return fail(HF_ERR_INVAL, "hf_chain_select: %s", why);
+    if (!d_order || !d_counters) return fail(HF_ERR_INVAL, "hf_chain_select: order or counters is NULL");
+    if (ev->n > 0 && !d_survive) return fail(HF_ERR_INVAL, "hf_chain_select: survive is NULL");
+    const int n_cuts = (int)ch->cuts.size();
+    const size_t need = hf::select_ws_bytes(ev->n, n_cuts);
+    if (!d_ws || ws_bytes < need)
+        return fail(HF_ERR_CAPACITY, "hf_chain_select: workspace %zu bytes < %zu required", ws_bytes, need);
+    hf::CutTable ct;
+    memset(&ct, 0, sizeof ct);
+    for (int c = 0; c < n_cuts; ++c) ct.c[c] = ch->cuts[c];
+    ct.n = n_cuts;
+    hf::EvView v = hf::make_view(*ev);
+    const int grid = hf::select_grid(ev->n);
+    uint64_t *partial = static_cast<uint64_t *>(d_ws);
+    void *args[] = {&v, &ct, &d_order, &d_survive, &partial};
+    hipError_t e = hipModuleLaunchKernel(ch->fn, grid, 1, 1, hf::kChainBlock, 1, 1, 0, stream, args, nullptr);
+    if (e != hipSuccess) return device_fail("hf_chain_select launch", e);
+    e = hf::launch_select_reduce(partial, grid, n_cuts, d_counters, stream);
+    if (e != hipSuccess) return device_fail("hf_chain_select reduce", e);
+    return HF_OK;
+}
+
+const char *hf_chain_log(const hf_chain_t *ch) { return ch ? ch->log.c_str() : ""; }
+
+void hf_chain_destroy(hf_chain_t *ch) {
+    if (!ch) return;
+    if (ch->module) (void)hipModuleUnload(ch->module);
+    delete ch;
 }
 
 int hf_semilep_reco(const hf_events_t *ev, const int32_t *d_idx, const int64_t *d_count, int64_t capacity,

@@ -106,6 +106,8 @@ class Channel:
         self.cuts = cuts
         self.n_cuts = len(cuts)
         self.cut_arr = B.cut_table(cuts)
+        # user predicates (USER cuts) need the chain kernel compiled at run time
+        self.compiled = B.CompiledChain(cuts) if any(c["kind"] == "USER" for c in cuts) else None
         kinds = [c["kind"] for c in cuts]
         self.reco_id = kinds.index("RECO") if "RECO" in kinds else -1
         cap = max(1, int(capacity))
@@ -134,7 +136,10 @@ class Channel:
         """select -> compact -> reconstruction -> compact -> reorder on the
         chunk in `slot`, queued on `stream`."""
         n = slot.n
-        B.select(slot, self.cut_arr, self.n_cuts, self.order, self.survive, self.counters, self.ws_sel, stream)
+        if self.compiled is not None:
+            B.chain_select(self.compiled, slot, self.order, self.survive, self.counters, self.ws_sel, stream)
+        else:
+            B.select(slot, self.cut_arr, self.n_cuts, self.order, self.survive, self.counters, self.ws_sel, stream)
         B.compact(self.survive, n, self.idx, self.count, self.ws_cmp, index_base=slot.index_base, stream=stream)
         if self.semilep:
             B.semilep_reco(slot, self.idx, self.count, self.capacity, self.params, self.out, self.counters, stream)

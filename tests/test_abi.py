@@ -168,3 +168,34 @@ def test_semilep_validation(B):
     bad.chi2 = None
     assert call(p, o=bad) == -1 and b"NULL" in L.hf_last_error()
     assert call(p, ev=B.Events(n=10, index_base=0)) == -1
+
+
+def test_user_chain_validation(B):
+    L = B.lib()
+    user = [{"name": "U", "kind": "USER", "f": [], "i": [], "deps": [], "src": "return n_jet() >= 2;"}]
+    arr = B.cut_table(user)
+    srcs = (C.c_char_p * 1)(b"return n_jet() >= 2;")
+    h = C.c_void_p()
+    assert L.hf_chain_compile(C.cast(arr, C.c_void_p), 1, C.cast(srcs, C.c_void_p), 1, None) == -1
+    assert L.hf_chain_compile(C.cast(arr, C.c_void_p), 1, None, 1, C.byref(h)) == -1
+    assert L.hf_chain_compile(C.cast(arr, C.c_void_p), 1, C.cast(srcs, C.c_void_p), 0, C.byref(h)) == -1
+    assert b"user source" in L.hf_last_error() and not h.value
+    bad = (C.c_char_p * 1)(b"return n_jet( > 2;")
+    assert L.hf_chain_compile(C.cast(arr, C.c_void_p), 1, C.cast(bad, C.c_void_p), 1, C.byref(h)) == -1
+    assert b"do not compile" in L.hf_last_error() and b"error" in L.hf_last_error() and not h.value
+    noret = (C.c_char_p * 1)(b"int x = n_jet(); (void)x;")
+    assert L.hf_chain_compile(C.cast(arr, C.c_void_p), 1, C.cast(noret, C.c_void_p), 1, C.byref(h)) == -1
+    # a valid source compiles here; loading it needs a device (HF_ERR_DEVICE without one)
+    rc = L.hf_chain_compile(C.cast(arr, C.c_void_p), 1, C.cast(srcs, C.c_void_p), 1, C.byref(h))
+    assert rc in (0, -3), L.hf_last_error()
+    if rc == 0:
+        L.hf_chain_destroy(h)
+    else:
+        assert not h.value
+    L.hf_chain_destroy(None)
+    # the library's own chain kernel refuses user cuts
+    dummy = C.c_void_p(16)
+    ev = B.Events(n=10, index_base=0)
+    assert L.hf_select(C.byref(ev), C.cast(arr, C.c_void_p), 1, dummy, dummy, dummy, dummy, 1 << 20, None) == -1
+    assert b"hf_chain_compile" in L.hf_last_error()
+    assert L.hf_chain_select(None, C.byref(ev), dummy, dummy, dummy, dummy, 1 << 20, None) == -1
