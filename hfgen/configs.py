@@ -67,6 +67,17 @@ SEMILEP_DEFAULTS = {
     "lep_pt_min": 20.0, "lep_eta_max": 2.5, "jet_pt_min": 25.0, "jet_eta_max": 2.5, "max_cands": 12,
 }
 
+# Dileptonic chi^2 fit with a MET split (section 6.2): the masses and widths
+# of Eq. (chi2); the split grid (offsets from the even split within
+# +-half_range GeV, n_grid points per axis, n_refine 5x5 refinements at a
+# quarter of the previous step) is a reading.
+CHI2_DEFAULTS = {
+    "m_t": 172.5, "m_w": 80.4, "sigma_t": 11.5, "sigma_w": 7.5,
+    "half_range": 200.0, "n_grid": 17, "n_refine": 2,
+    "lep_pt_min": 20.0, "lep_eta_max": 2.5, "jet_pt_min": 25.0, "jet_eta_max": 2.5, "btag_min": 0.5,
+    "pair_mode": "BTAG_FILL", "max_cands": 12,
+}
+
 RECO_DEFAULTS = {
     "m_t": 172.5, "m_w": 80.4, "lambda_pt": 100.0,
     "jet_a": 1.0, "jet_c": 0.05, "lep_sigma": 0.02, "met_sigma": 10.0,
@@ -209,6 +220,7 @@ def config(name):
     reco["seed"] = c["seed"]
     c["reco"] = reco
     c["semilep"] = dict(SEMILEP_DEFAULTS)
+    c["chi2"] = dict(CHI2_DEFAULTS)
     if c["chain"] == "hlhc":
         c["chains"] = {"dilepton": chain_hlhc_dilepton(), "single": chain_hlhc_single()}
         c["cuts"] = c["chains"]["dilepton"] + c["chains"]["single"]

@@ -76,6 +76,17 @@ class SemilepOut(C.Structure):
                                           "m_tl", "m_wl", "m_th", "m_wh", "chi2")]
 
 
+class Chi2Params(C.Structure):
+    _fields_ = [(k, C.c_double) for k in ("m_t", "m_w", "sigma_t", "sigma_w", "half_range", "lep_pt_min",
+                                          "lep_eta_max", "jet_pt_min", "jet_eta_max", "btag_min")] + \
+               [(k, C.c_int32) for k in ("pair_mode", "max_cands", "n_grid", "n_refine")]
+
+
+class Chi2Out(C.Structure):
+    _fields_ = [(k, C.c_void_p) for k in ("has_sol", "root_nu", "root_nubar", "best_i", "best_j", "nu", "nubar",
+                                          "m_t", "m_tbar", "m_wp", "m_wm", "chi2", "split")]
+
+
 _lib = None
 
 
@@ -101,6 +112,9 @@ def lib():
                                      C.POINTER(RecoOut), C.c_int]
         L.orc_ttbar_reco.restype = C.c_int64
         L.orc_nu_pz.argtypes = [P, C.c_double, C.c_double, C.c_double, P, P]
+        L.orc_dilep_chi2_reco.argtypes = [C.POINTER(Events), P, C.c_int64, C.POINTER(Chi2Params),
+                                          C.POINTER(Chi2Out), C.c_int]
+        L.orc_dilep_chi2_reco.restype = C.c_int64
         L.orc_semilep_reco.argtypes = [C.POINTER(Events), P, C.c_int64, C.POINTER(SemilepParams),
                                        C.POINTER(SemilepOut), C.c_int]
         L.orc_semilep_reco.restype = C.c_int64
@@ -342,6 +356,33 @@ def semilep_reco(ev, idx, sl, topology="TCHAN", index_base=0, n_threads=0, fp64=
     so = SemilepOut(**{k: _ptr(v) for k, v in o.items()})
     prm = semilep_params(sl, topology)
     npass = lib().orc_semilep_reco(C.byref(h.s), _ptr(idx), S, C.byref(prm), C.byref(so), int(n_threads))
+    res = {k: v[:S].copy() for k, v in o.items()}
+    res["n_pass"] = int(npass)
+    return res
+
+
+def chi2_params(cp):
+    f32 = lambda k: float(np.float32(cp[k]))
+    return Chi2Params(m_t=cp["m_t"], m_w=cp["m_w"], sigma_t=cp["sigma_t"], sigma_w=cp["sigma_w"],
+                      half_range=cp["half_range"], lep_pt_min=f32("lep_pt_min"), lep_eta_max=f32("lep_eta_max"),
+                      jet_pt_min=f32("jet_pt_min"), jet_eta_max=f32("jet_eta_max"), btag_min=f32("btag_min"),
+                      pair_mode=PAIR_MODE[cp["pair_mode"]], max_cands=int(cp["max_cands"]),
+                      n_grid=int(cp["n_grid"]), n_refine=int(cp["n_refine"]))
+
+
+def dilep_chi2_reco(ev, idx, cp, index_base=0, n_threads=0, fp64=False):
+    """Dileptonic chi^2 fit with a MET split (section 6.2) of events idx."""
+    h = _EventsHolder(ev, index_base, fp64=fp64)
+    idx = np.ascontiguousarray(idx, dtype=np.int32)
+    S = idx.size
+    m = max(S, 1)
+    o = {"has_sol": np.zeros(m, np.uint8), "root_nu": np.zeros(m, np.int8), "root_nubar": np.zeros(m, np.int8),
+         "best_i": np.zeros(m, np.int16), "best_j": np.zeros(m, np.int16), "nu": np.zeros((m, 3)),
+         "nubar": np.zeros((m, 3)), "m_t": np.zeros(m), "m_tbar": np.zeros(m), "m_wp": np.zeros(m),
+         "m_wm": np.zeros(m), "chi2": np.zeros(m), "split": np.zeros((m, 2))}
+    co = Chi2Out(**{k: _ptr(v) for k, v in o.items()})
+    prm = chi2_params(cp)
+    npass = lib().orc_dilep_chi2_reco(C.byref(h.s), _ptr(idx), S, C.byref(prm), C.byref(co), int(n_threads))
     res = {k: v[:S].copy() for k, v in o.items()}
     res["n_pass"] = int(npass)
     return res

@@ -1117,3 +1117,145 @@ int64_t orc_semilep_reco(const orc_events *ev, const int32_t *idx, int64_t S, co
     }
     return npass;
 }
+
+/* -------------------------------- dileptonic chi^2 fit with a MET split
+ * Section 6.2: for the dileptonic final states the missing transverse
+ * momentum is split between the two neutrinos and each neutrino's p_z then
+ * follows from the mass constraints; the choice minimises Eq. (chi2) with
+ * two tops (b l+ nu, bbar l- nubar) and two W (l+ nu, l- nubar).
+ * Readings: the split is nu_T = MET/2 + (u, v), nubar_T = MET/2 - (u, v);
+ * each p_z is the single-neutrino solution of orc_nu_pz (both roots, or the
+ * real part); the minimum is searched on a square grid of (u, v) with
+ * n_grid points per axis over [-half_range, half_range], then refined
+ * n_refine times on a 5 x 5 grid centred on the best point so far with a
+ * quarter of the previous step.  At every grid point every ordered pairing
+ * of b candidates (i with l+, j with l-, i != j; candidates as in
+ * orc_stage) and every pair of p_z candidates is scored; the first minimum
+ * in the order (level, point, i, j, root of nu, root of nubar) is kept.   */
+
+typedef struct {
+    double m_t, m_w, sigma_t, sigma_w, half_range;
+    double lep_pt_min, lep_eta_max, jet_pt_min, jet_eta_max, btag_min;
+    int32_t pair_mode, max_cands, n_grid, n_refine;
+} orc_chi2_params;
+
+typedef struct {
+    uint8_t *has_sol;
+    int8_t *root_nu, *root_nubar;
+    int16_t *best_i, *best_j;
+    double *nu, *nubar; /* [S][3] */
+    double *m_t, *m_tbar, *m_wp, *m_wm, *chi2, *split; /* split: [S][2] = (u, v) */
+} orc_chi2_out;
+
+typedef struct {
+    double chi2, u, v;
+    int i, j, r1, r2, have;
+} orc_chi2_best;
+
+/* chi^2 of every pairing and root pair at one split point; keeps the first
+ * minimum in (i, j, r1, r2) order into *b when it beats b->chi2 strictly. */
+static void orc_chi2_point(const orc_staged *st, double mx, double my, double u, double v,
+                           const orc_chi2_params *p, orc_chi2_best *b)
+{
+    double n1x = 0.5 * mx + u, n1y = 0.5 * my + v;
+    double n2x = 0.5 * mx - u, n2y = 0.5 * my - v;
+    double lp[4] = {st->lp.e, st->lp.x, st->lp.y, st->lp.z};
+    double lm[4] = {st->lm.e, st->lm.x, st->lm.y, st->lm.z};
+    double pz1[2], pz2[2];
+    int k1[2], k2[2];
+    int n1 = orc_nu_pz(lp, n1x, n1y, p->m_w, pz1, k1);
+    int n2 = orc_nu_pz(lm, n2x, n2y, p->m_w, pz2, k2);
+    for (int i = 0; i < st->nc; ++i)
+        for (int j = 0; j < st->nc; ++j) {
+            if (i == j) continue;
+            for (int r1 = 0; r1 < n1; ++r1)
+                for (int r2 = 0; r2 < n2; ++r2) {
+                    vec4 nu = {sqrt(n1x * n1x + n1y * n1y + pz1[r1] * pz1[r1]), n1x, n1y, pz1[r1]};
+                    vec4 nb = {sqrt(n2x * n2x + n2y * n2y + pz2[r2] * pz2[r2]), n2x, n2y, pz2[r2]};
+                    vec4 wp = orc_add(st->lp, nu), wm = orc_add(st->lm, nb);
+                    double mt1 = orc_mass(orc_add(st->cv[i], wp));
+                    double mt2 = orc_mass(orc_add(st->cv[j], wm));
+                    double chi2 = orc_sq(mt1 - p->m_t) / orc_sq(p->sigma_t) + orc_sq(orc_mass(wp) - p->m_w) /
+                                  orc_sq(p->sigma_w) + orc_sq(mt2 - p->m_t) / orc_sq(p->sigma_t) +
+                                  orc_sq(orc_mass(wm) - p->m_w) / orc_sq(p->sigma_w);
+                    if (!b->have || chi2 < b->chi2) {
+                        b->have = 1; b->chi2 = chi2; b->u = u; b->v = v;
+                        b->i = i; b->j = j; b->r1 = r1; b->r2 = r2;
+                    }
+                }
+        }
+}
+
+int64_t orc_dilep_chi2_reco(const orc_events *ev, const int32_t *idx, int64_t S, const orc_chi2_params *p,
+                            const orc_chi2_out *out, int n_threads)
+{
+    orc_reco_params rp;
+    memset(&rp, 0, sizeof rp);
+    rp.lep_pt_min = p->lep_pt_min; rp.lep_eta_max = p->lep_eta_max;
+    rp.jet_pt_min = p->jet_pt_min; rp.jet_eta_max = p->jet_eta_max; rp.btag_min = p->btag_min;
+    rp.pair_mode = p->pair_mode; rp.max_cands = p->max_cands;
+    int64_t npass = 0;
+#ifdef _OPENMP
+    if (n_threads > 0) omp_set_num_threads(n_threads);
+#pragma omp parallel for schedule(dynamic, 16) reduction(+ : npass)
+#endif
+    for (int64_t s = 0; s < S; ++s) {
+        int64_t e = (int64_t)idx[s] - ev->index_base;
+        orc_staged st;
+        memset(&st, 0, sizeof st);
+        if (e >= 0 && e < ev->n) st = orc_stage(ev, e, &rp);
+        orc_chi2_best b;
+        memset(&b, 0, sizeof b);
+        double mx = 0.0, my = 0.0;
+        if (st.ok) {
+            mx = ev->met_x[e];
+            my = ev->met_y[e];
+            /* coarse grid, then the refinements around the best point so far */
+            double step = 2.0 * p->half_range / (double)(p->n_grid - 1);
+            for (int a = 0; a < p->n_grid; ++a)
+                for (int c = 0; c < p->n_grid; ++c)
+                    orc_chi2_point(&st, mx, my, -p->half_range + step * a, -p->half_range + step * c, p, &b);
+            for (int level = 0; level < p->n_refine && b.have; ++level) {
+                step *= 0.25;
+                double cu = b.u, cv = b.v;
+                for (int a = -2; a <= 2; ++a)
+                    for (int c = -2; c <= 2; ++c)
+                        orc_chi2_point(&st, mx, my, cu + step * a, cv + step * c, p, &b);
+            }
+        }
+        out->has_sol[s] = (uint8_t)b.have;
+        if (!b.have) {
+            out->root_nu[s] = out->root_nubar[s] = -1;
+            out->best_i[s] = out->best_j[s] = -1;
+            for (int k = 0; k < 3; ++k) out->nu[3 * s + k] = out->nubar[3 * s + k] = ORC_NOSOL;
+            out->m_t[s] = out->m_tbar[s] = out->m_wp[s] = out->m_wm[s] = out->chi2[s] = ORC_NOSOL;
+            out->split[2 * s] = out->split[2 * s + 1] = ORC_NOSOL;
+            continue;
+        }
+        ++npass;
+        /* the winner's kinematics */
+        double n1x = 0.5 * mx + b.u, n1y = 0.5 * my + b.v, n2x = 0.5 * mx - b.u, n2y = 0.5 * my - b.v;
+        double lp[4] = {st.lp.e, st.lp.x, st.lp.y, st.lp.z};
+        double lm[4] = {st.lm.e, st.lm.x, st.lm.y, st.lm.z};
+        double pz1[2], pz2[2];
+        int k1[2], k2[2];
+        orc_nu_pz(lp, n1x, n1y, p->m_w, pz1, k1);
+        orc_nu_pz(lm, n2x, n2y, p->m_w, pz2, k2);
+        vec4 nu = {sqrt(n1x * n1x + n1y * n1y + pz1[b.r1] * pz1[b.r1]), n1x, n1y, pz1[b.r1]};
+        vec4 nb = {sqrt(n2x * n2x + n2y * n2y + pz2[b.r2] * pz2[b.r2]), n2x, n2y, pz2[b.r2]};
+        out->root_nu[s] = (int8_t)k1[b.r1];
+        out->root_nubar[s] = (int8_t)k2[b.r2];
+        out->best_i[s] = (int16_t)st.cand[b.i];
+        out->best_j[s] = (int16_t)st.cand[b.j];
+        out->nu[3 * s + 0] = nu.x; out->nu[3 * s + 1] = nu.y; out->nu[3 * s + 2] = nu.z;
+        out->nubar[3 * s + 0] = nb.x; out->nubar[3 * s + 1] = nb.y; out->nubar[3 * s + 2] = nb.z;
+        out->m_wp[s] = orc_mass(orc_add(st.lp, nu));
+        out->m_wm[s] = orc_mass(orc_add(st.lm, nb));
+        out->m_t[s] = orc_mass(orc_add(st.cv[b.i], orc_add(st.lp, nu)));
+        out->m_tbar[s] = orc_mass(orc_add(st.cv[b.j], orc_add(st.lm, nb)));
+        out->chi2[s] = b.chi2;
+        out->split[2 * s] = b.u;
+        out->split[2 * s + 1] = b.v;
+    }
+    return npass;
+}

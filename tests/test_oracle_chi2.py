@@ -1,0 +1,179 @@
+"""Pins of the oracle's dileptonic chi^2 fit with a MET split (section 6.2:
+the missing momentum is split between the two neutrinos, each p_z follows
+from the mass constraints, and Eq. (chi2) with two tops and two W is
+minimised).
+
+  brute force  the same grid search written with numpy: p_z from numpy.roots
+               of the squared mass condition rebuilt from samples of the
+               unsquared one, every pairing and root pair by itertools;
+  search       the minimum found is no worse than the coarse grid point
+               nearest the generated neutrinos with the true pairing;
+  invariants   W masses on shell where both p_z are real roots; chi^2 >= 0.
+"""
+
+import itertools
+
+import numpy as np
+import pytest
+
+import hfgen
+
+M_T, M_W, S_T, S_W = 172.5, 80.4, 11.5, 7.5
+
+
+def _m2(p):
+    return p[0] ** 2 - p[1] ** 2 - p[2] ** 2 - p[3] ** 2
+
+
+def _mass(p):
+    return np.sqrt(max(_m2(p), 0.0))
+
+
+def _pz_candidates(lep, nx, ny):
+    """Roots of g(pz) = (E_l E_nu)^2 - (E_l E_nu - f/2)^2 with f the unsquared
+    W mass condition, from three samples; the real part if they are complex."""
+    xs = np.array([-100.0, 0.0, 100.0])
+    g = []
+    for z in xs:
+        nu = np.array([np.sqrt(nx * nx + ny * ny + z * z), nx, ny, z])
+        a = lep[0] * nu[0]
+        f = _m2(lep + nu) - M_W * M_W
+        g.append(a * a - (a - 0.5 * f) ** 2)
+    r = np.roots(np.polyfit(xs, g, 2))
+    return sorted(r.real) if np.all(np.abs(r.imag) == 0) else [float(r.real[0])]
+
+
+def _polar(pt, eta, phi, e):
+    return np.array([e, pt * np.cos(phi), pt * np.sin(phi), pt * np.sinh(eta)])
+
+
+def _stage(ev, e, cp):
+    """Leptons and b candidates as the reconstruction stages them (tagged
+    selected jets, filled to two with untagged ones)."""
+    f = lambda k, i: float(ev[k][i])
+    l0, l1 = int(ev["lep_off"][e]), int(ev["lep_off"][e + 1])
+    sel = [k for k in range(l0, l1) if f("lep_pt", k) > 20 and abs(f("lep_eta", k)) < 2.5]
+    if len(sel) != 2 or f("lep_q", sel[0]) * f("lep_q", sel[1]) >= 0:
+        return None
+    kp, km = (sel[0], sel[1]) if f("lep_q", sel[0]) > 0 else (sel[1], sel[0])
+    lp = _polar(f("lep_pt", kp), f("lep_eta", kp), f("lep_phi", kp), f("lep_e", kp))
+    lm = _polar(f("lep_pt", km), f("lep_eta", km), f("lep_phi", km), f("lep_e", km))
+    j0, j1 = int(ev["jet_off"][e]), int(ev["jet_off"][e + 1])
+    js = [k for k in range(j0, j1) if f("jet_pt", k) > 25 and abs(f("jet_eta", k)) < 2.5]
+    cand = [k for k in js if f("jet_btag", k) > 0.5][:12]
+    for k in js:
+        if len(cand) >= 2:
+            break
+        if not f("jet_btag", k) > 0.5:
+            cand.append(k)
+    if len(cand) < 2:
+        return None
+    cv = [_polar(f("jet_pt", k), f("jet_eta", k), f("jet_phi", k), f("jet_e", k)) for k in cand]
+    return lp, lm, cv, [k - j0 for k in cand]
+
+
+def _chi2_at(lp, lm, cv, mx, my, u, v):
+    """(chi2, i, j, pz1, pz2) of the first minimum at one split point."""
+    n1x, n1y, n2x, n2y = 0.5 * mx + u, 0.5 * my + v, 0.5 * mx - u, 0.5 * my - v
+    best = None
+    for i, j in itertools.permutations(range(len(cv)), 2):
+        for z1 in _pz_candidates(lp, n1x, n1y):
+            for z2 in _pz_candidates(lm, n2x, n2y):
+                nu = np.array([np.sqrt(n1x ** 2 + n1y ** 2 + z1 ** 2), n1x, n1y, z1])
+                nb = np.array([np.sqrt(n2x ** 2 + n2y ** 2 + z2 ** 2), n2x, n2y, z2])
+                c = ((_mass(cv[i] + lp + nu) - M_T) ** 2 / S_T ** 2 + (_mass(lp + nu) - M_W) ** 2 / S_W ** 2 +
+                     (_mass(cv[j] + lm + nb) - M_T) ** 2 / S_T ** 2 + (_mass(lm + nb) - M_W) ** 2 / S_W ** 2)
+                if best is None or c < best[0]:
+                    best = (c, i, j, z1, z2)
+    return best
+
+
+def _search(lp, lm, cv, mx, my, cp):
+    R, N = cp["half_range"], cp["n_grid"]
+    step = 2.0 * R / (N - 1)
+    best = None
+    pts = [(-R + step * a, -R + step * c) for a in range(N) for c in range(N)]
+    for level in range(cp["n_refine"] + 1):
+        if level:
+            step *= 0.25
+            cu, cv_ = best[5], best[6]
+            pts = [(cu + step * a, cv_ + step * c) for a in range(-2, 3) for c in range(-2, 3)]
+        for u, v in pts:
+            c = _chi2_at(lp, lm, cv, mx, my, u, v)
+            if best is None or c[0] < best[0]:
+                best = c + (u, v)
+    return best
+
+
+@pytest.fixture(scope="module")
+def sample(orc):
+    cfg = hfgen.config("ttbar10k")
+    ev = hfgen.generate(cfg, n_events=400, keep_fp64=True, seed=21)
+    surv, _, _ = orc.select(ev, cfg["cuts"], list(range(len(cfg["cuts"]))))
+    idx = orc.compact(surv)
+    cp = dict(cfg["chi2"])
+    return ev, idx, cp
+
+
+def test_brute_force_grid_search(orc, sample):
+    ev, idx, cp = sample
+    cp = dict(cp, n_grid=9, n_refine=1)  # a smaller grid keeps the numpy search quick
+    sub = idx[:25]
+    r = orc.dilep_chi2_reco(ev, sub, cp)
+    agree = 0
+    for s, e in enumerate(sub):
+        st = _stage(ev, e, cp)
+        assert st is not None and r["has_sol"][s] == 1
+        lp, lm, cv, loc = st
+        b = _search(lp, lm, cv, float(ev["met_x"][e]), float(ev["met_y"][e]), cp)
+        assert abs(r["chi2"][s] - b[0]) <= 1e-9 * max(1.0, b[0])
+        if (r["best_i"][s], r["best_j"][s]) == (loc[b[1]], loc[b[2]]) and \
+                np.allclose(r["split"][s], b[5:7], rtol=0, atol=1e-9):
+            agree += 1
+            assert abs(r["nu"][s, 2] - b[3]) <= 1e-6 * max(1.0, abs(b[3]))
+            assert abs(r["nubar"][s, 2] - b[4]) <= 1e-6 * max(1.0, abs(b[4]))
+    # the same minimum value everywhere; the same point and pairing unless two
+    # candidates tie to rounding
+    assert agree >= len(sub) - 1
+
+
+def test_search_beats_the_truth_nearest_grid_point(orc, sample):
+    ev, idx, cp = sample
+    tr = ev["truth"]
+    r = orc.dilep_chi2_reco(ev, idx, cp)
+    R, N = cp["half_range"], cp["n_grid"]
+    step = 2.0 * R / (N - 1)
+    n_checked = 0
+    for s, e in enumerate(idx[:60]):
+        st = _stage(ev, e, cp)
+        lp, lm, cv, loc = st
+        if tr["b_idx"][e] not in loc or tr["bbar_idx"][e] not in loc:
+            continue
+        i, j = loc.index(tr["b_idx"][e]), loc.index(tr["bbar_idx"][e])
+        mx, my = float(ev["met_x"][e]), float(ev["met_y"][e])
+        ut = tr["nu"][e, 1] - 0.5 * mx
+        vt = tr["nu"][e, 2] - 0.5 * my
+        a = int(np.clip(np.rint((ut + R) / step), 0, N - 1))
+        c = int(np.clip(np.rint((vt + R) / step), 0, N - 1))
+        near = _chi2_at(lp, lm, [cv[i], cv[j]], mx, my, -R + step * a, -R + step * c)
+        assert r["chi2"][s] <= near[0] + 1e-12
+        n_checked += 1
+    assert n_checked > 10
+
+
+def test_invariants(orc, sample):
+    ev, idx, cp = sample
+    r = orc.dilep_chi2_reco(ev, idx, cp)
+    hs = r["has_sol"] == 1
+    assert hs.all() and np.all(r["chi2"] >= 0)
+    real = (r["root_nu"] != 2) & (r["root_nubar"] != 2)
+    assert real.sum() > 0.5 * hs.sum()
+    assert np.all(np.abs(r["m_wp"][real] - M_W) < 1e-9 * M_W)
+    assert np.all(np.abs(r["m_wm"][real] - M_W) < 1e-9 * M_W)
+    # nu_T + nubar_T = MET
+    mx, my = ev["met_x"][idx].astype(float), ev["met_y"][idx].astype(float)
+    assert np.allclose(r["nu"][:, 0] + r["nubar"][:, 0], mx, atol=1e-9)
+    assert np.allclose(r["nu"][:, 1] + r["nubar"][:, 1], my, atol=1e-9)
+    # the fit is ambiguous (up to four exact solutions per pairing) but its
+    # minimum is small on unsmeared ttbar
+    assert np.median(r["chi2"]) < 0.05
