@@ -64,6 +64,7 @@ def _parse():
     ap.add_argument("--profile-only", action="store_true", help="few steps, no CPU baseline (for profilers)")
     ap.add_argument("--no-semilep", action="store_true", help="skip the single-neutrino reconstruction leg")
     ap.add_argument("--no-stream", action="store_true", help="skip the chunked-stream leg")
+    ap.add_argument("--no-chi2", action="store_true", help="skip the dileptonic chi^2 fit leg")
     ap.add_argument("--stream-only", action="store_true",
                     help="run only the chunked-stream leg and print its JSON object (for profilers)")
     ap.add_argument("--stream-chunks", type=int, default=50)
@@ -178,10 +179,107 @@ def main():
         del ch
         torch.cuda.empty_cache()
         out["semilep"] = semilep_leg(args, torch)
+    if not args.no_chi2:
+        torch.cuda.empty_cache()
+        out["chi2"] = chi2_leg(args, torch, ev, cfg)
     if not args.no_stream:
         torch.cuda.empty_cache()
         out["stream"] = stream_leg(args, torch)
     print(json.dumps(out))
+
+
+# Algorithmic FP64 operations of the chi^2 fit (hf_dilep_chi2_reco), counted
+# by hand from its formulas (add, mul, div, sqrt = 1, FMA = 2): per lepton
+# side and split point the p_z quadratic (33) and per p_z root the neutrino
+# energy, l + nu, its mass and the W term (18); per candidate, side and root
+# the top mass and its term (16); per candidate the sum of the two sides (1).
+# Per split point: 2 * (33 + 2 * 18) = 138, plus 65 per candidate.
+CHI2_FLOP_POINT = 138
+CHI2_FLOP_POINT_CAND = 65
+
+
+def chi2_candidates(ev, idx, cp):
+    """b candidates per compacted event, by the staging rule: tagged selected
+    jets (at most max_cands), filled up to two with untagged selected ones."""
+    e = np.asarray(idx, dtype=np.int64)
+    jo = ev["jet_off"].astype(np.int64)
+    sel = (ev["jet_pt"] > np.float32(cp["jet_pt_min"])) & (np.abs(ev["jet_eta"]) < np.float32(cp["jet_eta_max"]))
+    tag = sel & (ev["jet_btag"] > np.float32(cp["btag_min"]))
+    cs = np.concatenate([[0], np.cumsum(sel, dtype=np.int64)])
+    ct = np.concatenate([[0], np.cumsum(tag, dtype=np.int64)])
+    n_sel = cs[jo[e + 1]] - cs[jo[e]]
+    n_tag = np.minimum(ct[jo[e + 1]] - ct[jo[e]], cp["max_cands"])
+    return np.where(n_tag >= 2, n_tag, np.minimum(n_sel, 2))
+
+
+def chi2_leg(args, torch, ev, cfg):
+    """select -> compact -> hf_dilep_chi2_reco -> compact -> reorder over the
+    benchmark batch (1M events), one HIP graph per step; the fit's kernel
+    timed alone with HIP events on its stream; the oracle beside it."""
+    from paper_2211_14346_amd.chain import Chain
+
+    cp = cfg["chi2"]
+    n = ev["n"]
+    ch = Chain(ev, cfg["cuts"], None, chi2=cp)
+    for _ in range(max(1, args.warmup)):
+        ch.step()
+    torch.cuda.synchronize()
+    ch.capture(reorder=True)
+    ch.reset_counters()
+    torch.cuda.synchronize()
+    steps = max(3, args.steps // 4)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ch.replay()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    res = ch.results()
+    s = torch.cuda.current_stream()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(3)]
+    for a, b in evs:
+        a.record(s)
+        ch.run_reco()
+        b.record(s)
+    torch.cuda.synchronize()
+    kernel_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    nc = chi2_candidates(ev, res["idx"], cp)
+    ok = res["reco"]["has_sol"].astype(bool)
+    points = cp["n_grid"] ** 2 + 25 * cp["n_refine"]
+    flops = float(points * (CHI2_FLOP_POINT * ok.sum() + CHI2_FLOP_POINT_CAND * nc[ok].sum()))
+    tf = flops / (kernel_ms * 1e-3) / 1e12
+    leg = {"metric": "events/s through cut chain + dileptonic chi^2 fit with a MET split",
+           "value": round(n * steps / dt, 1), "unit": "events/s", "ms_per_step": round(1e3 * dt / steps, 4),
+           "dtype": "f64",
+           "config": {"workload": WORKLOAD, "events": n, "grid": f"{cp['n_grid']}x{cp['n_grid']} + "
+                      f"{cp['n_refine']} x 5x5", "survivors": int(res["count"]), "fitted": int(ok.sum())},
+           "roofline": {"bound": "alu", "kernel": "k_chi2", "achieved": round(tf, 3), "peak": PEAK_ALU_TFLOPS,
+                        "unit": "TFLOP/s", "frac": round(tf / PEAK_ALU_TFLOPS, 4), "traffic": None,
+                        "kernel_ms": round(kernel_ms, 4), "flop_per_launch": flops,
+                        "units_per_launch": {"events": int(ok.sum()), "split_points_per_event": points,
+                                             "candidates": int(nc[ok].sum())},
+                        "flop_per_unit": {"point": CHI2_FLOP_POINT, "point_candidate": CHI2_FLOP_POINT_CAND}}}
+    print(f"[bench] chi2: {leg['ms_per_step']} ms/step, kernel {kernel_ms:.3f} ms, {tf:.2f} TFLOP/s",
+          file=sys.stderr, flush=True)
+    if not args.profile_only and not args.no_cpu_baseline:
+        import hfgen
+        import oracle
+        from tests.gpu_compare import compare_chi2
+        threads = min(os.cpu_count() or 1, 16)
+        m = min(args.cpu_sample, n)
+        sub = hfgen.subset(ev, np.arange(m))
+        t0 = time.perf_counter()
+        surv, _, _ = oracle.select(sub, cfg["cuts"], list(range(len(cfg["cuts"]))))
+        idx = oracle.compact(surv)
+        rec = oracle.dilep_chi2_reco(sub, idx, cp, n_threads=threads)
+        oracle.compact(rec["has_sol"], 0, idx)
+        dtc = time.perf_counter() - t0
+        leg["cpu_baseline"] = {"value": round(m / dtc, 1), "unit": "events/s", "cores": threads, "kind": "oracle",
+                               "sample": f"first {m} events of the {WORKLOAD} batch, select+compact+fit+compact, "
+                                         f"{dtc:.1f} s wall on {threads} threads"}
+        k = int(idx.size)
+        st = compare_chi2({kk: v[:k] for kk, v in res["reco"].items()}, rec)
+        leg["accuracy_vs_oracle"] = {kk: (round(v, 12) if isinstance(v, float) else v) for kk, v in st.items()}
+    return leg
 
 
 def stream_leg(args, torch):

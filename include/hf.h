@@ -381,6 +381,51 @@ int hf_semilep_reco(const hf_events_t *ev, const int32_t *d_idx, const int64_t *
                     const hf_semilep_params_t *h_params, const hf_semilep_out_t *out, hf_counters_t *d_counters,
                     hipStream_t stream);
 
+/* --------------------------- dileptonic chi^2 fit with a MET split */
+
+/* Parameters of the chi^2 fit of the dileptonic final state (section 6.2):
+ * the masses and widths of Eq. (chi2) (172.5, 80.4, 11.5, 7.5 GeV in the
+ * paper); leptons and b candidates as for hf_ttbar_reco (pair_mode,
+ * max_cands in [2, HF_MAX_CANDS], the selection thresholds); the split
+ * search: n_grid in [2, 129] points per axis over [-half_range, half_range]
+ * (GeV, > 0), n_refine in [0, 8] refinements; reco_cut as for hf_ttbar_reco;
+ * reserved must be 0. */
+typedef struct hf_chi2_params {
+    double m_t, m_w, sigma_t, sigma_w, half_range;
+    float lep_pt_min, lep_eta_max, jet_pt_min, jet_eta_max, btag_min;
+    int32_t pair_mode, max_cands, n_grid, n_refine, reco_cut, reserved;
+} hf_chi2_params_t;
+
+/* Outputs over the compacted positions [0, capacity) (positions >= *d_count
+ * untouched): root_nu, root_nubar as hf_semilep_out_t's root; best_i, best_j
+ * the b jets (indices within the event) of the l+ and l- sides; nu, nubar
+ * (px, py, pz) [capacity][3]; the top and W masses; chi2 the minimum; split
+ * the offset (u, v) of nu_T from MET/2 [capacity][2].  No solution (fewer
+ * than two opposite-sign leptons or two candidates, an id outside the
+ * chunk): has_sol = 0, -1 indices, HF_NO_SOLUTION floats. */
+typedef struct hf_chi2_out {
+    uint8_t *has_sol;
+    int8_t *root_nu, *root_nubar;
+    int16_t *best_i, *best_j;
+    double *nu, *nubar;
+    double *m_t, *m_tbar, *m_wp, *m_wm, *chi2, *split;
+} hf_chi2_out_t;
+
+/* The chi^2 fit of the dileptonic final state (section 6.2): E_T^miss is
+ * split between the two neutrinos, nu_T = MET/2 + (u, v) and
+ * nubar_T = MET/2 - (u, v); each neutrino's p_z follows from its W mass as
+ * in hf_semilep_reco; every ordered pairing of two b candidates (the first
+ * with l+) and every pair of p_z candidates is scored by Eq. (chi2) with two
+ * tops and two W.  (u, v) is searched on an n_grid x n_grid grid, then
+ * refined n_refine times on a 5 x 5 grid centred on the best point with a
+ * quarter of the previous step (a refined point must be strictly better).
+ * Ties go to the first grid point, then pairing, then roots.  FP64 on the
+ * device.  Updates d_counters[reco_cut].  Allocates nothing.  Errors:
+ * HF_ERR_INVAL for null pointers or parameters out of range. */
+int hf_dilep_chi2_reco(const hf_events_t *ev, const int32_t *d_idx, const int64_t *d_count, int64_t capacity,
+                       const hf_chi2_params_t *h_params, const hf_chi2_out_t *out, hf_counters_t *d_counters,
+                       hipStream_t stream);
+
 /* -------------------------------------------------------- random draws */
 
 /* The variation draws the reconstruction uses (paper section 5.3 draws its

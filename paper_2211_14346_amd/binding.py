@@ -69,7 +69,19 @@ class SemilepOut(C.Structure):
                                           "m_wl", "m_th", "m_wh", "chi2")]
 
 
+class Chi2Params(C.Structure):
+    _fields_ = [(k, C.c_double) for k in ("m_t", "m_w", "sigma_t", "sigma_w", "half_range")] + \
+               [(k, C.c_float) for k in ("lep_pt_min", "lep_eta_max", "jet_pt_min", "jet_eta_max", "btag_min")] + \
+               [(k, C.c_int32) for k in ("pair_mode", "max_cands", "n_grid", "n_refine", "reco_cut", "reserved")]
+
+
+class Chi2Out(C.Structure):
+    _fields_ = [(k, C.c_void_p) for k in ("has_sol", "root_nu", "root_nubar", "best_i", "best_j", "nu", "nubar",
+                                          "m_t", "m_tbar", "m_wp", "m_wm", "chi2", "split")]
+
+
 assert C.sizeof(Cut) == 64 and C.sizeof(RecoParams) == 120 and C.sizeof(Counters) == 24
+assert C.sizeof(Chi2Params) == 88
 assert C.sizeof(SemilepParams) == 64
 
 _lib = None
@@ -108,11 +120,13 @@ def lib():
         L.hf_chain_log.restype = C.c_char_p
         L.hf_chain_destroy.argtypes = [P]
         L.hf_chain_destroy.restype = None
+        L.hf_dilep_chi2_reco.argtypes = [C.POINTER(Events), P, P, C.c_int64, C.POINTER(Chi2Params),
+                                         C.POINTER(Chi2Out), P, P]
         L.hf_semilep_reco.argtypes = [C.POINTER(Events), P, P, C.c_int64, C.POINTER(SemilepParams),
                                       C.POINTER(SemilepOut), P, P]
         for f in ("hf_select", "hf_compact", "hf_ttbar_reco", "hf_ttbar_reco_autotune", "hf_reorder_stats",
                   "hf_reorder_device", "hf_philox_blocks", "hf_gauss_draws", "hf_semilep_reco", "hf_chain_compile",
-                  "hf_chain_select"):
+                  "hf_chain_select", "hf_dilep_chi2_reco"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -307,6 +321,42 @@ def semilep_reco(dev, idx, count, capacity, params, outs, counters=None, stream=
     rc = lib().hf_semilep_reco(dev.ptr, _p(idx), _p(count), int(capacity), C.byref(params), C.byref(outs.s),
                                _p(counters), _stream(stream))
     _check(rc, "hf_semilep_reco")
+
+
+def chi2_params(cp, reco_cut=-1):
+    return Chi2Params(m_t=cp["m_t"], m_w=cp["m_w"], sigma_t=cp["sigma_t"], sigma_w=cp["sigma_w"],
+                      half_range=cp["half_range"], lep_pt_min=cp["lep_pt_min"], lep_eta_max=cp["lep_eta_max"],
+                      jet_pt_min=cp["jet_pt_min"], jet_eta_max=cp["jet_eta_max"], btag_min=cp["btag_min"],
+                      pair_mode=PAIR[cp["pair_mode"]], max_cands=int(cp["max_cands"]), n_grid=int(cp["n_grid"]),
+                      n_refine=int(cp["n_refine"]), reco_cut=int(reco_cut), reserved=0)
+
+
+class Chi2Outputs:
+    """Device output arrays of hf_dilep_chi2_reco for `capacity` positions."""
+
+    def __init__(self, capacity, device="cuda"):
+        cap = max(1, int(capacity))
+        f64 = dict(dtype=torch.float64, device=device)
+        self.t = {
+            "has_sol": torch.zeros(cap, dtype=torch.uint8, device=device),
+            "root_nu": torch.zeros(cap, dtype=torch.int8, device=device),
+            "root_nubar": torch.zeros(cap, dtype=torch.int8, device=device),
+            "best_i": torch.zeros(cap, dtype=torch.int16, device=device),
+            "best_j": torch.zeros(cap, dtype=torch.int16, device=device),
+            "nu": torch.zeros(cap, 3, **f64), "nubar": torch.zeros(cap, 3, **f64),
+            "m_t": torch.zeros(cap, **f64), "m_tbar": torch.zeros(cap, **f64), "m_wp": torch.zeros(cap, **f64),
+            "m_wm": torch.zeros(cap, **f64), "chi2": torch.zeros(cap, **f64), "split": torch.zeros(cap, 2, **f64),
+        }
+        self.s = Chi2Out(**{k: v.data_ptr() for k, v in self.t.items()})
+
+    def host(self, n):
+        return {k: v[:n].cpu().numpy() for k, v in self.t.items()}
+
+
+def dilep_chi2_reco(dev, idx, count, capacity, params, outs, counters=None, stream=None):
+    rc = lib().hf_dilep_chi2_reco(dev.ptr, _p(idx), _p(count), int(capacity), C.byref(params), C.byref(outs.s),
+                                  _p(counters), _stream(stream))
+    _check(rc, "hf_dilep_chi2_reco")
 
 
 def reorder_stats(counters_host, cuts_arr, n_cuts):

@@ -15,10 +15,11 @@ from . import binding as B
 
 class Chain:
     def __init__(self, ev, cuts, reco, precision="mixed", device="cuda", index_base=0, order=None,
-                 schedule="auto", semilep=None, topology="TCHAN"):
-        """reco: dileptonic reconstruction parameters (hfgen reco dict), or
+                 schedule="auto", semilep=None, topology="TCHAN", chi2=None):
+        """reco: dileptonic reconstruction parameters (hfgen reco dict); or
         None with semilep (hfgen semilep dict) and topology for the
-        single-neutrino reconstruction."""
+        single-neutrino reconstruction; or None with chi2 (hfgen chi2 dict)
+        for the dileptonic chi^2 fit with a MET split."""
         self.device = device
         self.cuts = cuts
         self.n_cuts = len(cuts)
@@ -31,7 +32,11 @@ class Chain:
         n = self.dev.n
         self.n = n
         self.semilep = semilep is not None
-        if self.semilep:
+        self.chi2 = chi2 is not None
+        if self.chi2:
+            self.params = B.chi2_params(chi2, reco_cut=self.reco_id)
+            self.want_mbb = False
+        elif self.semilep:
             self.params = B.semilep_params(semilep, topology, reco_cut=self.reco_id)
             self.want_mbb = False
         else:
@@ -47,7 +52,10 @@ class Chain:
         self.count = torch.zeros(1, dtype=torch.int64, device=device)
         self.final_idx = torch.zeros(max(n, 1), dtype=torch.int32, device=device)
         self.final_count = torch.zeros(1, dtype=torch.int64, device=device)
-        if self.semilep:
+        if self.chi2:
+            self.out = B.Chi2Outputs(n, device=device)
+            self.ws_reco = None
+        elif self.semilep:
             self.out = B.SemilepOutputs(n, device=device)
             self.ws_reco = None
         else:
@@ -71,7 +79,9 @@ class Chain:
                   stream=stream)
 
     def run_reco(self, stream=None):
-        if self.semilep:
+        if self.chi2:
+            B.dilep_chi2_reco(self.dev, self.idx, self.count, self.n, self.params, self.out, self.counters, stream)
+        elif self.semilep:
             B.semilep_reco(self.dev, self.idx, self.count, self.n, self.params, self.out, self.counters, stream)
         else:
             B.ttbar_reco(self.dev, self.idx, self.count, self.n, self.params, self.out, self.counters,

@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "../../include/hf.h"
+#include "hf_chi2.hpp"
 #include "hf_internal.hpp"
 #include "hf_reco_math.hpp"
 #include "hf_rtc.hpp"
@@ -368,6 +369,58 @@ void hf_chain_destroy(hf_chain_t *ch) {
     if (!ch) return;
     if (ch->module) (void)hipModuleUnload(ch->module);
     delete ch;
+}
+
+int hf_dilep_chi2_reco(const hf_events_t *ev, const int32_t *d_idx, const int64_t *d_count, int64_t capacity,
+                       const hf_chi2_params_t *p, const hf_chi2_out_t *out, hf_counters_t *d_counters,
+                       hipStream_t stream) {
+    const char *why = nullptr;
+    if (!events_ok(ev, true, &why)) return fail(HF_ERR_INVAL, "hf_dilep_chi2_reco: %s", why);
+    if (!p || !out) return fail(HF_ERR_INVAL, "hf_dilep_chi2_reco: params or out is NULL");
+    if (capacity < 0 || capacity >= ((int64_t)1 << 31))
+        return fail(HF_ERR_INVAL, "hf_dilep_chi2_reco: capacity out of range");
+    if (!d_count) return fail(HF_ERR_INVAL, "hf_dilep_chi2_reco: count is NULL");
+    if (capacity > 0 && (!d_idx || !out->has_sol || !out->root_nu || !out->root_nubar || !out->best_i ||
+                         !out->best_j || !out->nu || !out->nubar || !out->m_t || !out->m_tbar || !out->m_wp ||
+                         !out->m_wm || !out->chi2 || !out->split))
+        return fail(HF_ERR_INVAL, "hf_dilep_chi2_reco: an index or output array is NULL");
+    if (p->pair_mode != HF_PAIR_BTAG_FILL && p->pair_mode != HF_PAIR_ALL_JETS)
+        return fail(HF_ERR_INVAL, "hf_dilep_chi2_reco: unknown pair_mode %d", p->pair_mode);
+    if (p->max_cands < 2 || p->max_cands > HF_MAX_CANDS)
+        return fail(HF_ERR_INVAL, "hf_dilep_chi2_reco: max_cands %d outside [2, %d]", p->max_cands, HF_MAX_CANDS);
+    if (p->n_grid < 2 || p->n_grid > 129 || p->n_refine < 0 || p->n_refine > 8)
+        return fail(HF_ERR_INVAL, "hf_dilep_chi2_reco: grid n_grid %d / n_refine %d out of range", p->n_grid,
+                    p->n_refine);
+    if (!(p->half_range > 0.0) || !isfinite(p->half_range))
+        return fail(HF_ERR_INVAL, "hf_dilep_chi2_reco: half_range must be finite and > 0");
+    if (!(p->m_t > p->m_w && p->m_w > 0.0) || !isfinite(p->m_t))
+        return fail(HF_ERR_INVAL, "hf_dilep_chi2_reco: masses invalid");
+    if (!(p->sigma_t > 0.0) || !(p->sigma_w > 0.0) || !isfinite(p->sigma_t) || !isfinite(p->sigma_w))
+        return fail(HF_ERR_INVAL, "hf_dilep_chi2_reco: widths must be finite and > 0");
+    if (p->reserved != 0) return fail(HF_ERR_INVAL, "hf_dilep_chi2_reco: reserved field must be 0");
+    hf::Chi2Args a;
+    a.m_t = p->m_t;
+    a.m_w = p->m_w;
+    a.sigma_t = p->sigma_t;
+    a.sigma_w = p->sigma_w;
+    a.inv_st2 = 1.0 / (p->sigma_t * p->sigma_t);
+    a.inv_sw2 = 1.0 / (p->sigma_w * p->sigma_w);
+    a.half_range = p->half_range;
+    a.lep_pt_min = p->lep_pt_min;
+    a.lep_eta_max = p->lep_eta_max;
+    a.jet_pt_min = p->jet_pt_min;
+    a.jet_eta_max = p->jet_eta_max;
+    a.btag_min = p->btag_min;
+    a.pair_mode = p->pair_mode;
+    a.max_cands = p->max_cands;
+    a.n_grid = p->n_grid;
+    a.n_refine = p->n_refine;
+    hf::Chi2OutView o{out->has_sol, out->root_nu, out->root_nubar, out->best_i, out->best_j, out->nu, out->nubar,
+                      out->m_t,     out->m_tbar,  out->m_wp,       out->m_wm,   out->chi2,   out->split};
+    hf_counters_t *rc = (d_counters && p->reco_cut >= 0) ? d_counters + p->reco_cut : nullptr;
+    hipError_t e = hf::launch_chi2(hf::make_view(*ev), d_idx, d_count, capacity, a, o, rc, stream);
+    if (e != hipSuccess) return device_fail("hf_dilep_chi2_reco launch", e);
+    return HF_OK;
 }
 
 int hf_semilep_reco(const hf_events_t *ev, const int32_t *d_idx, const int64_t *d_count, int64_t capacity,

@@ -1,0 +1,406 @@
+// Dileptonic chi^2 fit with a split of the missing transverse momentum
+// (paper section 6.2): the two neutrinos share E_T^miss, each neutrino's p_z
+// follows from its W mass, and Eq. (chi2) with two tops (b l+ nu, bbar l-
+// nubar) and two W is minimised over the split, the ordered b-candidate
+// pairings and the p_z roots.
+//
+// The split is an offset (u, v) from the even split, nu_T = MET/2 + (u, v),
+// nubar_T = MET/2 - (u, v), searched on an n_grid x n_grid grid over
+// [-half_range, half_range]^2 and refined n_refine times on a 5 x 5 grid
+// around the best point at a quarter of the previous step.
+//
+// One wavefront per compacted event, lanes over grid points.  The wave
+// stages its event cooperatively (lanes over the objects, ballots for the
+// selection and the candidate order), keeping the leptons' and candidates'
+// FP64 4-vectors in LDS.  At a grid point chi^2 separates: the l+ side
+// depends on (i, r1) only and the l- side on (j, r2) only, so a lane forms
+// A+(i) = min over r1 of chi_t + chi_W for every candidate i, A-(j) likewise,
+// and the best ordered pairing i != j from the smallest two A- values, at
+// O(candidates) rather than O(candidates^2) per point.  A butterfly argmin
+// (value, then point index) gives the level's best; a refined point replaces
+// the best only when strictly smaller, as in a sequential scan.  FP64
+// throughout.
+#include <math.h>
+
+#include "hf_chi2.hpp"
+#include "hf_device.hpp"
+#include "hf_internal.hpp"
+
+namespace hf {
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kWaves = kBlock / kWave;
+constexpr int kMaxC = HF_MAX_CANDS;
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+__device__ __forceinline__ int64_t clamp_count(const int64_t *count, int64_t capacity) {
+    const int64_t S = *count;
+    return S < 0 ? 0 : (S > capacity ? capacity : S);
+}
+
+__device__ __forceinline__ void to_cart(float pt, float eta, float phi, float e, double v[4]) {
+    double s, c;
+    sincospi((double)phi * 0.31830988618379067, &s, &c);  // |phi| <= pi: no wide reduction
+    v[0] = (double)e;
+    v[1] = (double)pt * c;
+    v[2] = (double)pt * s;
+    v[3] = (double)pt * sinh((double)eta);
+}
+
+__device__ __forceinline__ double mass4(double e, double x, double y, double z) {
+    const double m2 = e * e - x * x - y * y - z * z;
+    return m2 > 0.0 ? sqrt(m2) : 0.0;
+}
+
+__device__ __forceinline__ double sq(double x) { return x * x; }
+
+// One lepton side at one split point: the neutrino p_z candidates from the
+// W mass (both roots of the squared condition, or the real part), l + nu
+// and the W term of chi^2 per candidate.
+struct Side {
+    double w[2][4];
+    double pz[2];
+    double cw[2];
+    int kind[2];
+    int n;
+};
+
+__device__ __forceinline__ Side side(const double *l, double nx, double ny, const Chi2Args &a) {
+    Side S;
+    S.n = 0;
+    const double ml2 = l[0] * l[0] - l[1] * l[1] - l[2] * l[2] - l[3] * l[3];
+    const double qa = l[0] * l[0] - l[3] * l[3];
+    if (!(qa > 0.0)) return S;
+    const double pt2 = nx * nx + ny * ny;
+    const double mu = 0.5 * (a.m_w * a.m_w - ml2) + l[1] * nx + l[2] * ny;
+    const double d = mu * mu - qa * pt2;
+    if (d < 0.0) {
+        S.pz[0] = mu * l[3] / qa;
+        S.kind[0] = 2;
+        S.n = 1;
+    } else {
+        const double s = l[0] * sqrt(d);
+        S.pz[0] = (mu * l[3] - s) / qa;
+        S.pz[1] = (mu * l[3] + s) / qa;
+        S.kind[0] = 0;
+        S.kind[1] = 1;
+        S.n = 2;
+    }
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        if (r >= S.n) break;
+        const double en = sqrt(pt2 + S.pz[r] * S.pz[r]);
+        S.w[r][0] = l[0] + en;
+        S.w[r][1] = l[1] + nx;
+        S.w[r][2] = l[2] + ny;
+        S.w[r][3] = l[3] + S.pz[r];
+        S.cw[r] = sq(mass4(S.w[r][0], S.w[r][1], S.w[r][2], S.w[r][3]) - a.m_w) * a.inv_sw2;
+    }
+    return S;
+}
+
+template <typename T>
+__device__ __forceinline__ T at2(const T (&x)[2], int r) {
+    return r ? x[1] : x[0];
+}
+
+// The best (chi^2, packed i | j << 4 | r1 << 8 | r2 << 9) at one split point.
+__device__ __forceinline__ double point_best(const double *lp, const double *lm, const double *cv, int nc, double mx,
+                                             double my, double u, double v, const Chi2Args &a, int &packed) {
+    const Side P = side(lp, 0.5 * mx + u, 0.5 * my + v, a);
+    const Side M = side(lm, 0.5 * mx - u, 0.5 * my - v, a);
+    double A1[kMaxC], A2[kMaxC];
+    int R1[kMaxC], R2[kMaxC];
+#pragma unroll
+    for (int c = 0; c < kMaxC; ++c) {
+        A1[c] = A2[c] = INFINITY;
+        R1[c] = R2[c] = 0;
+        if (c < nc) {
+            const double b0 = cv[4 * c], b1 = cv[4 * c + 1], b2 = cv[4 * c + 2], b3 = cv[4 * c + 3];
+#pragma unroll
+            for (int r = 0; r < 2; ++r) {
+                if (r < P.n) {
+                    const double t = sq(mass4(b0 + P.w[r][0], b1 + P.w[r][1], b2 + P.w[r][2], b3 + P.w[r][3]) -
+                                        a.m_t) * a.inv_st2 + P.cw[r];
+                    if (t < A1[c]) {
+                        A1[c] = t;
+                        R1[c] = r;
+                    }
+                }
+                if (r < M.n) {
+                    const double t = sq(mass4(b0 + M.w[r][0], b1 + M.w[r][1], b2 + M.w[r][2], b3 + M.w[r][3]) -
+                                        a.m_t) * a.inv_st2 + M.cw[r];
+                    if (t < A2[c]) {
+                        A2[c] = t;
+                        R2[c] = r;
+                    }
+                }
+            }
+        }
+    }
+    // the smallest two of A2 (first index on ties)
+    int ja = 0, jb = -1;
+#pragma unroll
+    for (int c = 1; c < kMaxC; ++c)
+        if (c < nc) {
+            if (A2[c] < A2[ja]) {
+                jb = ja;
+                ja = c;
+            } else if (jb < 0 || A2[c] < A2[jb]) {
+                jb = c;
+            }
+        }
+    double best = INFINITY;
+    packed = 0;
+#pragma unroll
+    for (int i = 0; i < kMaxC; ++i)
+        if (i < nc) {
+            const int j = i != ja ? ja : jb;
+            double a2 = 0.0;
+            int r2 = 0;
+#pragma unroll
+            for (int c = 0; c < kMaxC; ++c)
+                if (c == j) {
+                    a2 = A2[c];
+                    r2 = R2[c];
+                }
+            const double t = A1[i] + a2;
+            if (t < best) {
+                best = t;
+                packed = i | (j << 4) | (R1[i] << 8) | (r2 << 9);
+            }
+        }
+    return best;
+}
+
+// Wave argmin of (value, point index); every lane gets the winner.
+__device__ __forceinline__ void wave_argmin(double &val, int &pidx, int &packed) {
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        const double ov = __shfl_xor(val, off);
+        const int op = __shfl_xor(pidx, off);
+        const int ok = __shfl_xor(packed, off);
+        if (ov < val || (ov == val && op < pidx)) {
+            val = ov;
+            pidx = op;
+            packed = ok;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_chi2(EvView ev, const int32_t *__restrict__ idx,
+                                                 const int64_t *__restrict__ count, int64_t capacity, Chi2Args a,
+                                                 Chi2OutView o, hf_counters_t *__restrict__ counter) {
+    __shared__ double s_lep[kWaves][8];
+    __shared__ double s_cv[kWaves][kMaxC * 4];
+    __shared__ int s_loc[kWaves][kMaxC];
+    __shared__ uint32_t s_pass[kWaves];
+    const int wave = threadIdx.x / kWave, lane = lane_id();
+    const int64_t S = clamp_count(count, capacity);
+    const int64_t k = (int64_t)blockIdx.x * kWaves + wave;
+    bool have = false;
+    if (k < S) {
+        const int64_t e = (int64_t)idx[k] - ev.index_base;
+        int nc = 0;
+        bool ok = false;
+        if (e >= 0 && e < ev.n) {
+            // ---- leptons: exactly two selected, opposite charges; l+ first
+            const uint32_t l0 = ev.lep_off[e], l1 = ev.lep_off[e + 1];
+            int nl = 0;
+            uint32_t ka = 0, kb = 0;
+            for (uint32_t c0 = l0; c0 < l1; c0 += kWave) {
+                const uint32_t q = c0 + lane;
+                const bool in = q < l1;
+                const float pt = in ? ev.lep_pt[q] : 0.0f, eta = in ? ev.lep_eta[q] : 0.0f;
+                uint64_t m = ballot(in && pt > a.lep_pt_min && fabsf(eta) < a.lep_eta_max);
+                while (m && nl < 2) {
+                    const uint32_t b = c0 + (uint32_t)(__ffsll((unsigned long long)m) - 1);
+                    if (nl == 0) ka = b;
+                    else kb = b;
+                    ++nl;
+                    m &= m - 1;
+                }
+                nl += popc64(m);
+            }
+            if (nl == 2 && ev.lep_q[ka] * ev.lep_q[kb] < 0.0f) {
+                const uint32_t kp = ev.lep_q[ka] > 0.0f ? ka : kb, km = ev.lep_q[ka] > 0.0f ? kb : ka;
+                // ---- b candidates: tagged selected jets in order (or all selected), capped,
+                // filled up to two with the leading untagged selected jets
+                const uint32_t j0 = ev.jet_off[e], j1 = ev.jet_off[e + 1];
+                const bool all = a.pair_mode == HF_PAIR_ALL_JETS;
+                int nfill = 0;
+                uint32_t f0 = 0, f1 = 0;
+                for (uint32_t c0 = j0; c0 < j1; c0 += kWave) {
+                    const uint32_t q = c0 + lane;
+                    const bool in = q < j1;
+                    const float pt = in ? ev.jet_pt[q] : 0.0f, eta = in ? ev.jet_eta[q] : 0.0f;
+                    const float bt = in ? ev.jet_btag[q] : 0.0f;
+                    const bool sel = in && pt > a.jet_pt_min && fabsf(eta) < a.jet_eta_max;
+                    const bool tag = all || bt > a.btag_min;
+                    const uint64_t mt = ballot(sel && tag);
+                    uint64_t mu = ballot(sel && !tag);
+                    const int pos = nc + popc64(mt & lanemask_lt());
+                    if (sel && tag && pos < a.max_cands) s_loc[wave][pos] = (int)(q - j0);
+                    nc = min(a.max_cands, nc + popc64(mt));
+                    while (mu && nfill < 2) {
+                        const uint32_t b = c0 + (uint32_t)(__ffsll((unsigned long long)mu) - 1);
+                        if (nfill == 0) f0 = b;
+                        else f1 = b;
+                        ++nfill;
+                        mu &= mu - 1;
+                    }
+                    nfill += popc64(mu);
+                }
+                if (!all) {
+                    if (nc < 2 && nfill > 0) {
+                        if (lane == 0) s_loc[wave][nc] = (int)(f0 - j0);
+                        ++nc;
+                    }
+                    if (nc < 2 && nfill > 1) {
+                        if (lane == 0) s_loc[wave][nc] = (int)(f1 - j0);
+                        ++nc;
+                    }
+                }
+                wave_sync();
+                ok = nc >= 2;
+                if (ok) {
+                    double v[4];
+                    if (lane < nc) {
+                        const uint32_t q = j0 + (uint32_t)s_loc[wave][lane];
+                        to_cart(ev.jet_pt[q], ev.jet_eta[q], ev.jet_phi[q], ev.jet_e[q], v);
+                        for (int c = 0; c < 4; ++c) s_cv[wave][4 * lane + c] = v[c];
+                    } else if (lane == kWave - 1 || lane == kWave - 2) {
+                        const uint32_t q = lane == kWave - 1 ? kp : km;
+                        to_cart(ev.lep_pt[q], ev.lep_eta[q], ev.lep_phi[q], ev.lep_e[q], v);
+                        for (int c = 0; c < 4; ++c) s_lep[wave][(lane == kWave - 1 ? 0 : 4) + c] = v[c];
+                    }
+                    wave_sync();
+                }
+            }
+        }
+        if (ok) {
+            const double mx = (double)ev.met_x[e], my = (double)ev.met_y[e];
+            const double *lp = &s_lep[wave][0], *lm = &s_lep[wave][4], *cv = &s_cv[wave][0];
+            // ---- coarse grid
+            const int N = a.n_grid;
+            double step = 2.0 * a.half_range / (double)(N - 1);
+            double bval = INFINITY, bu = 0.0, bv = 0.0;
+            int bpk = 0;
+            {
+                double val = INFINITY;
+                int pidx = 0x7fffffff, pk = 0;
+                for (int p0 = 0; p0 < N * N; p0 += kWave) {
+                    const int p = p0 + lane;
+                    if (p < N * N) {
+                        int q;
+                        const double t = point_best(lp, lm, cv, nc, mx, my, -a.half_range + step * (p / N),
+                                                    -a.half_range + step * (p % N), a, q);
+                        if (t < val) {
+                            val = t;
+                            pidx = p;
+                            pk = q;
+                        }
+                    }
+                }
+                wave_argmin(val, pidx, pk);
+                bval = val;
+                bpk = pk;
+                bu = -a.half_range + step * (pidx / N);
+                bv = -a.half_range + step * (pidx % N);
+            }
+            // ---- refinements: 5 x 5 around the best point, a quarter of the step
+            for (int level = 0; level < a.n_refine; ++level) {
+                step *= 0.25;
+                double val = INFINITY;
+                int pidx = 0x7fffffff, pk = 0;
+                if (lane < 25) {
+                    int q;
+                    const double t = point_best(lp, lm, cv, nc, mx, my, bu + step * (lane / 5 - 2),
+                                                bv + step * (lane % 5 - 2), a, q);
+                    val = t;
+                    pidx = lane;
+                    pk = q;
+                }
+                wave_argmin(val, pidx, pk);
+                if (val < bval) {
+                    bval = val;
+                    bpk = pk;
+                    bu = bu + step * (pidx / 5 - 2);
+                    bv = bv + step * (pidx % 5 - 2);
+                }
+            }
+            have = bval < INFINITY;  // no p_z candidate at all (a lepton with E = |p_z|) leaves none
+            if (have && lane == 0) {
+                // the winner's kinematics, in the definition's order of operations
+                const int i = bpk & 15, j = (bpk >> 4) & 15, r1 = (bpk >> 8) & 1, r2 = (bpk >> 9) & 1;
+                const double n1x = 0.5 * mx + bu, n1y = 0.5 * my + bv, n2x = 0.5 * mx - bu, n2y = 0.5 * my - bv;
+                const Side P = side(lp, n1x, n1y, a), M = side(lm, n2x, n2y, a);
+                const double z1 = at2(P.pz, r1), z2 = at2(M.pz, r2);
+                const double nu[4] = {sqrt(n1x * n1x + n1y * n1y + z1 * z1), n1x, n1y, z1};
+                const double nb[4] = {sqrt(n2x * n2x + n2y * n2y + z2 * z2), n2x, n2y, z2};
+                double wp[4], wm[4], tp[4], tm[4];
+                for (int c = 0; c < 4; ++c) {
+                    wp[c] = lp[c] + nu[c];
+                    wm[c] = lm[c] + nb[c];
+                    tp[c] = cv[4 * i + c] + wp[c];
+                    tm[c] = cv[4 * j + c] + wm[c];
+                }
+                const double mwp = mass4(wp[0], wp[1], wp[2], wp[3]), mwm = mass4(wm[0], wm[1], wm[2], wm[3]);
+                const double mt = mass4(tp[0], tp[1], tp[2], tp[3]), mtb = mass4(tm[0], tm[1], tm[2], tm[3]);
+                const double st2 = a.sigma_t * a.sigma_t, sw2 = a.sigma_w * a.sigma_w;
+                o.has_sol[k] = 1;
+                o.root_nu[k] = (int8_t)at2(P.kind, r1);
+                o.root_nubar[k] = (int8_t)at2(M.kind, r2);
+                o.best_i[k] = (int16_t)s_loc[wave][i];
+                o.best_j[k] = (int16_t)s_loc[wave][j];
+                for (int c = 0; c < 3; ++c) {
+                    o.nu[3 * k + c] = nu[c + 1];
+                    o.nubar[3 * k + c] = nb[c + 1];
+                }
+                o.m_t[k] = mt;
+                o.m_tbar[k] = mtb;
+                o.m_wp[k] = mwp;
+                o.m_wm[k] = mwm;
+                o.chi2[k] = sq(mt - a.m_t) / st2 + sq(mwp - a.m_w) / sw2 + sq(mtb - a.m_t) / st2 +
+                            sq(mwm - a.m_w) / sw2;
+                o.split[2 * k] = bu;
+                o.split[2 * k + 1] = bv;
+            }
+        }
+        if (!have && lane == 0) {
+            o.has_sol[k] = 0;
+            o.root_nu[k] = o.root_nubar[k] = -1;
+            o.best_i[k] = o.best_j[k] = -1;
+            for (int c = 0; c < 3; ++c) o.nu[3 * k + c] = o.nubar[3 * k + c] = HF_NO_SOLUTION;
+            o.m_t[k] = o.m_tbar[k] = o.m_wp[k] = o.m_wm[k] = o.chi2[k] = HF_NO_SOLUTION;
+            o.split[2 * k] = o.split[2 * k + 1] = HF_NO_SOLUTION;
+        }
+    }
+    // RECO counters: one atomic per block
+    if (lane == 0) s_pass[wave] = (k < S && have) ? 1u : 0u;
+    __syncthreads();
+    if (threadIdx.x == 0 && counter) {
+        uint32_t tot = 0;
+        for (int w = 0; w < kWaves; ++w) tot += s_pass[w];
+        if (tot) atomicAdd((unsigned long long *)&counter->passed, (unsigned long long)tot);
+        if (blockIdx.x == 0) atomicAdd((unsigned long long *)&counter->reached, (unsigned long long)S);
+    }
+}
+
+}  // namespace
+
+hipError_t launch_chi2(const EvView &ev, const int32_t *idx, const int64_t *count, int64_t capacity, const Chi2Args &a,
+                       const Chi2OutView &out, hf_counters_t *counter, hipStream_t s) {
+    if (capacity <= 0) return hipSuccess;
+    const int64_t nb = (capacity + kWaves - 1) / kWaves;
+    hipLaunchKernelGGL(k_chi2, dim3((unsigned)nb), dim3(kBlock), 0, s, ev, idx, count, capacity, a, out, counter);
+    return hipGetLastError();
+}
+
+}  // namespace hf

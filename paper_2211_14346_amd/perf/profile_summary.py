@@ -16,6 +16,8 @@ Writes
                                           second leg), with --semilep-hash
   stream_hlhc50M_kernel_stats.txt         per-kernel durations of the chunked
                                           stream, with --stream-trace
+  k_chi2_ttbar1M_v64.txt                  duration (and traffic) of the
+                                          dileptonic chi^2 fit's kernel
 FETCH_SIZE and WRITE_SIZE (KiB per dispatch) are scaled into bytes by what
 each reads for a plain device copy of known size (--cal-bytes read and
 written once per copy): factor = copy bytes / (counter KiB * 1024).
@@ -126,6 +128,23 @@ def main():
         for name, calls, avg, mn, mx, pct in kernel_stats(a.stream_trace):
             lines.append(f"{name[:40]:40s} {calls:6d} {avg / 1e3:10.2f} {mn / 1e3:10.2f} {mx / 1e3:10.2f} {pct:7.2f}")
         with open(os.path.join(a.out, "stream_hlhc50M_kernel_stats.txt"), "w") as f:
+            f.write("\n".join(lines) + "\n")
+
+    row = [r for r in ks if r[0] == "k_chi2"]
+    if row:
+        name, calls, avg, mn, mx, pct = row[0]
+        cf, cw = merged.get(("k_chi2", "FETCH_SIZE")), merged.get(("k_chi2", "WRITE_SIZE"))
+        lines = ["# Dileptonic chi^2 fit with a MET split (hf_dilep_chi2_reco), bench workload ttbar1M_v64 "
+                 "(311868 events after the 4 cuts, 17x17 + 2 x 5x5 split points)",
+                 f"# trace command: {TRACE_CMD}", "",
+                 f"{'kernel':40s} {'calls':>6s} {'avg_us':>10s} {'min_us':>10s} {'max_us':>10s}",
+                 f"{name[:40]:40s} {calls:6d} {avg / 1e3:10.2f} {mn / 1e3:10.2f} {mx / 1e3:10.2f}"]
+        if cf and cw:
+            lines += ["", f"# counter command (one run per counter): {PMC_CMD}",
+                      f"FETCH_SIZE KiB per dispatch  {cf[0]:12.1f}   ({cf[1]} dispatches)",
+                      f"WRITE_SIZE KiB per dispatch  {cw[0]:12.1f}   ({cw[1]} dispatches)",
+                      f"chi2_traffic_bytes_per_launch: {cf[0] * 1024.0 * fetch_f + cw[0] * 1024.0 * write_f:.0f}"]
+        with open(os.path.join(a.out, "k_chi2_ttbar1M_v64.txt"), "w") as f:
             f.write("\n".join(lines) + "\n")
 
     lf, lw = merged.get((SEMILEP, "FETCH_SIZE")), merged.get((SEMILEP, "WRITE_SIZE"))

@@ -99,3 +99,38 @@ def assert_agree_semilep(st, min_agree=0.999, tol=1e-4):
     assert st["decision_equal"], st
     assert st["choice_agree"] >= min_agree, st
     assert st["max_rel_any"] <= tol, st
+
+
+CHI2_FLOATS = ("m_t", "m_tbar", "m_wp", "m_wm", "chi2")
+
+
+def compare_chi2(g, w):
+    """Dileptonic chi^2 fit: the decision (two opposite-sign leptons, two
+    candidates) is integer logic and must be identical; the choice (split
+    point, pairing, roots) must agree in >= 99.9 % of events; where it agrees,
+    momenta as |dp| / max(|p_ref|, 1 GeV), masses and chi^2 as
+    |d| / max(|ref|, 1)."""
+    S = len(w["has_sol"])
+    hs_g, hs_w = g["has_sol"][:S].astype(bool), w["has_sol"][:S].astype(bool)
+    both = hs_g & hs_w
+    same = both.copy()
+    for k in ("root_nu", "root_nubar", "best_i", "best_j"):
+        same &= g[k][:S] == w[k][:S]
+    same &= np.all(g["split"][:S] == w["split"][:S], axis=1)
+    st = {"S": int(S), "decision_equal": bool(np.array_equal(hs_g, hs_w)), "n_both": int(both.sum()),
+          "choice_agree": float(same.sum() / both.sum()) if both.sum() else 1.0}
+    rels = []
+    for k in ("nu", "nubar"):
+        d = np.linalg.norm(g[k][:S][same] - w[k][:S][same], axis=1)
+        r = d / np.maximum(np.linalg.norm(w[k][:S][same], axis=1), 1.0)
+        st["max_rel_" + k] = float(r.max()) if r.size else 0.0
+        rels.append(r)
+    for k in CHI2_FLOATS:
+        r = np.abs(g[k][:S][same] - w[k][:S][same]) / np.maximum(np.abs(w[k][:S][same]), 1.0)
+        st["max_rel_" + k] = float(r.max()) if r.size else 0.0
+        rels.append(r)
+    st["max_rel_any"] = float(np.max([r.max() for r in rels if r.size])) if same.any() else 0.0
+    nos = ~hs_g
+    st["sentinel_ok"] = bool(np.all(g["chi2"][:S][nos] == -9999.0) and np.all(g["nu"][:S][nos] == -9999.0)
+                             and np.all(g["best_i"][:S][nos] == -1))
+    return st

@@ -1,0 +1,127 @@
+"""GPU parity of the dileptonic chi^2 fit with a MET split (section 6.2)
+through the C ABI against the FP64 oracle: decisions identical, the chosen
+split point, pairing and roots in >= 99.9 % of events, every output within
+1e-4 relative (gpu_compare.compare_chi2)."""
+
+import sys
+
+import numpy as np
+import pytest
+
+import hfgen
+
+from .gpu_compare import assert_agree_semilep, compare_chi2
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(*a):
+    print("[gpu]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2211_14346_amd import binding
+    binding.lib()
+    return binding
+
+
+def _direct(B, ev, ids, cp, index_base=0):
+    dev = B.DeviceEvents(ev, index_base=index_base)
+    cap = max(1, len(ids))
+    idx = torch.zeros(cap, dtype=torch.int32, device="cuda")
+    idx[:len(ids)] = torch.as_tensor(np.asarray(ids, dtype=np.int32))
+    cnt = torch.tensor([len(ids)], dtype=torch.int64, device="cuda")
+    outs = B.Chi2Outputs(cap)
+    counters = torch.zeros(1, 3, dtype=torch.int64, device="cuda")
+    B.dilep_chi2_reco(dev, idx, cnt, cap, B.chi2_params(cp, reco_cut=0), outs, counters)
+    torch.cuda.synchronize()
+    return outs.host(len(ids)), counters.cpu().numpy()[0]
+
+
+@pytest.mark.parametrize("name,n,over", [
+    ("ttbar10k", 8000, {}),
+    ("ttbar1M_v64", 4000, {"pair_mode": "ALL_JETS", "max_cands": 6, "n_grid": 9, "n_refine": 3}),
+])
+def test_chi2_chain_matches_oracle(B, orc, name, n, over):
+    from paper_2211_14346_amd.chain import Chain
+    cfg = hfgen.config(name)
+    ev = hfgen.generate(cfg, n_events=n, seed=401)
+    cp = dict(cfg["chi2"], **over)
+    _say("chi2 chain", name, n, over)
+    ch = Chain(ev, cfg["cuts"], None, chi2=cp)
+    ch.step()
+    got = ch.results()
+    s_w, _, _ = orc.select(ev, cfg["cuts"], list(range(len(cfg["cuts"]))))
+    assert np.array_equal(got["survive"], s_w)
+    want = orc.dilep_chi2_reco(ev, got["idx"], cp)
+    st = compare_chi2(got["reco"], want)
+    _say(st)
+    assert_agree_semilep(st)
+    assert np.array_equal(got["final"], got["idx"][got["reco"]["has_sol"].astype(bool)])
+
+
+def test_chi2_edge_cases(B, orc):
+    from .test_gpu_parity import _edge_sample
+    ev = _edge_sample()
+    cp = dict(hfgen.config("ttbar10k")["chi2"], pair_mode="ALL_JETS")
+    base = 500
+    ids = list(np.random.default_rng(3).permutation(ev["n"]) + base) + [base - 1, base + ev["n"]]
+    _say("chi2 edge cases")
+    got, cnt = _direct(B, ev, ids, cp, index_base=base)
+    want = orc.dilep_chi2_reco(ev, np.array(ids[:-2]) - base, cp)
+    st = compare_chi2({k: v[:len(ids) - 2] for k, v in got.items()}, want)
+    _say(st)
+    assert_agree_semilep(st, min_agree=0.98)
+    assert np.all(got["has_sol"][-2:] == 0)
+    assert cnt[0] == len(ids) and cnt[1] == got["has_sol"].sum()
+
+
+def test_chi2_full_size_sampled(B, orc):
+    """1M events of the benchmark sample: the reconstruction against the
+    oracle on a sample of the compacted events, properties on all."""
+    from paper_2211_14346_amd.chain import Chain
+    cfg = hfgen.config("ttbar1M_v64")
+    ev = hfgen.generate(cfg)
+    _say("chi2 full size", ev["n"])
+    ch = Chain(ev, cfg["cuts"], None, chi2=cfg["chi2"])
+    ch.step()
+    got = ch.results()
+    S = got["count"]
+    pos = np.sort(np.random.default_rng(6).choice(S, size=1500, replace=False))
+    want = orc.dilep_chi2_reco(ev, got["idx"][pos], cfg["chi2"], n_threads=16)
+    st = compare_chi2({k: v[pos] for k, v in got["reco"].items()}, want)
+    _say(st)
+    assert_agree_semilep(st)
+    r = got["reco"]
+    hs = r["has_sol"].astype(bool)
+    e = got["idx"][hs]
+    assert np.allclose(r["nu"][hs, 0] + r["nubar"][hs, 0], ev["met_x"][e].astype(float), atol=1e-9)
+    assert np.allclose(r["nu"][hs, 1] + r["nubar"][hs, 1], ev["met_y"][e].astype(float), atol=1e-9)
+    real = hs & (r["root_nu"] != 2)
+    assert np.all(np.abs(r["m_wp"][real] - 80.4) < 1e-9 * 80.4)
+    assert np.all(r["chi2"][hs] >= 0)
+
+
+def test_chi2_graph_replay(B):
+    from paper_2211_14346_amd.chain import Chain
+    cfg = hfgen.config("ttbar10k")
+    ev = hfgen.generate(cfg, n_events=5000, seed=93)
+    ch = Chain(ev, cfg["cuts"], None, chi2=cfg["chi2"])
+    ch.step()
+    ref = ch.results()
+    ch.capture()
+    for rep in range(3):
+        ch.reset_counters()
+        ch.out.t["chi2"].fill_(7.0)
+        ch.replay()
+        torch.cuda.synchronize()
+        r = ch.results()
+        for k in ("chi2", "best_i", "best_j", "split", "nu"):
+            assert np.array_equal(r["reco"][k], ref["reco"][k]), k
+        assert np.array_equal(r["counters"][:, :2], ref["counters"][:, :2])
