@@ -189,12 +189,15 @@ def main():
 
 
 # Algorithmic FP64 operations of the chi^2 fit (hf_dilep_chi2_reco), counted
-# by hand from its formulas (add, mul, div, sqrt = 1, FMA = 2): per lepton
-# side and split point the p_z quadratic (33) and per p_z root the neutrino
-# energy, l + nu, its mass and the W term (18); per candidate, side and root
-# the top mass and its term (16); per candidate the sum of the two sides (1).
-# Per split point: 2 * (33 + 2 * 18) = 138, plus 65 per candidate.
-CHI2_FLOP_POINT = 138
+# by hand from its formulas (add, mul, div, sqrt = 1, FMA = 2): per split
+# point the two neutrinos' transverse momenta (8); per lepton side the p_z
+# quadratic with both roots and their mass-shell tests (21) and per root the
+# neutrino energy and l + nu (7); per candidate, side and root the top mass
+# and its term (16); per candidate the sum of the two sides (1).  A root on
+# the W mass shell has a zero W term, which is not computed (the real part of
+# a complex pair and the squaring's extra root are rare and not counted).
+# Per split point: 8 + 2 * (21 + 2 * 7) = 78, plus 65 per candidate.
+CHI2_FLOP_POINT = 78
 CHI2_FLOP_POINT_CAND = 65
 
 

@@ -25,6 +25,7 @@
 #include "hf_chi2.hpp"
 #include "hf_device.hpp"
 #include "hf_internal.hpp"
+#include "hf_reco_math.hpp"
 
 namespace hf {
 namespace {
@@ -60,9 +61,30 @@ __device__ __forceinline__ double mass4(double e, double x, double y, double z) 
 
 __device__ __forceinline__ double sq(double x) { return x * x; }
 
+// A lepton's split-independent terms: its 4-vector, (m_W^2 - m_l^2) / 2 and
+// a = E^2 - p_z^2 with its reciprocal (the p_z quadratic's leading term).
+struct Lep {
+    double l[4];
+    double c0, qa, inv_qa;
+};
+
+__device__ __forceinline__ Lep make_lep(const double *l, const Chi2Args &a) {
+    Lep L;
+    for (int c = 0; c < 4; ++c) L.l[c] = l[c];
+    const double ml2 = l[0] * l[0] - l[1] * l[1] - l[2] * l[2] - l[3] * l[3];
+    L.c0 = 0.5 * (a.m_w * a.m_w - ml2);
+    L.qa = l[0] * l[0] - l[3] * l[3];
+    L.inv_qa = L.qa > 0.0 ? 1.0 / L.qa : 0.0;
+    return L;
+}
+
 // One lepton side at one split point: the neutrino p_z candidates from the
 // W mass (both roots of the squared condition, or the real part), l + nu
-// and the W term of chi^2 per candidate.
+// and the W term of chi^2 per candidate.  A real root that solves the
+// unsquared condition (mu + p_zl p_z >= 0) puts l + nu on the W mass shell,
+// so its W term is zero; the squaring's extra root and the real part of a
+// complex pair get theirs computed.  Square roots and the quadratic's
+// division use the hardware estimates refined to about one ulp.
 struct Side {
     double w[2][4];
     double pz[2];
@@ -71,38 +93,51 @@ struct Side {
     int n;
 };
 
-__device__ __forceinline__ Side side(const double *l, double nx, double ny, const Chi2Args &a) {
+__device__ __forceinline__ Side side(const Lep &L, double nx, double ny, const Chi2Args &a) {
     Side S;
     S.n = 0;
-    const double ml2 = l[0] * l[0] - l[1] * l[1] - l[2] * l[2] - l[3] * l[3];
-    const double qa = l[0] * l[0] - l[3] * l[3];
-    if (!(qa > 0.0)) return S;
+    if (!(L.qa > 0.0)) return S;
+    const double *l = L.l;
     const double pt2 = nx * nx + ny * ny;
-    const double mu = 0.5 * (a.m_w * a.m_w - ml2) + l[1] * nx + l[2] * ny;
-    const double d = mu * mu - qa * pt2;
+    const double mu = L.c0 + l[1] * nx + l[2] * ny;
+    const double d = mu * mu - L.qa * pt2;
+    const double ml3 = mu * l[3];
+    bool shell[2] = {false, false};
     if (d < 0.0) {
-        S.pz[0] = mu * l[3] / qa;
+        S.pz[0] = ml3 * L.inv_qa;
         S.kind[0] = 2;
         S.n = 1;
     } else {
-        const double s = l[0] * sqrt(d);
-        S.pz[0] = (mu * l[3] - s) / qa;
-        S.pz[1] = (mu * l[3] + s) / qa;
+        const double s = l[0] * fast_sqrt(d);
+        S.pz[0] = (ml3 - s) * L.inv_qa;
+        S.pz[1] = (ml3 + s) * L.inv_qa;
         S.kind[0] = 0;
         S.kind[1] = 1;
         S.n = 2;
+        shell[0] = mu + l[3] * S.pz[0] >= 0.0;
+        shell[1] = mu + l[3] * S.pz[1] >= 0.0;
     }
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
         if (r >= S.n) break;
-        const double en = sqrt(pt2 + S.pz[r] * S.pz[r]);
+        const double en = fast_sqrt(pt2 + S.pz[r] * S.pz[r]);
         S.w[r][0] = l[0] + en;
         S.w[r][1] = l[1] + nx;
         S.w[r][2] = l[2] + ny;
         S.w[r][3] = l[3] + S.pz[r];
-        S.cw[r] = sq(mass4(S.w[r][0], S.w[r][1], S.w[r][2], S.w[r][3]) - a.m_w) * a.inv_sw2;
+        S.cw[r] = shell[r] ? 0.0
+                           : sq(fast_sqrt(fmax(S.w[r][0] * S.w[r][0] - S.w[r][1] * S.w[r][1] -
+                                               S.w[r][2] * S.w[r][2] - S.w[r][3] * S.w[r][3], 0.0)) -
+                                a.m_w) * a.inv_sw2;
     }
     return S;
+}
+
+// top term of chi^2 for candidate b with l + nu = w
+__device__ __forceinline__ double top_term(double b0, double b1, double b2, double b3, const double *w,
+                                           const Chi2Args &a) {
+    const double e = b0 + w[0], x = b1 + w[1], y = b2 + w[2], z = b3 + w[3];
+    return sq(fast_sqrt(fmax(e * e - x * x - y * y - z * z, 0.0)) - a.m_t) * a.inv_st2;
 }
 
 template <typename T>
@@ -111,71 +146,59 @@ __device__ __forceinline__ T at2(const T (&x)[2], int r) {
 }
 
 // The best (chi^2, packed i | j << 4 | r1 << 8 | r2 << 9) at one split point.
-__device__ __forceinline__ double point_best(const double *lp, const double *lm, const double *cv, int nc, double mx,
-                                             double my, double u, double v, const Chi2Args &a, int &packed) {
-    const Side P = side(lp, 0.5 * mx + u, 0.5 * my + v, a);
-    const Side M = side(lm, 0.5 * mx - u, 0.5 * my - v, a);
-    double A1[kMaxC], A2[kMaxC];
-    int R1[kMaxC], R2[kMaxC];
+// The l- side goes first and keeps only its two smallest terms (first index
+// on ties); the l+ side then pairs each candidate i with the smallest l-
+// term of a j != i.  Nothing per candidate is kept.
+__device__ __forceinline__ double side_min(const double *b, const Side &S, const Chi2Args &a, int &root) {
+    double t = INFINITY;
+    root = 0;
 #pragma unroll
-    for (int c = 0; c < kMaxC; ++c) {
-        A1[c] = A2[c] = INFINITY;
-        R1[c] = R2[c] = 0;
-        if (c < nc) {
-            const double b0 = cv[4 * c], b1 = cv[4 * c + 1], b2 = cv[4 * c + 2], b3 = cv[4 * c + 3];
-#pragma unroll
-            for (int r = 0; r < 2; ++r) {
-                if (r < P.n) {
-                    const double t = sq(mass4(b0 + P.w[r][0], b1 + P.w[r][1], b2 + P.w[r][2], b3 + P.w[r][3]) -
-                                        a.m_t) * a.inv_st2 + P.cw[r];
-                    if (t < A1[c]) {
-                        A1[c] = t;
-                        R1[c] = r;
-                    }
-                }
-                if (r < M.n) {
-                    const double t = sq(mass4(b0 + M.w[r][0], b1 + M.w[r][1], b2 + M.w[r][2], b3 + M.w[r][3]) -
-                                        a.m_t) * a.inv_st2 + M.cw[r];
-                    if (t < A2[c]) {
-                        A2[c] = t;
-                        R2[c] = r;
-                    }
-                }
+    for (int r = 0; r < 2; ++r)
+        if (r < S.n) {
+            const double v = top_term(b[0], b[1], b[2], b[3], S.w[r], a) + S.cw[r];
+            if (v < t) {
+                t = v;
+                root = r;
             }
+        }
+    return t;
+}
+
+__device__ __forceinline__ double point_best(const Lep &LP, const Lep &LM, const double *cv, int nc, double mx,
+                                             double my, double u, double v, const Chi2Args &a, int &packed) {
+    const Side P = side(LP, 0.5 * mx + u, 0.5 * my + v, a);
+    const Side M = side(LM, 0.5 * mx - u, 0.5 * my - v, a);
+    double va = INFINITY, vb = INFINITY;
+    int ja = -1, jb = -1, ra = 0, rb = 0;
+    for (int c = 0; c < nc; ++c) {
+        int r;
+        const double t = side_min(cv + 4 * c, M, a, r);
+        if (t < va) {
+            vb = va;
+            jb = ja;
+            rb = ra;
+            va = t;
+            ja = c;
+            ra = r;
+        } else if (t < vb) {
+            vb = t;
+            jb = c;
+            rb = r;
         }
     }
-    // the smallest two of A2 (first index on ties)
-    int ja = 0, jb = -1;
-#pragma unroll
-    for (int c = 1; c < kMaxC; ++c)
-        if (c < nc) {
-            if (A2[c] < A2[ja]) {
-                jb = ja;
-                ja = c;
-            } else if (jb < 0 || A2[c] < A2[jb]) {
-                jb = c;
-            }
-        }
     double best = INFINITY;
     packed = 0;
-#pragma unroll
-    for (int i = 0; i < kMaxC; ++i)
-        if (i < nc) {
-            const int j = i != ja ? ja : jb;
-            double a2 = 0.0;
-            int r2 = 0;
-#pragma unroll
-            for (int c = 0; c < kMaxC; ++c)
-                if (c == j) {
-                    a2 = A2[c];
-                    r2 = R2[c];
-                }
-            const double t = A1[i] + a2;
-            if (t < best) {
-                best = t;
-                packed = i | (j << 4) | (R1[i] << 8) | (r2 << 9);
-            }
+    for (int i = 0; i < nc; ++i) {
+        int r1;
+        const double t1 = side_min(cv + 4 * i, P, a, r1);
+        const bool other = i != ja;
+        const int j = other ? ja : jb;
+        const double t = t1 + (other ? va : vb);
+        if (j >= 0 && t < best) {
+            best = t;
+            packed = i | (j << 4) | (r1 << 8) | ((other ? ra : rb) << 9);
         }
+    }
     return best;
 }
 
@@ -287,6 +310,7 @@ __global__ __launch_bounds__(kBlock) void k_chi2(EvView ev, const int32_t *__res
         if (ok) {
             const double mx = (double)ev.met_x[e], my = (double)ev.met_y[e];
             const double *lp = &s_lep[wave][0], *lm = &s_lep[wave][4], *cv = &s_cv[wave][0];
+            const Lep LP = make_lep(lp, a), LM = make_lep(lm, a);
             // ---- coarse grid
             const int N = a.n_grid;
             double step = 2.0 * a.half_range / (double)(N - 1);
@@ -299,7 +323,7 @@ __global__ __launch_bounds__(kBlock) void k_chi2(EvView ev, const int32_t *__res
                     const int p = p0 + lane;
                     if (p < N * N) {
                         int q;
-                        const double t = point_best(lp, lm, cv, nc, mx, my, -a.half_range + step * (p / N),
+                        const double t = point_best(LP, LM, cv, nc, mx, my, -a.half_range + step * (p / N),
                                                     -a.half_range + step * (p % N), a, q);
                         if (t < val) {
                             val = t;
@@ -321,7 +345,7 @@ __global__ __launch_bounds__(kBlock) void k_chi2(EvView ev, const int32_t *__res
                 int pidx = 0x7fffffff, pk = 0;
                 if (lane < 25) {
                     int q;
-                    const double t = point_best(lp, lm, cv, nc, mx, my, bu + step * (lane / 5 - 2),
+                    const double t = point_best(LP, LM, cv, nc, mx, my, bu + step * (lane / 5 - 2),
                                                 bv + step * (lane % 5 - 2), a, q);
                     val = t;
                     pidx = lane;
@@ -340,7 +364,7 @@ __global__ __launch_bounds__(kBlock) void k_chi2(EvView ev, const int32_t *__res
                 // the winner's kinematics, in the definition's order of operations
                 const int i = bpk & 15, j = (bpk >> 4) & 15, r1 = (bpk >> 8) & 1, r2 = (bpk >> 9) & 1;
                 const double n1x = 0.5 * mx + bu, n1y = 0.5 * my + bv, n2x = 0.5 * mx - bu, n2y = 0.5 * my - bv;
-                const Side P = side(lp, n1x, n1y, a), M = side(lm, n2x, n2y, a);
+                const Side P = side(LP, n1x, n1y, a), M = side(LM, n2x, n2y, a);
                 const double z1 = at2(P.pz, r1), z2 = at2(M.pz, r2);
                 const double nu[4] = {sqrt(n1x * n1x + n1y * n1y + z1 * z1), n1x, n1y, z1};
                 const double nb[4] = {sqrt(n2x * n2x + n2y * n2y + z2 * z2), n2x, n2y, z2};
