@@ -152,7 +152,8 @@ def main():
                 "units_per_launch": {"events": int(per[0]), "variations": int(per[1]), "pairings": int(per[2]),
                                      "intervals": int(per[3]), "solutions": int(per[4])},
                 "flop_per_unit": {"variation": FLOP_PER_VARIATION, "pairing": FLOP_PER_PAIRING,
-                                  "interval": FLOP_PER_INTERVAL}}
+                                  "interval": FLOP_PER_INTERVAL},
+                "issued_view": issued_view(kname, kernel_ms)}
 
     out = {"metric": cfg_metric(), "value": round(value, 1), "unit": "events/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
@@ -476,8 +477,53 @@ def measured_traffic(kernel, kind="search"):
     return int(kv[f"{kind}_traffic_bytes_per_launch"])
 
 
+def issued_view(kernel, kernel_ms):
+    """Second view of the search kernel's roofline: the floating-point VALU
+    instructions it issues (rocprofv3 SQ_INSTS_VALU_* per launch, from the
+    committed counter summary) priced at the issue rates, against its
+    measured time.  Each FP64 or FP32 add, multiply or FMA wave instruction
+    takes 64 lane slots of the 39.3e12 per second behind the 78.6 TFLOP/s
+    FP64 peak (FP32 without packed instructions issues at the same rate);
+    transcendental instructions take four slots per lane.  None when the
+    summary does not match the built sources."""
+    from paper_2211_14346_amd.perf import built_source_hash, source_hash
+    built = built_source_hash("search")
+    path = os.path.join(ROOT, "profiles", "k_search_ttbar1M_v64_counters.txt")
+    if built is None or built != source_hash("search") or not os.path.exists(path):
+        return None
+    vals, cur = {}, None
+    for line in open(path):
+        line = line.rstrip()
+        if line.startswith("[") and line.endswith("]"):
+            cur = line[1:-1]
+        elif cur == kernel and line.startswith("  ") and "(" in line:
+            parts = line.split()
+            vals[parts[0]] = float(parts[1])
+        elif line.startswith("search_source_hash:") and line.split(":", 1)[1].strip() != built:
+            return None
+    need = [f"SQ_INSTS_VALU_{op}_{t}" for t in ("F64", "F32") for op in ("FMA", "MUL", "ADD", "TRANS")]
+    if any(k not in vals for k in need):
+        return None
+    slots = sum(vals[f"SQ_INSTS_VALU_{op}_{t}"] * (4.0 if op == "TRANS" else 1.0)
+                for t in ("F64", "F32") for op in ("FMA", "MUL", "ADD", "TRANS"))
+    t_star = 64.0 * slots / (PEAK_ALU_TFLOPS * 1e12 / 2.0)
+    return {"t_star_ms": round(1e3 * t_star, 4), "frac": round(1e3 * t_star / kernel_ms, 4),
+            "fp_wave_instructions": {k.replace("SQ_INSTS_VALU_", ""): vals[k] for k in need},
+            "source": "profiles/k_search_ttbar1M_v64_counters.txt"}
+
+
 def cfg_metric():
     return "events/s through cut chain + ttbar reco @64 variations; % HBM/VALU roofline"
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def cpu_baseline(ev, cfg, args, torch):
@@ -500,7 +546,19 @@ def cpu_baseline(ev, cfg, args, torch):
     dt = time.perf_counter() - t0
     base = {"value": round(m / dt, 1), "unit": "events/s", "cores": threads, "kind": "oracle",
             "sample": f"first {m} events of the {WORKLOAD} batch, select+compact+reco+compact, "
-                      f"{dt:.1f} s wall on {threads} threads"}
+                      f"{dt:.1f} s wall on {threads} threads",
+            "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
+    # one core, on the first tenth of the sample
+    m1 = max(1, m // 10)
+    sub1 = hfgen.subset(ev, np.arange(m1))
+    t0 = time.perf_counter()
+    surv1, _, _ = oracle.select(sub1, cfg["cuts"], list(range(len(cfg["cuts"]))))
+    idx1 = oracle.compact(surv1)
+    rec1 = oracle.ttbar_reco(sub1, idx1, cfg["reco"], n_threads=1)
+    oracle.compact(rec1["has_sol"], 0, idx1)
+    dt1 = time.perf_counter() - t0
+    base["single_core"] = {"value": round(m1 / dt1, 1), "unit": "events/s",
+                           "sample": f"first {m1} events, {dt1:.1f} s on 1 thread"}
     acc = {}
     for prec in ("mixed", "fp64"):
         ch = Chain(sub, cfg["cuts"], cfg["reco"], precision=prec)
