@@ -278,6 +278,25 @@ int hf_ttbar_reco_autotune(const hf_events_t *ev, const int32_t *d_idx, const in
  * Errors: HF_ERR_INVAL if exactly one of the two is NULL. */
 int hf_reco_timing_events(hipEvent_t start, hipEvent_t stop);
 
+/* One segment of a cut chain (section 5.2: heavy cuts placed late in the
+ * pipeline process fewer events): the cuts at positions [pos_begin, pos_end)
+ * of d_order, over all events of the chunk (d_idx == NULL; d_survive[n]
+ * indexed by event) or over the compacted global ids
+ * d_idx[0, min(*d_count, capacity)) (d_survive[capacity] indexed by
+ * position; an id outside the chunk fails without being counted).  Running
+ * positions [0, s) over all events, compacting, then [s, n_cuts) over the
+ * compacted ids (hf_compact with d_map = d_idx carries the ids forward)
+ * gives the same survivors and counters as one hf_select, with the later
+ * cuts evaluated by densely packed wavefronts.  Counters accumulate as in
+ * hf_select.  Workspace: hf_select_workspace_size(d_idx ? capacity : n,
+ * n_cuts).  Errors: those of hf_select; HF_ERR_INVAL unless
+ * 0 <= pos_begin <= pos_end <= n_cuts, or for d_idx without d_count or a
+ * capacity outside [0, 2^31). */
+int hf_select_segment(const hf_events_t *ev, const hf_cut_t *h_cuts, int n_cuts, const int32_t *d_order,
+                      int pos_begin, int pos_end, const int32_t *d_idx, const int64_t *d_count, int64_t capacity,
+                      uint8_t *d_survive, hf_counters_t *d_counters, void *d_ws, size_t ws_bytes,
+                      hipStream_t stream);
+
 /* ------------------------------------------------ user-defined cuts */
 
 /* A cut chain with user predicates (section 3: the user registers each cut
@@ -317,6 +336,12 @@ int hf_chain_compile(const hf_cut_t *h_cuts, int n_cuts, const char *const *h_us
  * be recorded into a HIP graph.  Errors: those of hf_select. */
 int hf_chain_select(const hf_chain_t *chain, const hf_events_t *ev, const int32_t *d_order, uint8_t *d_survive,
                     hf_counters_t *d_counters, void *d_ws, size_t ws_bytes, hipStream_t stream);
+
+/* hf_select_segment for a compiled chain. */
+int hf_chain_select_segment(const hf_chain_t *chain, const hf_events_t *ev, const int32_t *d_order, int pos_begin,
+                            int pos_end, const int32_t *d_idx, const int64_t *d_count, int64_t capacity,
+                            uint8_t *d_survive, hf_counters_t *d_counters, void *d_ws, size_t ws_bytes,
+                            hipStream_t stream);
 
 /* The compiler's messages for the chain ("" if none). */
 const char *hf_chain_log(const hf_chain_t *chain);

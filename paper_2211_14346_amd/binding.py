@@ -116,6 +116,10 @@ def lib():
         L.hf_gauss_draws.argtypes = [C.c_uint64, P, P, P, C.c_int64, C.c_int, P, P]
         L.hf_chain_compile.argtypes = [P, C.c_int, P, C.c_int, C.POINTER(C.c_void_p)]
         L.hf_chain_select.argtypes = [P, C.POINTER(Events), P, P, P, P, C.c_size_t, P]
+        L.hf_select_segment.argtypes = [C.POINTER(Events), P, C.c_int, P, C.c_int, C.c_int, P, P, C.c_int64, P, P,
+                                        P, C.c_size_t, P]
+        L.hf_chain_select_segment.argtypes = [P, C.POINTER(Events), P, C.c_int, C.c_int, P, P, C.c_int64, P, P, P,
+                                              C.c_size_t, P]
         L.hf_chain_log.argtypes = [P]
         L.hf_chain_log.restype = C.c_char_p
         L.hf_chain_destroy.argtypes = [P]
@@ -126,7 +130,7 @@ def lib():
                                       C.POINTER(SemilepOut), P, P]
         for f in ("hf_select", "hf_compact", "hf_ttbar_reco", "hf_ttbar_reco_autotune", "hf_reorder_stats",
                   "hf_reorder_device", "hf_philox_blocks", "hf_gauss_draws", "hf_semilep_reco", "hf_chain_compile",
-                  "hf_chain_select", "hf_dilep_chi2_reco"):
+                  "hf_chain_select", "hf_dilep_chi2_reco", "hf_select_segment", "hf_chain_select_segment"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -250,6 +254,20 @@ def select(dev, cuts_arr, n_cuts, order, survive, counters, ws, stream=None):
     rc = lib().hf_select(dev.ptr, C.cast(cuts_arr, C.c_void_p), n_cuts, _p(order), _p(survive), _p(counters),
                          _p(ws), ws.numel() * ws.element_size(), _stream(stream))
     _check(rc, "hf_select")
+
+
+def select_segment(dev, cuts_arr, n_cuts, order, pos_begin, pos_end, survive, counters, ws, idx=None, count=None,
+                   capacity=0, chain=None, stream=None):
+    """Cuts at order positions [pos_begin, pos_end) over all events (idx None)
+    or over compacted ids idx[0:*count] (survive then indexed by position).
+    With `chain` (a CompiledChain) its compiled kernel runs."""
+    args = (int(pos_begin), int(pos_end), _p(idx), _p(count), int(capacity), _p(survive), _p(counters), _p(ws),
+            ws.numel() * ws.element_size(), _stream(stream))
+    if chain is not None:
+        rc = lib().hf_chain_select_segment(chain.h, dev.ptr, _p(order), *args)
+    else:
+        rc = lib().hf_select_segment(dev.ptr, C.cast(cuts_arr, C.c_void_p), n_cuts, _p(order), *args)
+    _check(rc, "hf_select_segment")
 
 
 def compact(mask, capacity, idx, count, ws, d_n=None, index_base=0, mapping=None, stream=None):

@@ -15,11 +15,14 @@ from . import binding as B
 
 class Chain:
     def __init__(self, ev, cuts, reco, precision="mixed", device="cuda", index_base=0, order=None,
-                 schedule="auto", semilep=None, topology="TCHAN", chi2=None):
+                 schedule="auto", semilep=None, topology="TCHAN", chi2=None, segment_at=None):
         """reco: dileptonic reconstruction parameters (hfgen reco dict); or
         None with semilep (hfgen semilep dict) and topology for the
         single-neutrino reconstruction; or None with chi2 (hfgen chi2 dict)
-        for the dileptonic chi^2 fit with a MET split."""
+        for the dileptonic chi^2 fit with a MET split.  segment_at=s runs
+        the cuts at order positions [0, s) over all events, compacts, and
+        the rest over the compacted survivors (section 5.2: heavy cuts late
+        see fewer events; here they also run on densely packed wavefronts)."""
         self.device = device
         self.cuts = cuts
         self.n_cuts = len(cuts)
@@ -62,19 +65,44 @@ class Chain:
             self.out = B.RecoOutputs(n, device=device, want_mbb=self.want_mbb)
             self.ws_reco = B.workspace(B.lib().hf_ttbar_reco_workspace_size(n), device)
         self.ws_sel = B.workspace(B.lib().hf_select_workspace_size(n, self.n_cuts), device)
+        self.segment_at = segment_at
+        if segment_at is not None:
+            if not 0 <= segment_at <= self.n_cuts:
+                raise ValueError("segment_at outside [0, n_cuts]")
+            self.seg_idx = torch.zeros(max(n, 1), dtype=torch.int32, device=device)
+            self.seg_count = torch.zeros(1, dtype=torch.int64, device=device)
+            self.seg_survive = torch.zeros(max(n, 1), dtype=torch.uint8, device=device)
+            self.ws_seg = B.workspace(B.lib().hf_compact_workspace_size(n), device)
         self.ws_cmp = B.workspace(B.lib().hf_compact_workspace_size(n), device)
         self.ws_cmp2 = B.workspace(B.lib().hf_compact_workspace_size(n), device)
         self.graph = None
 
     # -------------------------------------------------------------- stages
     def run_select(self, stream=None):
+        if self.segment_at is not None:
+            return self._run_segments(stream)
         if self.compiled is not None:
             B.chain_select(self.compiled, self.dev, self.order, self.survive, self.counters, self.ws_sel, stream)
         else:
             B.select(self.dev, self.cut_arr, self.n_cuts, self.order, self.survive, self.counters, self.ws_sel,
                      stream)
 
+    def _run_segments(self, stream=None):
+        s = self.segment_at
+        B.select_segment(self.dev, self.cut_arr, self.n_cuts, self.order, 0, s, self.survive, self.counters,
+                         self.ws_sel, chain=self.compiled, stream=stream)
+        B.compact(self.survive, self.n, self.seg_idx, self.seg_count, self.ws_seg, index_base=self.dev.index_base,
+                  stream=stream)
+        B.select_segment(self.dev, self.cut_arr, self.n_cuts, self.order, s, self.n_cuts, self.seg_survive,
+                         self.counters, self.ws_sel, idx=self.seg_idx, count=self.seg_count, capacity=self.n,
+                         chain=self.compiled, stream=stream)
+
     def run_compact(self, stream=None):
+        if self.segment_at is not None:
+            # survivors of the second segment, carried through the first one's ids
+            B.compact(self.seg_survive, self.n, self.idx, self.count, self.ws_cmp, d_n=self.seg_count,
+                      mapping=self.seg_idx, stream=stream)
+            return
         B.compact(self.survive, self.n, self.idx, self.count, self.ws_cmp, index_base=self.dev.index_base,
                   stream=stream)
 
@@ -146,6 +174,12 @@ class Chain:
         S = int(self.count.item())
         F = int(self.final_count.item())
         out = self.out.host(S)
-        return {"survive": self.survive[:self.n].cpu().numpy(), "idx": self.idx[:S].cpu().numpy(),
+        idx = self.idx[:S].cpu().numpy()
+        if self.segment_at is not None:  # the chain's survive mask, rebuilt from the survivors' ids
+            survive = np.zeros(self.n, dtype=np.uint8)
+            survive[idx - self.dev.index_base] = 1
+        else:
+            survive = self.survive[:self.n].cpu().numpy()
+        return {"survive": survive, "idx": idx,
                 "count": S, "final": self.final_idx[:F].cpu().numpy(), "reco": out,
                 "counters": self.counters_host()}

@@ -337,29 +337,96 @@ int hf_chain_compile(const hf_cut_t *h_cuts, int n_cuts, const char *const *h_us
     return HF_OK;
 }
 
-int hf_chain_select(const hf_chain_t *ch, const hf_events_t *ev, const int32_t *d_order, uint8_t *d_survive,
-                    hf_counters_t *d_counters, void *d_ws, size_t ws_bytes, hipStream_t stream) {
-    if (!ch || !ch->fn) return fail(HF_ERR_INVAL, "hf_chain_select: chain is NULL");
-    const char *why = nullptr;
-    if (!events_ok(ev, true, &why)) return fail(HF_ERR_INVAL, "hf_chain_select: %s", why);
-    if (!d_order || !d_counters) return fail(HF_ERR_INVAL, "hf_chain_select: order or counters is NULL");
-    if (ev->n > 0 && !d_survive) return fail(HF_ERR_INVAL, "hf_chain_select: survive is NULL");
-    const int n_cuts = (int)ch->cuts.size();
-    const size_t need = hf::select_ws_bytes(ev->n, n_cuts);
+namespace {
+
+// Checks shared by the segment entry points; *items receives the number of
+// survive entries (events or compacted positions) the launch writes.
+int check_segment(const char *who, const hf_events_t *ev, int n_cuts, const int32_t *d_order, int pos_begin,
+                  int pos_end, const int32_t *d_idx, const int64_t *d_count, int64_t capacity, uint8_t *d_survive,
+                  hf_counters_t *d_counters, void *d_ws, size_t ws_bytes) {
+    if (!d_order || !d_counters) return fail(HF_ERR_INVAL, "%s: order or counters is NULL", who);
+    if (pos_begin < 0 || pos_begin > pos_end || pos_end > n_cuts)
+        return fail(HF_ERR_INVAL, "%s: positions [%d, %d) outside [0, %d]", who, pos_begin, pos_end, n_cuts);
+    if (d_idx && !d_count) return fail(HF_ERR_INVAL, "%s: d_idx given without d_count", who);
+    if (capacity < 0 || capacity >= ((int64_t)1 << 31)) return fail(HF_ERR_INVAL, "%s: capacity out of range", who);
+    const int64_t items = d_idx ? capacity : ev->n;
+    if (items > 0 && !d_survive) return fail(HF_ERR_INVAL, "%s: survive is NULL", who);
+    const size_t need = hf::select_ws_bytes(items, n_cuts);
     if (!d_ws || ws_bytes < need)
-        return fail(HF_ERR_CAPACITY, "hf_chain_select: workspace %zu bytes < %zu required", ws_bytes, need);
+        return fail(HF_ERR_CAPACITY, "%s: workspace %zu bytes < %zu required", who, ws_bytes, need);
+    return HF_OK;
+}
+
+int chain_launch(const hf_chain_t *ch, const hf_events_t *ev, const int32_t *d_order, int pos_begin, int pos_end,
+                 const int32_t *d_idx, const int64_t *d_count, int64_t capacity, uint8_t *d_survive,
+                 hf_counters_t *d_counters, void *d_ws, const char *who, hipStream_t stream) {
+    const int n_cuts = (int)ch->cuts.size();
     hf::CutTable ct;
     memset(&ct, 0, sizeof ct);
     for (int c = 0; c < n_cuts; ++c) ct.c[c] = ch->cuts[c];
     ct.n = n_cuts;
     hf::EvView v = hf::make_view(*ev);
-    const int grid = hf::select_grid(ev->n);
+    const int grid = hf::select_grid(d_idx ? capacity : ev->n);
     uint64_t *partial = static_cast<uint64_t *>(d_ws);
-    void *args[] = {&v, &ct, &d_order, &d_survive, &partial};
+    void *args[] = {&v, &ct, &d_order, &d_survive, &partial, &d_idx, &d_count, &capacity, &pos_begin, &pos_end};
     hipError_t e = hipModuleLaunchKernel(ch->fn, grid, 1, 1, hf::kChainBlock, 1, 1, 0, stream, args, nullptr);
-    if (e != hipSuccess) return device_fail("hf_chain_select launch", e);
+    if (e != hipSuccess) return device_fail(who, e);
     e = hf::launch_select_reduce(partial, grid, n_cuts, d_counters, stream);
-    if (e != hipSuccess) return device_fail("hf_chain_select reduce", e);
+    if (e != hipSuccess) return device_fail(who, e);
+    return HF_OK;
+}
+
+}  // namespace
+
+int hf_chain_select(const hf_chain_t *ch, const hf_events_t *ev, const int32_t *d_order, uint8_t *d_survive,
+                    hf_counters_t *d_counters, void *d_ws, size_t ws_bytes, hipStream_t stream) {
+    if (!ch || !ch->fn) return fail(HF_ERR_INVAL, "hf_chain_select: chain is NULL");
+    const char *why = nullptr;
+    if (!events_ok(ev, true, &why)) return fail(HF_ERR_INVAL, "hf_chain_select: %s", why);
+    const int n_cuts = (int)ch->cuts.size();
+    int rc = check_segment("hf_chain_select", ev, n_cuts, d_order, 0, n_cuts, nullptr, nullptr, 0, d_survive,
+                           d_counters, d_ws, ws_bytes);
+    if (rc != HF_OK) return rc;
+    return chain_launch(ch, ev, d_order, 0, n_cuts, nullptr, nullptr, 0, d_survive, d_counters, d_ws,
+                        "hf_chain_select launch", stream);
+}
+
+int hf_chain_select_segment(const hf_chain_t *ch, const hf_events_t *ev, const int32_t *d_order, int pos_begin,
+                            int pos_end, const int32_t *d_idx, const int64_t *d_count, int64_t capacity,
+                            uint8_t *d_survive, hf_counters_t *d_counters, void *d_ws, size_t ws_bytes,
+                            hipStream_t stream) {
+    if (!ch || !ch->fn) return fail(HF_ERR_INVAL, "hf_chain_select_segment: chain is NULL");
+    const char *why = nullptr;
+    if (!events_ok(ev, true, &why)) return fail(HF_ERR_INVAL, "hf_chain_select_segment: %s", why);
+    int rc = check_segment("hf_chain_select_segment", ev, (int)ch->cuts.size(), d_order, pos_begin, pos_end, d_idx,
+                           d_count, capacity, d_survive, d_counters, d_ws, ws_bytes);
+    if (rc != HF_OK) return rc;
+    return chain_launch(ch, ev, d_order, pos_begin, pos_end, d_idx, d_count, capacity, d_survive, d_counters, d_ws,
+                        "hf_chain_select_segment launch", stream);
+}
+
+int hf_select_segment(const hf_events_t *ev, const hf_cut_t *h_cuts, int n_cuts, const int32_t *d_order,
+                      int pos_begin, int pos_end, const int32_t *d_idx, const int64_t *d_count, int64_t capacity,
+                      uint8_t *d_survive, hf_counters_t *d_counters, void *d_ws, size_t ws_bytes,
+                      hipStream_t stream) {
+    bool need_pe = false;
+    int rc = check_cuts(h_cuts, n_cuts, &need_pe);
+    if (rc != HF_OK) return rc;
+    for (int c = 0; c < n_cuts; ++c)
+        if (h_cuts[c].kind == HF_CUT_USER)
+            return fail(HF_ERR_INVAL, "hf_select_segment: cut %d is a user predicate; use hf_chain_select_segment", c);
+    const char *why = nullptr;
+    if (!events_ok(ev, need_pe, &why)) return fail(HF_ERR_INVAL, "hf_select_segment: %s", why);
+    rc = check_segment("hf_select_segment", ev, n_cuts, d_order, pos_begin, pos_end, d_idx, d_count, capacity,
+                       d_survive, d_counters, d_ws, ws_bytes);
+    if (rc != HF_OK) return rc;
+    hf::CutTable ct;
+    memset(&ct, 0, sizeof ct);
+    for (int c = 0; c < n_cuts; ++c) ct.c[c] = h_cuts[c];
+    ct.n = n_cuts;
+    hipError_t e = hf::launch_select_segment(hf::make_view(*ev), ct, d_order, pos_begin, pos_end, d_idx, d_count,
+                                             capacity, d_survive, d_counters, d_ws, stream);
+    if (e != hipSuccess) return device_fail("hf_select_segment launch", e);
     return HF_OK;
 }
 

@@ -205,10 +205,20 @@ __device__ inline bool eval_cut(const EvView &ev, int64_t e, const hf_cut_t &c) 
 // The chain kernel.  User::eval(u, ev, e) evaluates user predicate u (cuts of
 // kind HF_CUT_USER, u = the cut's i[0]); the library's own instantiation has
 // none, a chain compiled at run time supplies them.
+//
+// A launch evaluates the cuts at positions [pos_begin, pos_end) of the order
+// (a segment of the chain) over all events of the chunk (idx == nullptr;
+// survive indexed by event) or over the compacted ids idx[0, min(*count,
+// capacity)) (survive indexed by position; an id outside the chunk fails
+// without being counted), so that the later cuts of a chain can run on the
+// compacted survivors of the earlier ones.
 template <class User>
 __global__ __launch_bounds__(kSelBlock) void k_select_t(EvView ev, CutTable ct, const int32_t *__restrict__ order,
                                                         uint8_t *__restrict__ survive,
-                                                        uint64_t *__restrict__ partial) {
+                                                        uint64_t *__restrict__ partial,
+                                                        const int32_t *__restrict__ idx,
+                                                        const int64_t *__restrict__ count, int64_t capacity,
+                                                        int pos_begin, int pos_end) {
     __shared__ hf_cut_t s_cut[HF_MAX_CUTS];
     __shared__ int s_order[HF_MAX_CUTS];
     __shared__ uint64_t s_cnt[kSelWaves][HF_MAX_CUTS * 3];
@@ -222,11 +232,21 @@ __global__ __launch_bounds__(kSelBlock) void k_select_t(EvView ev, CutTable ct, 
     for (int t = tid; t < kSelWaves * HF_MAX_CUTS * 3; t += kSelBlock) (&s_cnt[0][0])[t] = 0;
     __syncthreads();
 
+    int64_t n_items = ev.n;
+    if (idx) {
+        const int64_t S = *count;
+        n_items = S < 0 ? 0 : (S > capacity ? capacity : S);
+    }
     const int64_t stride = (int64_t)gridDim.x * kSelBlock;
-    for (int64_t base = (int64_t)blockIdx.x * kSelBlock + wave * kWave; base < ev.n; base += stride) {
-        const int64_t e = base + lane;
-        bool alive = e < ev.n;
-        for (int k = 0; k < nc; ++k) {
+    for (int64_t base = (int64_t)blockIdx.x * kSelBlock + wave * kWave; base < n_items; base += stride) {
+        const int64_t item = base + lane;
+        int64_t e = item;
+        bool alive = item < n_items;
+        if (idx && alive) {
+            e = (int64_t)idx[item] - ev.index_base;
+            alive = e >= 0 && e < ev.n;
+        }
+        for (int k = pos_begin; k < pos_end; ++k) {
             const int c = s_order[k];
             if (c < 0 || s_cut[c].kind == HF_CUT_RECO) continue;
             const uint64_t am = ballot(alive);
@@ -244,7 +264,7 @@ __global__ __launch_bounds__(kSelBlock) void k_select_t(EvView ev, CutTable ct, 
             }
             alive = pass;
         }
-        if (e < ev.n) survive[e] = alive ? 1 : 0;
+        if (item < n_items) survive[item] = alive ? 1 : 0;
     }
     __syncthreads();
     for (int t = tid; t < nc * 3; t += kSelBlock) {

@@ -19,6 +19,12 @@ constexpr int kChainBlock = 256;
 hipError_t launch_select_reduce(const uint64_t *partial, int grid, int n_cuts, hf_counters_t *counters,
                                 hipStream_t s);
 
+// One segment of a chain (positions [pos_begin, pos_end) of the order) over
+// all events (idx == nullptr) or over compacted ids (hf_select_segment).
+hipError_t launch_select_segment(const EvView &ev, const CutTable &ct, const int32_t *order, int pos_begin,
+                                 int pos_end, const int32_t *idx, const int64_t *count, int64_t capacity,
+                                 uint8_t *survive, hf_counters_t *counters, void *ws, hipStream_t s);
+
 // The device sources a generated chain kernel includes, embedded at build
 // time: header names as the generated source and the headers include them,
 // and their text.

@@ -51,7 +51,20 @@ hipError_t launch_select(const EvView &ev, const CutTable &ct, const int32_t *or
                          hf_counters_t *counters, void *ws, hipStream_t s) {
     const int grid = select_grid(ev.n);
     uint64_t *partial = static_cast<uint64_t *>(ws);
-    hipLaunchKernelGGL(k_select_t<NoUserCuts>, dim3(grid), dim3(kSelBlock), 0, s, ev, ct, order, survive, partial);
+    hipLaunchKernelGGL(k_select_t<NoUserCuts>, dim3(grid), dim3(kSelBlock), 0, s, ev, ct, order, survive, partial,
+                       (const int32_t *)nullptr, (const int64_t *)nullptr, (int64_t)0, 0, ct.n);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    return launch_select_reduce(partial, grid, ct.n, counters, s);
+}
+
+hipError_t launch_select_segment(const EvView &ev, const CutTable &ct, const int32_t *order, int pos_begin,
+                                 int pos_end, const int32_t *idx, const int64_t *count, int64_t capacity,
+                                 uint8_t *survive, hf_counters_t *counters, void *ws, hipStream_t s) {
+    const int grid = select_grid(idx ? capacity : ev.n);
+    uint64_t *partial = static_cast<uint64_t *>(ws);
+    hipLaunchKernelGGL(k_select_t<NoUserCuts>, dim3(grid), dim3(kSelBlock), 0, s, ev, ct, order, survive, partial,
+                       idx, count, capacity, pos_begin, pos_end);
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
     return launch_select_reduce(partial, grid, ct.n, counters, s);

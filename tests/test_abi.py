@@ -199,3 +199,22 @@ def test_user_chain_validation(B):
     assert L.hf_select(C.byref(ev), C.cast(arr, C.c_void_p), 1, dummy, dummy, dummy, dummy, 1 << 20, None) == -1
     assert b"hf_chain_compile" in L.hf_last_error()
     assert L.hf_chain_select(None, C.byref(ev), dummy, dummy, dummy, dummy, 1 << 20, None) == -1
+
+
+def test_segment_validation(B):
+    L = B.lib()
+    full = B.Events(n=10, index_base=0, **{k: 16 for k in ("lep_off", "jet_off", "lep_pt", "lep_eta", "lep_phi",
+                                                           "lep_e", "lep_q", "jet_pt", "jet_eta", "jet_phi",
+                                                           "jet_e", "jet_btag", "met_x", "met_y")})
+    cuts = B.cut_table(hfgen.config("ttbar10k")["cuts"])
+    d = C.c_void_p(16)
+
+    def call(pb, pe, idx=None, cnt=None, cap=10, ws=1 << 20):
+        return L.hf_select_segment(C.byref(full), C.cast(cuts, C.c_void_p), 5, d, pb, pe, idx, cnt, cap, d, d, d, ws,
+                                   None)
+
+    assert call(-1, 2) == -1 and call(3, 2) == -1 and call(0, 6) == -1
+    assert call(0, 2, idx=d) == -1 and b"d_count" in L.hf_last_error()
+    assert call(0, 2, idx=d, cnt=d, cap=-1) == -1
+    assert call(0, 2, ws=0) == -2
+    assert L.hf_chain_select_segment(None, C.byref(full), d, 0, 1, None, None, 0, d, d, d, 1 << 20, None) == -1
