@@ -257,7 +257,8 @@ def chi2_leg(args, torch, ev, cfg):
            "config": {"workload": WORKLOAD, "events": n, "grid": f"{cp['n_grid']}x{cp['n_grid']} + "
                       f"{cp['n_refine']} x 5x5", "survivors": int(res["count"]), "fitted": int(ok.sum())},
            "roofline": {"bound": "alu", "kernel": "k_chi2", "achieved": round(tf, 3), "peak": PEAK_ALU_TFLOPS,
-                        "unit": "TFLOP/s", "frac": round(tf / PEAK_ALU_TFLOPS, 4), "traffic": None,
+                        "unit": "TFLOP/s", "frac": round(tf / PEAK_ALU_TFLOPS, 4),
+                        "traffic": measured_traffic("k_chi2", "chi2"),
                         "kernel_ms": round(kernel_ms, 4), "flop_per_launch": flops,
                         "units_per_launch": {"events": int(ok.sum()), "split_points_per_event": points,
                                              "candidates": int(nc[ok].sum())},
@@ -463,7 +464,8 @@ def measured_traffic(kernel, kind="search"):
     built = built_source_hash(kind)
     if built is None or built != source_hash(kind):
         return None  # library and sources differ: the counters cannot be attributed
-    name = {"search": "k_search_ttbar1M_v64_counters.txt", "semilep": "k_semilep_tchan1M.txt"}[kind]
+    name = {"search": "k_search_ttbar1M_v64_counters.txt", "semilep": "k_semilep_tchan1M.txt",
+            "chi2": "k_chi2_ttbar1M_v64.txt"}[kind]
     path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None

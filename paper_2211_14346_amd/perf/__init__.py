@@ -8,10 +8,12 @@ import os
 _CSRC = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "csrc")
 
 # Sources that determine each profiled kernel's code: the dileptonic
-# reconstruction search and the single-neutrino reconstruction.
+# reconstruction search, the single-neutrino reconstruction and the
+# dileptonic chi^2 fit.
 SOURCES = {
     "search": ("hf_reco.hip", "hf_reco_math.hpp", "hf_device.hpp", "hf_internal.hpp"),
     "semilep": ("hf_semilep.hip", "hf_device.hpp", "hf_internal.hpp"),
+    "chi2": ("hf_chi2.hip", "hf_chi2.hpp", "hf_device.hpp", "hf_internal.hpp", "hf_reco_math.hpp"),
 }
 SEARCH_SOURCES = SOURCES["search"]
 

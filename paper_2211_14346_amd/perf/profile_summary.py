@@ -77,6 +77,7 @@ def main():
     ap.add_argument("--cal-bytes", type=int, default=256 << 20)
     ap.add_argument("--hash", required=True, help="search kernel source hash of the profiled tree")
     ap.add_argument("--semilep-hash", default=None, help="single-neutrino kernel source hash of the profiled tree")
+    ap.add_argument("--chi2-hash", default=None, help="chi^2 fit kernel source hash of the profiled tree")
     ap.add_argument("--out", default="profiles")
     a = ap.parse_args()
     os.makedirs(a.out, exist_ok=True)
@@ -143,7 +144,12 @@ def main():
             lines += ["", f"# counter command (one run per counter): {PMC_CMD}",
                       f"FETCH_SIZE KiB per dispatch  {cf[0]:12.1f}   ({cf[1]} dispatches)",
                       f"WRITE_SIZE KiB per dispatch  {cw[0]:12.1f}   ({cw[1]} dispatches)",
+                      f"calibration on a {a.cal_bytes} B device copy: bytes = FETCH_SIZE * 1024 * {fetch_f:.4f}, "
+                      f"bytes = WRITE_SIZE * 1024 * {write_f:.4f}", "",
+                      "chi2_kernel: k_chi2", f"chi2_avg_us: {avg / 1e3:.2f}",
                       f"chi2_traffic_bytes_per_launch: {cf[0] * 1024.0 * fetch_f + cw[0] * 1024.0 * write_f:.0f}"]
+            if a.chi2_hash:
+                lines.append(f"chi2_source_hash: {a.chi2_hash}")
         with open(os.path.join(a.out, "k_chi2_ttbar1M_v64.txt"), "w") as f:
             f.write("\n".join(lines) + "\n")
 
