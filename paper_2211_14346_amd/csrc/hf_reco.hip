@@ -5,7 +5,7 @@
 //
 // Kernels, in launch order.
 //
-// k_stage: one thread per compacted event; selects the leptons and b
+// k_stage: eight lanes per compacted event; selects the leptons and b
 // candidates, writes their FP64 Cartesian 4-vectors to a record, the
 // event's count of lane granules (16 variations each; none when no
 // pairing is valid) and an empty best record.
@@ -178,183 +178,174 @@ __device__ __forceinline__ int64_t clamp_count(const int64_t *count, int64_t cap
     return S < 0 ? 0 : (S > capacity ? capacity : S);
 }
 
-// One thread per compacted event: selection of the two leptons (exactly two
-// selected, opposite charges; l+ first) and of the b candidates (b-tagged
-// selected jets in input order up to max_cands, filled up to two with the
-// leading untagged selected jets; or every selected jet), converted to FP64
-// Cartesian 4-vectors.  Objects are examined in chunks whose columns are
-// loaded together, and the selected objects' columns are loaded together
-// before the conversions, so that each stage costs one memory round trip
-// rather than one per object.
-constexpr int kChunk = 8;
+// Eight lanes per compacted event (eight events per wavefront): selection of
+// the two leptons (exactly two selected, opposite charges; l+ first) and of
+// the b candidates (b-tagged selected jets in input order up to max_cands,
+// filled up to two with the leading untagged selected jets; or every
+// selected jet), converted to FP64 Cartesian 4-vectors.  The lanes of an
+// event read its objects eight at a time; ballots restricted to the event's
+// eight bits give the selection, the candidates' order and the first
+// untagged jets; each lane then converts and writes at most two candidates,
+// and the record's fields are written by the lanes that own them.  Spreading
+// an event over lanes keeps many more wavefronts in flight than one thread
+// per event, which is what hides the chain of dependent loads.
+constexpr int kStageLanes = 8;
+constexpr int kStageEvents = 256 / kStageLanes;  // events per block
 
 __global__ __launch_bounds__(256) void k_stage(EvView ev, const int32_t *__restrict__ idx,
                                                const int64_t *__restrict__ count, int64_t capacity, RecoArgs a,
                                                StageRec *__restrict__ stage, int32_t *__restrict__ gcnt,
                                                BestRec *__restrict__ best) {
+    __shared__ uint32_t s_jl[kStageEvents][kMaxC];  // candidates' jet positions
+    __shared__ double s_lep[kStageEvents][8];       // l+ then l-
+    const int lane = lane_id(), sub = lane & (kStageLanes - 1);
+    const int slot = threadIdx.x / kStageLanes;
+    const int shift = lane & ~(kStageLanes - 1);     // the event's first lane in the wave
+    const uint64_t lt = lanemask_lt() >> shift;      // lanes of this event below this one (low bits)
     const int64_t S = clamp_count(count, capacity);
-    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (k >= S) return;
+    const int64_t k = (int64_t)blockIdx.x * kStageEvents + slot;
+    if (k >= S) return;  // whole events only: the eight lanes of an event leave together
     StageRec &r = stage[k];
     const uint64_t g = (uint64_t)idx[k];
     const int64_t e = (int64_t)g - ev.index_base;
     const bool in_chunk = e >= 0 && e < ev.n;  // ids outside the chunk get no solution
-    r.g = g;
+    auto bits = [&](bool p) { return (uint32_t)((ballot(p) >> shift) & 0xffu); };
     int nc = 0, V = 0;
+    uint32_t kp = 0, km = 0;
+    bool lep_ok = false;
     if (in_chunk) {
         V = ev.n_var ? (int)ev.n_var[e] : a.n_var_uniform;
-        r.met[0] = (double)ev.met_x[e];
-        r.met[1] = (double)ev.met_y[e];
+        // ---- leptons: the first two selected, and how many are selected
         const uint32_t l0 = ev.lep_off[e], l1 = ev.lep_off[e + 1];
-        const uint32_t j0 = ev.jet_off[e], j1 = ev.jet_off[e + 1];
-        // The first chunk of each object list is loaded before anything is
-        // decided, so that leptons and jets share one memory round trip.
-        float lpt[kChunk], leta[kChunk], lq[kChunk], jpt[kChunk], jeta[kChunk], jbt[kChunk];
-        auto load_leps = [&](uint32_t c0) {
-#pragma unroll
-            for (int u = 0; u < kChunk; ++u) {
-                const bool in = c0 + u < l1;
-                lpt[u] = in ? ev.lep_pt[c0 + u] : 0.0f;
-                leta[u] = in ? ev.lep_eta[c0 + u] : 0.0f;
-                lq[u] = in ? ev.lep_q[c0 + u] : 0.0f;
-            }
-        };
-        auto load_jets = [&](uint32_t c0) {
-#pragma unroll
-            for (int u = 0; u < kChunk; ++u) {
-                const bool in = c0 + u < j1;
-                jpt[u] = in ? ev.jet_pt[c0 + u] : 0.0f;
-                jeta[u] = in ? ev.jet_eta[c0 + u] : 0.0f;
-                jbt[u] = in ? ev.jet_btag[c0 + u] : 0.0f;
-            }
-        };
-        load_leps(l0);
-        load_jets(j0);
-        // ---- leptons
-        uint32_t ls0 = 0, ls1 = 0;
-        float q0 = 0.0f, q1 = 0.0f;
         int nl = 0;
-        for (uint32_t c0 = l0; c0 < l1; c0 += kChunk) {
-            if (c0 != l0) load_leps(c0);
-#pragma unroll
-            for (int u = 0; u < kChunk; ++u)
-                if (c0 + u < l1 && lpt[u] > a.lep_pt_min && fabsf(leta[u]) < a.lep_eta_max) {
-                    if (nl == 0) {
-                        ls0 = c0 + u;
-                        q0 = lq[u];
-                    }
-                    if (nl == 1) {
-                        ls1 = c0 + u;
-                        q1 = lq[u];
-                    }
-                    ++nl;
-                }
+        uint32_t ka = 0, kb = 0;
+        for (uint32_t c0 = l0; c0 < l1; c0 += kStageLanes) {
+            const uint32_t q = c0 + sub;
+            const bool in = q < l1;
+            const float pt = in ? ev.lep_pt[q] : 0.0f, eta = in ? ev.lep_eta[q] : 0.0f;
+            uint32_t m = bits(in && pt > a.lep_pt_min && fabsf(eta) < a.lep_eta_max);
+            while (m && nl < 2) {
+                const uint32_t b = c0 + (uint32_t)(__ffs(m) - 1);
+                if (nl == 0) ka = b;
+                else kb = b;
+                ++nl;
+                m &= m - 1;
+            }
+            nl += __popc(m);
         }
-        // ---- b candidates: tagged selected jets in order (or all selected), then the fill
-        const int cap = a.max_cands < kMaxC ? a.max_cands : kMaxC;
-        const bool all = a.pair_mode == HF_PAIR_ALL_JETS;
-        uint32_t jl[kMaxC];
-        uint32_t f0 = 0, f1 = 0;
-        int nfill = 0;
-#pragma unroll
-        for (int c = 0; c < kMaxC; ++c) jl[c] = 0;
-        for (uint32_t c0 = j0; c0 < j1; c0 += kChunk) {
-            if (c0 != j0) load_jets(c0);
-#pragma unroll
-            for (int u = 0; u < kChunk; ++u) {
-                if (!(c0 + u < j1 && jpt[u] > a.jet_pt_min && fabsf(jeta[u]) < a.jet_eta_max)) continue;
-                if (all || jbt[u] > a.btag_min) {
-                    if (nc < cap) {
-#pragma unroll
-                        for (int c = 0; c < kMaxC; ++c) jl[c] = c == nc ? c0 + u : jl[c];
-                        ++nc;
-                    }
-                } else {
-                    if (nfill == 0) f0 = c0 + u;
-                    if (nfill == 1) f1 = c0 + u;
+        if (nl == 2) {
+            const float qa = ev.lep_q[ka], qb = ev.lep_q[kb];
+            lep_ok = qa * qb < 0.0f;
+            kp = qa > 0.0f ? ka : kb;
+            km = qa > 0.0f ? kb : ka;
+        }
+        if (lep_ok) {
+            // ---- b candidates
+            const int cap = a.max_cands < kMaxC ? a.max_cands : kMaxC;
+            const bool all = a.pair_mode == HF_PAIR_ALL_JETS;
+            const uint32_t j0 = ev.jet_off[e], j1 = ev.jet_off[e + 1];
+            int nfill = 0;
+            uint32_t f0 = 0, f1 = 0;
+            for (uint32_t c0 = j0; c0 < j1; c0 += kStageLanes) {
+                const uint32_t q = c0 + sub;
+                const bool in = q < j1;
+                const float pt = in ? ev.jet_pt[q] : 0.0f, eta = in ? ev.jet_eta[q] : 0.0f;
+                const float bt = in ? ev.jet_btag[q] : 0.0f;
+                const bool sel = in && pt > a.jet_pt_min && fabsf(eta) < a.jet_eta_max;
+                const bool tag = all || bt > a.btag_min;
+                const uint32_t mt = bits(sel && tag);
+                uint32_t mu = bits(sel && !tag);
+                const int pos = nc + __popc(mt & (uint32_t)lt);
+                if (sel && tag && pos < cap) s_jl[slot][pos] = q;
+                nc = min(cap, nc + __popc(mt));
+                while (mu && nfill < 2) {
+                    const uint32_t b = c0 + (uint32_t)(__ffs(mu) - 1);
+                    if (nfill == 0) f0 = b;
+                    else f1 = b;
                     ++nfill;
+                    mu &= mu - 1;
                 }
+                nfill += __popc(mu);
             }
-        }
-        if (!all) {
-            // leading untagged selected jets fill the list up to two
-            if (nc < 2 && nfill > 0) {
-#pragma unroll
-                for (int c = 0; c < 2; ++c) jl[c] = c == nc ? f0 : jl[c];
-                ++nc;
-            }
-            if (nc < 2 && nfill > 1) {
-                jl[1] = f1;
-                ++nc;
-            }
-        }
-        if (!(nl == 2 && q0 * q1 < 0.0f)) nc = 0;
-        if (nc > 0) {
-            const uint32_t kp = q0 > 0.0f ? ls0 : ls1, km = q0 > 0.0f ? ls1 : ls0;
-            // ---- columns of the selected objects, loaded together (the leptons with
-            // the first four candidates, then four at a time), then FP64 Cartesian;
-            // all loads of a round precede the stores, which may alias them
-            float cpt[4], ceta[4], cphi[4], ce[4];
-            auto load_cands = [&](int c0) {
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const bool in = c0 + u < nc;
-                    const uint32_t q = in ? jl[c0 + u] : j0;
-                    cpt[u] = in ? ev.jet_pt[q] : 0.0f;
-                    ceta[u] = in ? ev.jet_eta[q] : 0.0f;
-                    cphi[u] = in ? ev.jet_phi[q] : 0.0f;
-                    ce[u] = in ? ev.jet_e[q] : 1.0f;
+            if (!all) {
+                // leading untagged selected jets fill the list up to two
+                if (nc < 2 && nfill > 0) {
+                    if (sub == 0) s_jl[slot][nc] = f0;
+                    ++nc;
                 }
-            };
-            const float pa = ev.lep_pt[kp], ea = ev.lep_eta[kp], fa = ev.lep_phi[kp], xa = ev.lep_e[kp];
-            const float pb = ev.lep_pt[km], eb = ev.lep_eta[km], fb = ev.lep_phi[km], xb = ev.lep_e[km];
-            load_cands(0);
-            double v[4];
-            polar_to_cart(pa, ea, fa, xa, v);
-            for (int q = 0; q < 4; ++q) r.lp[q] = v[q];
-            r.ml2p = v[0] * v[0] - v[1] * v[1] - v[2] * v[2] - v[3] * v[3];
-            polar_to_cart(pb, eb, fb, xb, v);
-            for (int q = 0; q < 4; ++q) r.lm[q] = v[q];
-            r.ml2m = v[0] * v[0] - v[1] * v[1] - v[2] * v[2] - v[3] * v[3];
-#pragma unroll
-            for (int c0 = 0; c0 < kMaxC; c0 += 4) {
-                if (c0 >= nc) break;
-                if (c0 > 0) load_cands(c0);
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int c = c0 + u;
-                    if (c < nc) {
-                        polar_to_cart(cpt[u], ceta[u], cphi[u], ce[u], v);
-                        for (int q = 0; q < 4; ++q) r.cand[c][q] = v[q];
-                        r.sigma[c] = sqrt(a.jet_a * a.jet_a / (double)ce[u] + a.jet_c * a.jet_c);
-                        r.jidx[c] = (int32_t)(jl[c] - j0);
-                    }
+                if (nc < 2 && nfill > 1) {
+                    if (sub == 0) s_jl[slot][nc] = f1;
+                    ++nc;
                 }
             }
         }
     }
-    r.nc = nc;
-    r.V = V;
-    // valid pairings (both sides non-degenerate, the same test as make_side)
-    int npair = 0;
-    if (nc >= 2) {
-        uint32_t okp = 0, okm = 0;
-        double sd[kSide];
-        for (int c = 0; c < nc; ++c) {
-            if (make_side(r.lp, r.cand[c], sd)) okp |= 1u << c;
-            if (make_side(r.lm, r.cand[c], sd)) okm |= 1u << c;
+    if (!lep_ok) nc = 0;
+    // ---- the record: leptons by lanes 0 and 1, candidates two per lane
+    uint32_t okp = 0, okm = 0;
+    if (nc > 0) {
+        const uint32_t j0 = ev.jet_off[e];
+        if (sub < 2) {
+            const uint32_t q = sub == 0 ? kp : km;
+            double v[4];
+            polar_to_cart(ev.lep_pt[q], ev.lep_eta[q], ev.lep_phi[q], ev.lep_e[q], v);
+            double *dst = sub == 0 ? r.lp : r.lm;
+            for (int c = 0; c < 4; ++c) {
+                dst[c] = v[c];
+                s_lep[slot][4 * sub + c] = v[c];
+            }
+            const double m2 = v[0] * v[0] - v[1] * v[1] - v[2] * v[2] - v[3] * v[3];
+            if (sub == 0) r.ml2p = m2;
+            else r.ml2m = m2;
         }
+        wave_sync();
+        double lp[4], lm[4];
+        for (int c = 0; c < 4; ++c) {
+            lp[c] = s_lep[slot][c];
+            lm[c] = s_lep[slot][4 + c];
+        }
+        for (int c = sub; c < nc; c += kStageLanes) {
+            const uint32_t q = s_jl[slot][c];
+            double v[4];
+            const float en = ev.jet_e[q];
+            polar_to_cart(ev.jet_pt[q], ev.jet_eta[q], ev.jet_phi[q], en, v);
+            for (int u = 0; u < 4; ++u) r.cand[c][u] = v[u];
+            r.sigma[c] = sqrt(a.jet_a * a.jet_a / (double)en + a.jet_c * a.jet_c);
+            r.jidx[c] = (int32_t)(q - j0);
+            // valid sides (the same test as make_side)
+            double sd[kSide];
+            if (make_side(lp, v, sd)) okp |= 1u << c;
+            if (make_side(lm, v, sd)) okm |= 1u << c;
+        }
+    }
+    // the event's masks: OR over its eight lanes
+#pragma unroll
+    for (int off = 1; off < kStageLanes; off <<= 1) {
+        okp |= __shfl_xor(okp, off);
+        okm |= __shfl_xor(okm, off);
+    }
+    if (sub == 2) {
+        r.g = g;
+        if (in_chunk) {
+            r.met[0] = (double)ev.met_x[e];
+            r.met[1] = (double)ev.met_y[e];
+        }
+        r.nc = nc;
+        r.V = V;
+    }
+    if (sub == 3) {
+        int npair = 0;
         for (int c = 0; c < nc; ++c)
             if ((okp >> c) & 1u) npair += __popc(okm & ~(1u << c));
+        gcnt[k] = (npair > 0 && V > 0) ? (V + kGran - 1) / kGran : 0;
+        BestRec b;
+        b.score = -INFINITY;
+        b.x = b.y = 0.0;
+        b.v = b.p = kNoBest;
+        b.nsol = 0;
+        b.nc = nc;
+        best[k] = b;
     }
-    gcnt[k] = (npair > 0 && V > 0) ? (V + kGran - 1) / kGran : 0;
-    BestRec b;
-    b.score = -INFINITY;
-    b.x = b.y = 0.0;
-    b.v = b.p = kNoBest;
-    b.nsol = 0;
-    b.nc = nc;
-    best[k] = b;
 }
 
 // ------------------------------------------------------------ prefix sum
@@ -1382,9 +1373,10 @@ hipError_t launch_t(const EvView &ev, const int32_t *idx, const int64_t *count, 
     int64_t *tsum = reinterpret_cast<int64_t *>(ws + L.tsum);
     PartRec *part = reinterpret_cast<PartRec *>(ws + L.part);
     const int64_t eg = capacity > 0 ? (capacity + 255) / 256 : 1;
+    const int64_t sg = capacity > 0 ? (capacity + kStageEvents - 1) / kStageEvents : 1;
     if (capacity > 0) {
         const unsigned tiles = (unsigned)((capacity + kScanTile - 1) / kScanTile);
-        hipLaunchKernelGGL(k_stage, dim3((unsigned)eg), dim3(256), 0, s, ev, idx, count, capacity, a, stage, gcnt,
+        hipLaunchKernelGGL(k_stage, dim3((unsigned)sg), dim3(256), 0, s, ev, idx, count, capacity, a, stage, gcnt,
                            best);
         if (worklist) {
             hipLaunchKernelGGL(k_scan_tiles, dim3(tiles), dim3(256), 0, s, gcnt, count, capacity, tsum);
