@@ -305,13 +305,7 @@ def stream_leg(args, torch):
     print(f"[bench] stream: generated {len(pool)} chunks in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
     # chunk i reuses pool[i % P]'s kinematics with its own event ids (and so its own variation draws)
     host = [HostChunk(ev, 0) for ev in pool]
-    chunks = []
-    for i in range(n_chunks):
-        hc = host[i % len(host)]
-        view = object.__new__(HostChunk)
-        view.__dict__.update(hc.__dict__)
-        view.index_base = i * m
-        chunks.append(view)
+    chunks = [host[i % len(host)].with_base(i * m) for i in range(n_chunks)]
     lep_cap = max(c.n_lep for c in host)
     jet_cap = max(c.n_jet for c in host)
     chans = [Channel("dilepton", cfg["chains"]["dilepton"], m, reco=cfg["reco"]),

@@ -45,6 +45,14 @@ class HostChunk:
         nv = ev.get("n_var")
         self.t["n_var"] = None if nv is None else self._pinned(np.asarray(nv, dtype=np.int16))
 
+    def with_base(self, index_base):
+        """The same pinned columns under other global event ids (the ids key
+        the variation draws, so the events count as new ones)."""
+        other = object.__new__(HostChunk)
+        other.__dict__.update(self.__dict__)
+        other.index_base = int(index_base)
+        return other
+
     @staticmethod
     def _pinned(a):
         t = torch.empty(a.shape, dtype=torch.from_numpy(a[:0]).dtype, pin_memory=True)
