@@ -303,8 +303,9 @@ def stream_leg(args, torch):
     t0 = time.time()
     pool = [hfgen.stream_chunk(cfg, i)[0] for i in range(max(1, args.stream_pool))]
     print(f"[bench] stream: generated {len(pool)} chunks in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
-    # chunk i reuses pool[i % P]'s kinematics with its own event ids (and so its own variation draws)
-    host = [HostChunk(ev, 0) for ev in pool]
+    # chunk i reuses pool[i % P]'s kinematics with its own event ids (and so its own variation draws);
+    # chunks travel in the packed transfer format (bytes for counts, charges, b-tags) when lossless
+    host = [HostChunk(ev, 0, packed="auto") for ev in pool]
     chunks = [host[i % len(host)].with_base(i * m) for i in range(n_chunks)]
     lep_cap = max(c.n_lep for c in host)
     jet_cap = max(c.n_jet for c in host)
@@ -341,6 +342,17 @@ def stream_leg(args, torch):
     dt_comp = (time.perf_counter() - t2) / reps
     nbytes = sum(c.nbytes for c in chunks)
     n = m * n_chunks
+    # the same stream in the plain layout (32-bit offsets, float charges and b-tags), for comparison
+    plain_host = [HostChunk(ev, 0, packed=False) for ev in pool]
+    plain = [plain_host[i % len(plain_host)].with_base(i * m) for i in range(n_chunks)]
+    es.run(plain)
+    torch.cuda.synchronize()
+    es.reset()
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    es.run(plain)
+    torch.cuda.synchronize()
+    dt_plain = time.perf_counter() - t3
     leg = {"metric": "events/s end to end, pinned host chunks -> 2 channels (12 cuts, dileptonic quartic @64 "
                      "variations + single-neutrino chi^2)",
            "value": round(n / dt, 1), "unit": "events/s", "dtype": "f32+f64",
@@ -354,7 +366,10 @@ def stream_leg(args, torch):
            "compute_only": {"events_per_s": round(m / dt_comp, 1), "ms_per_chunk": round(1e3 * dt_comp, 4)},
            "overlap": round(max(dt_copy / n_chunks, dt_comp) / (dt / n_chunks), 3),
            "host_issue_ms_per_chunk": round(1e3 * t_issue / n_chunks, 4),
-           "h2d_GB_per_s_in_stream": round(nbytes / dt / 1e9, 2)}
+           "h2d_GB_per_s_in_stream": round(nbytes / dt / 1e9, 2),
+           "transfer_format": "packed" if all(c.packed for c in chunks) else "plain",
+           "plain_layout": {"events_per_s": round(n / dt_plain, 1), "ms_per_chunk": round(1e3 * dt_plain / n_chunks, 4),
+                            "input_bytes": int(sum(c.nbytes for c in plain))}}
     print(f"[bench] stream: {leg['ms_per_chunk']} ms/chunk, copy {leg['h2d_only']['ms_per_chunk']} ms, "
           f"compute {leg['compute_only']['ms_per_chunk']} ms", file=sys.stderr, flush=True)
     return leg

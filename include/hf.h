@@ -297,6 +297,28 @@ int hf_select_segment(const hf_events_t *ev, const hf_cut_t *h_cuts, int n_cuts,
                       uint8_t *d_survive, hf_counters_t *d_counters, void *d_ws, size_t ws_bytes,
                       hipStream_t stream);
 
+/* ------------------------------------------------------------- ingest */
+
+/* Workspace bytes hf_unpack_events needs for n events. */
+size_t hf_unpack_workspace_size(int64_t n);
+
+/* Rebuild the offsets and the charge and b-tag columns of hf_events_t from a
+ * packed transfer format, so that a chunk crosses the host link in fewer
+ * bytes (section 3: many events are loaded and processed at once; the
+ * loading is overlapped with the processing).  In: per-event lepton and jet
+ * counts as bytes d_lep_cnt[n], d_jet_cnt[n] (16-byte aligned), charges as
+ * signed bytes d_lep_q8[n_lep], b-tags as bytes d_jet_btag8[n_jet].  Out:
+ * d_lep_off[n + 1], d_jet_off[n + 1] (exclusive prefix sums of the counts),
+ * d_lep_q[n_lep], d_jet_btag[n_jet] (the bytes as float32).  The other
+ * columns travel as float32 unchanged.  Byte and integer work: the result
+ * equals the unpacked columns exactly; the counts must sum to n_lep and
+ * n_jet, both below 2^32.  Asynchronous, allocates nothing.  Errors:
+ * HF_ERR_INVAL for null pointers, sizes out of range or misaligned counts;
+ * HF_ERR_CAPACITY for a short workspace. */
+int hf_unpack_events(int64_t n, const uint8_t *d_lep_cnt, const uint8_t *d_jet_cnt, int64_t n_lep, int64_t n_jet,
+                     const int8_t *d_lep_q8, const uint8_t *d_jet_btag8, uint32_t *d_lep_off, uint32_t *d_jet_off,
+                     float *d_lep_q, float *d_jet_btag, void *d_ws, size_t ws_bytes, hipStream_t stream);
+
 /* ------------------------------------------------ user-defined cuts */
 
 /* A cut chain with user predicates (section 3: the user registers each cut

@@ -120,6 +120,9 @@ def lib():
                                         P, C.c_size_t, P]
         L.hf_chain_select_segment.argtypes = [P, C.POINTER(Events), P, C.c_int, C.c_int, P, P, C.c_int64, P, P, P,
                                               C.c_size_t, P]
+        L.hf_unpack_workspace_size.argtypes = [C.c_int64]
+        L.hf_unpack_workspace_size.restype = C.c_size_t
+        L.hf_unpack_events.argtypes = [C.c_int64, P, P, C.c_int64, C.c_int64, P, P, P, P, P, P, P, C.c_size_t, P]
         L.hf_chain_log.argtypes = [P]
         L.hf_chain_log.restype = C.c_char_p
         L.hf_chain_destroy.argtypes = [P]
@@ -130,7 +133,8 @@ def lib():
                                       C.POINTER(SemilepOut), P, P]
         for f in ("hf_select", "hf_compact", "hf_ttbar_reco", "hf_ttbar_reco_autotune", "hf_reorder_stats",
                   "hf_reorder_device", "hf_philox_blocks", "hf_gauss_draws", "hf_semilep_reco", "hf_chain_compile",
-                  "hf_chain_select", "hf_dilep_chi2_reco", "hf_select_segment", "hf_chain_select_segment"):
+                  "hf_chain_select", "hf_dilep_chi2_reco", "hf_select_segment", "hf_chain_select_segment",
+                  "hf_unpack_events"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -268,6 +272,14 @@ def select_segment(dev, cuts_arr, n_cuts, order, pos_begin, pos_end, survive, co
     else:
         rc = lib().hf_select_segment(dev.ptr, C.cast(cuts_arr, C.c_void_p), n_cuts, _p(order), *args)
     _check(rc, "hf_select_segment")
+
+
+def unpack_events(n, lep_cnt, jet_cnt, n_lep, n_jet, lep_q8, jet_btag8, lep_off, jet_off, lep_q, jet_btag, ws,
+                  stream=None):
+    rc = lib().hf_unpack_events(int(n), _p(lep_cnt), _p(jet_cnt), int(n_lep), int(n_jet), _p(lep_q8), _p(jet_btag8),
+                                _p(lep_off), _p(jet_off), _p(lep_q), _p(jet_btag), _p(ws),
+                                ws.numel() * ws.element_size(), _stream(stream))
+    _check(rc, "hf_unpack_events")
 
 
 def compact(mask, capacity, idx, count, ws, d_n=None, index_base=0, mapping=None, stream=None):

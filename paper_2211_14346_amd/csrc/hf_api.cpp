@@ -16,6 +16,7 @@
 #include "hf_internal.hpp"
 #include "hf_reco_math.hpp"
 #include "hf_rtc.hpp"
+#include "hf_unpack.hpp"
 
 namespace {
 
@@ -487,6 +488,28 @@ int hf_dilep_chi2_reco(const hf_events_t *ev, const int32_t *d_idx, const int64_
     hf_counters_t *rc = (d_counters && p->reco_cut >= 0) ? d_counters + p->reco_cut : nullptr;
     hipError_t e = hf::launch_chi2(hf::make_view(*ev), d_idx, d_count, capacity, a, o, rc, stream);
     if (e != hipSuccess) return device_fail("hf_dilep_chi2_reco launch", e);
+    return HF_OK;
+}
+
+size_t hf_unpack_workspace_size(int64_t n) { return n < 0 ? 0 : hf::unpack_ws_bytes(n); }
+
+int hf_unpack_events(int64_t n, const uint8_t *d_lep_cnt, const uint8_t *d_jet_cnt, int64_t n_lep, int64_t n_jet,
+                     const int8_t *d_lep_q8, const uint8_t *d_jet_btag8, uint32_t *d_lep_off, uint32_t *d_jet_off,
+                     float *d_lep_q, float *d_jet_btag, void *d_ws, size_t ws_bytes, hipStream_t stream) {
+    if (n < 0 || n >= ((int64_t)1 << 31)) return fail(HF_ERR_INVAL, "hf_unpack_events: n out of range [0, 2^31)");
+    if (n_lep < 0 || n_jet < 0 || n_lep >= ((int64_t)1 << 32) || n_jet >= ((int64_t)1 << 32))
+        return fail(HF_ERR_INVAL, "hf_unpack_events: object counts out of range [0, 2^32)");
+    if (!d_lep_off || !d_jet_off || (n > 0 && (!d_lep_cnt || !d_jet_cnt)) || (n_lep > 0 && (!d_lep_q8 || !d_lep_q)) ||
+        (n_jet > 0 && (!d_jet_btag8 || !d_jet_btag)))
+        return fail(HF_ERR_INVAL, "hf_unpack_events: a pointer is NULL");
+    if (((uintptr_t)d_lep_cnt | (uintptr_t)d_jet_cnt) & 15u)
+        return fail(HF_ERR_INVAL, "hf_unpack_events: the count arrays must be 16-byte aligned");
+    const size_t need = hf::unpack_ws_bytes(n);
+    if (!d_ws || ws_bytes < need)
+        return fail(HF_ERR_CAPACITY, "hf_unpack_events: workspace %zu bytes < %zu required", ws_bytes, need);
+    hipError_t e = hf::launch_unpack(n, d_lep_cnt, d_jet_cnt, n_lep, n_jet, d_lep_q8, d_jet_btag8, d_lep_off,
+                                     d_jet_off, d_lep_q, d_jet_btag, d_ws, stream);
+    if (e != hipSuccess) return device_fail("hf_unpack_events launch", e);
     return HF_OK;
 }
 

@@ -23,25 +23,52 @@ import torch
 from . import binding as B
 
 COLS = B.DeviceEvents.COLS
+PACKED_FLOAT_COLS = tuple(k for k in COLS if k not in ("lep_q", "jet_btag"))
+
+
+def pack_plan(ev):
+    """True when a sample can travel in the packed transfer format without
+    loss: fewer than 256 leptons and jets per event, integer charges in
+    [-128, 127] and integer b-tags in [0, 255] (hf_unpack_events rebuilds the
+    offsets and the float columns from bytes)."""
+    lc = np.diff(np.asarray(ev["lep_off"], dtype=np.int64))
+    jc = np.diff(np.asarray(ev["jet_off"], dtype=np.int64))
+    q = np.asarray(ev["lep_q"], dtype=np.float32)
+    b = np.asarray(ev["jet_btag"], dtype=np.float32)
+    return bool((lc.size == 0 or (lc.max() < 256 and jc.max() < 256)) and np.all(q == np.rint(q)) and
+                np.all((q >= -128) & (q <= 127)) and np.all(b == np.rint(b)) and np.all((b >= 0) & (b <= 255)))
 
 
 class HostChunk:
-    """One chunk of events in pinned host memory (the ingest layout of
-    include/hf.h: float32 columns, 32-bit offsets)."""
+    """One chunk of events in pinned host memory: the ingest layout of
+    include/hf.h (float32 columns, 32-bit offsets), or with packed=True (or
+    "auto" when lossless) the packed transfer format: per-event object
+    counts, charges and b-tags as bytes, the other columns as float32."""
 
-    def __init__(self, ev, index_base=0):
+    def __init__(self, ev, index_base=0, packed=False):
         self.n = int(ev["n"])
         self.index_base = int(index_base)
         self.n_lep = int(ev["lep_off"][-1])
         self.n_jet = int(ev["jet_off"][-1])
+        if packed == "auto":
+            packed = pack_plan(ev)
+        elif packed and not pack_plan(ev):
+            raise ValueError("this sample cannot be packed without loss")
+        self.packed = bool(packed)
         self.t = {}
-        for k in COLS:
+        for k in (PACKED_FLOAT_COLS if self.packed else COLS):
             self.t[k] = self._pinned(np.ascontiguousarray(ev[k], dtype=np.float32))
-        for k in ("lep_off", "jet_off"):
-            off = np.asarray(ev[k], dtype=np.int64)
-            if off[-1] >= 2 ** 31:
-                raise ValueError(f"{k}: object count too large for a chunk")
-            self.t[k] = self._pinned(off.astype(np.int32))
+        if self.packed:
+            self.t["lep_cnt"] = self._pinned(np.diff(np.asarray(ev["lep_off"], dtype=np.int64)).astype(np.uint8))
+            self.t["jet_cnt"] = self._pinned(np.diff(np.asarray(ev["jet_off"], dtype=np.int64)).astype(np.uint8))
+            self.t["lep_q8"] = self._pinned(np.asarray(ev["lep_q"], dtype=np.float32).astype(np.int8))
+            self.t["jet_btag8"] = self._pinned(np.asarray(ev["jet_btag"], dtype=np.float32).astype(np.uint8))
+        else:
+            for k in ("lep_off", "jet_off"):
+                off = np.asarray(ev[k], dtype=np.int64)
+                if off[-1] >= 2 ** 31:
+                    raise ValueError(f"{k}: object count too large for a chunk")
+                self.t[k] = self._pinned(off.astype(np.int32))
         nv = ev.get("n_var")
         self.t["n_var"] = None if nv is None else self._pinned(np.asarray(nv, dtype=np.int16))
 
@@ -79,6 +106,12 @@ class DeviceSlot:
         self.s = B.Events(n=0, index_base=0, **{k: (None if v is None else v.data_ptr()) for k, v in self.t.items()})
         self.n = 0
         self.index_base = 0
+        # landing buffers of the packed transfer format (counts 16-byte aligned)
+        self.p = {"lep_cnt": torch.zeros(max(16, self.n_cap), dtype=torch.uint8, device=device),
+                  "jet_cnt": torch.zeros(max(16, self.n_cap), dtype=torch.uint8, device=device),
+                  "lep_q8": torch.zeros(max(1, self.lep_cap), dtype=torch.int8, device=device),
+                  "jet_btag8": torch.zeros(max(1, self.jet_cap), dtype=torch.uint8, device=device)}
+        self.ws_unpack = B.workspace(B.lib().hf_unpack_workspace_size(self.n_cap), device)
 
     @property
     def ptr(self):
@@ -94,7 +127,12 @@ class DeviceSlot:
         with torch.cuda.stream(stream):
             for k, src in hc.t.items():
                 if src is not None and src.numel():
-                    self.t[k][:src.numel()].copy_(src, non_blocking=True)
+                    dst = self.p[k] if k in self.p else self.t[k]
+                    dst[:src.numel()].copy_(src, non_blocking=True)
+        if hc.packed:
+            B.unpack_events(hc.n, self.p["lep_cnt"], self.p["jet_cnt"], hc.n_lep, hc.n_jet, self.p["lep_q8"],
+                            self.p["jet_btag8"], self.t["lep_off"], self.t["jet_off"], self.t["lep_q"],
+                            self.t["jet_btag"], self.ws_unpack, stream)
         self.n = hc.n
         self.index_base = hc.index_base
         self.s.n = hc.n

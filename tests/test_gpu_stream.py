@@ -33,11 +33,12 @@ def B():
     return binding
 
 
-def _setup(n_chunk, n_chunks):
+def _setup(n_chunk, n_chunks, packed=False):
     from paper_2211_14346_amd.stream import Channel, EventStream, HostChunk
     cfg = hfgen.config("hlhc50M")
     samples = [hfgen.stream_chunk(cfg, i, n=n_chunk) for i in range(n_chunks)]
-    chunks = [HostChunk(ev, base) for ev, base in samples]
+    chunks = [HostChunk(ev, base, packed=packed) for ev, base in samples]
+    assert all(c.packed == bool(packed) for c in chunks)
     lep_cap = max(c.n_lep for c in chunks)
     jet_cap = max(c.n_jet for c in chunks) + 3  # ragged: slots larger than any chunk
     chans = [Channel("dilepton", cfg["chains"]["dilepton"], n_chunk, reco=cfg["reco"]),
@@ -46,8 +47,9 @@ def _setup(n_chunk, n_chunks):
     return cfg, samples, chunks, chans, es
 
 
-def test_stream_chunks_match_oracle(B, orc):
-    cfg, samples, chunks, chans, es = _setup(20000, 3)
+@pytest.mark.parametrize("packed", [False, True])
+def test_stream_chunks_match_oracle(B, orc, packed):
+    cfg, samples, chunks, chans, es = _setup(20011, 3, packed)
     sums = [np.zeros((ch.n_cuts, 2), dtype=np.uint64) for ch in chans]
     seen = []
 
@@ -125,3 +127,35 @@ def test_stream_overlapped_matches_oracle(B, orc):
         ev, base = samples[-1]
         surv, _, _ = orc.select(ev, ch.cuts, list(range(ch.n_cuts)), index_base=base)
         assert np.array_equal(last["survive"], surv), ch.name
+
+
+@pytest.mark.parametrize("n", [0, 1, 17, 20011, 70000])
+def test_unpack_events_bit_exact(B, n):
+    """hf_unpack_events rebuilds offsets, charges and b-tags exactly."""
+    from paper_2211_14346_amd.stream import pack_plan
+    cfg = hfgen.config("hlhc50M")
+    ev = hfgen.generate(cfg, n_events=n, seed=600 + n)
+    assert pack_plan(ev)
+    lc = np.diff(ev["lep_off"].astype(np.int64)).astype(np.uint8)
+    jc = np.diff(ev["jet_off"].astype(np.int64)).astype(np.uint8)
+    n_lep, n_jet = int(ev["lep_off"][-1]), int(ev["jet_off"][-1])
+    dev = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a)).to(dt).cuda() if a.size else \
+        torch.zeros(16, dtype=dt, device="cuda")
+    d_lc = torch.zeros(max(16, n + 16), dtype=torch.uint8, device="cuda")
+    d_jc = torch.zeros(max(16, n + 16), dtype=torch.uint8, device="cuda")
+    if n:
+        d_lc[:n] = torch.as_tensor(lc).cuda()
+        d_jc[:n] = torch.as_tensor(jc).cuda()
+    q8 = dev(ev["lep_q"].astype(np.int8), torch.int8)
+    b8 = dev(ev["jet_btag"].astype(np.uint8), torch.uint8)
+    loff = torch.full((n + 1,), -1, dtype=torch.int32, device="cuda")
+    joff = torch.full((n + 1,), -1, dtype=torch.int32, device="cuda")
+    q = torch.full((max(1, n_lep),), 9.0, dtype=torch.float32, device="cuda")
+    b = torch.full((max(1, n_jet),), 9.0, dtype=torch.float32, device="cuda")
+    ws = B.workspace(B.lib().hf_unpack_workspace_size(n))
+    B.unpack_events(n, d_lc, d_jc, n_lep, n_jet, q8, b8, loff, joff, q, b, ws)
+    torch.cuda.synchronize()
+    assert np.array_equal(loff.cpu().numpy().astype(np.int64), ev["lep_off"].astype(np.int64))
+    assert np.array_equal(joff.cpu().numpy().astype(np.int64), ev["jet_off"].astype(np.int64))
+    assert np.array_equal(q.cpu().numpy()[:n_lep], ev["lep_q"].astype(np.float32))
+    assert np.array_equal(b.cpu().numpy()[:n_jet], ev["jet_btag"].astype(np.float32))
