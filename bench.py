@@ -41,8 +41,8 @@ STREAM_WORKLOAD = "hlhc50M"
 # eliminant and root intervals; per root interval the Newton solve, recovery
 # of y, acceptance test and score.
 FLOP_PER_VARIATION = 78
-FLOP_PER_PAIRING = 286
-FLOP_PER_INTERVAL = 196
+FLOP_PER_PAIRING = 289
+FLOP_PER_INTERVAL = 216
 
 # MI355X vector peaks (256 CUs at 2.4 GHz): FP64 78.6 TFLOP/s; FP32 157.3 with
 # packed FP32, which this build does not use (non-packed FP32 issues at the

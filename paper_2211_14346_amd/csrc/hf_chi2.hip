@@ -33,6 +33,7 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / kWave;
 constexpr int kMaxC = HF_MAX_CANDS;
+constexpr int kRefPts = 25;  // points of a refinement level (5 x 5)
 
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
@@ -224,6 +225,8 @@ __global__ __launch_bounds__(kBlock) void k_chi2(EvView ev, const int32_t *__res
     __shared__ double s_cv[kWaves][kMaxC * 4];
     __shared__ int s_loc[kWaves][kMaxC];
     __shared__ uint32_t s_pass[kWaves];
+    __shared__ double s_t[kWaves][kRefPts][kMaxC];  // refinement: l+ term per point and candidate
+    __shared__ int s_r[kWaves][kRefPts][kMaxC];     // and its p_z root
     const int wave = threadIdx.x / kWave, lane = lane_id();
     const int64_t S = clamp_count(count, capacity);
     const int64_t k = (int64_t)blockIdx.x * kWaves + wave;
@@ -319,17 +322,27 @@ __global__ __launch_bounds__(kBlock) void k_chi2(EvView ev, const int32_t *__res
             {
                 double val = INFINITY;
                 int pidx = 0x7fffffff, pk = 0;
+                // row and column of point p = p0 + lane, advanced by 64 points per pass
+                // (no integer division in the loop)
+                int row = lane / N, col = lane % N;
+                const int drow = kWave / N, dcol = kWave % N;
                 for (int p0 = 0; p0 < N * N; p0 += kWave) {
                     const int p = p0 + lane;
                     if (p < N * N) {
                         int q;
-                        const double t = point_best(LP, LM, cv, nc, mx, my, -a.half_range + step * (p / N),
-                                                    -a.half_range + step * (p % N), a, q);
+                        const double t = point_best(LP, LM, cv, nc, mx, my, -a.half_range + step * row,
+                                                    -a.half_range + step * col, a, q);
                         if (t < val) {
                             val = t;
                             pidx = p;
                             pk = q;
                         }
+                    }
+                    row += drow;
+                    col += dcol;
+                    if (col >= N) {
+                        col -= N;
+                        ++row;
                     }
                 }
                 wave_argmin(val, pidx, pk);
@@ -338,20 +351,69 @@ __global__ __launch_bounds__(kBlock) void k_chi2(EvView ev, const int32_t *__res
                 bu = -a.half_range + step * (pidx / N);
                 bv = -a.half_range + step * (pidx % N);
             }
-            // ---- refinements: 5 x 5 around the best point, a quarter of the step
+            // ---- refinements: 5 x 5 around the best point, a quarter of the step.
+            // 25 points would leave most lanes idle, so the two lepton sides go to
+            // different lanes: lanes [0, 25) take the l+ side of point q = lane and
+            // keep each candidate's term in LDS, lanes [32, 57) the l- side of point
+            // q = lane - 32 and keep its two smallest terms, which then go to the l+
+            // lane of the same point (the same operations as point_best).
             for (int level = 0; level < a.n_refine; ++level) {
                 step *= 0.25;
+                const bool plus = lane < 32;
+                const int q = plus ? lane : lane - 32;
+                double va = INFINITY, vb = INFINITY;
+                int ja = -1, jb = -1, ra = 0, rb = 0;
+                if (q < kRefPts) {
+                    const double u = bu + step * (q / 5 - 2), v = bv + step * (q % 5 - 2);
+                    const Side Sd = plus ? side(LP, 0.5 * mx + u, 0.5 * my + v, a)
+                                         : side(LM, 0.5 * mx - u, 0.5 * my - v, a);
+                    for (int c = 0; c < nc; ++c) {
+                        int r;
+                        const double t = side_min(cv + 4 * c, Sd, a, r);
+                        if (plus) {
+                            s_t[wave][q][c] = t;
+                            s_r[wave][q][c] = r;
+                        } else if (t < va) {
+                            vb = va;
+                            jb = ja;
+                            rb = ra;
+                            va = t;
+                            ja = c;
+                            ra = r;
+                        } else if (t < vb) {
+                            vb = t;
+                            jb = c;
+                            rb = r;
+                        }
+                    }
+                }
+                wave_sync();
+                const int src = (lane + 32) & (kWave - 1);
+                const double mva = __shfl(va, src), mvb = __shfl(vb, src);
+                const int mja = __shfl(ja, src), mjb = __shfl(jb, src);
+                const int mra = __shfl(ra, src), mrb = __shfl(rb, src);
                 double val = INFINITY;
                 int pidx = 0x7fffffff, pk = 0;
-                if (lane < 25) {
-                    int q;
-                    const double t = point_best(LP, LM, cv, nc, mx, my, bu + step * (lane / 5 - 2),
-                                                bv + step * (lane % 5 - 2), a, q);
-                    val = t;
-                    pidx = lane;
-                    pk = q;
+                if (plus && q < kRefPts) {
+                    double best = INFINITY;
+                    int packed = 0;
+                    for (int i = 0; i < nc; ++i) {
+                        const double t1 = s_t[wave][q][i];
+                        const int r1 = s_r[wave][q][i];
+                        const bool other = i != mja;
+                        const int j = other ? mja : mjb;
+                        const double t = t1 + (other ? mva : mvb);
+                        if (j >= 0 && t < best) {
+                            best = t;
+                            packed = i | (j << 4) | (r1 << 8) | ((other ? mra : mrb) << 9);
+                        }
+                    }
+                    val = best;
+                    pidx = q;
+                    pk = packed;
                 }
                 wave_argmin(val, pidx, pk);
+                wave_sync();  // the next level overwrites the l+ terms
                 if (val < bval) {
                     bval = val;
                     bpk = pk;

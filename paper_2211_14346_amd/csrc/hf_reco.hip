@@ -24,7 +24,7 @@
 // pairing of its event, assembles the eliminant quartic in FP64 and brackets
 // its real roots (critical points from the closed-form cubic in T, one FP64
 // Newton step each); the wavefront then deals the root intervals out 64 at
-// a time: Newton in FP64, recovery and polish of (x, y), the acceptance
+// a time: Halley iteration in FP64, recovery and polish of (x, y), the acceptance
 // test, the energies' signs and the score, each result handed back to the
 // lane that owns the variation.  A segmented argmax with a total-order
 // tie-break (score, then smallest variation, pairing, x) gives each event's

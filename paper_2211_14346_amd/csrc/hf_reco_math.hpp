@@ -24,8 +24,8 @@
 
 // Host-and-device so that the numerics can also be exercised on the CPU.
 #define HF_HD __host__ __device__
-#ifndef HF_NEWTON_HOOK
-#define HF_NEWTON_HOOK()
+#ifndef HF_ITER_HOOK
+#define HF_ITER_HOOK()
 #endif
 
 namespace hf {
@@ -166,7 +166,7 @@ HF_HD __forceinline__ void eliminant(const Conic &P, const Conic &Q, double q[5]
 // Real roots of the quartic by critical points: the critical points (roots
 // of the derivative) come from the closed-form cubic in precision T and are
 // polished once in FP64; every monotone interval whose end values differ in
-// sign is then solved by Newton's method in FP64, safeguarded by bisection.
+// sign is then solved by Halley's method in FP64, safeguarded by bisection.
 // Like the oracle, the polynomial is taken in t = x / 100 GeV, normalised by
 // its largest coefficient, and coefficients <= 1e-14 are dropped from the top.
 
@@ -198,12 +198,27 @@ HF_HD __forceinline__ double peval_d2(const Poly4 &c, double t) {
 
 // Elementary functions for the templated cubic.  FP64: the accurate library
 // functions.  FP32 (seeds only, refined in FP64 afterwards): hardware
-// approximations -- cube root through the base-2 exponential and logarithm
-// units, arc cosine by the four-term approximation of Abramowitz & Stegun
-// 4.4.45 (|error| < 7e-5 rad), cosine/sine through the revolution-scaled
-// hardware units.
-HF_HD __forceinline__ float tsqrt(float v) { return sqrtf(v); }
+// approximations -- square root and reciprocal by the single-instruction
+// units (about one ulp, no correction sequence), cube root through the base-2
+// exponential and logarithm units, arc cosine by the four-term approximation
+// of Abramowitz & Stegun 4.4.45 (|error| < 7e-5 rad), cosine/sine through the
+// revolution-scaled hardware units.
+HF_HD __forceinline__ float tsqrt(float v) {
+#ifdef __HIP_DEVICE_COMPILE__
+    return __builtin_amdgcn_sqrtf(v);
+#else
+    return sqrtf(v);
+#endif
+}
 HF_HD __forceinline__ double tsqrt(double v) { return sqrt(v); }
+HF_HD __forceinline__ float trcp(float v) {
+#ifdef __HIP_DEVICE_COMPILE__
+    return __builtin_amdgcn_rcpf(v);
+#else
+    return 1.0f / v;
+#endif
+}
+HF_HD __forceinline__ double trcp(double v) { return 1.0 / v; }
 HF_HD __forceinline__ double tcbrt(double v) { return cbrt(v); }
 HF_HD __forceinline__ float tcbrt(float v) {
 #ifdef __HIP_DEVICE_COMPILE__
@@ -253,12 +268,12 @@ HF_HD __forceinline__ int cubic_roots(T A, T B, T C, T &r0, T &r1, T &r2) {
         const T sq = tsqrt(disc);
         const T w = -h - (h >= (T)0 ? sq : -sq);
         const T u = tcbrt(w);
-        const T r = (u != (T)0) ? u - p3 / u : (T)0;
+        const T r = (u != (T)0) ? u - p3 * trcp(u) : (T)0;
         r0 = r1 = r2 = r - a3;
         return 1;
     }
     const T rr = tsqrt(tmax(-p3, (T)0));
-    T cosarg = (rr > (T)0) ? -h / (rr * rr * rr) : (T)0;
+    T cosarg = (rr > (T)0) ? -h * trcp(rr * rr * rr) : (T)0;
     cosarg = tmin(tmax(cosarg, (T)-1), (T)1);
     const T phi = tacos(cosarg) * third;
     T sn, cs;
@@ -275,20 +290,23 @@ HF_HD __forceinline__ int cubic_roots(T A, T B, T C, T &r0, T &r1, T &r2) {
 }
 
 // Root of c on (lo, hi) where c(lo) < 0 iff lo_neg; x is the first iterate.
-// Newton steps that leave the bracket are replaced by bisection.  Converged
-// when the Newton step is below 1e-12 max(1, |t|) (t = x / 100 GeV), or below
-// 1e-7 max(1, |t|) and 1e-3 of the previous step (quadratic convergence: the
-// error after that step is of the order of its square).  The test comes
-// before the bracket update so that an iterate sitting on a bracket end at
-// convergence is not bisected away.  A root next to a critical point (a near
-// double root) is fixed only to the polynomial's rounding, where the step
-// tests can fail forever: from the sixth iterate on, the search also stops
-// when |p| is at its rounding floor (1e-15 of the sum of its terms'
-// magnitudes) or the bracket is narrower than the tolerance.
-HF_HD __forceinline__ double bracket_newton(const Poly4 &c, double lo, double hi, bool lo_neg, double x) {
+// Halley's step  dx = p p' / (p'^2 - p p'' / 2)  (cubic convergence, so a
+// wavefront's slowest lane needs fewer iterations), taken as the Newton step
+// p / p' wherever Halley's correction factor p'^2 / (p'^2 - p p'' / 2) leaves
+// (1/2, 2), i.e. far from the root; steps that leave the bracket are replaced
+// by bisection.  Converged when the step is below 1e-12 max(1, |t|) (t = x /
+// 100 GeV), or below 1e-7 max(1, |t|) and 1e-3 of the previous step (the
+// error after that step is far below its size).  The test comes before the
+// bracket update so that an iterate sitting on a bracket end at convergence
+// is not bisected away.  A root next to a critical point (a near double root)
+// is fixed only to the polynomial's rounding, where the step tests can fail
+// forever: from the sixth iterate on, the search also stops when |p| is at
+// its rounding floor (1e-15 of the sum of its terms' magnitudes) or the
+// bracket is narrower than the tolerance.
+HF_HD __forceinline__ double bracket_halley(const Poly4 &c, double lo, double hi, bool lo_neg, double x) {
     double dx_prev = 0.0;
     for (int it = 0; it < 60; ++it) {
-        HF_NEWTON_HOOK();
+        HF_ITER_HOOK();
         double p, dp;
         peval_d(c, x, p, dp);
         if (p == 0.0) return x;
@@ -296,7 +314,11 @@ HF_HD __forceinline__ double bracket_newton(const Poly4 &c, double lo, double hi
             lo = x;
         else
             hi = x;
-        const double dx = p * fast_rcp(dp);
+        const double d2 = peval_d2(c, x);
+        const double g = dp * dp;
+        const double hd = fma(-0.5 * p, d2, g);
+        const double den = (hd > 0.5 * g && hd < 2.0 * g) ? hd : g;
+        const double dx = p * dp * fast_rcp(den);
         const double tol = 1e-12 * fmax(1.0, fabs(x));
         if (fabs(dx) <= tol) return x - dx;
         if (it >= 1 && fabs(dx) <= 1e5 * tol && fabs(dx) <= 1e-3 * fabs(dx_prev)) return x - dx;
@@ -332,7 +354,7 @@ HF_HD __forceinline__ void solve_interval(const Poly4 &c, double lo, double hi, 
         const double fv = from_lo ? flo : fhi;
         const double r = -2.0 * fv * fast_rcp(peval_d2(c, cp));
         if (r > 0.0)
-            x0 = from_lo ? cp + sqrt(r) : cp - sqrt(r);
+            x0 = from_lo ? cp + fast_sqrt(r) : cp - fast_sqrt(r);
         else
             x0 = (lo_crit && hi_crit) ? lo : from_lo ? cp + fmax(1.0, fabs(cp)) : cp - fmax(1.0, fabs(cp));
         if (lo_crit && hi_crit && !(x0 > lo && x0 < hi)) x0 = lo - flo * (hi - lo) * fast_rcp(fhi - flo);
@@ -340,15 +362,15 @@ HF_HD __forceinline__ void solve_interval(const Poly4 &c, double lo, double hi, 
         x0 = 0.0;
     }
     if (!(x0 > lo && x0 < hi)) x0 = 0.5 * (lo + hi);
-    root = kXScale * bracket_newton(c, lo, hi, flo < 0.0, x0);
+    root = kXScale * bracket_halley(c, lo, hi, flo < 0.0, x0);
     found = true;
 }
 
 // Sign-changing real roots of q0 + q1 x + ... + q4 x^4 by critical points:
 // the roots of the derivative (closed-form cubic in precision T, one FP64
 // Newton step each) split the line into monotone intervals; each interval
-// whose end values differ in sign holds one root, found by safeguarded Newton
-// in FP64.  As in the oracle, the polynomial is taken in t = x / 100 GeV,
+// whose end values differ in sign holds one root, found by safeguarded
+// Halley iteration in FP64.  As in the oracle, the polynomial is taken in t = x / 100 GeV,
 // normalised by its largest coefficient, and leading coefficients <= 1e-14
 // are dropped; the outer intervals end at the Cauchy bound.
 //
