@@ -38,7 +38,7 @@ STREAM_WORKLOAD = "hlhc50M"
 # own math header on the host with counting scalar types over a sample of
 # this workload: per variation the Box-Muller draws, smear factors, MET shifts
 # and lepton-side terms; per pairing the side terms, MET substitution,
-# eliminant and root intervals; per root interval the Newton solve, recovery
+# eliminant and root intervals; per root interval the Halley solve, recovery
 # of y, acceptance test and score.
 FLOP_PER_VARIATION = 78
 FLOP_PER_PAIRING = 289

@@ -10,7 +10,7 @@
 // Input (binary, float64 rows of 18 values): l+ (E, px, py, pz), b, l-,
 // bbar, MET x, MET y, of one smeared pairing.  Output: the mean operation
 // counts per pairing for stage 1 (quartic assembly, intervals) and per
-// solved interval (Newton, recovery of y, acceptance, score), and the share
+// solved interval (Halley iteration, recovery of y, acceptance, score), and the share
 // of pairings and intervals.
 #include <cmath>
 #include <cstdio>
