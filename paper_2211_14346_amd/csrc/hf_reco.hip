@@ -113,6 +113,7 @@ struct WaveStage {
     int gb_v[kGpb], gb_p[kGpb], gb_n[kGpb];
     T z[kMaxC][kWave];  // per-lane draw of each candidate of the lane's event
     T zl[4][kWave];     // per-lane draws of l+, l-, MET x, MET y
+    PartRec headp, tailp;  // partial records of the range's first and last event
 };
 
 __device__ __forceinline__ void wave_sync() {
@@ -507,16 +508,19 @@ __global__ __launch_bounds__(kRecoBlock, 2) void k_search(const int64_t *__restr
     int open_nc = 0;
     bool open_head = false;
     Acc acc{-INFINITY, 0.0, 0.0, kNoBest, kNoBest, 0};
-    PartRec headp, tailp;
-    headp.k = b0 < b1 ? -1 : -2;
-    tailp.k = -1;
-    headp.cont = tailp.cont = 0;
+    // the partial records live in LDS (lane 0 writes them) rather than in
+    // registers for the whole kernel
+    if (lane == 0) {
+        st.headp.k = b0 < b1 ? -1 : -2;
+        st.tailp.k = -1;
+        st.headp.cont = st.tailp.cont = 0;
+    }
 
     auto flush = [&](bool cont) {
         if (open_k < 0) return;
         if (lane == 0) {
             if (open_head || cont) {
-                PartRec &pr = open_head ? headp : tailp;
+                PartRec &pr = open_head ? st.headp : st.tailp;
                 pr.k = open_k;
                 pr.cont = cont ? 1 : 0;
                 pr.nsol = acc.n;
@@ -880,8 +884,8 @@ __global__ __launch_bounds__(kRecoBlock, 2) void k_search(const int64_t *__restr
         flush(cont);
     }
     if (lane == 0) {
-        part[2 * wid] = headp;
-        part[2 * wid + 1] = tailp;
+        part[2 * wid] = st.headp;
+        part[2 * wid + 1] = st.tailp;
     }
     // intervals and variations are counted per lane
     uint64_t ni = acc_int, nv = acc_var, npr = acc_pair, nso = acc_sol;
