@@ -96,7 +96,6 @@ struct WaveStageEv {
     StageRec rec;
     double sp[kMaxC][kSide];  // side constants with l+
     double sm[kMaxC][kSide];  // side constants with l-
-    int okp[kMaxC], okm[kMaxC];
     T z[kMaxC][kWave];  // per-lane draw of each candidate
     T zl[4][kWave];     // per-lane draws of l+, l-, MET x, MET y
 };
@@ -947,14 +946,21 @@ __global__ __launch_bounds__(kRecoBlock, 2) void k_search_ev(const int64_t *__re
         wave_sync();
         const int nc = __builtin_amdgcn_readfirstlane(st.rec.nc);
         const bool ok = nc >= 2;
+        // valid sides as wave-uniform bit masks: bit c of okp / okm when the
+        // l+ / l- side with candidate c is not degenerate
+        uint32_t okp = 0, okm = 0;
         if (ok) {
             // side constants: lanes [0, nc) with l+, lanes [16, 16 + nc) with l-
+            bool side_ok = false;
             if (lane < nc) {
-                st.okp[lane] = make_side(st.rec.lp, st.rec.cand[lane], st.sp[lane]) ? 1 : 0;
+                side_ok = make_side(st.rec.lp, st.rec.cand[lane], st.sp[lane]);
             } else if (lane >= 16 && lane < 16 + nc) {
                 const int c = lane - 16;
-                st.okm[c] = make_side(st.rec.lm, st.rec.cand[c], st.sm[c]) ? 1 : 0;
+                side_ok = make_side(st.rec.lm, st.rec.cand[c], st.sm[c]);
             }
+            const uint64_t okb = ballot(side_ok);
+            okp = (uint32_t)okb & 0xffffu;
+            okm = (uint32_t)(okb >> 16) & 0xffffu;
             wave_sync();
         }
 
@@ -963,11 +969,8 @@ __global__ __launch_bounds__(kRecoBlock, 2) void k_search_ev(const int64_t *__re
         double best_s = -INFINITY, best_x = 0.0, best_y = 0.0;
         int best_v = kNoBest, best_p = kNoBest;
         int nsol = 0;
-        int npair_valid = 0;
-        if (ok) {
-            for (int i = 0; i < nc; ++i)
-                for (int j = 0; j < nc; ++j) npair_valid += (i != j && st.okp[i] && st.okm[j]) ? 1 : 0;
-        }
+        // ordered pairings (i, j), i != j, with both sides valid
+        const int npair_valid = __popc(okp) * __popc(okm) - __popc(okp & okm);
         if (npair_valid > 0) {
             const double metx = st.rec.met[0], mety = st.rec.met[1];
             const uint64_t g = st.rec.g;
@@ -1008,11 +1011,11 @@ __global__ __launch_bounds__(kRecoBlock, 2) void k_search_ev(const int64_t *__re
                 const double Wp = (0.5 * mw2) * fast_rcp(slp) - 0.5 * slp * st.rec.ml2p;
                 const double Wm = (0.5 * mw2) * fast_rcp(slm) - 0.5 * slm * st.rec.ml2m;
                 for (int i = 0; i < nc; ++i) {
-                    if (!st.okp[i]) continue;
+                    if (!((okp >> i) & 1u)) continue;
                     const double si = smear(st.rec.sigma[i], st.z[i][lane]);
                     const SideVar A = side_var(st.sp[i], Wp, slp, si, mt2_mw2);
                     for (int j = 0; j < nc; ++j) {
-                        if (j == i || !st.okm[j]) continue;
+                        if (j == i || !((okm >> j) & 1u)) continue;
                         // ---- stage 1 (own variation): eliminant quartic and its root intervals
                         const double sj = smear(st.rec.sigma[j], st.z[j][lane]);
                         const SideVar Bv = side_var(st.sm[j], Wm, slm, sj, mt2_mw2);
@@ -1061,53 +1064,63 @@ __global__ __launch_bounds__(kRecoBlock, 2) void k_search_ev(const int64_t *__re
                             const Conic Qs{Q.xx, Q.xy, Q.yy, from_lane(Q.x, src), from_lane(Q.y, src),
                                            from_lane(Q.c, src)};
                             const double ae0 = from_lane(A.e0, src), be0 = from_lane(Bv.e0, src);
-                            if (!live) continue;
-                            ++acc_int;
-                            double x;
-                            if ((fp >> 4) & 1) {  // degree <= 2: the roots are given
-                                x = kXScale * (k == 0 ? fe1 : fe2);
-                            } else {
-                                const double f0 = (fp & 32) ? -1.0 : 1.0, f4 = (fp & 64) ? -1.0 : 1.0;
-                                const double lo = k == 0 ? -fbd : k == 1 ? fe1 : k == 2 ? fe2 : fe3;
-                                const double hi = k == 0 ? fe1 : k == 1 ? fe2 : k == 2 ? fe3 : fbd;
-                                const double flo = k == 0 ? f0 : k == 1 ? ff1 : k == 2 ? ff2 : ff3;
-                                const double fhi = k == 0 ? ff1 : k == 1 ? ff2 : k == 2 ? ff3 : f4;
-                                bool found;
-                                solve_interval(fc, lo, hi, flo, fhi, k > 0 && lo < fbd, k < 3 && hi < fbd, x, found);
+                            // accepted solutions are counted per pass with a ballot
+                            bool accepted = false;
+                            double x = 0.0, y = 0.0;
+                            if (live) {
+                                if ((fp >> 4) & 1) {  // degree <= 2: the roots are given
+                                    x = kXScale * (k == 0 ? fe1 : fe2);
+                                } else {
+                                    const double f0 = (fp & 32) ? -1.0 : 1.0, f4 = (fp & 64) ? -1.0 : 1.0;
+                                    const double lo = k == 0 ? -fbd : k == 1 ? fe1 : k == 2 ? fe2 : fe3;
+                                    const double hi = k == 0 ? fe1 : k == 1 ? fe2 : k == 2 ? fe3 : fbd;
+                                    const double flo = k == 0 ? f0 : k == 1 ? ff1 : k == 2 ? ff2 : ff3;
+                                    const double fhi = k == 0 ? ff1 : k == 1 ? ff2 : k == 2 ? ff3 : f4;
+                                    bool found;
+                                    solve_interval(fc, lo, hi, flo, fhi, k > 0 && lo < fbd, k < 3 && hi < fbd, x,
+                                                   found);
+                                }
+                                accepted = recover_y(P, Qs, x, y) &&
+                                           polish_xy(P, Qs, x, y, 4, a.polish_skip_m2) <= a.accept_m2;
                             }
-                            double y;
-                            if (!recover_y(P, Qs, x, y)) continue;
-                            if (!(polish_xy(P, Qs, x, y, 4, a.polish_skip_m2) <= a.accept_m2)) continue;
-                            // the source variation's smear factors and MET, rebuilt from its draws
-                            const T zli0 = st.zl[0][src], zli1 = st.zl[1][src];
-                            const T zi = st.z[i][src], zj = st.z[j][src];
-                            const double rslp = smear(a.lep_sigma, zli0), rslm = smear(a.lep_sigma, zli1);
-                            const double rsi = smear(st.rec.sigma[i], zi), rsj = smear(st.rec.sigma[j], zj);
-                            const double rmx = metx + a.met_sigma * (double)st.zl[2][src];
-                            const double rmy = mety + a.met_sigma * (double)st.zl[3][src];
-                            const double en = st.sp[i][kE1] * x + st.sp[i][kE2] * y + ae0;
-                            const double xb = rmx - x, yb = rmy - y;
-                            const double eb = st.sm[j][kE1] * xb + st.sm[j][kE2] * yb + be0;
-                            if (en < 0.0 || eb < 0.0) continue;
-                            ++nsol;
-                            const double tx = rsi * st.rec.cand[i][1] + rslp * st.rec.lp[1] + x;  // top pT components
-                            const double ty = rsi * st.rec.cand[i][2] + rslp * st.rec.lp[2] + y;
-                            const double tbx = rsj * st.rec.cand[j][1] + rslm * st.rec.lm[1] + xb;
-                            const double tby = rsj * st.rec.cand[j][2] + rslm * st.rec.lm[2] + yb;
-                            const double zz = (double)zli0 * zli0 + (double)zli1 * zli1 +
-                                              (double)st.zl[2][src] * st.zl[2][src] +
-                                              (double)st.zl[3][src] * st.zl[3][src] + (double)zi * zi + (double)zj * zj;
-                            const double w = -0.5 * zz - (fast_sqrt(tx * tx + ty * ty) + fast_sqrt(tbx * tbx + tby * tby)) *
-                                                             a.inv_lambda;
-                            const int vs = vb + src;
-                            if (better(w, vs, p, x, best_s, best_v, best_p, best_x)) {
-                                best_s = w;
-                                best_v = vs;
-                                best_p = p;
-                                best_x = x;
-                                best_y = y;
+                            if (accepted) {
+                                // the source variation's smear factors and MET, rebuilt from its draws
+                                const T zli0 = st.zl[0][src], zli1 = st.zl[1][src];
+                                const T zi = st.z[i][src], zj = st.z[j][src];
+                                const double rslp = smear(a.lep_sigma, zli0), rslm = smear(a.lep_sigma, zli1);
+                                const double rsi = smear(st.rec.sigma[i], zi), rsj = smear(st.rec.sigma[j], zj);
+                                const double rmx = metx + a.met_sigma * (double)st.zl[2][src];
+                                const double rmy = mety + a.met_sigma * (double)st.zl[3][src];
+                                const double en = st.sp[i][kE1] * x + st.sp[i][kE2] * y + ae0;
+                                const double xb = rmx - x, yb = rmy - y;
+                                const double eb = st.sm[j][kE1] * xb + st.sm[j][kE2] * yb + be0;
+                                accepted = en >= 0.0 && eb >= 0.0;
+                                if (accepted) {
+                                    // top pT components
+                                    const double tx = rsi * st.rec.cand[i][1] + rslp * st.rec.lp[1] + x;
+                                    const double ty = rsi * st.rec.cand[i][2] + rslp * st.rec.lp[2] + y;
+                                    const double tbx = rsj * st.rec.cand[j][1] + rslm * st.rec.lm[1] + xb;
+                                    const double tby = rsj * st.rec.cand[j][2] + rslm * st.rec.lm[2] + yb;
+                                    const double zz = (double)zli0 * zli0 + (double)zli1 * zli1 +
+                                                      (double)st.zl[2][src] * st.zl[2][src] +
+                                                      (double)st.zl[3][src] * st.zl[3][src] + (double)zi * zi +
+                                                      (double)zj * zj;
+                                    const double w =
+                                        -0.5 * zz -
+                                        (fast_sqrt(tx * tx + ty * ty) + fast_sqrt(tbx * tbx + tby * tby)) * a.inv_lambda;
+                                    const int vs = vb + src;
+                                    if (better(w, vs, p, x, best_s, best_v, best_p, best_x)) {
+                                        best_s = w;
+                                        best_v = vs;
+                                        best_p = p;
+                                        best_x = x;
+                                        best_y = y;
+                                    }
+                                }
                             }
+                            nsol += popc64(ballot(accepted));
                         }
+                        acc_int += (uint64_t)total;
                     }
                 }
                 wave_sync();
@@ -1127,7 +1140,6 @@ __global__ __launch_bounds__(kRecoBlock, 2) void k_search_ev(const int64_t *__re
                 best_x = ox;
                 best_y = oy;
             }
-            nsol += __shfl_xor(nsol, off);
         }
         acc_var += (uint64_t)V;
         acc_pair += (uint64_t)V * (uint64_t)npair_valid;
@@ -1145,11 +1157,6 @@ __global__ __launch_bounds__(kRecoBlock, 2) void k_search_ev(const int64_t *__re
         }
         wave_sync();
     }
-    // intervals are counted per lane (each lane solves its own queue entries)
-    uint32_t ni = (uint32_t)acc_int;
-#pragma unroll
-    for (int off = kWave / 2; off > 0; off >>= 1) ni += __shfl_xor(ni, off);
-    acc_int = ni;
     if (lane == 0 && wstats) {
         atomicAdd((unsigned long long *)&wstats[1], (unsigned long long)acc_var);
         atomicAdd((unsigned long long *)&wstats[2], (unsigned long long)acc_pair);
