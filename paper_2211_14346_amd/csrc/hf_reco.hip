@@ -914,9 +914,12 @@ __global__ __launch_bounds__(kRecoBlock, 2) void k_search_ev(const int64_t *__re
                                                           BestRec *__restrict__ best_out,
                                                           uint64_t *__restrict__ wstats) {
     __shared__ WaveStageEv<T> stage_all[kRecoWaves];
+    __shared__ int queue_all[kRecoWaves][4 * kWave];  // stage-2 queue: source lane | interval << 6
     const int lane = lane_id();
     const int wave = threadIdx.x / kWave;
     WaveStageEv<T> &st = stage_all[wave];
+    int *queue = queue_all[wave];
+    const uint64_t lt = lanemask_lt();
     const int64_t S = clamp_count(count, capacity);
     const int64_t nwaves = (int64_t)gridDim.x * kRecoWaves;
     const double mt2_mw2 = a.m_t * a.m_t - a.m_w * a.m_w;
@@ -1034,21 +1037,17 @@ __global__ __launch_bounds__(kRecoBlock, 2) void k_search_ev(const int64_t *__re
                         const int total = n0 + n1 + n2 + n3;
                         const int p = i * nc + j;
                         const int packed = Bk.mask | (Bk.direct << 4) | (Bk.signs << 5);
+                        // the queue: every interval 0 in lane order, then every interval 1, ...
+                        if (Bk.mask & 1) queue[popc64(m0 & lt)] = lane;
+                        if (Bk.mask & 2) queue[n0 + popc64(m1 & lt)] = lane | (1 << 6);
+                        if (Bk.mask & 4) queue[n0 + n1 + popc64(m2 & lt)] = lane | (2 << 6);
+                        if (Bk.mask & 8) queue[n0 + n1 + n2 + popc64(m3 & lt)] = lane | (3 << 6);
+                        wave_sync();
                         for (int base = 0; base < total; base += kWave) {
                             const int t = base + lane;
-                            int k, r;
-                            uint64_t mk;
-                            if (t < n0) {
-                                k = 0; r = t; mk = m0;
-                            } else if (t < n0 + n1) {
-                                k = 1; r = t - n0; mk = m1;
-                            } else if (t < n0 + n1 + n2) {
-                                k = 2; r = t - n0 - n1; mk = m2;
-                            } else {
-                                k = 3; r = t - n0 - n1 - n2; mk = m3;
-                            }
                             const bool live = t < total;
-                            const int src = live ? nth_set_bit(mk, r) : lane;
+                            const int qe = live ? queue[t] : lane;
+                            const int src = qe & (kWave - 1), k = qe >> 6;
                             // the source lane's intervals, as plain values (no aggregate whose
                             // fields get selected by k, which would force it into scratch)
                             const Poly4 fc{from_lane(Bk.c.c0, src), from_lane(Bk.c.c1, src),
@@ -1120,6 +1119,7 @@ __global__ __launch_bounds__(kRecoBlock, 2) void k_search_ev(const int64_t *__re
                             }
                             nsol += popc64(ballot(accepted));
                         }
+                        wave_sync();  // the next pairing rewrites the queue
                         acc_int += (uint64_t)total;
                     }
                 }
