@@ -113,6 +113,7 @@ struct WaveStage {
     T z[kMaxC][kWave];  // per-lane draw of each candidate of the lane's event
     T zl[4][kWave];     // per-lane draws of l+, l-, MET x, MET y
     PartRec headp, tailp;  // partial records of the range's first and last event
+    int queue[4 * kWave];  // stage-2 queue: source lane | interval << 6
 };
 
 __device__ __forceinline__ void wave_sync() {
@@ -152,20 +153,6 @@ __device__ __forceinline__ bool lep_sel(const EvView &ev, uint32_t k, const Reco
 
 __device__ __forceinline__ bool jet_sel(const EvView &ev, uint32_t k, const RecoArgs &a) {
     return ev.jet_pt[k] > a.jet_pt_min && fabsf(ev.jet_eta[k]) < a.jet_eta_max;
-}
-
-// Index of the r-th set bit (from 0) of m; r < popcount(m).
-__device__ __forceinline__ int nth_set_bit(uint64_t m, int r) {
-    int pos = 0;
-#pragma unroll
-    for (int w = 32; w >= 1; w >>= 1) {
-        const int c = popc64((m >> pos) & ((1ull << w) - 1));
-        if (r >= c) {
-            r -= c;
-            pos += w;
-        }
-    }
-    return pos;
 }
 
 template <typename X>
@@ -729,21 +716,16 @@ __global__ __launch_bounds__(kRecoBlock, 2) void k_search(const int64_t *__restr
                     const int pos0 = popc64(m0 & lt), pos1 = n0 + popc64(m1 & lt);
                     const int pos2 = n0 + n1 + popc64(m2 & lt), pos3 = n0 + n1 + n2 + popc64(m3 & lt);
                     const int my_p = i * my_nc + j;
+                    if (Bk.mask & 1) st.queue[pos0] = lane;
+                    if (Bk.mask & 2) st.queue[pos1] = lane | (1 << 6);
+                    if (Bk.mask & 4) st.queue[pos2] = lane | (2 << 6);
+                    if (Bk.mask & 8) st.queue[pos3] = lane | (3 << 6);
+                    wave_sync();
                     for (int base = 0; base < total; base += kWave) {
                         const int t = base + lane;
-                        int k, r;
-                        uint64_t mk;
-                        if (t < n0) {
-                            k = 0; r = t; mk = m0;
-                        } else if (t < n0 + n1) {
-                            k = 1; r = t - n0; mk = m1;
-                        } else if (t < n0 + n1 + n2) {
-                            k = 2; r = t - n0 - n1; mk = m2;
-                        } else {
-                            k = 3; r = t - n0 - n1 - n2; mk = m3;
-                        }
                         const bool live = t < total;
-                        const int src = live ? nth_set_bit(mk, r) : lane;
+                        const int qe = live ? st.queue[t] : lane;
+                        const int src = qe & (kWave - 1), k = qe >> 6;
                         // the source lane's intervals and event, as plain values (no aggregate
                         // whose fields get selected by k, which would force it into scratch)
                         const Poly4 fc{from_lane(Bk.c.c0, src), from_lane(Bk.c.c1, src), from_lane(Bk.c.c2, src),
