@@ -160,6 +160,22 @@ __device__ __forceinline__ X from_lane(X v, int src) {
     return __shfl(v, src);
 }
 
+// In-row lane exchanges by DPP (no LDS round trip): kCtrl is the DPP control
+// word (quad_perm 0xB1 = lane ^ 1, 0x4E = lane ^ 2; 0x141 = row_half_mirror,
+// lane i <-> 7 - i within eight lanes; 0x140 = row_mirror, i <-> 15 - i
+// within sixteen).  Every pattern used is a permutation inside each row, so
+// no lane reads outside the wavefront.
+template <int kCtrl>
+__device__ __forceinline__ int dpp_i32(int v) {
+    return __builtin_amdgcn_update_dpp(v, v, kCtrl, 0xF, 0xF, false);
+}
+
+template <int kCtrl>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const int lo = __double2loint(v), hi = __double2hiint(v);
+    return __hiloint2double(dpp_i32<kCtrl>(hi), dpp_i32<kCtrl>(lo));
+}
+
 __device__ __forceinline__ int64_t clamp_count(const int64_t *count, int64_t capacity) {
     const int64_t S = *count;
     return S < 0 ? 0 : (S > capacity ? capacity : S);
@@ -1017,6 +1033,7 @@ __global__ __launch_bounds__(kRecoBlock, 2) void k_search_ev(const int64_t *__re
                         const uint64_t m2 = ballot(Bk.mask & 4), m3 = ballot(Bk.mask & 8);
                         const int n0 = popc64(m0), n1 = popc64(m1), n2 = popc64(m2), n3 = popc64(m3);
                         const int total = n0 + n1 + n2 + n3;
+                        if (total == 0) continue;
                         const int p = i * nc + j;
                         const int packed = Bk.mask | (Bk.direct << 4) | (Bk.signs << 5);
                         // the queue: every interval 0 in lane order, then every interval 1, ...
@@ -1109,12 +1126,10 @@ __global__ __launch_bounds__(kRecoBlock, 2) void k_search_ev(const int64_t *__re
             }
         }
         // --------------------------------------------------- wave argmax
-        for (int off = kWave / 2; off > 0; off >>= 1) {
-            const double os = __shfl_xor(best_s, off);
-            const int ov = __shfl_xor(best_v, off);
-            const int op = __shfl_xor(best_p, off);
-            const double ox = __shfl_xor(best_x, off);
-            const double oy = __shfl_xor(best_y, off);
+        // better() is a total order, so any pairing of lanes that reaches all
+        // of them gives every lane the maximum: four in-row DPP steps (pairs,
+        // quads, eights, rows), then across rows by shuffles
+        auto take = [&](double os, int ov, int op, double ox, double oy) {
             if (better(os, ov, op, ox, best_s, best_v, best_p, best_x)) {
                 best_s = os;
                 best_v = ov;
@@ -1122,7 +1137,18 @@ __global__ __launch_bounds__(kRecoBlock, 2) void k_search_ev(const int64_t *__re
                 best_x = ox;
                 best_y = oy;
             }
-        }
+        };
+        take(dpp_f64<0xB1>(best_s), dpp_i32<0xB1>(best_v), dpp_i32<0xB1>(best_p), dpp_f64<0xB1>(best_x),
+             dpp_f64<0xB1>(best_y));
+        take(dpp_f64<0x4E>(best_s), dpp_i32<0x4E>(best_v), dpp_i32<0x4E>(best_p), dpp_f64<0x4E>(best_x),
+             dpp_f64<0x4E>(best_y));
+        take(dpp_f64<0x141>(best_s), dpp_i32<0x141>(best_v), dpp_i32<0x141>(best_p), dpp_f64<0x141>(best_x),
+             dpp_f64<0x141>(best_y));
+        take(dpp_f64<0x140>(best_s), dpp_i32<0x140>(best_v), dpp_i32<0x140>(best_p), dpp_f64<0x140>(best_x),
+             dpp_f64<0x140>(best_y));
+        for (int off = 16; off < kWave; off <<= 1)
+            take(__shfl_xor(best_s, off), __shfl_xor(best_v, off), __shfl_xor(best_p, off), __shfl_xor(best_x, off),
+                 __shfl_xor(best_y, off));
         acc_var += (uint64_t)V;
         acc_pair += (uint64_t)V * (uint64_t)npair_valid;
         acc_sol += (uint64_t)nsol;
