@@ -44,6 +44,19 @@ HF_HD __forceinline__ double fast_rcp(double d) {
 #endif
 }
 
+// 1/d to about 2^-46 relative (the hardware estimate, good to about 2^-23,
+// plus one Newton refinement), where the result only scales a correction
+// step or a residual ratio: an error there changes the step taken, not the
+// point the iteration converges to.
+HF_HD __forceinline__ double step_rcp(double d) {
+#ifdef __HIP_DEVICE_COMPILE__
+    const double r = __builtin_amdgcn_rcp(d);
+    return fma(fma(-d, r, 1.0), r, r);
+#else
+    return 1.0 / d;
+#endif
+}
+
 // sqrt(v) for v >= 0 to about one ulp: the hardware reciprocal square root
 // and one Goldschmidt refinement (no IEEE correction sequence).
 HF_HD __forceinline__ double fast_sqrt(double v) {
@@ -318,7 +331,7 @@ HF_HD __forceinline__ double bracket_halley(const Poly4 &c, double lo, double hi
         const double g = dp * dp;
         const double hd = fma(-0.5 * p, d2, g);
         const double den = (hd > 0.5 * g && hd < 2.0 * g) ? hd : g;
-        const double dx = p * dp * fast_rcp(den);
+        const double dx = p * dp * step_rcp(den);
         const double tol = 1e-12 * fmax(1.0, fabs(x));
         if (fabs(dx) <= tol) return x - dx;
         if (it >= 1 && fabs(dx) <= 1e5 * tol && fabs(dx) <= 1e-3 * fabs(dx_prev)) return x - dx;
@@ -352,12 +365,12 @@ HF_HD __forceinline__ void solve_interval(const Poly4 &c, double lo, double hi, 
         const bool from_lo = lo_crit && (!hi_crit || fabs(flo) <= fabs(fhi));
         const double cp = from_lo ? lo : hi;
         const double fv = from_lo ? flo : fhi;
-        const double r = -2.0 * fv * fast_rcp(peval_d2(c, cp));
+        const double r = -2.0 * fv * step_rcp(peval_d2(c, cp));
         if (r > 0.0)
             x0 = from_lo ? cp + fast_sqrt(r) : cp - fast_sqrt(r);
         else
             x0 = (lo_crit && hi_crit) ? lo : from_lo ? cp + fmax(1.0, fabs(cp)) : cp - fmax(1.0, fabs(cp));
-        if (lo_crit && hi_crit && !(x0 > lo && x0 < hi)) x0 = lo - flo * (hi - lo) * fast_rcp(fhi - flo);
+        if (lo_crit && hi_crit && !(x0 > lo && x0 < hi)) x0 = lo - flo * (hi - lo) * step_rcp(fhi - flo);
     } else {
         x0 = 0.0;
     }
@@ -473,13 +486,13 @@ HF_HD __forceinline__ Brackets quartic_brackets(const double qx[5]) {
         double g, gp;
         g = peval_d1(c, k0);
         gp = peval_d2(c, k0);
-        if (gp != 0.0) k0 -= g * fast_rcp(gp);
+        if (gp != 0.0) k0 -= g * step_rcp(gp);
         g = peval_d1(c, k1);
         gp = peval_d2(c, k1);
-        if (gp != 0.0) k1 -= g * fast_rcp(gp);
+        if (gp != 0.0) k1 -= g * step_rcp(gp);
         g = peval_d1(c, k2);
         gp = peval_d2(c, k2);
-        if (gp != 0.0) k2 -= g * fast_rcp(gp);
+        if (gp != 0.0) k2 -= g * step_rcp(gp);
     }
     // interval ends -B, k0, k1, k2, B; missing or out-of-range critical points
     // collapse onto +B, which empties their intervals
@@ -629,18 +642,18 @@ HF_HD __forceinline__ double polish_xy(const Conic &P, const Conic &Q, double &x
     double f1 = conic_eval(P, x, y), f2 = conic_eval(Q, x, y);
     double phys = fmax(fabs(f1), fabs(f2));
     if (!(phys > skip_below)) return phys;
-    double res = fmax(fabs(f1) * fast_rcp(conic_mag(P, x, y)), fabs(f2) * fast_rcp(conic_mag(Q, x, y)));
+    double res = fmax(fabs(f1) * step_rcp(conic_mag(P, x, y)), fabs(f2) * step_rcp(conic_mag(Q, x, y)));
     for (int it = 0; it < iters; ++it) {
         if (res == 0.0) break;
         const double a11 = 2.0 * P.xx * x + P.xy * y + P.x, a12 = P.xy * x + 2.0 * P.yy * y + P.y;
         const double a21 = 2.0 * Q.xx * x + Q.xy * y + Q.x, a22 = Q.xy * x + 2.0 * Q.yy * y + Q.y;
         const double det = a11 * a22 - a12 * a21;
         if (det == 0.0) break;
-        const double id = fast_rcp(det);
+        const double id = step_rcp(det);
         const double xn = x + (-f1 * a22 + f2 * a12) * id;
         const double yn = y + (-a11 * f2 + a21 * f1) * id;
         const double g1 = conic_eval(P, xn, yn), g2 = conic_eval(Q, xn, yn);
-        const double rn = fmax(fabs(g1) * fast_rcp(conic_mag(P, xn, yn)), fabs(g2) * fast_rcp(conic_mag(Q, xn, yn)));
+        const double rn = fmax(fabs(g1) * step_rcp(conic_mag(P, xn, yn)), fabs(g2) * step_rcp(conic_mag(Q, xn, yn)));
         if (!(rn < res)) break;
         x = xn;
         y = yn;
