@@ -62,6 +62,18 @@ __device__ __forceinline__ double mass4(double e, double x, double y, double z) 
 
 __device__ __forceinline__ double sq(double x) { return x * x; }
 
+// sqrt(v) for v >= 0 to about 2^-46 relative: the hardware reciprocal square
+// root (good to about 2^-23) and one Goldschmidt step, without the final
+// correction to the last ulp.  Used for the p_z roots and the chi^2 terms of
+// every grid point, where the fit is issue-bound; the winner's outputs are
+// recomputed with the library square root.
+__device__ __forceinline__ double sqrt_fit(double v) {
+    if (!(v > 0.0)) return 0.0;
+    const double y = __builtin_amdgcn_rsq(v);
+    const double s = v * y, h = 0.5 * y;
+    return fma(s, fma(-s, h, 0.5), s);
+}
+
 // A lepton's split-independent terms: its 4-vector, (m_W^2 - m_l^2) / 2 and
 // a = E^2 - p_z^2 with its reciprocal (the p_z quadratic's leading term).
 struct Lep {
@@ -84,8 +96,8 @@ __device__ __forceinline__ Lep make_lep(const double *l, const Chi2Args &a) {
 // and the W term of chi^2 per candidate.  A real root that solves the
 // unsquared condition (mu + p_zl p_z >= 0) puts l + nu on the W mass shell,
 // so its W term is zero; the squaring's extra root and the real part of a
-// complex pair get theirs computed.  Square roots and the quadratic's
-// division use the hardware estimates refined to about one ulp.
+// complex pair get theirs computed.  Square roots use the hardware estimate
+// with one refinement (sqrt_fit); the quadratic's division is exact.
 struct Side {
     double w[2][4];
     double pz[2];
@@ -109,7 +121,7 @@ __device__ __forceinline__ Side side(const Lep &L, double nx, double ny, const C
         S.kind[0] = 2;
         S.n = 1;
     } else {
-        const double s = l[0] * fast_sqrt(d);
+        const double s = l[0] * sqrt_fit(d);
         S.pz[0] = (ml3 - s) * L.inv_qa;
         S.pz[1] = (ml3 + s) * L.inv_qa;
         S.kind[0] = 0;
@@ -121,13 +133,13 @@ __device__ __forceinline__ Side side(const Lep &L, double nx, double ny, const C
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
         if (r >= S.n) break;
-        const double en = fast_sqrt(pt2 + S.pz[r] * S.pz[r]);
+        const double en = sqrt_fit(pt2 + S.pz[r] * S.pz[r]);
         S.w[r][0] = l[0] + en;
         S.w[r][1] = l[1] + nx;
         S.w[r][2] = l[2] + ny;
         S.w[r][3] = l[3] + S.pz[r];
         S.cw[r] = shell[r] ? 0.0
-                           : sq(fast_sqrt(fmax(S.w[r][0] * S.w[r][0] - S.w[r][1] * S.w[r][1] -
+                           : sq(sqrt_fit(fmax(S.w[r][0] * S.w[r][0] - S.w[r][1] * S.w[r][1] -
                                                S.w[r][2] * S.w[r][2] - S.w[r][3] * S.w[r][3], 0.0)) -
                                 a.m_w) * a.inv_sw2;
     }
@@ -138,7 +150,7 @@ __device__ __forceinline__ Side side(const Lep &L, double nx, double ny, const C
 __device__ __forceinline__ double top_term(double b0, double b1, double b2, double b3, const double *w,
                                            const Chi2Args &a) {
     const double e = b0 + w[0], x = b1 + w[1], y = b2 + w[2], z = b3 + w[3];
-    return sq(fast_sqrt(fmax(e * e - x * x - y * y - z * z, 0.0)) - a.m_t) * a.inv_st2;
+    return sq(sqrt_fit(fmax(e * e - x * x - y * y - z * z, 0.0)) - a.m_t) * a.inv_st2;
 }
 
 template <typename T>
