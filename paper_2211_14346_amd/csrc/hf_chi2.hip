@@ -62,13 +62,16 @@ __device__ __forceinline__ double mass4(double e, double x, double y, double z) 
 
 __device__ __forceinline__ double sq(double x) { return x * x; }
 
-// sqrt(v) for v >= 0 to about 2^-46 relative: the hardware reciprocal square
-// root (good to about 2^-23) and one Goldschmidt step, without the final
-// correction to the last ulp.  Used for the p_z roots and the chi^2 terms of
-// every grid point, where the fit is issue-bound; the winner's outputs are
-// recomputed with the library square root.
+// sqrt(v) for v >= kTiny to about 2^-46 relative: the hardware reciprocal
+// square root (good to about 2^-23) and one Goldschmidt step, without the
+// final correction to the last ulp.  Used for the p_z roots and the chi^2
+// terms of every grid point, where the fit is issue-bound; the winner's
+// outputs are recomputed with the library square root.  Callers clamp the
+// argument to kTiny instead of testing for zero (one max instead of a compare
+// and two selects): sqrt(kTiny) = 1e-150 stands for 0, a difference far
+// below FP64 rounding of any chi^2 term at GeV scales.
+constexpr double kTiny = 1e-300;
 __device__ __forceinline__ double sqrt_fit(double v) {
-    if (!(v > 0.0)) return 0.0;
     const double y = __builtin_amdgcn_rsq(v);
     const double s = v * y, h = 0.5 * y;
     return fma(s, fma(-s, h, 0.5), s);
@@ -121,7 +124,7 @@ __device__ __forceinline__ Side side(const Lep &L, double nx, double ny, const C
         S.kind[0] = 2;
         S.n = 1;
     } else {
-        const double s = l[0] * sqrt_fit(d);
+        const double s = l[0] * sqrt_fit(fmax(d, kTiny));
         S.pz[0] = (ml3 - s) * L.inv_qa;
         S.pz[1] = (ml3 + s) * L.inv_qa;
         S.kind[0] = 0;
@@ -133,14 +136,14 @@ __device__ __forceinline__ Side side(const Lep &L, double nx, double ny, const C
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
         if (r >= S.n) break;
-        const double en = sqrt_fit(pt2 + S.pz[r] * S.pz[r]);
+        const double en = sqrt_fit(fmax(pt2 + S.pz[r] * S.pz[r], kTiny));
         S.w[r][0] = l[0] + en;
         S.w[r][1] = l[1] + nx;
         S.w[r][2] = l[2] + ny;
         S.w[r][3] = l[3] + S.pz[r];
         S.cw[r] = shell[r] ? 0.0
                            : sq(sqrt_fit(fmax(S.w[r][0] * S.w[r][0] - S.w[r][1] * S.w[r][1] -
-                                               S.w[r][2] * S.w[r][2] - S.w[r][3] * S.w[r][3], 0.0)) -
+                                               S.w[r][2] * S.w[r][2] - S.w[r][3] * S.w[r][3], kTiny)) -
                                 a.m_w) * a.inv_sw2;
     }
     return S;
@@ -150,7 +153,7 @@ __device__ __forceinline__ Side side(const Lep &L, double nx, double ny, const C
 __device__ __forceinline__ double top_term(double b0, double b1, double b2, double b3, const double *w,
                                            const Chi2Args &a) {
     const double e = b0 + w[0], x = b1 + w[1], y = b2 + w[2], z = b3 + w[3];
-    return sq(sqrt_fit(fmax(e * e - x * x - y * y - z * z, 0.0)) - a.m_t) * a.inv_st2;
+    return sq(sqrt_fit(fmax(e * e - x * x - y * y - z * z, kTiny)) - a.m_t) * a.inv_st2;
 }
 
 template <typename T>
