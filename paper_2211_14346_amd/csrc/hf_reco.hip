@@ -51,7 +51,12 @@ constexpr int kRecoBlock = 256;
 constexpr int kRecoWaves = kRecoBlock / kWave;
 constexpr int kMaxC = HF_MAX_CANDS;
 constexpr int kNoBest = 0x7fffffff;
-constexpr size_t kWsHeader = 256;
+constexpr size_t kWsHeader = 2048;
+// Event counters of the one-wavefront-per-event search: kTicketClasses of
+// them at words kTicketWord + 16 c of the workspace header, each on its own
+// 128-byte line.
+constexpr int kTicketWord = 16;
+constexpr int kTicketClasses = 8;
 constexpr int kGran = 16;              // lanes per granule of the worklist
 constexpr int kGpb = kWave / kGran;    // granules per 64-lane block: at most 4 events per block
 constexpr int kSideCap = 24;           // side-constant slots shared by a block's events
@@ -919,30 +924,44 @@ __global__ __launch_bounds__(kRecoBlock, 2) void k_search_ev(const int64_t *__re
     int *queue = queue_all[wave];
     const uint64_t lt = lanemask_lt();
     const int64_t S = clamp_count(count, capacity);
-    const int64_t nwaves = (int64_t)gridDim.x * kRecoWaves;
     const double mt2_mw2 = a.m_t * a.m_t - a.m_w * a.m_w;
     const double mw2 = a.m_w * a.m_w;
     uint64_t acc_var = 0, acc_pair = 0, acc_int = 0, acc_sol = 0;
 
-    // the staged record of the wave's next event is loaded one event ahead
+    // Events are handed out by counters, not dealt round robin: the cost of an
+    // event varies (root intervals, iterations), and with a static deal the
+    // waves' busy times spread by a sixth of the kernel.  Blocks of class c
+    // (blockIdx mod ncls, which follows the round-robin placement of blocks on
+    // the XCDs) take events c, c + ncls, c + 2 ncls, ... in the order of their
+    // class's counter; one counter for the whole grid serialises its atomics.
+    // Lane 0 takes the next ticket one event ahead and the wave reads it at
+    // the top of the next event, when the atomic has long returned; the staged
+    // record of that event is loaded one event ahead as well.
+    const int ncls = gridDim.x < (unsigned)kTicketClasses ? (int)gridDim.x : kTicketClasses;
+    const int cls = (int)(blockIdx.x % (unsigned)ncls);
+    unsigned long long *ticket = reinterpret_cast<unsigned long long *>(wstats) + kTicketWord + 16 * cls;
     const uint64_t *recw = reinterpret_cast<const uint64_t *>(stage);
     constexpr int kTail = kRecWords - kWave;
-    int64_t k = (int64_t)blockIdx.x * kRecoWaves + wave;
+    unsigned long long tk = 0;
+    if (lane == 0) tk = atomicAdd(ticket, 1ull);
+    int64_t k = cls + (int64_t)ncls * (int64_t)__shfl(tk, 0);
     uint64_t w0 = 0, w1 = 0;
     if (k < S) {
         w0 = recw[k * kRecWords + lane];
         if (lane < kTail) w1 = recw[k * kRecWords + kWave + lane];
+        if (lane == 0) tk = atomicAdd(ticket, 1ull);
     }
-    for (; k < S; k += nwaves) {
+    while (k < S) {
         {
             uint64_t *dst = reinterpret_cast<uint64_t *>(&st.rec);
             dst[lane] = w0;
             if (lane < kTail) dst[kWave + lane] = w1;
         }
-        const int64_t kn = k + nwaves;
+        const int64_t kn = cls + (int64_t)ncls * (int64_t)__shfl(tk, 0);
         if (kn < S) {
             w0 = recw[kn * kRecWords + lane];
             if (lane < kTail) w1 = recw[kn * kRecWords + kWave + lane];
+            if (lane == 0) tk = atomicAdd(ticket, 1ull);
         }
         wave_sync();
         const int nc = __builtin_amdgcn_readfirstlane(st.rec.nc);
@@ -1164,8 +1183,9 @@ __global__ __launch_bounds__(kRecoBlock, 2) void k_search_ev(const int64_t *__re
             best_out[k] = r;
         }
         wave_sync();
+        k = kn;
     }
-    if (lane == 0 && wstats) {
+    if (lane == 0) {
         atomicAdd((unsigned long long *)&wstats[1], (unsigned long long)acc_var);
         atomicAdd((unsigned long long *)&wstats[2], (unsigned long long)acc_pair);
         atomicAdd((unsigned long long *)&wstats[3], (unsigned long long)acc_int);
@@ -1204,6 +1224,7 @@ __global__ __launch_bounds__(256) void k_fixup(const PartRec *__restrict__ part,
 
 __global__ void k_reco_init(uint64_t *wstats) {
     if (threadIdx.x < 5) wstats[threadIdx.x] = 0;
+    if (threadIdx.x < kTicketClasses) wstats[kTicketWord + 16 * threadIdx.x] = 0;
 }
 
 __device__ __forceinline__ double mass4(double E, double X, double Y, double Z) {
