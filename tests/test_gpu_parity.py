@@ -283,6 +283,42 @@ def _reco_direct(B, ev, ids, reco, precision, schedule, index_base=0):
     return outs.host(S), (dev, idx, cnt, S, p, outs, ws)
 
 
+def test_event_counters_cover_every_position(B, orc):
+    """The one-wavefront-per-event search takes its events from counters in
+    the workspace header (one per class of blocks, cleared at every launch).
+    With device counts far below the capacity, fewer blocks than classes,
+    and launches repeated on one workspace, every position below the count
+    must get the same result as in a run over all events, the statistics
+    must count exactly those events, and positions past the count stay
+    untouched."""
+    _say("event counters")
+    from paper_2211_14346_amd.binding import DeviceEvents, RecoOutputs
+    cfg = hfgen.config("ttbar1M_v64")
+    ev = hfgen.generate(cfg, n_events=3000, seed=97)
+    s_w, _, _ = orc.select(ev, cfg["cuts"], list(range(len(cfg["cuts"]))))
+    ids = np.flatnonzero(s_w)
+    ref, _ = _reco_direct(B, ev, ids, cfg["reco"], "mixed", "event")
+    keys = ("has_sol", "n_sol", "best_v", "best_i", "best_j", "nu", "nubar", "m_t", "m_tbar", "m_wp", "m_wm", "logw")
+    dev = DeviceEvents(ev)
+    cap = len(ids)
+    idx = torch.from_numpy(np.ascontiguousarray(ids, dtype=np.int32)).cuda()
+    p = B.reco_params(cfg["reco"], precision="mixed", reco_cut=0, schedule="event")
+    ws = B.workspace(B.lib().hf_ttbar_reco_workspace_size(cap))
+    for S, capacity in ((1, cap), (2, 5), (7, 7), (8, cap), (9, 9), (65, cap), (1000, cap), (cap, cap), (3, cap)):
+        outs = RecoOutputs(cap)
+        outs.t["has_sol"].fill_(7)
+        cnt = torch.tensor([S], dtype=torch.int64, device="cuda")
+        for rep in range(2):
+            outs.t["stats"].zero_()
+            B.ttbar_reco(dev, idx, cnt, capacity, p, outs, torch.zeros(1, 3, dtype=torch.int64, device="cuda"), ws)
+            got = outs.host(cap)
+            for k in keys:
+                assert np.array_equal(got[k][:S], ref[k][:S]), (S, capacity, rep, k)
+            assert np.all(got["has_sol"][S:] == 7), (S, capacity, "wrote past the count")
+            assert got["stats"][0] == S, (S, capacity, got["stats"])
+            assert got["stats"][4] == ref["n_sol"][:S].sum(), (S, capacity, got["stats"])
+
+
 @pytest.mark.parametrize("name,n", [("stress2M_heavytail", 2000), ("ttbar1M_v64", 2000)])
 def test_schedules_give_identical_results(B, orc, name, n):
     """The two schedules assign the same arithmetic to different lanes and
