@@ -304,10 +304,13 @@ def test_event_counters_cover_every_position(B, orc):
     idx = torch.from_numpy(np.ascontiguousarray(ids, dtype=np.int32)).cuda()
     p = B.reco_params(cfg["reco"], precision="mixed", reco_cut=0, schedule="event")
     ws = B.workspace(B.lib().hf_ttbar_reco_workspace_size(cap))
-    for S, capacity in ((1, cap), (2, 5), (7, 7), (8, cap), (9, 9), (65, cap), (1000, cap), (cap, cap), (3, cap)):
+    # (device count, capacity); a count above the capacity is clamped to it
+    for n, capacity in ((1, cap), (2, 5), (7, 7), (8, cap), (9, 9), (65, cap), (cap - 1, cap), (cap, cap),
+                        (cap + 5, cap), (40, 31), (3, cap)):
+        S = min(n, capacity)
         outs = RecoOutputs(cap)
         outs.t["has_sol"].fill_(7)
-        cnt = torch.tensor([S], dtype=torch.int64, device="cuda")
+        cnt = torch.tensor([n], dtype=torch.int64, device="cuda")
         for rep in range(2):
             outs.t["stats"].zero_()
             B.ttbar_reco(dev, idx, cnt, capacity, p, outs, torch.zeros(1, 3, dtype=torch.int64, device="cuda"), ws)
