@@ -311,15 +311,17 @@ __global__ __launch_bounds__(kBlock) void k_chi2(EvView ev, const int32_t *__res
                 wave_sync();
                 ok = nc >= 2;
                 if (ok) {
-                    double v[4];
-                    if (lane < nc) {
-                        const uint32_t q = j0 + (uint32_t)s_loc[wave][lane];
-                        to_cart(ev.jet_pt[q], ev.jet_eta[q], ev.jet_phi[q], ev.jet_e[q], v);
-                        for (int c = 0; c < 4; ++c) s_cv[wave][4 * lane + c] = v[c];
-                    } else if (lane == kWave - 1 || lane == kWave - 2) {
-                        const uint32_t q = lane == kWave - 1 ? kp : km;
-                        to_cart(ev.lep_pt[q], ev.lep_eta[q], ev.lep_phi[q], ev.lep_e[q], v);
-                        for (int c = 0; c < 4; ++c) s_lep[wave][(lane == kWave - 1 ? 0 : 4) + c] = v[c];
+                    // candidates on lanes [0, nc), l+ and l- on the last two lanes: one
+                    // conversion on per-lane columns rather than one per object kind
+                    const bool isj = lane < nc, isl = lane >= kWave - 2;
+                    if (isj || isl) {
+                        const float *cpt = isj ? ev.jet_pt : ev.lep_pt, *ceta = isj ? ev.jet_eta : ev.lep_eta;
+                        const float *cphi = isj ? ev.jet_phi : ev.lep_phi, *ce = isj ? ev.jet_e : ev.lep_e;
+                        const uint32_t q = isj ? j0 + (uint32_t)s_loc[wave][lane] : (lane == kWave - 1 ? kp : km);
+                        double v[4];
+                        to_cart(cpt[q], ceta[q], cphi[q], ce[q], v);
+                        double *dst = isj ? &s_cv[wave][4 * lane] : &s_lep[wave][lane == kWave - 1 ? 0 : 4];
+                        for (int c = 0; c < 4; ++c) dst[c] = v[c];
                     }
                     wave_sync();
                 }
