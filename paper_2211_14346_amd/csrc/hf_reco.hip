@@ -907,10 +907,11 @@ __global__ __launch_bounds__(kRecoBlock, 2) void k_search(const int64_t *__restr
 }
 
 // Search with one wavefront per event (lanes = variations in chunks of 64,
-// events dealt round-robin to a persistent grid, the next event's record
-// loaded one event ahead).  Used when every event has the same number of
-// variations: then no block is shared between events and nothing needs
-// merging, and this form avoids the worklist's indirections.
+// events taken from per-class counters by a persistent grid, the next
+// event's ticket and record fetched one event ahead).  Used when every event
+// has the same number of variations: then no block is shared between events
+// and nothing needs merging, and this form avoids the worklist's
+// indirections.
 template <typename T>
 __global__ __launch_bounds__(kRecoBlock, 2) void k_search_ev(const int64_t *__restrict__ count, int64_t capacity,
                                                           RecoArgs a, const StageRec *__restrict__ stage,
