@@ -16,7 +16,8 @@
  *   - Device work is queued on the given stream and the call returns without
  *     waiting.  No entry point allocates, frees or synchronises; scratch
  *     memory is passed in as a workspace whose size the matching
- *     *_workspace_size query reports.  Every entry point may be recorded into
+ *     *_workspace_size query reports (hf_compact_noalloc alone uses a fixed
+ *     array the library holds).  Every entry point may be recorded into
  *     a HIP graph (no memset nodes, no host reads of device data).
  *   - The caller owns all memory.  Concurrent calls that share outputs,
  *     counters or workspace race.
@@ -174,6 +175,21 @@ size_t hf_compact_workspace_size(int64_t capacity);
 int hf_compact(const uint8_t *d_mask, int64_t capacity, const int64_t *d_n, int64_t index_base,
                const int32_t *d_map, int32_t *d_idx, int64_t *d_count, void *d_ws, size_t ws_bytes,
                hipStream_t stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): hf_compact
+ * with the workspace held by the library instead of passed in.  Same
+ * arguments, semantics and errors as hf_compact without d_ws and ws_bytes;
+ * capacity is limited to HF_COMPACT_NOALLOC_MAX_ENTRIES (HF_ERR_CAPACITY
+ * above it).  The workspace is a fixed device array of about 256 KiB per
+ * GPU, resolved on the first call with each device current and kept until
+ * the process ends; the call allocates and frees nothing.  The stream must
+ * belong to the current device.  Every call on one GPU shares that array:
+ * calls whose work overlaps on one GPU (other streams, other host threads)
+ * race and must be ordered by the caller. */
+#define HF_COMPACT_NOALLOC_MAX_ENTRIES ((int64_t)1 << 28)
+int hf_compact_noalloc(const uint8_t *d_mask, int64_t capacity, const int64_t *d_n, int64_t index_base,
+                       const int32_t *d_map, int32_t *d_idx, int64_t *d_count, hipStream_t stream);
 
 /* ------------------------------------------------------- reconstruction */
 

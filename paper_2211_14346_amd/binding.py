@@ -102,6 +102,7 @@ def lib():
         L.hf_compact_workspace_size.argtypes = [C.c_int64]
         L.hf_compact_workspace_size.restype = C.c_size_t
         L.hf_compact.argtypes = [P, C.c_int64, P, C.c_int64, P, P, P, P, C.c_size_t, P]
+        L.hf_compact_noalloc.argtypes = [P, C.c_int64, P, C.c_int64, P, P, P, P]
         L.hf_ttbar_reco_workspace_size.argtypes = [C.c_int64]
         L.hf_ttbar_reco_workspace_size.restype = C.c_size_t
         L.hf_ttbar_reco.argtypes = [C.POINTER(Events), P, P, C.c_int64, C.POINTER(RecoParams), C.POINTER(RecoOut), P,
@@ -131,7 +132,7 @@ def lib():
                                          C.POINTER(Chi2Out), P, P]
         L.hf_semilep_reco.argtypes = [C.POINTER(Events), P, P, C.c_int64, C.POINTER(SemilepParams),
                                       C.POINTER(SemilepOut), P, P]
-        for f in ("hf_select", "hf_compact", "hf_ttbar_reco", "hf_ttbar_reco_autotune", "hf_reorder_stats",
+        for f in ("hf_select", "hf_compact", "hf_compact_noalloc", "hf_ttbar_reco", "hf_ttbar_reco_autotune", "hf_reorder_stats",
                   "hf_reorder_device", "hf_philox_blocks", "hf_gauss_draws", "hf_semilep_reco", "hf_chain_compile",
                   "hf_chain_select", "hf_dilep_chi2_reco", "hf_select_segment", "hf_chain_select_segment",
                   "hf_unpack_events"):
@@ -286,6 +287,12 @@ def compact(mask, capacity, idx, count, ws, d_n=None, index_base=0, mapping=None
     rc = lib().hf_compact(_p(mask), int(capacity), _p(d_n), int(index_base), _p(mapping), _p(idx), _p(count),
                           _p(ws), ws.numel() * ws.element_size(), _stream(stream))
     _check(rc, "hf_compact")
+
+
+def compact_noalloc(mask, capacity, idx, count, d_n=None, index_base=0, mapping=None, stream=None):
+    rc = lib().hf_compact_noalloc(_p(mask), int(capacity), _p(d_n), int(index_base), _p(mapping), _p(idx),
+                                  _p(count), _stream(stream))
+    _check(rc, "hf_compact_noalloc")
 
 
 class RecoOutputs:

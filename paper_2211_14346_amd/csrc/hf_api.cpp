@@ -184,6 +184,21 @@ int hf_compact(const uint8_t *d_mask, int64_t capacity, const int64_t *d_n, int6
     return HF_OK;
 }
 
+int hf_compact_noalloc(const uint8_t *d_mask, int64_t capacity, const int64_t *d_n, int64_t index_base,
+                       const int32_t *d_map, int32_t *d_idx, int64_t *d_count, hipStream_t stream) {
+    if (capacity < 0) return fail(HF_ERR_INVAL, "hf_compact_noalloc: capacity < 0");
+    if (capacity > HF_COMPACT_NOALLOC_MAX_ENTRIES)
+        return fail(HF_ERR_CAPACITY, "hf_compact_noalloc: capacity %lld above the maximum %lld",
+                    (long long)capacity, (long long)HF_COMPACT_NOALLOC_MAX_ENTRIES);
+    if (!d_count) return fail(HF_ERR_INVAL, "hf_compact_noalloc: count is NULL");
+    if (capacity > 0 && (!d_mask || !d_idx)) return fail(HF_ERR_INVAL, "hf_compact_noalloc: mask or idx is NULL");
+    if (!d_map && (index_base < 0 || index_base + capacity > ((int64_t)1 << 31)))
+        return fail(HF_ERR_INVAL, "hf_compact_noalloc: index_base + capacity must lie in [0, 2^31]");
+    hipError_t e = hf::launch_compact_noalloc(d_mask, capacity, d_n, index_base, d_map, d_idx, d_count, stream);
+    if (e != hipSuccess) return device_fail("hf_compact_noalloc launch", e);
+    return HF_OK;
+}
+
 size_t hf_ttbar_reco_workspace_size(int64_t capacity) {
     if (capacity < 0) return 0;
     return hf::reco_ws_bytes(capacity);

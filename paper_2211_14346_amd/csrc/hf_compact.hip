@@ -15,6 +15,9 @@
 // Status words (64 bit): bits 62-63 = 0 (not ready), 1 (aggregate), 2
 // (inclusive prefix); bits 0-61 the value.  A tiny first kernel clears the
 // status words and the ticket, so the pair can be recorded in a graph.
+#include <atomic>
+#include <mutex>
+
 #include "hf_device.hpp"
 #include "hf_internal.hpp"
 
@@ -161,6 +164,56 @@ hipError_t launch_compact(const uint8_t *mask, int64_t capacity, const int64_t *
     hipLaunchKernelGGL(k_compact, dim3((unsigned)nt), dim3(kCB), 0, s, mask, capacity, d_n, index_base, map, idx,
                        count, status, ticket, nt, aligned);
     return hipGetLastError();
+}
+
+// ---- workspace held by the library (hf_compact_noalloc)
+//
+// Ticket and status words of up to HF_COMPACT_NOALLOC_MAX_ENTRIES mask
+// entries, one copy per device for the life of the process.  On the host the
+// name `scratch` is only a stand-in for the symbol: its device address comes
+// from hipGetSymbolAddress, taken once per device with that device current.
+constexpr size_t kStaticScratchBytes =
+    kHeader + (size_t)((HF_COMPACT_NOALLOC_MAX_ENTRIES + kTile - 1) / kTile) * sizeof(uint64_t);
+
+}  // namespace hf
+
+static __device__ __align__(256) uint8_t scratch[hf::kStaticScratchBytes];
+
+namespace hf {
+namespace {
+constexpr int kMaxDevices = 64;
+std::atomic<void *> g_scratch_ptr[kMaxDevices];
+std::mutex g_scratch_mu;
+}  // namespace
+
+hipError_t compact_static_scratch(void **out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    void *p = g_scratch_ptr[dev].load(std::memory_order_acquire);
+    if (!p) {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        p = g_scratch_ptr[dev].load(std::memory_order_relaxed);
+        if (!p) {
+            e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+            if (e != hipSuccess) return e;
+            if (!p) return hipErrorInvalidSymbol;
+            g_scratch_ptr[dev].store(p, std::memory_order_release);
+        }
+    }
+    *out = p;
+    return hipSuccess;
+}
+
+hipError_t launch_compact_noalloc(const uint8_t *mask, int64_t capacity, const int64_t *d_n, int64_t index_base,
+                                  const int32_t *map, int32_t *idx, int64_t *count, hipStream_t s) {
+    if (compact_ws_bytes(capacity) > kStaticScratchBytes) return hipErrorInvalidValue;
+    void *ws = nullptr;
+    hipError_t e = compact_static_scratch(&ws);
+    if (e != hipSuccess) return e;
+    // the first kernel of launch_compact clears the ticket and the status words
+    return launch_compact(mask, capacity, d_n, index_base, map, idx, count, ws, s);
 }
 
 }  // namespace hf

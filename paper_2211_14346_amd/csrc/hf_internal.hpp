@@ -44,6 +44,8 @@ hipError_t launch_reorder(const hf_counters_t *counters, const CutTable &ct, int
 size_t compact_ws_bytes(int64_t capacity);
 hipError_t launch_compact(const uint8_t *mask, int64_t capacity, const int64_t *d_n, int64_t index_base,
                           const int32_t *map, int32_t *idx, int64_t *count, void *ws, hipStream_t s);
+hipError_t launch_compact_noalloc(const uint8_t *mask, int64_t capacity, const int64_t *d_n, int64_t index_base,
+                                  const int32_t *map, int32_t *idx, int64_t *count, hipStream_t s);
 
 // ---- reconstruction (hf_reco.hip)
 struct RecoArgs {
