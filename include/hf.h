@@ -194,11 +194,15 @@ int hf_compact_noalloc(const uint8_t *d_mask, int64_t capacity, const int64_t *d
 /* ------------------------------------------------------- reconstruction */
 
 #define HF_PREC_FP64 0  /* every step in FP64 */
-#define HF_PREC_MIXED 1 /* draws, smearing, kinematic staging and root seeds in FP32;
-                           quartic assembly, root polishing, back-substitution and
-                           scores in FP64 */
-#define HF_PAIR_BTAG_FILL 0 /* b candidates: tagged selected jets (pT order, at most
-                               max_cands), filled up to two with leading untagged ones */
+#define HF_PREC_MIXED 1 /* the Box-Muller transcendentals of the draws and the cubic
+                           that seeds the critical points of the eliminant in FP32;
+                           kinematic staging, smear factors, linear maps, eliminant
+                           assembly, root polishing, back-substitution and scores in
+                           FP64 (FP32 staging and smearing miss the 1e-4 agreement
+                           with the FP64 oracle on near-tangent solutions) */
+#define HF_PAIR_BTAG_FILL 0 /* b candidates: tagged selected jets in input order
+                               (descending pT), at most max_cands, filled up to two
+                               with the leading untagged selected jets */
 #define HF_PAIR_ALL_JETS 1  /* b candidates: every selected jet (at most max_cands) */
 
 /* Reconstruction parameters (section 4; the resolution model and the choice

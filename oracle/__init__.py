@@ -118,6 +118,8 @@ def lib():
         L.orc_semilep_reco.argtypes = [C.POINTER(Events), P, C.c_int64, C.POINTER(SemilepParams),
                                        C.POINTER(SemilepOut), C.c_int]
         L.orc_semilep_reco.restype = C.c_int64
+        L.orc_stage_vary.argtypes = [C.POINTER(Events), C.c_int64, C.c_int, C.POINTER(RecoParams), P, P, P, P]
+        L.orc_stage_vary.restype = C.c_int
         _lib = L
     return _lib
 
@@ -324,6 +326,27 @@ def ttbar_reco(ev, idx, reco, index_base=0, n_threads=0, fp64=False):
     res = {k: v[:S].copy() for k, v in o.items()}
     res["n_pass"] = int(npass)
     return res
+
+
+def stage_vary(ev, e, v, reco, index_base=0):
+    """Staged candidates and one resolution variation of event e (local index).
+
+    Returns None when the event lacks two selected opposite-sign leptons, else
+    a dict: cand (jet indices within the event), lp, lm (E, px, py, pz),
+    cands [nc, 4], met (x, y) and the draws z_lp, z_lm, z_mx, z_my, z_cand."""
+    h = _EventsHolder(ev, index_base)
+    prm = reco_params(reco)
+    cand = np.zeros(16, np.int32)
+    vecs = np.zeros(4 * 16)
+    met = np.zeros(2)
+    z = np.zeros(16)
+    nc = lib().orc_stage_vary(C.byref(h.s), int(e), int(v), C.byref(prm), _ptr(cand), _ptr(vecs), _ptr(met),
+                              _ptr(z))
+    if nc < 0:
+        return None
+    vecs = vecs.reshape(16, 4)
+    return {"cand": cand[:nc].copy(), "lp": vecs[0].copy(), "lm": vecs[1].copy(), "cands": vecs[2:2 + nc].copy(),
+            "met": met.copy(), "z_lp": z[0], "z_lm": z[1], "z_mx": z[2], "z_my": z[3], "z_cand": z[4:4 + nc].copy()}
 
 
 def nu_pz(lep, metx, mety, mw=80.4):

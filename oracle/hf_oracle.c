@@ -744,6 +744,7 @@ int orc_pairing_quartic(const double lp[4], const double b[4], const double lm[4
 
 typedef struct {
     int ok;
+    int leps;                  /* two selected opposite-sign leptons */
     vec4 lp, lm;
     int nc;
     int cand[ORC_MAX_CANDS];   /* jet index within the event, candidate order */
@@ -769,6 +770,7 @@ static orc_staged orc_stage(const orc_events *ev, int64_t e, const orc_reco_para
             ++nl;
         }
     if (nl != 2 || !(ev->lep_q[lk[0]] * ev->lep_q[lk[1]] < 0.0)) return s;
+    s.leps = 1;
     uint32_t kp = ev->lep_q[lk[0]] > 0.0 ? lk[0] : lk[1];
     uint32_t km = ev->lep_q[lk[0]] > 0.0 ? lk[1] : lk[0];
     s.lp = orc_from_polar(ev->lep_pt[kp], ev->lep_eta[kp], ev->lep_phi[kp], ev->lep_e[kp]);
@@ -803,6 +805,67 @@ static double orc_smear_factor(double sigma, double z)
     return s > 0.01 ? s : 0.01;
 }
 
+/* One resolution variation of a staged event (reading of section 4's
+ * pseudo-experiments): Gaussian draws for l+ (slot 0), l- (1), MET x (2),
+ * MET y (3) and jet k of the event in input order (4 + k); every 4-vector
+ * component scaled by max(1 + sigma z, 0.01); MET shifted by met_sigma z.
+ * With smear = 0 every draw is zero. */
+typedef struct {
+    double z_lp, z_lm, z_mx, z_my;
+    double zj[ORC_MAX_CANDS];
+    vec4 lp, lm;
+    vec4 cv[ORC_MAX_CANDS];
+    double mx, my;
+} orc_variation;
+
+static void orc_vary(const orc_staged *st, const orc_events *ev, int64_t e, uint64_t g, int v,
+                     const orc_reco_params *p, orc_variation *o)
+{
+    memset(o, 0, sizeof *o);
+    if (p->smear) {
+        o->z_lp = orc_gauss(p->seed, g, (uint32_t)v, 0);
+        o->z_lm = orc_gauss(p->seed, g, (uint32_t)v, 1);
+        o->z_mx = orc_gauss(p->seed, g, (uint32_t)v, 2);
+        o->z_my = orc_gauss(p->seed, g, (uint32_t)v, 3);
+        for (int c = 0; c < st->nc; ++c)
+            o->zj[c] = orc_gauss(p->seed, g, (uint32_t)v, 4u + (uint32_t)st->cand[c]);
+    }
+    o->lp = orc_scale(st->lp, orc_smear_factor(p->lep_sigma, o->z_lp));
+    o->lm = orc_scale(st->lm, orc_smear_factor(p->lep_sigma, o->z_lm));
+    o->mx = ev->met_x[e] + p->met_sigma * o->z_mx;
+    o->my = ev->met_y[e] + p->met_sigma * o->z_my;
+    for (int c = 0; c < st->nc; ++c) o->cv[c] = orc_scale(st->cv[c], orc_smear_factor(st->sigma[c], o->zj[c]));
+}
+
+/* Inspection of one (event, variation) for the tests: the staged candidates
+ * (jet indices within the event) and the varied objects.  Returns -1 when
+ * the event does not have two selected opposite-sign leptons, else the
+ * number of candidates (which may be below two).  vecs: (E, px, py, pz) of
+ * l+, l-, then each candidate; met: shifted (x, y); z: the draws of l+, l-,
+ * MET x, MET y, then each candidate.                                      */
+int orc_stage_vary(const orc_events *ev, int64_t e, int v, const orc_reco_params *p, int32_t *cand,
+                   double *vecs, double *met, double *z)
+{
+    orc_staged st = orc_stage(ev, e, p);
+    if (!st.leps) return -1;
+    orc_variation o;
+    orc_vary(&st, ev, e, (uint64_t)(ev->index_base + e), v, p, &o);
+    const vec4 *all[2 + ORC_MAX_CANDS];
+    all[0] = &o.lp;
+    all[1] = &o.lm;
+    for (int c = 0; c < st.nc; ++c) all[2 + c] = &o.cv[c];
+    for (int k = 0; k < 2 + st.nc; ++k) {
+        vecs[4 * k + 0] = all[k]->e; vecs[4 * k + 1] = all[k]->x;
+        vecs[4 * k + 2] = all[k]->y; vecs[4 * k + 3] = all[k]->z;
+    }
+    for (int c = 0; c < st.nc; ++c) cand[c] = st.cand[c];
+    met[0] = o.mx;
+    met[1] = o.my;
+    z[0] = o.z_lp; z[1] = o.z_lm; z[2] = o.z_mx; z[3] = o.z_my;
+    for (int c = 0; c < st.nc; ++c) z[4 + c] = o.zj[c];
+    return st.nc;
+}
+
 /* Reconstruct the compacted events idx[0..S) (global ids).  For each event,
  * variation v and pairing (i, j) (candidate i with l+, candidate j with l-,
  * i != j, pairing index p = i*nc + j), every accepted solution is scored by
@@ -832,27 +895,17 @@ int64_t orc_ttbar_reco(const orc_events *ev, const int32_t *idx, int64_t S, cons
         memset(&best_s, 0, sizeof best_s);
         if (st.ok) {
             for (int v = 0; v < V; ++v) {
-                double z_lp = 0, z_lm = 0, z_mx = 0, z_my = 0;
-                double zj[ORC_MAX_CANDS];
-                for (int c = 0; c < st.nc; ++c) zj[c] = 0.0;
-                if (p->smear) {
-                    z_lp = orc_gauss(p->seed, (uint64_t)g, (uint32_t)v, 0);
-                    z_lm = orc_gauss(p->seed, (uint64_t)g, (uint32_t)v, 1);
-                    z_mx = orc_gauss(p->seed, (uint64_t)g, (uint32_t)v, 2);
-                    z_my = orc_gauss(p->seed, (uint64_t)g, (uint32_t)v, 3);
-                    for (int c = 0; c < st.nc; ++c)
-                        zj[c] = orc_gauss(p->seed, (uint64_t)g, (uint32_t)v, 4u + (uint32_t)st.cand[c]);
-                }
-                /* every component of each 4-vector scaled by max(1 + sigma z, 0.01) */
-                vec4 lp = orc_scale(st.lp, orc_smear_factor(p->lep_sigma, z_lp));
-                vec4 lm = orc_scale(st.lm, orc_smear_factor(p->lep_sigma, z_lm));
-                double mx = ev->met_x[e] + p->met_sigma * z_mx;
-                double my = ev->met_y[e] + p->met_sigma * z_my;
+                orc_variation o;
+                orc_vary(&st, ev, e, (uint64_t)g, v, p, &o);
+                const double z_lp = o.z_lp, z_lm = o.z_lm, z_mx = o.z_mx, z_my = o.z_my;
+                const double *zj = o.zj;
+                const vec4 lp = o.lp, lm = o.lm;
+                const double mx = o.mx, my = o.my;
                 for (int i = 0; i < st.nc; ++i) {
-                    vec4 b = orc_scale(st.cv[i], orc_smear_factor(st.sigma[i], zj[i]));
+                    const vec4 b = o.cv[i];
                     for (int j = 0; j < st.nc; ++j) {
                         if (j == i) continue;
-                        vec4 bb = orc_scale(st.cv[j], orc_smear_factor(st.sigma[j], zj[j]));
+                        const vec4 bb = o.cv[j];
                         orc_solution sol[4];
                         int ns = orc_solve_pairing_v(lp, b, lm, bb, mx, my, p->m_t, p->m_w, sol);
                         nsol += ns;
