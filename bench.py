@@ -31,6 +31,8 @@ sys.path.insert(0, ROOT)
 WORKLOAD = "ttbar1M_v64"
 SEMILEP_WORKLOAD = "tchan1M"
 STREAM_WORKLOAD = "hlhc50M"
+# further workloads, each reported under "workloads" with its own roofline and oracle baseline
+EXTRA_WORKLOADS = ("ttbar10k", "tth4M_v256", "stress2M_heavytail")
 
 # Algorithmic FP operations of the reconstruction search kernel per unit of
 # work (one each for add, mul, div, sqrt, transcendental; two for FMA),
@@ -65,6 +67,9 @@ def _parse():
     ap.add_argument("--no-semilep", action="store_true", help="skip the single-neutrino reconstruction leg")
     ap.add_argument("--no-stream", action="store_true", help="skip the chunked-stream leg")
     ap.add_argument("--no-chi2", action="store_true", help="skip the dileptonic chi^2 fit leg")
+    ap.add_argument("--no-workloads", action="store_true",
+                    help="skip the further workloads (10k unsmeared, 4M ttH at 256 variations, 2M heavy-tailed)")
+    ap.add_argument("--workloads-only", action="store_true", help="run only the further workloads")
     ap.add_argument("--stream-only", action="store_true",
                     help="run only the chunked-stream leg and print its JSON object (for profilers)")
     ap.add_argument("--stream-chunks", type=int, default=50)
@@ -103,6 +108,9 @@ def main():
     if args.stream_only:
         print(json.dumps({"stream": stream_leg(args, torch)}))
         return
+    if args.workloads_only:
+        print(json.dumps({"workloads": {name: workload_leg(args, torch, name) for name in EXTRA_WORKLOADS}}))
+        return
     cfg = hfgen.config(WORKLOAD)
     t0 = time.time()
     ev = hfgen.generate(cfg)
@@ -131,29 +139,11 @@ def main():
 
     # ---- dominant kernel: the reconstruction search, timed alone with HIP events
     res = ch.results()
-    stats0 = ch.out.t["stats"].cpu().numpy().astype(np.int64).copy()
-    timer = B.KernelTimer()
-    kms = []
-    with timer:
-        for _ in range(max(3, min(10, args.steps))):
-            ch.run_reco()
-            kms.append(timer.elapsed_ms())
-    timer.close()
-    stats1 = ch.out.t["stats"].cpu().numpy().astype(np.int64)
-    per = (stats1 - stats0) / len(kms)  # events, variations, pairings, intervals, solutions per launch
-    kernel_ms = float(np.mean(kms))
-    flops = FLOP_PER_VARIATION * per[1] + FLOP_PER_PAIRING * per[2] + FLOP_PER_INTERVAL * per[3]
-    achieved = flops / (kernel_ms * 1e-3) / 1e12
     kname = "k_search_ev<float>" if args.precision == "mixed" else "k_search_ev<double>"
-    roofline = {"bound": "alu", "kernel": kname,
-                "achieved": round(achieved, 3), "peak": PEAK_ALU_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_ALU_TFLOPS, 4), "traffic": measured_traffic(kname),
-                "kernel_ms": round(kernel_ms, 4), "flop_per_launch": float(flops),
-                "units_per_launch": {"events": int(per[0]), "variations": int(per[1]), "pairings": int(per[2]),
-                                     "intervals": int(per[3]), "solutions": int(per[4])},
-                "flop_per_unit": {"variation": FLOP_PER_VARIATION, "pairing": FLOP_PER_PAIRING,
-                                  "interval": FLOP_PER_INTERVAL},
-                "issued_view": issued_view(kname, kernel_ms)}
+    roofline = search_roofline(B, ch, args.steps, kname)
+    roofline["traffic"] = measured_traffic(kname)
+    roofline["issued_view"] = issued_view(kname, roofline["kernel_ms"])
+    sel_roof = select_roofline(torch, ch, ev)
 
     out = {"metric": cfg_metric(), "value": round(value, 1), "unit": "events/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
@@ -163,7 +153,7 @@ def main():
                       "cuts": [c["name"] for c in cfg["cuts"]], "precision": args.precision,
                       "survivors": int(res["count"]), "reconstructed": int(len(res["final"])),
                       "parallelism": "1 GPU"},
-           "roofline": roofline}
+           "roofline": roofline, "select_roofline": sel_roof}
 
     if not args.profile_only and not args.no_fp64_form and args.precision == "mixed":
         del ch
@@ -186,7 +176,183 @@ def main():
     if not args.no_stream:
         torch.cuda.empty_cache()
         out["stream"] = stream_leg(args, torch)
+    if not args.no_workloads:
+        out["workloads"] = {}
+        for name in EXTRA_WORKLOADS:
+            torch.cuda.empty_cache()
+            out["workloads"][name] = workload_leg(args, torch, name)
     print(json.dumps(out))
+
+
+def search_roofline(B, ch, steps, kname):
+    """The reconstruction search kernel of a chain timed alone (HIP events that
+    hf_ttbar_reco records around it) over a few launches; its algorithmic
+    FP64 work from the launch's unit counts (variations, pairings, root
+    intervals) against the FP64 vector peak."""
+    stats0 = ch.out.t["stats"].cpu().numpy().astype(np.int64).copy()
+    timer = B.KernelTimer()
+    kms = []
+    with timer:
+        for _ in range(max(3, min(10, steps))):
+            ch.run_reco()
+            kms.append(timer.elapsed_ms())
+    timer.close()
+    stats1 = ch.out.t["stats"].cpu().numpy().astype(np.int64)
+    per = (stats1 - stats0) / len(kms)  # events, variations, pairings, intervals, solutions per launch
+    kernel_ms = float(np.mean(kms))
+    flops = FLOP_PER_VARIATION * per[1] + FLOP_PER_PAIRING * per[2] + FLOP_PER_INTERVAL * per[3]
+    achieved = flops / (kernel_ms * 1e-3) / 1e12
+    return {"bound": "alu", "kernel": kname,
+            "achieved": round(achieved, 3), "peak": PEAK_ALU_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(achieved / PEAK_ALU_TFLOPS, 4), "traffic": None,
+            "kernel_ms": round(kernel_ms, 4), "flop_per_launch": float(flops),
+            "units_per_launch": {"events": int(per[0]), "variations": int(per[1]), "pairings": int(per[2]),
+                                 "intervals": int(per[3]), "solutions": int(per[4])},
+            "flop_per_unit": {"variation": FLOP_PER_VARIATION, "pairing": FLOP_PER_PAIRING,
+                              "interval": FLOP_PER_INTERVAL}}
+
+
+# Algorithmic HBM bytes of the cut stage per event (hf_select): the two
+# offsets of each object list (16), per lepton pT, eta and charge (12), per
+# jet pT, eta and b-tag (12), MET (8) and the survive byte (1); cuts that
+# read phi and E (M_ll, isolation) add 8 per object.  A cut after an event's
+# first failure reads nothing, so this counts every column once per event:
+# the bytes a chain of these cuts needs when no event is dropped early.
+def select_bytes(ev, cuts):
+    n = ev["n"]
+    n_lep, n_jet = int(ev["lep_off"][-1]), int(ev["jet_off"][-1])
+    kinds = {c["kind"] for c in cuts}
+    per_obj = 12 + (8 if kinds & {"MLL_MIN", "LEP_ISO"} else 0)
+    return n * (16 + 8 + 1) + (n_lep + n_jet) * per_obj
+
+
+def select_roofline(torch, ch, ev):
+    """hf_select of a chain timed alone with torch events on its stream, against
+    the HBM peak with the cut stage's algorithmic bytes."""
+    s = torch.cuda.current_stream()
+    pairs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(10)]
+    ch.run_select()
+    for a, b in pairs:
+        a.record(s)
+        ch.run_select()
+        b.record(s)
+    torch.cuda.synchronize()
+    ms = float(np.median([a.elapsed_time(b) for a, b in pairs]))
+    nbytes = select_bytes(ev, ch.cuts)
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    return {"bound": "hbm", "kernel": "k_select", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": round(gbs / PEAK_HBM_GBS, 4), "kernel_ms": round(ms, 4), "bytes_per_launch": int(nbytes),
+            "note": "bytes of every column the chain reads, once per event; waves whose events have all "
+                    "failed skip the later cuts' columns, so the kernel may read less"}
+
+
+def workload_leg(args, torch, name):
+    """One further workload of the hot path: generated at its stated size,
+    select -> compact -> reconstruction -> compact -> device reorder recorded
+    as one HIP graph per step; the search kernel's roofline from its unit
+    counts; the oracle on the first 2^16 events beside it (with the GPU's
+    agreement on those events).  The 8-cut ttH chain also runs with the cut
+    order fixed at the user's order (no reordering) for comparison; the
+    heavy-tailed batch reports the autotuner's choice of launch."""
+    import hfgen
+    from paper_2211_14346_amd import binding as B
+    from paper_2211_14346_amd.chain import Chain
+
+    cfg = hfgen.config(name)
+    t0 = time.time()
+    ev = hfgen.generate(cfg)
+    n = ev["n"]
+    print(f"[bench] {name}: generated {n} events in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    steps = max(3, args.steps // 2) if n >= 2_000_000 else args.steps
+    leg = {"metric": "events/s through cut chain + ttbar reco; % VALU roofline of the search kernel",
+           "unit": "events/s", "dtype": "f32+f64", "data": "synthetic",
+           "config": {"workload": name, "events": n, "cuts": [c["name"] for c in cfg["cuts"]],
+                      "variations": "per event (1..1024 log-uniform)" if cfg.get("var_mode") else cfg["reco"]["n_var"],
+                      "precision": "mixed"}}
+    ch = Chain(ev, cfg["cuts"], cfg["reco"], precision="mixed")
+    ch.step()
+    torch.cuda.synchronize()
+    if cfg.get("var_mode"):
+        # the autotuner on this batch: both schedules timed, the faster one kept
+        res0 = ch.results()
+        p = ch.params
+        ms = B.ttbar_reco_autotune(ch.dev, ch.idx, ch.count, ch.n, p, ch.out, ch.ws_reco)
+        leg["autotune"] = {"choice": B.SCHED_NAME.get(int(p.schedule), int(p.schedule)),
+                           "ms_per_call": {"event (4 waves/workgroup)": round(ms[0], 4),
+                                           "event_wg128 (2 waves/workgroup)": round(ms[1], 4),
+                                           "event_wg64 (1 wave/workgroup)": round(ms[2], 4)},
+                           "survivors": int(res0["count"])}
+        ch.params = p
+    if name == "tth4M_v256":
+        # the user's order, never reordered
+        g_user = ch.capture(reorder=False)
+        ch.reset_counters()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ch.replay()
+        torch.cuda.synchronize()
+        dt_user = time.perf_counter() - t0
+        sel_user = select_roofline(torch, ch, ev)
+        del g_user
+        ch.graph = None
+        # adaptive: reorder from the counters after each step until the order settles
+        for _ in range(3):
+            ch.step(reorder=True)
+        torch.cuda.synchronize()
+        order = [cfg["cuts"][k]["name"] for k in ch.order.cpu().numpy()]
+        leg["orders"] = {"user": {"order": [c["name"] for c in cfg["cuts"]], "ms_per_step": round(1e3 * dt_user / steps, 4),
+                                  "select_ms": sel_user["kernel_ms"]},
+                         "adaptive": {"order": order}}
+    for _ in range(max(1, args.warmup)):
+        ch.step(reorder=True)
+    torch.cuda.synchronize()
+    ch.capture(reorder=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ch.replay()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    leg["value"] = round(n * steps / dt, 1)
+    leg["ms_per_step"] = round(1e3 * dt / steps, 4)
+    leg["steps"] = steps
+    res = ch.results()
+    leg["config"]["survivors"] = int(res["count"])
+    leg["config"]["reconstructed"] = int(len(res["final"]))
+    leg["roofline"] = search_roofline(B, ch, steps, "k_search_ev<float>")
+    leg["select_roofline"] = select_roofline(torch, ch, ev)
+    if "orders" in leg:
+        leg["orders"]["adaptive"]["ms_per_step"] = leg["ms_per_step"]
+        leg["orders"]["adaptive"]["select_ms"] = leg["select_roofline"]["kernel_ms"]
+    if name == "ttbar10k":
+        leg["roofline"]["note"] = ("10k events at one variation: the launch is too small to fill the GPU, "
+                                   "its time is launch latency, not arithmetic")
+    print(f"[bench] {name}: {leg['ms_per_step']} ms/step, search {leg['roofline']['kernel_ms']} ms, "
+          f"frac {leg['roofline']['frac']}", file=sys.stderr, flush=True)
+    if not args.profile_only and not args.no_cpu_baseline:
+        import oracle
+        from tests.gpu_compare import compare
+        m = min(n, 1 << 16)
+        sub = hfgen.subset(ev, np.arange(m))
+        threads = min(os.cpu_count() or 1, 16)
+        oracle.lib()
+        t0 = time.perf_counter()
+        surv, _, _ = oracle.select(sub, cfg["cuts"], list(range(len(cfg["cuts"]))))
+        idx = oracle.compact(surv)
+        rec = oracle.ttbar_reco(sub, idx, cfg["reco"], n_threads=threads)
+        oracle.compact(rec["has_sol"], 0, idx)
+        dtc = time.perf_counter() - t0
+        leg["cpu_baseline"] = {"value": round(m / dtc, 1), "unit": "events/s", "cores": threads, "kind": "oracle",
+                               "sample": f"first {m} events of the {name} batch (a seeded subset: the generator "
+                                         f"draws events independently), select+compact+reco+compact, "
+                                         f"{dtc:.1f} s wall on {threads} threads"}
+        k = int(np.searchsorted(res["idx"], m))  # compacted positions of the sample's survivors
+        assert np.array_equal(res["idx"][:k], idx)
+        st = compare({kk: v[:k] for kk, v in res["reco"].items() if kk != "stats"}, rec)
+        leg["accuracy_vs_oracle"] = {kk: (round(v, 8) if isinstance(v, float) else v) for kk, v in st.items()}
+    del ch
+    return leg
 
 
 # Algorithmic FP64 operations of the chi^2 fit (hf_dilep_chi2_reco), counted

@@ -215,17 +215,18 @@ int hf_compact_noalloc(const uint8_t *d_mask, int64_t capacity, const int64_t *d
  * smear = 0 gives every variation z = 0.  Random streams: Philox4x32-10
  * keyed by seed, counter (global event id, variation, block).  reco_cut is
  * the id of the RECO cut whose counters the call updates (-1: none).
- * schedule is a scheduling choice that leaves every result unchanged:
- * HF_SCHED_AUTO, HF_SCHED_EVENT (one wavefront per event, lanes over its
- * variations) or HF_SCHED_WORKLIST (the variations of all events laid end to
- * end in 16-lane granules and cut into 64-lane blocks: events with few
- * variations share a block, events with many are split over blocks and
- * wavefronts).  HF_SCHED_AUTO takes the choice that hf_ttbar_reco_autotune
- * stored for this configuration in the file named by HF_AUTOTUNE_CACHE, if
- * any, else one wavefront per event. */
+ * schedule is a launch choice that leaves every result unchanged: the
+ * search runs one wavefront per event (lanes over its variations) on a
+ * persistent grid, in workgroups of four (HF_SCHED_EVENT), two
+ * (HF_SCHED_EVENT_WG128) or one (HF_SCHED_EVENT_WG64) wavefronts, eight
+ * wavefronts per CU in every case.  HF_SCHED_AUTO takes the choice that
+ * hf_ttbar_reco_autotune stored for this configuration in the file named by
+ * HF_AUTOTUNE_CACHE, if any, else HF_SCHED_EVENT.  (The value 2 named a
+ * worklist schedule that was slower on every workload and is rejected.) */
 #define HF_SCHED_AUTO 0
 #define HF_SCHED_EVENT 1
-#define HF_SCHED_WORKLIST 2
+#define HF_SCHED_EVENT_WG64 3
+#define HF_SCHED_EVENT_WG128 4
 
 typedef struct hf_reco_params {
     double m_t, m_w, lambda_pt;
@@ -272,18 +273,19 @@ int hf_ttbar_reco(const hf_events_t *ev, const int32_t *d_idx, const int64_t *d_
                   const hf_reco_params_t *h_params, const hf_reco_out_t *out, hf_counters_t *d_counters,
                   void *d_ws, size_t ws_bytes, hipStream_t stream);
 
-/* Autotuner for the schedule of hf_ttbar_reco (section 5: the framework
+/* Autotuner for the launch of hf_ttbar_reco (section 5: the framework
  * adapts its execution to the hardware and the workload).  Runs the same
  * reconstruction once per candidate schedule (HF_SCHED_EVENT,
- * HF_SCHED_WORKLIST) after a warm-up, times each with HIP events on
- * `stream`, writes the faster one into h_params->schedule and, when the
+ * HF_SCHED_EVENT_WG128, HF_SCHED_EVENT_WG64) after a warm-up, times each
+ * with HIP events on `stream`, writes the fastest into h_params->schedule
+ * and, when the
  * environment variable HF_AUTOTUNE_CACHE names a file, appends the choice
  * under this configuration's key (device, precision, pairing mode, variation
  * layout, capacity bucket) so that later HF_SCHED_AUTO calls in any process
  * use it.  The outputs are those of an ordinary call; counters and stats are
  * not updated.  Synchronises `stream` (not for graph capture).
- *   h_ms: NULL or double[2], receives the measured milliseconds per call of
- *         HF_SCHED_EVENT and HF_SCHED_WORKLIST.
+ *   h_ms: NULL or double[3], receives the measured milliseconds per call of
+ *         HF_SCHED_EVENT, HF_SCHED_EVENT_WG128 and HF_SCHED_EVENT_WG64.
  * Errors: those of hf_ttbar_reco; HF_ERR_DEVICE if timing fails. */
 int hf_ttbar_reco_autotune(const hf_events_t *ev, const int32_t *d_idx, const int64_t *d_count, int64_t capacity,
                            hf_reco_params_t *h_params, const hf_reco_out_t *out, void *d_ws, size_t ws_bytes,

@@ -216,7 +216,8 @@ def chain_select(chain, dev, order, survive, counters, ws, stream=None):
     _check(rc, "hf_chain_select")
 
 
-SCHED = {"auto": 0, "event": 1, "worklist": 2}
+SCHED = {"auto": 0, "event": 1, "event_wg64": 3, "event_wg128": 4}
+SCHED_NAME = {v: k for k, v in SCHED.items()}
 
 
 def reco_params(reco, precision="mixed", reco_cut=-1, schedule="auto"):
@@ -408,13 +409,14 @@ def reorder_stats(counters_host, cuts_arr, n_cuts):
 
 
 def ttbar_reco_autotune(dev, idx, count, capacity, params, outs, ws, stream=None):
-    """Times the two schedules on this input, stores the faster one in params
-    (and in the HF_AUTOTUNE_CACHE file if set); returns (ms_event, ms_worklist)."""
-    ms = (C.c_double * 2)()
+    """Times the candidate launches on this input, stores the fastest in params
+    (and in the HF_AUTOTUNE_CACHE file if set); returns the milliseconds of
+    (event, event_wg128, event_wg64)."""
+    ms = (C.c_double * 3)()
     rc = lib().hf_ttbar_reco_autotune(dev.ptr, _p(idx), _p(count), int(capacity), C.byref(params), C.byref(outs.s),
                                       _p(ws), ws.numel() * ws.element_size(), _stream(stream), ms)
     _check(rc, "hf_ttbar_reco_autotune")
-    return ms[0], ms[1]
+    return ms[0], ms[1], ms[2]
 
 
 def reorder_device(counters, cuts_arr, n_cuts, order, stream=None):

@@ -68,7 +68,7 @@ int check_cuts(const hf_cut_t *h_cuts, int n_cuts, bool *need_phi_e) {
     return HF_OK;
 }
 
-// ---- autotuner cache: one line per configuration, "key schedule ms_event ms_worklist";
+// ---- autotuner cache: one line per configuration, "key schedule ms_wg256 ms_wg128 ms_wg64";
 // the last line for a key wins.  Read once per process from HF_AUTOTUNE_CACHE.
 std::mutex g_tune_mu;
 bool g_tune_loaded = false;
@@ -90,6 +90,13 @@ std::string tune_key(const hf_events_t *ev, const hf_reco_params_t *p, int64_t c
     return key;
 }
 
+bool valid_schedule(int s) {
+    return s == HF_SCHED_AUTO || s == HF_SCHED_EVENT || s == HF_SCHED_EVENT_WG64 || s == HF_SCHED_EVENT_WG128;
+}
+
+// wavefronts per workgroup of the search for a schedule
+int schedule_waves(int s) { return s == HF_SCHED_EVENT_WG64 ? 1 : s == HF_SCHED_EVENT_WG128 ? 2 : 4; }
+
 void load_tune_cache() {
     if (g_tune_loaded) return;
     g_tune_loaded = true;
@@ -99,9 +106,9 @@ void load_tune_cache() {
     if (!f) return;
     char key[256];
     int sched;
-    double a, b;
-    while (fscanf(f, "%255s %d %lf %lf", key, &sched, &a, &b) == 4)
-        if (sched == HF_SCHED_EVENT || sched == HF_SCHED_WORKLIST) g_tune[key] = sched;
+    double a, b, c;
+    while (fscanf(f, "%255s %d %lf %lf %lf", key, &sched, &a, &b, &c) == 5)
+        if (valid_schedule(sched) && sched != HF_SCHED_AUTO) g_tune[key] = sched;
     fclose(f);
 }
 
@@ -112,7 +119,7 @@ int tuned_schedule(const std::string &key) {
     return it == g_tune.end() ? HF_SCHED_AUTO : it->second;
 }
 
-void store_schedule(const std::string &key, int sched, const double ms[2]) {
+void store_schedule(const std::string &key, int sched, const double ms[3]) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     load_tune_cache();
     g_tune[key] = sched;
@@ -120,7 +127,7 @@ void store_schedule(const std::string &key, int sched, const double ms[2]) {
     if (!path || !*path) return;
     FILE *f = fopen(path, "a");
     if (!f) return;
-    fprintf(f, "%s %d %.6f %.6f\n", key.c_str(), sched, ms[0], ms[1]);
+    fprintf(f, "%s %d %.6f %.6f %.6f\n", key.c_str(), sched, ms[0], ms[1], ms[2]);
     fclose(f);
 }
 
@@ -231,8 +238,7 @@ int hf_ttbar_reco(const hf_events_t *ev, const int32_t *d_idx, const int64_t *d_
     if (!(p->jet_a >= 0.0) || !(p->jet_c >= 0.0) || !(p->lep_sigma >= 0.0) || !(p->met_sigma >= 0.0))
         return fail(HF_ERR_INVAL, "hf_ttbar_reco: resolutions must be finite and >= 0");
     if (p->smear != 0 && p->smear != 1) return fail(HF_ERR_INVAL, "hf_ttbar_reco: smear must be 0 or 1");
-    if (p->schedule != HF_SCHED_AUTO && p->schedule != HF_SCHED_EVENT && p->schedule != HF_SCHED_WORKLIST)
-        return fail(HF_ERR_INVAL, "hf_ttbar_reco: unknown schedule %d", p->schedule);
+    if (!valid_schedule(p->schedule)) return fail(HF_ERR_INVAL, "hf_ttbar_reco: unknown schedule %d", p->schedule);
     const size_t need = hf::reco_ws_bytes(capacity);
     if (!d_ws || ws_bytes < need)
         return fail(HF_ERR_CAPACITY, "hf_ttbar_reco: workspace %zu bytes < %zu required", ws_bytes, need);
@@ -263,9 +269,9 @@ int hf_ttbar_reco(const hf_events_t *ev, const int32_t *d_idx, const int64_t *d_
     hf_counters_t *rc = (d_counters && p->reco_cut >= 0) ? d_counters + p->reco_cut : nullptr;
     int sched = p->schedule;
     if (sched == HF_SCHED_AUTO) sched = tuned_schedule(tune_key(ev, p, capacity));
-    if (sched == HF_SCHED_AUTO) sched = HF_SCHED_EVENT;  // measured faster on every workload here
+    if (sched == HF_SCHED_AUTO) sched = HF_SCHED_EVENT;
     hipError_t e = hf::launch_reco(hf::make_view(*ev), d_idx, d_count, capacity, a, p->precision, o, rc, d_ws,
-                                   sched == HF_SCHED_WORKLIST, stream);
+                                   schedule_waves(sched), stream);
     if (e != hipSuccess) return device_fail("hf_ttbar_reco launch", e);
     return HF_OK;
 }
@@ -277,8 +283,8 @@ int hf_ttbar_reco_autotune(const hf_events_t *ev, const int32_t *d_idx, const in
     hf_reco_params_t p = *h_params;
     hf_reco_out_t o = *out;
     o.stats = nullptr;  // the trial calls leave no trace in the statistics or counters
-    const int cand[2] = {HF_SCHED_EVENT, HF_SCHED_WORKLIST};
-    double ms[2] = {0.0, 0.0};
+    const int cand[3] = {HF_SCHED_EVENT, HF_SCHED_EVENT_WG128, HF_SCHED_EVENT_WG64};
+    double ms[3] = {0.0, 0.0, 0.0};
     hipEvent_t t0 = nullptr, t1 = nullptr;
     if (hipEventCreate(&t0) != hipSuccess || hipEventCreate(&t1) != hipSuccess) {
         if (t0) (void)hipEventDestroy(t0);
@@ -286,7 +292,7 @@ int hf_ttbar_reco_autotune(const hf_events_t *ev, const int32_t *d_idx, const in
     }
     int rc = HF_OK;
     constexpr int kReps = 3;
-    for (int c = 0; c < 2 && rc == HF_OK; ++c) {
+    for (int c = 0; c < 3 && rc == HF_OK; ++c) {
         p.schedule = cand[c];
         rc = hf_ttbar_reco(ev, d_idx, d_count, capacity, &p, &o, nullptr, d_ws, ws_bytes, stream);  // warm-up
         if (rc != HF_OK) break;
@@ -303,12 +309,13 @@ int hf_ttbar_reco_autotune(const hf_events_t *ev, const int32_t *d_idx, const in
     (void)hipEventDestroy(t0);
     (void)hipEventDestroy(t1);
     if (rc != HF_OK) return rc;
-    const int best = ms[1] < ms[0] ? HF_SCHED_WORKLIST : HF_SCHED_EVENT;
+    int bi = 0;
+    for (int c = 1; c < 3; ++c)
+        if (ms[c] < ms[bi]) bi = c;
+    const int best = cand[bi];
     h_params->schedule = best;
-    if (h_ms) {
-        h_ms[0] = ms[0];
-        h_ms[1] = ms[1];
-    }
+    if (h_ms)
+        for (int c = 0; c < 3; ++c) h_ms[c] = ms[c];
     store_schedule(tune_key(ev, h_params, capacity), best, ms);
     return HF_OK;
 }

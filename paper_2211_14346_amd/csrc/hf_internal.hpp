@@ -70,7 +70,7 @@ size_t reco_ws_bytes(int64_t capacity);
 void set_reco_timing(hipEvent_t start, hipEvent_t stop);
 hipError_t launch_reco(const EvView &ev, const int32_t *idx, const int64_t *count, int64_t capacity,
                        const RecoArgs &a, int precision, const RecoOutView &out, hf_counters_t *reco_counter,
-                       void *ws, bool worklist, hipStream_t s);
+                       void *ws, int waves, hipStream_t s);
 
 // ---- single-neutrino reconstruction (hf_semilep.hip)
 struct SemilepArgs {

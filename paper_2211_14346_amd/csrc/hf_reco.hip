@@ -6,31 +6,23 @@
 // Kernels, in launch order.
 //
 // k_stage: eight lanes per compacted event; selects the leptons and b
-// candidates, writes their FP64 Cartesian 4-vectors to a record, the
-// event's count of lane granules (16 variations each; none when no
-// pairing is valid) and an empty best record.
+// candidates, writes their FP64 Cartesian 4-vectors to a record and an
+// empty best record.
 //
-// k_scan_*: exclusive prefix sum of the granule counts (the worklist: the
-// variations of all events laid end to end, each event padded to whole
-// granules).
-//
-// k_search: persistent grid; each wavefront takes a contiguous range of
-// 64-lane blocks of the worklist.  A block holds up to four events (small
-// variation counts are packed) or one slice of a large one (large counts
-// are split over blocks and wavefronts).  The wavefront copies the block's
-// records into LDS and adds, per candidate and lepton side, the constants of
-// the linear maps and of the conic's quadratic part.  Each lane draws its
-// variation (Philox4x32-10 + Box-Muller in precision T) and, for every
-// pairing of its event, assembles the eliminant quartic in FP64 and brackets
-// its real roots (critical points from the closed-form cubic in T, one FP64
-// Newton step each); the wavefront then deals the root intervals out 64 at
-// a time: Halley iteration in FP64, recovery and polish of (x, y), the acceptance
-// test, the energies' signs and the score, each result handed back to the
-// lane that owns the variation.  A segmented argmax with a total-order
-// tie-break (score, then smallest variation, pairing, x) gives each event's
-// winner; an event that crosses a range boundary leaves partial records.
-//
-// k_fixup: merges the partial records of events that crossed a range.
+// k_search_ev: persistent grid, one wavefront per event (events taken from
+// per-class counters).  The wavefront copies the event's record into LDS and
+// adds, per candidate and lepton side, the constants of the linear maps and
+// of the conic's quadratic part.  Lanes run over the variations, 64 at a
+// time.  Each lane draws its variation (Philox4x32-10 + Box-Muller in
+// precision T) and, for every pairing, assembles the eliminant quartic in
+// FP64 and brackets its real roots (critical points from the closed-form
+// cubic in T, one FP64 Newton step each); the wavefront then deals the root
+// intervals out 64 at a time: Halley iteration in FP64, recovery and polish
+// of (x, y), the acceptance test, the energies' signs and the score.  A wave
+// argmax with a total-order tie-break (score, then smallest variation,
+// pairing, x) gives the event's winner.  Instantiated for workgroups of one,
+// two and four wavefronts (a launch choice that leaves every result
+// unchanged; the autotuner times them).
 //
 // k_epilogue: one thread per event; recomputes the winner's kinematics in
 // FP64 (draws recomputed bit-identically in T), writes the outputs, the
@@ -47,8 +39,6 @@
 namespace hf {
 namespace {
 
-constexpr int kRecoBlock = 256;
-constexpr int kRecoWaves = kRecoBlock / kWave;
 constexpr int kMaxC = HF_MAX_CANDS;
 constexpr int kNoBest = 0x7fffffff;
 constexpr size_t kWsHeader = 2048;
@@ -57,11 +47,6 @@ constexpr size_t kWsHeader = 2048;
 // 128-byte line.
 constexpr int kTicketWord = 16;
 constexpr int kTicketClasses = 8;
-constexpr int kGran = 16;              // lanes per granule of the worklist
-constexpr int kGpb = kWave / kGran;    // granules per 64-lane block: at most 4 events per block
-constexpr int kSideCap = 24;           // side-constant slots shared by a block's events
-constexpr int kMaxSearchWaves = 8192;  // bound on the search grid (partial-record space)
-constexpr int kScanTile = 1024;        // elements per block of the prefix sum
 
 // Per-event result of the search, read by the epilogue.
 struct BestRec {
@@ -87,15 +72,6 @@ struct StageRec {
 constexpr int kRecWords = (int)(sizeof(StageRec) / 8);
 static_assert(sizeof(StageRec) == 640 && kRecWords > kWave && kRecWords <= 2 * kWave, "record layout");
 
-// Best solution of an event seen by one wavefront at a boundary of its range
-// of blocks, merged by k_fixup.  k = -1: none; k = -2: the range is empty.
-struct PartRec {
-    int64_t k;
-    int32_t cont;  // the event continues past the end of the range
-    int32_t nsol, v, p, nc, pad;
-    double score, x, y;
-};
-
 template <typename T>
 struct WaveStageEv {
     StageRec rec;
@@ -103,22 +79,6 @@ struct WaveStageEv {
     double sm[kMaxC][kSide];  // side constants with l-
     T z[kMaxC][kWave];  // per-lane draw of each candidate
     T zl[4][kWave];     // per-lane draws of l+, l-, MET x, MET y
-};
-
-template <typename T>
-struct WaveStage {
-    StageRec rec[kGpb];             // the block's events
-    double sp[kSideCap][kSide];     // side constants with l+ (slot base + candidate)
-    double sm[kSideCap][kSide];     // side constants with l-
-    int okp[kSideCap], okm[kSideCap];
-    double res_w[kWave], res_x[kWave], res_y[kWave];  // stage-2 results, by queue position
-    int res_ok[kWave];
-    double gb_s[kGpb], gb_x[kGpb], gb_y[kGpb];       // per-granule best
-    int gb_v[kGpb], gb_p[kGpb], gb_n[kGpb];
-    T z[kMaxC][kWave];  // per-lane draw of each candidate of the lane's event
-    T zl[4][kWave];     // per-lane draws of l+, l-, MET x, MET y
-    PartRec headp, tailp;  // partial records of the range's first and last event
-    int queue[4 * kWave];  // stage-2 queue: source lane | interval << 6
 };
 
 __device__ __forceinline__ void wave_sync() {
@@ -202,10 +162,9 @@ constexpr int kStageEvents = 256 / kStageLanes;  // events per block
 
 __global__ __launch_bounds__(256) void k_stage(EvView ev, const int32_t *__restrict__ idx,
                                                const int64_t *__restrict__ count, int64_t capacity, RecoArgs a,
-                                               StageRec *__restrict__ stage, int32_t *__restrict__ gcnt,
+                                               StageRec *__restrict__ stage,
                                                BestRec *__restrict__ best) {
     __shared__ uint32_t s_jl[kStageEvents][kMaxC];  // candidates' jet positions
-    __shared__ double s_lep[kStageEvents][8];       // l+ then l-
     const int lane = lane_id(), sub = lane & (kStageLanes - 1);
     const int slot = threadIdx.x / kStageLanes;
     const int shift = lane & ~(kStageLanes - 1);     // the event's first lane in the wave
@@ -290,7 +249,6 @@ __global__ __launch_bounds__(256) void k_stage(EvView ev, const int32_t *__restr
     }
     if (!lep_ok) nc = 0;
     // ---- the record: leptons by lanes 0 and 1, candidates two per lane
-    uint32_t okp = 0, okm = 0;
     if (nc > 0) {
         const uint32_t j0 = ev.jet_off[e];
         if (sub < 2) {
@@ -298,20 +256,12 @@ __global__ __launch_bounds__(256) void k_stage(EvView ev, const int32_t *__restr
             double v[4];
             polar_to_cart(ev.lep_pt[q], ev.lep_eta[q], ev.lep_phi[q], ev.lep_e[q], v);
             double *dst = sub == 0 ? r.lp : r.lm;
-            for (int c = 0; c < 4; ++c) {
-                dst[c] = v[c];
-                s_lep[slot][4 * sub + c] = v[c];
-            }
+            for (int c = 0; c < 4; ++c) dst[c] = v[c];
             const double m2 = v[0] * v[0] - v[1] * v[1] - v[2] * v[2] - v[3] * v[3];
             if (sub == 0) r.ml2p = m2;
             else r.ml2m = m2;
         }
-        wave_sync();
-        double lp[4], lm[4];
-        for (int c = 0; c < 4; ++c) {
-            lp[c] = s_lep[slot][c];
-            lm[c] = s_lep[slot][4 + c];
-        }
+        wave_sync();  // the candidates' jet positions were written by other lanes
         for (int c = sub; c < nc; c += kStageLanes) {
             const uint32_t q = s_jl[slot][c];
             double v[4];
@@ -320,17 +270,7 @@ __global__ __launch_bounds__(256) void k_stage(EvView ev, const int32_t *__restr
             for (int u = 0; u < 4; ++u) r.cand[c][u] = v[u];
             r.sigma[c] = sqrt(a.jet_a * a.jet_a / (double)en + a.jet_c * a.jet_c);
             r.jidx[c] = (int32_t)(q - j0);
-            // valid sides (the same test as make_side)
-            double sd[kSide];
-            if (make_side(lp, v, sd)) okp |= 1u << c;
-            if (make_side(lm, v, sd)) okm |= 1u << c;
         }
-    }
-    // the event's masks: OR over its eight lanes
-#pragma unroll
-    for (int off = 1; off < kStageLanes; off <<= 1) {
-        okp |= __shfl_xor(okp, off);
-        okm |= __shfl_xor(okm, off);
     }
     if (sub == 2) {
         r.g = g;
@@ -342,10 +282,6 @@ __global__ __launch_bounds__(256) void k_stage(EvView ev, const int32_t *__restr
         r.V = V;
     }
     if (sub == 3) {
-        int npair = 0;
-        for (int c = 0; c < nc; ++c)
-            if ((okp >> c) & 1u) npair += __popc(okm & ~(1u << c));
-        gcnt[k] = (npair > 0 && V > 0) ? (V + kGran - 1) / kGran : 0;
         BestRec b;
         b.score = -INFINITY;
         b.x = b.y = 0.0;
@@ -356,569 +292,20 @@ __global__ __launch_bounds__(256) void k_stage(EvView ev, const int32_t *__restr
     }
 }
 
-// ------------------------------------------------------------ prefix sum
-// Exclusive prefix sum of the granule counts: per tile of kScanTile counts a
-// total (k_scan_tiles), the tile totals scanned by one block (k_scan_top),
-// then each tile's counts scanned from its tile offset (k_scan_apply).
-// gofs[S] receives the grand total.
-
-__device__ __forceinline__ int64_t block_exclusive_scan(int64_t v, int64_t *s_w, int64_t &total) {
-    // 256 threads: wave inclusive scans, then the four wave totals
-    const int lane = lane_id(), wave = threadIdx.x / kWave;
-    int64_t inc = v;
-#pragma unroll
-    for (int off = 1; off < kWave; off <<= 1) {
-        const int64_t o = __shfl_up(inc, off);
-        if (lane >= off) inc += o;
-    }
-    if (lane == kWave - 1) s_w[wave] = inc;
-    __syncthreads();
-    int64_t base = 0, tot = 0;
-#pragma unroll
-    for (int w = 0; w < 256 / kWave; ++w) {
-        if (w < wave) base += s_w[w];
-        tot += s_w[w];
-    }
-    __syncthreads();
-    total = tot;
-    return base + inc - v;
-}
-
-__global__ __launch_bounds__(256) void k_scan_tiles(const int32_t *__restrict__ gcnt,
-                                                    const int64_t *__restrict__ count, int64_t capacity,
-                                                    int64_t *__restrict__ tsum) {
-    __shared__ int64_t s_w[256 / kWave];
-    const int64_t S = clamp_count(count, capacity);
-    const int64_t t0 = (int64_t)blockIdx.x * kScanTile;
-    if (t0 >= S && blockIdx.x > 0) return;
-    int64_t v = 0;
-#pragma unroll
-    for (int u = 0; u < kScanTile / 256; ++u) {
-        const int64_t k = t0 + (int64_t)threadIdx.x * (kScanTile / 256) + u;
-        if (k < S) v += gcnt[k];
-    }
-    int64_t total;
-    block_exclusive_scan(v, s_w, total);
-    if (threadIdx.x == 0) tsum[blockIdx.x] = total;
-}
-
-__global__ __launch_bounds__(256) void k_scan_top(const int64_t *__restrict__ count, int64_t capacity,
-                                                  int64_t *__restrict__ tsum) {
-    __shared__ int64_t s_w[256 / kWave];
-    const int64_t S = clamp_count(count, capacity);
-    const int64_t nt = S > 0 ? (S + kScanTile - 1) / kScanTile : 1;
-    int64_t carry = 0;
-    for (int64_t c0 = 0; c0 < nt; c0 += 256) {
-        const int64_t t = c0 + threadIdx.x;
-        const int64_t v = t < nt ? tsum[t] : 0;
-        int64_t total;
-        const int64_t ex = block_exclusive_scan(v, s_w, total);
-        if (t < nt) tsum[t] = carry + ex;
-        carry += total;
-    }
-    if (threadIdx.x == 0) tsum[nt] = carry;
-}
-
-__global__ __launch_bounds__(256) void k_scan_apply(const int32_t *__restrict__ gcnt,
-                                                    const int64_t *__restrict__ count, int64_t capacity,
-                                                    const int64_t *__restrict__ tsum, int64_t *__restrict__ gofs) {
-    __shared__ int64_t s_w[256 / kWave];
-    const int64_t S = clamp_count(count, capacity);
-    const int64_t t0 = (int64_t)blockIdx.x * kScanTile;
-    if (t0 >= S) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) gofs[0] = 0;  // S == 0
-        return;
-    }
-    constexpr int kPer = kScanTile / 256;
-    int64_t c[kPer];
-    int64_t v = 0;
-#pragma unroll
-    for (int u = 0; u < kPer; ++u) {
-        const int64_t k = t0 + (int64_t)threadIdx.x * kPer + u;
-        c[u] = k < S ? gcnt[k] : 0;
-        v += c[u];
-    }
-    int64_t total;
-    int64_t run = tsum[blockIdx.x] + block_exclusive_scan(v, s_w, total);
-#pragma unroll
-    for (int u = 0; u < kPer; ++u) {
-        const int64_t k = t0 + (int64_t)threadIdx.x * kPer + u;
-        if (k < S) gofs[k] = run;
-        run += c[u];
-        if (k == S - 1) gofs[S] = run;
-    }
-}
-
 // ------------------------------------------------------------ search
-
-// Largest k in [lo, hi) with gofs[k] <= G, given gofs[lo] <= G (gofs is
-// non-decreasing): a 64-ary search, one load per lane per round.
-__device__ int64_t find_event(const int64_t *__restrict__ gofs, int64_t lo, int64_t hi, int64_t G) {
-    const int lane = lane_id();
-    while (hi - lo > kWave) {
-        const int64_t step = (hi - lo + kWave - 1) / kWave;
-        const int64_t pos = lo + (int64_t)lane * step;
-        const bool le = pos < hi && gofs[pos] <= G;
-        const int c = popc64(ballot(le));  // >= 1: gofs[lo] <= G
-        lo += (int64_t)(c - 1) * step;
-        const int64_t nh = lo + step;
-        hi = nh < hi ? nh : hi;
-    }
-    const int64_t pos = lo + lane;
-    const bool le = pos < hi && gofs[pos] <= G;
-    return lo + popc64(ballot(le)) - 1;
-}
-
-// Merge b into a by the total order of better(); solution counts add up.
-struct Acc {
-    double s, x, y;
-    int v, p, n;
-};
-
-__device__ __forceinline__ void acc_merge(Acc &a, const Acc &b) {
-    if (better(b.s, b.v, b.p, b.x, a.s, a.v, a.p, a.x)) {
-        a.s = b.s;
-        a.v = b.v;
-        a.p = b.p;
-        a.x = b.x;
-        a.y = b.y;
-    }
-    a.n += b.n;
-}
-
-template <typename T>
-__global__ __launch_bounds__(kRecoBlock, 2) void k_search(const int64_t *__restrict__ count, int64_t capacity,
-                                                          RecoArgs a, const StageRec *__restrict__ stage,
-                                                          const int64_t *__restrict__ gofs,
-                                                          BestRec *__restrict__ best_out, PartRec *__restrict__ part,
-                                                          uint64_t *__restrict__ wstats) {
-    __shared__ WaveStage<T> stage_all[kRecoWaves];
-    const int lane = lane_id();
-    const int wave = threadIdx.x / kWave;
-    WaveStage<T> &st = stage_all[wave];
-    const int64_t S = clamp_count(count, capacity);
-    const int64_t wid = (int64_t)blockIdx.x * kRecoWaves + wave;
-    const int64_t nw = (int64_t)gridDim.x * kRecoWaves;
-    const double mt2_mw2 = a.m_t * a.m_t - a.m_w * a.m_w;
-    const double mw2 = a.m_w * a.m_w;
-    uint64_t acc_var = 0, acc_pair = 0, acc_int = 0, acc_sol = 0;
-    const uint64_t lt = lanemask_lt();
-
-    // this wavefront's contiguous range of 64-lane blocks
-    const int64_t NG = S > 0 ? gofs[S] : 0;
-    const int64_t NB = (NG + kGpb - 1) / kGpb;
-    const int64_t b0 = wid * NB / nw, b1 = (wid + 1) * NB / nw;
-    const uint64_t *recw = reinterpret_cast<const uint64_t *>(stage);
-
-    // open event (lane 0 keeps the accumulator; the others follow uniformly)
-    int64_t open_k = -1;
-    int open_nc = 0;
-    bool open_head = false;
-    Acc acc{-INFINITY, 0.0, 0.0, kNoBest, kNoBest, 0};
-    // the partial records live in LDS (lane 0 writes them) rather than in
-    // registers for the whole kernel
-    if (lane == 0) {
-        st.headp.k = b0 < b1 ? -1 : -2;
-        st.tailp.k = -1;
-        st.headp.cont = st.tailp.cont = 0;
-    }
-
-    auto flush = [&](bool cont) {
-        if (open_k < 0) return;
-        if (lane == 0) {
-            if (open_head || cont) {
-                PartRec &pr = open_head ? st.headp : st.tailp;
-                pr.k = open_k;
-                pr.cont = cont ? 1 : 0;
-                pr.nsol = acc.n;
-                pr.v = acc.v;
-                pr.p = acc.p;
-                pr.nc = open_nc;
-                pr.score = acc.s;
-                pr.x = acc.x;
-                pr.y = acc.y;
-            } else {
-                BestRec r;
-                r.score = acc.s;
-                r.x = acc.x;
-                r.y = acc.y;
-                r.v = acc.v;
-                r.p = acc.p;
-                r.nsol = acc.n;
-                r.nc = open_nc;
-                best_out[open_k] = r;
-            }
-        }
-        open_k = -1;
-        open_head = false;
-    };
-
-    int64_t kc = b0 < b1 ? find_event(gofs, 0, S, b0 * kGpb) : 0;
-    for (int64_t b = b0; b < b1; ++b) {
-        // ---- which events the block's granules belong to
-        const int64_t g0 = b * kGpb;
-        const int64_t gw0 = gofs[kc];
-        const int64_t wpos = kc + 1 + lane;
-        const int64_t wv = wpos <= S ? gofs[wpos] : INT64_MAX;
-        int64_t kj[kGpb];
-        if (ballot(wv <= g0 + kGpb - 1) != ~0ull) {
-#pragma unroll
-            for (int j = 0; j < kGpb; ++j) kj[j] = kc + popc64(ballot(wv <= g0 + j));
-        } else {  // more than 64 events without granules in a row
-#pragma unroll
-            for (int j = 0; j < kGpb; ++j) kj[j] = find_event(gofs, kc, S, g0 + j);
-        }
-        // slots: the distinct events of the valid granules, in order
-        int slot_of[kGpb];
-        int64_t sk[kGpb];
-        int n_ev = 0;
-#pragma unroll
-        for (int j = 0; j < kGpb; ++j) {
-            const bool valid = g0 + j < NG;
-            if (valid && (n_ev == 0 || sk[n_ev - 1] != kj[j])) {
-                sk[n_ev] = kj[j];
-                ++n_ev;
-            }
-            slot_of[j] = valid ? n_ev - 1 : -1;
-        }
-        // granule offset of each slot's event
-        int64_t sg[kGpb];
-#pragma unroll
-        for (int q = 0; q < kGpb; ++q) {
-            if (q < n_ev) {
-                const int64_t d = sk[q] - kc - 1;
-                sg[q] = d < 0 ? gw0 : (d < kWave ? __shfl(wv, (int)d) : gofs[sk[q]]);
-            } else {
-                sg[q] = 0;
-            }
-        }
-        kc = sk[n_ev - 1];  // the next block starts in this event or a later one
-
-        // ---- records into LDS (80 words per slot; all loads issued before the stores)
-        {
-            constexpr int kIt = (kGpb * kRecWords + kWave - 1) / kWave;
-            uint64_t wd[kIt];
-#pragma unroll
-            for (int it = 0; it < kIt; ++it) {
-                const int w = it * kWave + lane;
-                const bool in = w < n_ev * kRecWords;
-                const int q = in ? w / kRecWords : 0, off = in ? w - q * kRecWords : 0;
-                const int64_t kq = q == 0 ? sk[0] : q == 1 ? sk[1] : q == 2 ? sk[2] : sk[3];
-                wd[it] = recw[kq * kRecWords + off];  // always a valid address (slot 0 when out of range)
-            }
-#pragma unroll
-            for (int it = 0; it < kIt; ++it) {
-                const int w = it * kWave + lane;
-                if (w < n_ev * kRecWords) reinterpret_cast<uint64_t *>(&st.rec[0])[w] = wd[it];
-            }
-        }
-        wave_sync();
-
-        // ---- this lane's event and variation
-        const int gj = lane / kGran;
-        const int my_slot = gj == 0 ? slot_of[0] : gj == 1 ? slot_of[1] : gj == 2 ? slot_of[2] : slot_of[3];
-        const int ms = my_slot < 0 ? 0 : my_slot;
-        const int64_t my_g0 = ms == 0 ? sg[0] : ms == 1 ? sg[1] : ms == 2 ? sg[2] : sg[3];
-        const int my_v = (int)((g0 + gj - my_g0) * kGran) + (lane % kGran);
-        const int my_nc = st.rec[ms].nc;
-        const bool in_block = my_slot >= 0 && my_v < st.rec[ms].V;
-
-        double best_s = -INFINITY, best_x = 0.0, best_y = 0.0;
-        int best_v = kNoBest, best_p = kNoBest, nsol = 0;
-
-        // ---- passes over the slots whose candidates fit the side-constant table
-        int s_lo = 0;
-        while (s_lo < n_ev) {
-            int s_hi = s_lo, used = 0, ncmax = 0;
-            int sbase[kGpb] = {0, 0, 0, 0};
-            while (s_hi < n_ev) {
-                const int ncq = __builtin_amdgcn_readfirstlane(st.rec[s_hi].nc);
-                if (used + ncq > kSideCap) break;
-#pragma unroll
-                for (int q = 0; q < kGpb; ++q)
-                    if (q == s_hi) sbase[q] = used;
-                used += ncq;
-                ncmax = ncq > ncmax ? ncq : ncmax;
-                ++s_hi;
-            }
-            // side constants: lanes [0, used) with l+, [32, 32 + used) with l-
-            {
-                const int e = lane & 31;
-                if (e < used) {
-                    int q = s_lo;
-                    while (q + 1 < s_hi && e >= (q + 1 == 1 ? sbase[1] : q + 1 == 2 ? sbase[2] : sbase[3])) ++q;
-                    const int qb = q == 0 ? sbase[0] : q == 1 ? sbase[1] : q == 2 ? sbase[2] : sbase[3];
-                    const int c = e - qb;
-                    if (lane < 32)
-                        st.okp[e] = make_side(st.rec[q].lp, st.rec[q].cand[c], st.sp[e]) ? 1 : 0;
-                    else
-                        st.okm[e] = make_side(st.rec[q].lm, st.rec[q].cand[c], st.sm[e]) ? 1 : 0;
-                }
-            }
-            wave_sync();
-            const bool act = in_block && my_slot >= s_lo && my_slot < s_hi;
-            const int sb = ms == 0 ? sbase[0] : ms == 1 ? sbase[1] : ms == 2 ? sbase[2] : sbase[3];
-            const StageRec &R = st.rec[ms];
-            // valid pairings of this lane's event (for the counters)
-            if (act) {
-                int np = 0;
-                for (int i = 0; i < my_nc; ++i)
-                    for (int j = 0; j < my_nc; ++j) np += (i != j && st.okp[sb + i] && st.okm[sb + j]) ? 1 : 0;
-                ++acc_var;
-                acc_pair += (uint64_t)np;
-            }
-            // ---- draws of this lane's variation, kept in LDS so that any lane can
-            // rebuild another lane's smear factors
-            {
-                T zl[4] = {(T)0, (T)0, (T)0, (T)0};
-                if (a.smear && act) {
-                    const uint64_t g = R.g;
-                    gauss_block<T>(a.seed, g, (uint32_t)my_v, 0u, zl);
-                    uint32_t last_blk = 0xffffffffu;
-                    T zb[4];
-                    for (int c = 0; c < my_nc; ++c) {
-                        const uint32_t slot = 4u + (uint32_t)R.jidx[c];
-                        const uint32_t blk = slot >> 2;
-                        if (blk != last_blk) {
-                            gauss_block<T>(a.seed, g, (uint32_t)my_v, blk, zb);
-                            last_blk = blk;
-                        }
-                        const uint32_t ln = slot & 3u;
-                        st.z[c][lane] = ln == 0 ? zb[0] : ln == 1 ? zb[1] : ln == 2 ? zb[2] : zb[3];
-                    }
-                } else {
-                    for (int c = 0; c < kMaxC; ++c) st.z[c][lane] = (T)0;
-                }
-                st.zl[0][lane] = zl[0];
-                st.zl[1][lane] = zl[1];
-                st.zl[2][lane] = zl[2];
-                st.zl[3][lane] = zl[3];
-            }
-            wave_sync();
-            const double slp = smear(a.lep_sigma, st.zl[0][lane]);
-            const double slm = smear(a.lep_sigma, st.zl[1][lane]);
-            const double mx = R.met[0] + a.met_sigma * (double)st.zl[2][lane];
-            const double my = R.met[1] + a.met_sigma * (double)st.zl[3][lane];
-            const double Wp = (0.5 * mw2) * fast_rcp(slp) - 0.5 * slp * R.ml2p;
-            const double Wm = (0.5 * mw2) * fast_rcp(slm) - 0.5 * slm * R.ml2m;
-            for (int i = 0; i < ncmax; ++i) {
-                const bool act_i = act && i < my_nc && st.okp[sb + i];
-                SideVar A;
-                A.e0 = A.z0 = 0.0;
-                A.q = Conic{0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-                if (act_i) A = side_var(st.sp[sb + i], Wp, slp, smear(R.sigma[i], st.z[i][lane]), mt2_mw2);
-                for (int j = 0; j < ncmax; ++j) {
-                    if (j == i) continue;
-                    const bool act_ij = act_i && j < my_nc && st.okm[sb + j];
-                    // ---- stage 1 (own variation): eliminant quartic and its root intervals
-                    SideVar Bv;
-                    Bv.e0 = Bv.z0 = 0.0;
-                    Conic Q{0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-                    Brackets Bk;
-                    Bk.mask = 0;
-                    Bk.direct = 0;
-                    Bk.signs = 0;
-                    if (act_ij) {
-                        Bv = side_var(st.sm[sb + j], Wm, slm, smear(R.sigma[j], st.z[j][lane]), mt2_mw2);
-                        Q = reflect(Bv.q, mx, my);
-                        double qc[5];
-                        eliminant(A.q, Q, qc);
-                        Bk = quartic_brackets<T>(qc);
-                    }
-                    // ---- stage 2: the wave's root intervals dealt out to lanes, 64 at a time;
-                    // each result goes back to the lane that owns the variation
-                    const uint64_t m0 = ballot(Bk.mask & 1), m1 = ballot(Bk.mask & 2);
-                    const uint64_t m2 = ballot(Bk.mask & 4), m3 = ballot(Bk.mask & 8);
-                    const int n0 = popc64(m0), n1 = popc64(m1), n2 = popc64(m2), n3 = popc64(m3);
-                    const int total = n0 + n1 + n2 + n3;
-                    if (total == 0) continue;
-                    const int packed = Bk.mask | (Bk.direct << 4) | (Bk.signs << 5);
-                    // queue positions of this lane's own intervals
-                    const int pos0 = popc64(m0 & lt), pos1 = n0 + popc64(m1 & lt);
-                    const int pos2 = n0 + n1 + popc64(m2 & lt), pos3 = n0 + n1 + n2 + popc64(m3 & lt);
-                    const int my_p = i * my_nc + j;
-                    if (Bk.mask & 1) st.queue[pos0] = lane;
-                    if (Bk.mask & 2) st.queue[pos1] = lane | (1 << 6);
-                    if (Bk.mask & 4) st.queue[pos2] = lane | (2 << 6);
-                    if (Bk.mask & 8) st.queue[pos3] = lane | (3 << 6);
-                    wave_sync();
-                    for (int base = 0; base < total; base += kWave) {
-                        const int t = base + lane;
-                        const bool live = t < total;
-                        const int qe = live ? st.queue[t] : lane;
-                        const int src = qe & (kWave - 1), k = qe >> 6;
-                        // the source lane's intervals and event, as plain values (no aggregate
-                        // whose fields get selected by k, which would force it into scratch)
-                        const Poly4 fc{from_lane(Bk.c.c0, src), from_lane(Bk.c.c1, src), from_lane(Bk.c.c2, src),
-                                       from_lane(Bk.c.c3, src), from_lane(Bk.c.c4, src)};
-                        const double fe1 = from_lane(Bk.e1, src), fe2 = from_lane(Bk.e2, src);
-                        const double fe3 = from_lane(Bk.e3, src), fbd = from_lane(Bk.bound, src);
-                        const double ff1 = from_lane(Bk.f1, src), ff2 = from_lane(Bk.f2, src);
-                        const double ff3 = from_lane(Bk.f3, src);
-                        const int fp = from_lane(packed, src);
-                        const int s_src = from_lane(ms, src), sb_src = from_lane(sb, src);
-                        const double px = from_lane(A.q.x, src), py = from_lane(A.q.y, src), pc = from_lane(A.q.c, src);
-                        const double qx = from_lane(Q.x, src), qy = from_lane(Q.y, src), qcc = from_lane(Q.c, src);
-                        const double ae0 = from_lane(A.e0, src), be0 = from_lane(Bv.e0, src);
-                        int ok = 0;
-                        double w = 0.0, x = 0.0, y = 0.0;
-                        if (live) {
-                            ++acc_int;
-                            const double *spi = st.sp[sb_src + i];
-                            const double *smj = st.sm[sb_src + j];
-                            const Conic P{spi[kQxx], spi[kQxy], spi[kQyy], px, py, pc};
-                            const Conic Qs{smj[kQxx], smj[kQxy], smj[kQyy], qx, qy, qcc};
-                            if ((fp >> 4) & 1) {  // degree <= 2: the roots are given
-                                x = kXScale * (k == 0 ? fe1 : fe2);
-                            } else {
-                                const double f0 = (fp & 32) ? -1.0 : 1.0, f4 = (fp & 64) ? -1.0 : 1.0;
-                                const double lo = k == 0 ? -fbd : k == 1 ? fe1 : k == 2 ? fe2 : fe3;
-                                const double hi = k == 0 ? fe1 : k == 1 ? fe2 : k == 2 ? fe3 : fbd;
-                                const double flo = k == 0 ? f0 : k == 1 ? ff1 : k == 2 ? ff2 : ff3;
-                                const double fhi = k == 0 ? ff1 : k == 1 ? ff2 : k == 2 ? ff3 : f4;
-                                bool found;
-                                solve_interval(fc, lo, hi, flo, fhi, k > 0 && lo < fbd, k < 3 && hi < fbd, x, found);
-                            }
-                            if (recover_y(P, Qs, x, y) &&
-                                polish_xy(P, Qs, x, y, 4, a.polish_skip_m2) <= a.accept_m2) {
-                                // the source variation's smear factors and MET, rebuilt from its draws
-                                const StageRec &Rs = st.rec[s_src];
-                                const T zli0 = st.zl[0][src], zli1 = st.zl[1][src];
-                                const T zi = st.z[i][src], zj = st.z[j][src];
-                                const double rslp = smear(a.lep_sigma, zli0), rslm = smear(a.lep_sigma, zli1);
-                                const double rsi = smear(Rs.sigma[i], zi), rsj = smear(Rs.sigma[j], zj);
-                                const double rmx = Rs.met[0] + a.met_sigma * (double)st.zl[2][src];
-                                const double rmy = Rs.met[1] + a.met_sigma * (double)st.zl[3][src];
-                                const double en = spi[kE1] * x + spi[kE2] * y + ae0;
-                                const double xb = rmx - x, yb = rmy - y;
-                                const double eb = smj[kE1] * xb + smj[kE2] * yb + be0;
-                                if (en >= 0.0 && eb >= 0.0) {
-                                    const double tx = rsi * Rs.cand[i][1] + rslp * Rs.lp[1] + x;  // top pT components
-                                    const double ty = rsi * Rs.cand[i][2] + rslp * Rs.lp[2] + y;
-                                    const double tbx = rsj * Rs.cand[j][1] + rslm * Rs.lm[1] + xb;
-                                    const double tby = rsj * Rs.cand[j][2] + rslm * Rs.lm[2] + yb;
-                                    const double zz = (double)zli0 * zli0 + (double)zli1 * zli1 +
-                                                      (double)st.zl[2][src] * st.zl[2][src] +
-                                                      (double)st.zl[3][src] * st.zl[3][src] + (double)zi * zi +
-                                                      (double)zj * zj;
-                                    w = -0.5 * zz -
-                                        (fast_sqrt(tx * tx + ty * ty) + fast_sqrt(tbx * tbx + tby * tby)) * a.inv_lambda;
-                                    ok = 1;
-                                }
-                            }
-                        }
-                        st.res_ok[lane] = ok;
-                        st.res_w[lane] = w;
-                        st.res_x[lane] = x;
-                        st.res_y[lane] = y;
-                        wave_sync();
-                        // the owner of each interval of this round takes its result
-#pragma unroll
-                        for (int kk = 0; kk < 4; ++kk) {
-                            const int pos = kk == 0 ? pos0 : kk == 1 ? pos1 : kk == 2 ? pos2 : pos3;
-                            if (!((Bk.mask >> kk) & 1) || pos < base || pos >= base + kWave) continue;
-                            const int q = pos - base;
-                            if (!st.res_ok[q]) continue;
-                            ++nsol;
-                            const double rw = st.res_w[q], rx = st.res_x[q];
-                            if (better(rw, my_v, my_p, rx, best_s, best_v, best_p, best_x)) {
-                                best_s = rw;
-                                best_v = my_v;
-                                best_p = my_p;
-                                best_x = rx;
-                                best_y = st.res_y[q];
-                            }
-                        }
-                        wave_sync();
-                    }
-                }
-            }
-            wave_sync();
-            s_lo = s_hi;
-        }
-
-        acc_sol += (uint64_t)nsol;
-        // ---- per granule (16 lanes of one event), then per event in order
-#pragma unroll
-        for (int off = kGran / 2; off > 0; off >>= 1) {
-            const double os = __shfl_xor(best_s, off);
-            const int ov = __shfl_xor(best_v, off);
-            const int op = __shfl_xor(best_p, off);
-            const double ox = __shfl_xor(best_x, off);
-            const double oy = __shfl_xor(best_y, off);
-            if (better(os, ov, op, ox, best_s, best_v, best_p, best_x)) {
-                best_s = os;
-                best_v = ov;
-                best_p = op;
-                best_x = ox;
-                best_y = oy;
-            }
-            nsol += __shfl_xor(nsol, off);
-        }
-        if ((lane % kGran) == 0) {
-            st.gb_s[gj] = best_s;
-            st.gb_x[gj] = best_x;
-            st.gb_y[gj] = best_y;
-            st.gb_v[gj] = best_v;
-            st.gb_p[gj] = best_p;
-            st.gb_n[gj] = nsol;
-        }
-        wave_sync();
-#pragma unroll
-        for (int j = 0; j < kGpb; ++j) {
-            if (slot_of[j] < 0) continue;
-            const int64_t kk = kj[j];
-            if (kk != open_k) {
-                flush(false);
-                open_k = kk;
-                open_head = (b == b0 && j == 0 && sg[0] < g0);  // started before this range
-                open_nc = st.rec[slot_of[j]].nc;
-                acc = Acc{-INFINITY, 0.0, 0.0, kNoBest, kNoBest, 0};
-            }
-            const Acc gbj{st.gb_s[j], st.gb_x[j], st.gb_y[j], st.gb_v[j], st.gb_p[j], st.gb_n[j]};
-            acc_merge(acc, gbj);
-        }
-        wave_sync();
-    }
-    // the open event at the end of the range: does it continue in the next range?
-    if (open_k >= 0) {
-        const bool cont = gofs[open_k + 1] > b1 * kGpb;
-        flush(cont);
-    }
-    if (lane == 0) {
-        part[2 * wid] = st.headp;
-        part[2 * wid + 1] = st.tailp;
-    }
-    // intervals and variations are counted per lane
-    uint64_t ni = acc_int, nv = acc_var, npr = acc_pair, nso = acc_sol;
-#pragma unroll
-    for (int off = kWave / 2; off > 0; off >>= 1) {
-        ni += __shfl_xor(ni, off);
-        nv += __shfl_xor(nv, off);
-        npr += __shfl_xor(npr, off);
-        nso += __shfl_xor(nso, off);
-    }
-    if (lane == 0 && wstats) {
-        atomicAdd((unsigned long long *)&wstats[1], (unsigned long long)nv);
-        atomicAdd((unsigned long long *)&wstats[2], (unsigned long long)npr);
-        atomicAdd((unsigned long long *)&wstats[3], (unsigned long long)ni);
-        atomicAdd((unsigned long long *)&wstats[4], (unsigned long long)nso);
-    }
-}
 
 // Search with one wavefront per event (lanes = variations in chunks of 64,
 // events taken from per-class counters by a persistent grid, the next
-// event's ticket and record fetched one event ahead).  Used when every event
-// has the same number of variations: then no block is shared between events
-// and nothing needs merging, and this form avoids the worklist's
-// indirections.
-template <typename T>
-__global__ __launch_bounds__(kRecoBlock, 2) void k_search_ev(const int64_t *__restrict__ count, int64_t capacity,
-                                                          RecoArgs a, const StageRec *__restrict__ stage,
-                                                          BestRec *__restrict__ best_out,
-                                                          uint64_t *__restrict__ wstats) {
-    __shared__ WaveStageEv<T> stage_all[kRecoWaves];
-    __shared__ int queue_all[kRecoWaves][4 * kWave];  // stage-2 queue: source lane | interval << 6
+// event's ticket and record fetched one event ahead).  NW wavefronts per
+// workgroup; the launch bound (two wavefronts per SIMD) gives every size the
+// same register budget.
+template <typename T, int NW>
+__global__ __launch_bounds__(NW * kWave, 2) void k_search_ev(const int64_t *__restrict__ count, int64_t capacity,
+                                                               RecoArgs a, const StageRec *__restrict__ stage,
+                                                               BestRec *__restrict__ best_out,
+                                                               uint64_t *__restrict__ wstats) {
+    __shared__ WaveStageEv<T> stage_all[NW];
+    __shared__ int queue_all[NW][4 * kWave];  // stage-2 queue: source lane | interval << 6
     const int lane = lane_id();
     const int wave = threadIdx.x / kWave;
     WaveStageEv<T> &st = stage_all[wave];
@@ -1195,34 +582,6 @@ __global__ __launch_bounds__(kRecoBlock, 2) void k_search_ev(const int64_t *__re
 }
 
 
-// One thread per search wavefront: an event that continues past the end of
-// the wavefront's range is merged with the head records of the following
-// ranges (in order) and its best record written.
-__global__ __launch_bounds__(256) void k_fixup(const PartRec *__restrict__ part, int64_t nw,
-                                               BestRec *__restrict__ best_out) {
-    const int64_t w = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (w >= nw) return;
-    const PartRec t = part[2 * w + 1];
-    if (t.k < 0) return;
-    Acc acc{t.score, t.x, t.y, t.v, t.p, t.nsol};
-    for (int64_t w2 = w + 1; w2 < nw; ++w2) {
-        const PartRec h = part[2 * w2];
-        if (h.k == -2) continue;  // empty range
-        if (h.k != t.k) break;
-        acc_merge(acc, Acc{h.score, h.x, h.y, h.v, h.p, h.nsol});
-        if (!h.cont) break;
-    }
-    BestRec r;
-    r.score = acc.s;
-    r.x = acc.x;
-    r.y = acc.y;
-    r.v = acc.v;
-    r.p = acc.p;
-    r.nsol = acc.n;
-    r.nc = t.nc;
-    best_out[t.k] = r;
-}
-
 __global__ void k_reco_init(uint64_t *wstats) {
     if (threadIdx.x < 5) wstats[threadIdx.x] = 0;
     if (threadIdx.x < kTicketClasses) wstats[kTicketWord + 16 * threadIdx.x] = 0;
@@ -1359,7 +718,7 @@ __global__ __launch_bounds__(256) void k_epilogue(EvView ev, const int64_t *__re
 }
 
 // Persistent grid: the resident blocks of one kernel on every CU.
-int resident_grid(const void *kernel, int *cache) {
+int resident_grid(const void *kernel, int block, int *cache) {
     if (*cache <= 0) {
         int dev = 0, n_cu = 0;
         if (hipGetDevice(&dev) != hipSuccess) dev = 0;
@@ -1367,98 +726,67 @@ int resident_grid(const void *kernel, int *cache) {
         if (hipGetDeviceProperties(&prop, dev) == hipSuccess) n_cu = prop.multiProcessorCount;
         if (n_cu <= 0) n_cu = 256;
         int nb = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, kRecoBlock, 0) != hipSuccess || nb < 1) nb = 1;
-        int64_t g = (int64_t)n_cu * nb;
-        if (g > kMaxSearchWaves / kRecoWaves) g = kMaxSearchWaves / kRecoWaves;
-        *cache = (int)g;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, block, 0) != hipSuccess || nb < 1) nb = 1;
+        *cache = n_cu * nb;
     }
     return *cache;
 }
 
 hipEvent_t g_time_start = nullptr, g_time_stop = nullptr;
 
-// Workspace layout (each part 256-byte aligned): counters, BestRec[capacity],
-// StageRec[capacity], granule counts int32[capacity], granule offsets
-// int64[capacity + 1], tile sums int64[tiles + 1], PartRec[2 kMaxSearchWaves].
+// Workspace layout (each part 256-byte aligned): header (statistics and the
+// search's event counters), BestRec[capacity], StageRec[capacity].
 struct WsLayout {
-    size_t best, stage, gcnt, gofs, tsum, part, total;
+    size_t best, stage, total;
 };
 
 static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 static WsLayout ws_layout(int64_t capacity) {
     const size_t c = (size_t)(capacity > 0 ? capacity : 0);
-    const size_t tiles = (c + kScanTile - 1) / kScanTile + 1;
     WsLayout L;
     L.best = kWsHeader;
     L.stage = align256(L.best + c * sizeof(BestRec));
-    L.gcnt = align256(L.stage + c * sizeof(StageRec));
-    L.gofs = align256(L.gcnt + c * sizeof(int32_t));
-    L.tsum = align256(L.gofs + (c + 1) * sizeof(int64_t));
-    L.part = align256(L.tsum + (tiles + 1) * sizeof(int64_t));
-    L.total = align256(L.part + 2 * (size_t)kMaxSearchWaves * sizeof(PartRec));
+    L.total = align256(L.stage + c * sizeof(StageRec));
     return L;
 }
 
-// worklist: the packed / split schedule (per-event variation counts); else one
-// wavefront per event.
+template <typename T, int NW>
+hipError_t launch_search(const int64_t *count, int64_t capacity, const RecoArgs &a, const StageRec *stage,
+                         BestRec *best, uint64_t *wstats, hipStream_t s) {
+    static int grid = 0;
+    int64_t g = resident_grid(reinterpret_cast<const void *>(&k_search_ev<T, NW>), NW * kWave, &grid);
+    const int64_t need = (capacity + NW - 1) / NW;  // no more wavefronts than events
+    g = g < need ? g : need;
+    hipLaunchKernelGGL((k_search_ev<T, NW>), dim3((unsigned)(g < 1 ? 1 : g)), dim3(NW * kWave), 0, s, count,
+                       capacity, a, stage, best, wstats);
+    return hipGetLastError();
+}
+
+// waves: wavefronts per workgroup of the search (1, 2 or 4)
 template <typename T>
 hipError_t launch_t(const EvView &ev, const int32_t *idx, const int64_t *count, int64_t capacity, const RecoArgs &a,
-                    const RecoOutView &out, hf_counters_t *reco_counter, uint64_t *wstats, char *ws, bool worklist,
+                    const RecoOutView &out, hf_counters_t *reco_counter, uint64_t *wstats, char *ws, int waves,
                     hipStream_t s) {
     const WsLayout L = ws_layout(capacity);
     BestRec *best = reinterpret_cast<BestRec *>(ws + L.best);
     StageRec *stage = reinterpret_cast<StageRec *>(ws + L.stage);
-    int32_t *gcnt = reinterpret_cast<int32_t *>(ws + L.gcnt);
-    int64_t *gofs = reinterpret_cast<int64_t *>(ws + L.gofs);
-    int64_t *tsum = reinterpret_cast<int64_t *>(ws + L.tsum);
-    PartRec *part = reinterpret_cast<PartRec *>(ws + L.part);
     const int64_t eg = capacity > 0 ? (capacity + 255) / 256 : 1;
     const int64_t sg = capacity > 0 ? (capacity + kStageEvents - 1) / kStageEvents : 1;
     if (capacity > 0) {
-        const unsigned tiles = (unsigned)((capacity + kScanTile - 1) / kScanTile);
-        hipLaunchKernelGGL(k_stage, dim3((unsigned)sg), dim3(256), 0, s, ev, idx, count, capacity, a, stage, gcnt,
-                           best);
-        if (worklist) {
-            hipLaunchKernelGGL(k_scan_tiles, dim3(tiles), dim3(256), 0, s, gcnt, count, capacity, tsum);
-            hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(256), 0, s, count, capacity, tsum);
-            hipLaunchKernelGGL(k_scan_apply, dim3(tiles), dim3(256), 0, s, gcnt, count, capacity, tsum, gofs);
-        }
-        hipError_t e1 = hipGetLastError();
-        if (e1 != hipSuccess) return e1;
+        hipLaunchKernelGGL(k_stage, dim3((unsigned)sg), dim3(256), 0, s, ev, idx, count, capacity, a, stage, best);
+        hipError_t err = hipGetLastError();
+        if (err != hipSuccess) return err;
         if (g_time_start) {
-            const hipError_t e0 = hipEventRecord(g_time_start, s);
-            if (e0 != hipSuccess) return e0;
+            err = hipEventRecord(g_time_start, s);
+            if (err != hipSuccess) return err;
         }
-        hipError_t err;
-        if (!worklist) {
-            // every event has the same number of variations: one wavefront per event
-            static int grid_ev = 0;
-            int64_t g = resident_grid(reinterpret_cast<const void *>(&k_search_ev<T>), &grid_ev);
-            const int64_t need = (capacity + kRecoWaves - 1) / kRecoWaves;
-            g = g < need ? g : need;
-            hipLaunchKernelGGL(k_search_ev<T>, dim3((unsigned)(g < 1 ? 1 : g)), dim3(kRecoBlock), 0, s, count,
-                               capacity, a, stage, best, wstats);
-            err = hipGetLastError();
-            if (err != hipSuccess) return err;
-            if (g_time_stop) {
-                err = hipEventRecord(g_time_stop, s);
-                if (err != hipSuccess) return err;
-            }
-        } else {
-            static int grid_wl = 0;
-            const int grid = resident_grid(reinterpret_cast<const void *>(&k_search<T>), &grid_wl);
-            hipLaunchKernelGGL(k_search<T>, dim3(grid), dim3(kRecoBlock), 0, s, count, capacity, a, stage, gofs,
-                               best, part, wstats);
-            err = hipGetLastError();
-            if (err != hipSuccess) return err;
-            if (g_time_stop) {
-                err = hipEventRecord(g_time_stop, s);
-                if (err != hipSuccess) return err;
-            }
-            const int64_t nw = (int64_t)grid * kRecoWaves;
-            hipLaunchKernelGGL(k_fixup, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, s, part, nw, best);
-            err = hipGetLastError();
+        err = waves == 1 ? launch_search<T, 1>(count, capacity, a, stage, best, wstats, s)
+              : waves == 2 ? launch_search<T, 2>(count, capacity, a, stage, best, wstats, s)
+                           : launch_search<T, 4>(count, capacity, a, stage, best, wstats, s);
+        if (err != hipSuccess) return err;
+        if (g_time_stop) {
+            err = hipEventRecord(g_time_stop, s);
             if (err != hipSuccess) return err;
         }
     }
@@ -1478,15 +806,15 @@ size_t reco_ws_bytes(int64_t capacity) { return ws_layout(capacity).total; }
 
 hipError_t launch_reco(const EvView &ev, const int32_t *idx, const int64_t *count, int64_t capacity,
                        const RecoArgs &a, int precision, const RecoOutView &out, hf_counters_t *reco_counter,
-                       void *ws, bool worklist, hipStream_t s) {
+                       void *ws, int waves, hipStream_t s) {
     uint64_t *wstats = static_cast<uint64_t *>(ws);
     hipLaunchKernelGGL(k_reco_init, dim3(1), dim3(64), 0, s, wstats);
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
     char *w = static_cast<char *>(ws);
     if (precision == HF_PREC_MIXED)
-        return launch_t<float>(ev, idx, count, capacity, a, out, reco_counter, wstats, w, worklist, s);
-    return launch_t<double>(ev, idx, count, capacity, a, out, reco_counter, wstats, w, worklist, s);
+        return launch_t<float>(ev, idx, count, capacity, a, out, reco_counter, wstats, w, waves, s);
+    return launch_t<double>(ev, idx, count, capacity, a, out, reco_counter, wstats, w, waves, s);
 }
 
 }  // namespace hf

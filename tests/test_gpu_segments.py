@@ -5,7 +5,6 @@ per-cut counters must equal one unsegmented pass and the oracle, for every
 split point, built-in and user-compiled chains, and graph replay."""
 
 import sys
-import time
 
 import numpy as np
 import pytest
@@ -95,28 +94,3 @@ def test_segmented_user_chain(B, orc):
     s_w, r_w, p_w = orc.select(ev, cuts, list(range(len(cuts))))
     assert np.array_equal(i_seg, np.flatnonzero(s_w))
     assert np.array_equal(c_seg[:, 0], r_w) and np.array_equal(c_seg[:, 1], p_w)
-
-
-def test_segment_timing_report(B):
-    """Not a pass/fail timing: prints the selection time of the 8-cut chain
-    with the expensive isolation cut behind a compaction or not."""
-    from paper_2211_14346_amd.chain import Chain
-    cfg = hfgen.config("tth4M_v256")
-    ev = hfgen.generate(cfg, n_events=1_000_000, seed=503)
-    # isolation (the costliest cut) last; the others first
-    cuts = cfg["cuts"]
-    iso = [k for k, c in enumerate(cuts) if c["kind"] == "LEP_ISO"][0]
-    order = [k for k in range(len(cuts)) if k != iso and cuts[k]["kind"] != "RECO"] + [iso] + \
-        [k for k in range(len(cuts)) if cuts[k]["kind"] == "RECO"]
-    for seg in (None, len(cuts) - 2):
-        ch = Chain(ev, cuts, cfg["reco"], order=order, segment_at=seg)
-        for _ in range(3):
-            ch.run_select()
-            ch.run_compact()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(20):
-            ch.run_select()
-            ch.run_compact()
-        torch.cuda.synchronize()
-        _say("select+compact, segment_at", seg, f"{(time.perf_counter() - t0) / 20 * 1e3:.3f} ms")
