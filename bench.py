@@ -10,9 +10,10 @@ HIP graph.  Inputs are resident in HBM before timing starts.
 A second leg measures the single-neutrino chi^2 reconstruction the same way
 (1M one-lepton t-channel-like events, four cuts plus hf_semilep_reco, one HIP
 graph per step) and reports it under "semilep" in the same line.  A third
-leg streams 50 chunks of 1M mixed events from pinned host memory through a
-dileptonic and a one-lepton channel (12 cuts, copies overlapped with
-compute) and reports the end-to-end rate under "stream".
+leg streams 50 chunks of 1M mixed events from pinned host memory through the
+five HL-LHC signal bins (copies overlapped with compute) and reports the
+end-to-end rate and the events per bin under "stream".  Further legs run the
+10k, 4M ttH and 2M heavy-tailed batches under "workloads".
 
 Prints one JSON line.  --gpus above 1 is refused: this build runs on one GPU.
 """
@@ -454,12 +455,12 @@ def chi2_leg(args, torch, ev, cfg):
 
 
 def stream_leg(args, torch):
-    """50 chunks of 1M mixed events (dileptonic ttbar, t-channel, Wt,
-    background) streamed from pinned host memory through the dileptonic
-    channel (6 cuts, quartic at 64 variations) and the one-lepton channel
-    (6 cuts, single-neutrino chi^2): two device slots, copies on their own
-    stream overlapped with compute.  Also the copy-only and compute-only
-    rates of the same chunks, to show which one bounds the stream."""
+    """50 chunks of 1M mixed events (dileptonic and semileptonic ttbar,
+    t-channel, semileptonic and dileptonic Wt, background) streamed from
+    pinned host memory through the five signal bins of section 6.1, each with
+    its reconstruction: two device slots, copies on their own stream
+    overlapped with compute.  Also the copy-only and compute-only rates of
+    the same chunks, to show which one bounds the stream."""
     import hfgen
     from paper_2211_14346_amd.stream import Channel, EventStream, HostChunk
 
@@ -475,8 +476,15 @@ def stream_leg(args, torch):
     chunks = [host[i % len(host)].with_base(i * m) for i in range(n_chunks)]
     lep_cap = max(c.n_lep for c in host)
     jet_cap = max(c.n_jet for c in host)
-    chans = [Channel("dilepton", cfg["chains"]["dilepton"], m, reco=cfg["reco"]),
-             Channel("single", cfg["chains"]["single"], m, semilep=cfg["semilep"], topology="TCHAN")]
+    chans = []
+    for name, cuts in cfg["chains"].items():  # the five signal bins, each with its reconstruction
+        kind, arg = hfgen.configs.HLHC_BIN_RECO[name]
+        if kind == "semilep":
+            chans.append(Channel(name, cuts, m, semilep=cfg["semilep"], topology=arg))
+        elif kind == "chi2":
+            chans.append(Channel(name, cuts, m, chi2=dict(cfg["chi2"], n_top=arg)))
+        else:
+            chans.append(Channel(name, cuts, m, reco=cfg["reco"]))
     es = EventStream(chans, m, lep_cap, jet_cap)
     # warm-up: one untimed pass over the whole stream (the first pass pays
     # one-time host costs of the copies and launches, about 0.5 ms a chunk)
@@ -519,14 +527,17 @@ def stream_leg(args, torch):
     es.run(plain)
     torch.cuda.synchronize()
     dt_plain = time.perf_counter() - t3
-    leg = {"metric": "events/s end to end, pinned host chunks -> 2 channels (12 cuts, dileptonic quartic @64 "
-                     "variations + single-neutrino chi^2)",
+    leg = {"metric": "events/s end to end, pinned host chunks -> the five HL-LHC signal bins (37 cuts; "
+                     "single-neutrino chi^2 x3, dileptonic quartic @64 variations, chi^2 fit with a MET split)",
            "value": round(n / dt, 1), "unit": "events/s", "dtype": "f32+f64",
            "ms_per_chunk": round(1e3 * dt / n_chunks, 4),
            "config": {"workload": STREAM_WORKLOAD, "events": n, "chunk": m, "chunks": n_chunks,
                       "distinct_chunks": len(pool), "cuts": len(cfg["cuts"]),
                       "fractions": cfg["fractions"], "variations": cfg["reco"]["n_var"],
-                      "reconstructed": {k: int(v[chans[j].reco_id, 1]) for j, (k, v) in enumerate(cnt.items())},
+                      "bins": {ch.name: {"reconstruction": "/".join(str(x) for x in hfgen.configs.HLHC_BIN_RECO[ch.name]
+                                                                   if x is not None),
+                                         "selected": int(cnt[ch.name][ch.reco_id, 0]),
+                                         "reconstructed": int(cnt[ch.name][ch.reco_id, 1])} for ch in chans},
                       "input_bytes": int(nbytes)},
            "h2d_only": {"GB_per_s": round(nbytes / dt_copy / 1e9, 2), "ms_per_chunk": round(1e3 * dt_copy / n_chunks, 4)},
            "compute_only": {"events_per_s": round(m / dt_comp, 1), "ms_per_chunk": round(1e3 * dt_comp, 4)},

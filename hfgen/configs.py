@@ -26,8 +26,9 @@ import copy
 #   RECO          marker for the kinematic reconstruction (last cut)
 #   MTW_MIN       f=[lep_pt_min, lep_abs_eta_max, mtw_min]  (W transverse mass of the leading lepton)
 #   USER          a user predicate: "src" holds the body of a C function of one event
+#   JET_N_RANGE   f=[pt_min, abs_eta_lo, abs_eta_hi]    i=[n_min, n_max]  (jets in [lo, hi) counted)
 CUT_KINDS = ("LEP_N_OS", "JET_N_MIN", "BTAG_N_MIN", "BTAG_N_EQ", "MET_MIN",
-             "MLL_MIN", "FWD_JET_VETO", "LEP_ISO", "RECO", "MTW_MIN", "USER")
+             "MLL_MIN", "FWD_JET_VETO", "LEP_ISO", "RECO", "MTW_MIN", "USER", "JET_N_RANGE")
 
 
 def _cut(name, kind, f=(), i=(), deps=()):
@@ -73,7 +74,7 @@ SEMILEP_DEFAULTS = {
 # quarter of the previous step) is a reading.
 CHI2_DEFAULTS = {
     "m_t": 172.5, "m_w": 80.4, "sigma_t": 11.5, "sigma_w": 7.5,
-    "half_range": 200.0, "n_grid": 17, "n_refine": 2,
+    "half_range": 200.0, "n_grid": 17, "n_refine": 2, "n_top": 2,
     "lep_pt_min": 20.0, "lep_eta_max": 2.5, "jet_pt_min": 25.0, "jet_eta_max": 2.5, "btag_min": 0.5,
     "pair_mode": "BTAG_FILL", "max_cands": 12,
 }
@@ -118,10 +119,11 @@ CONFIGS = {
     "hlhc50M": {
         "index": 4, "n_events": 50_000_000, "chunk": 1_000_000, "kind": "hlhc", "n_extra_max": 4,
         "bkg_jet_max": 8, "chain": "hlhc",
-        "fractions": {"ttbar": 0.35, "tchan": 0.20, "wt": 0.15, "bkg": 0.30},
+        "fractions": {"ttbar": 0.20, "ttsemi": 0.20, "tchan": 0.15, "wt": 0.10, "wtdilep": 0.05, "bkg": 0.30},
         "reco": {"smear": 1, "n_var": 64},
-        "desc": "50M mixed events in 1M chunks (35% dileptonic ttbar, 20% t-channel, 15% Wt, 30% background), "
-                "dileptonic (6 cuts, quartic at 64 variations) and one-lepton (6 cuts, chi^2) channels",
+        "desc": "50M mixed events in 1M chunks (20% dileptonic and 20% semileptonic ttbar, 15% t-channel, 10% "
+                "semileptonic and 5% dileptonic Wt, 30% background) through the five signal bins of the HL-LHC "
+                "selection, each with its reconstruction",
     },
     "stress2M_heavytail": {
         "index": 3, "n_events": 2_000_000, "kind": "ttbar", "n_extra_max": 10,
@@ -159,6 +161,73 @@ def chain_hlhc_single():
         _cut("S_MTW50", "MTW_MIN", [20.0, 2.5, 50.0], deps=["S_LEP1"]),
         _cut("S_RECO", "RECO", deps=["S_LEP1", "S_JETS2", "S_BTAG1", "S_MET30", "S_MTW50"]),
     ]
+
+
+# The HL-LHC signal bins (section 6.1).  Jet pseudorapidity regions: I
+# |eta| < 2.5, II 2.5 <= |eta| < 2.75, III 2.75 <= |eta| < 3.5 (the paper's
+# strict inequalities leave the boundaries unassigned; reading: each lower
+# edge belongs to its region).  Jets count with pT > 25 GeV, b jets are
+# tagged Region I jets, leptons have pT > 20 GeV and |eta| < 2.5, isolated
+# when no Region I jet lies within Delta R < 0.4 (reading of "isolated").
+# Every bin requires E_T^miss > 30 GeV.
+REGION_I = [0.0, 2.5]
+REGIONS_II_III = [2.5, 3.5]
+_MANY = 99
+
+
+def _lep(name, n):
+    return _cut(name, "LEP_N_OS", [20.0, 2.5], [n, 1 if n == 2 else 0])
+
+
+def _iso(name, lep):
+    return _cut(name, "LEP_ISO", [20.0, 2.5, 25.0, 2.5, 0.4], deps=[lep])
+
+
+def _jets(name, region, lo, hi):
+    return _cut(name, "JET_N_RANGE", [25.0] + list(region), [lo, hi])
+
+
+def chains_hlhc_bins():
+    """The five signal bins of section 6.1, each a chain ending in its
+    reconstruction (section 6.2):
+      ttsemi   1 lepton, >= 4 Region I jets, 2 b, no Region II/III jet;
+      ttdilep  2 opposite-sign leptons, >= 2 Region I jets, 2 b, no Region
+               II/III jet, M_ll > 40;
+      tchan    1 lepton, exactly 1 Region I jet and 1 Region II/III jet, 1 b;
+      wtsemi   1 lepton, 3 Region I jets, 1 b, no Region II/III jet,
+               M_T^W > 50;
+      wtdilep  2 opposite-sign leptons, 1 or 2 Region I jets, 1 b, no Region
+               II/III jet."""
+    fwd = lambda n: _cut(n, "FWD_JET_VETO", [25.0] + REGIONS_II_III)
+    btag = lambda n, k: _cut(n, "BTAG_N_EQ", [25.0, 2.5, 0.5], [k])
+    met = lambda n: _cut(n, "MET_MIN", [30.0])
+    bins = {
+        "ttsemi": [_lep("L1", 1), _iso("ISO", "L1"), _jets("JI4", REGION_I, 4, _MANY), btag("B2", 2), fwd("VETO"),
+                   met("MET30")],
+        "ttdilep": [_lep("L2", 2), _iso("ISO", "L2"), _jets("JI2", REGION_I, 2, _MANY), btag("B2", 2), fwd("VETO"),
+                    met("MET30"), _cut("MLL40", "MLL_MIN", [20.0, 2.5, 40.0], deps=["L2"])],
+        "tchan": [_lep("L1", 1), _iso("ISO", "L1"), _jets("JI1", REGION_I, 1, 1), _jets("JF1", REGIONS_II_III, 1, 1),
+                  btag("B1", 1), met("MET30")],
+        "wtsemi": [_lep("L1", 1), _iso("ISO", "L1"), _jets("JI3", REGION_I, 3, 3), btag("B1", 1), fwd("VETO"),
+                   met("MET30"), _cut("MTW50", "MTW_MIN", [20.0, 2.5, 50.0], deps=["L1"])],
+        "wtdilep": [_lep("L2", 2), _iso("ISO", "L2"), _jets("JI12", REGION_I, 1, 2), btag("B1", 1), fwd("VETO"),
+                    met("MET30")],
+    }
+    for name, cuts in bins.items():
+        cuts.append(_cut("RECO", "RECO", deps=[c["name"] for c in cuts]))
+    return bins
+
+
+# Reconstruction of each bin: the single-neutrino chi^2 in its topology, the
+# two-neutrino quartic at the configuration's variations, or the dileptonic
+# chi^2 fit with a MET split with one top (Wt: one top and two W bosons).
+HLHC_BIN_RECO = {
+    "ttsemi": ("semilep", "TTSEMI"),
+    "ttdilep": ("quartic", None),
+    "tchan": ("semilep", "TCHAN"),
+    "wtsemi": ("semilep", "WT"),
+    "wtdilep": ("chi2", 1),
+}
 
 
 def _user(name, src, deps=()):
@@ -222,8 +291,8 @@ def config(name):
     c["semilep"] = dict(SEMILEP_DEFAULTS)
     c["chi2"] = dict(CHI2_DEFAULTS)
     if c["chain"] == "hlhc":
-        c["chains"] = {"dilepton": chain_hlhc_dilepton(), "single": chain_hlhc_single()}
-        c["cuts"] = c["chains"]["dilepton"] + c["chains"]["single"]
+        c["chains"] = chains_hlhc_bins()
+        c["cuts"] = [cut for cuts in c["chains"].values() for cut in cuts]
     else:
         c["cuts"] = {"dilepton": chain_dilepton, "tth8": chain_tth8, "semilep": chain_semilep}[c["chain"]]()
     return c

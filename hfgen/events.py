@@ -132,8 +132,18 @@ def _chunk(rng, cfg, n):
         is_sig = rng.uniform(0.0, 1.0, n) >= cfg["bkg_frac"]
 
     t, b, lp, nu = _top_decay(rng, n)
-    tb, bb, lm, nub = _top_decay(rng, n)
-    truth = {"top": t, "tbar": tb, "b": b, "bbar": bb, "lp": lp, "lm": lm, "nu": nu, "nubar": nub}
+    if kind == "wtdilep":
+        # Wt: the top's W and a second W from the hard process (pT ~ Exp(100),
+        # |y| < 2.5), decaying isotropically to l- nubar; no second b
+        tb = _p4_pt_y_phi_m(rng.exponential(100.0, n), rng.uniform(-2.5, 2.5, n), rng.uniform(-np.pi, np.pi, n),
+                            M_W)
+        lm, nub = _two_body(rng, tb, M_W, 0.0, 0.0)
+        bb = None
+    else:
+        tb, bb, lm, nub = _top_decay(rng, n)
+    truth = {"top": t, "tbar": tb, "b": b, "lp": lp, "lm": lm, "nu": nu, "nubar": nub}
+    if bb is not None:
+        truth["bbar"] = bb
 
     # ---- leptons -----------------------------------------------------------
     nl_max = 3
@@ -159,12 +169,12 @@ def _chunk(rng, cfg, n):
 
     # ---- jets --------------------------------------------------------------
     nh = 2 if kind == "tth" else 0
-    nj_sig = 2 + nh + kx
+    nj_sig = (1 if kind == "wtdilep" else 2) + nh + kx
     nj_max = max(nj_sig, cfg.get("bkg_jet_max", 0))
     jpt = np.zeros((n, nj_max)); jeta = np.zeros((n, nj_max)); jphi = np.zeros((n, nj_max))
     je = np.zeros((n, nj_max)); jtag = np.zeros((n, nj_max)); jorig = np.full((n, nj_max), -1)
     jval = np.zeros((n, nj_max), dtype=bool)
-    bq = [b, bb]
+    bq = [b] if bb is None else [b, bb]
     if kind == "tth":
         hpt = rng.exponential(100.0, n)
         hy = rng.uniform(-2.5, 2.5, n)
@@ -231,7 +241,7 @@ def _chunk(rng, cfg, n):
     truth["lp_idx"] = _pos(lep["orig"], loff, 0)
     truth["lm_idx"] = _pos(lep["orig"], loff, 1)
     truth["b_idx"] = _pos(jet["orig"], joff, 0)
-    truth["bbar_idx"] = _pos(jet["orig"], joff, 1)
+    truth["bbar_idx"] = _pos(jet["orig"], joff, 1) if bb is not None else np.full(n, -1, dtype=np.int32)
     if kind == "tth":
         truth["hb1_idx"] = _pos(jet["orig"], joff, 2)
         truth["hb2_idx"] = _pos(jet["orig"], joff, 3)
@@ -358,16 +368,17 @@ def _chunk_single(rng, cfg, n):
     return ev64, loff, joff, None, truth
 
 
-HLHC_PROCESSES = ("ttbar", "tchan", "wt", "bkg")
+HLHC_PROCESSES = ("ttbar", "ttsemi", "tchan", "wt", "wtdilep", "bkg")
 
 
 def _chunk_hlhc(rng, cfg, n):
-    """Mixed HL-LHC-like chunk: dileptonic ttbar, t-channel and Wt single
-    top (one lepton) and background in the fractions cfg["fractions"],
+    """Mixed HL-LHC-like chunk: dileptonic and semileptonic ttbar, t-channel
+    and semileptonic Wt single top (one lepton), dileptonic Wt and
+    background in the fractions cfg["fractions"],
     generated per process and shuffled.  Truth keeps the process code
     (index into HLHC_PROCESSES) only."""
     fr = cfg["fractions"]
-    counts = rng.multinomial(n, [fr[p] for p in HLHC_PROCESSES])
+    counts = rng.multinomial(n, [fr.get(p, 0.0) for p in HLHC_PROCESSES])
     if n == 0:  # an empty chunk: the dileptonic generator's empty layout
         part = _chunk(rng, {"kind": "ttbar", "n_extra_max": cfg["n_extra_max"], "bkg_jet_max": cfg["bkg_jet_max"],
                             "bkg_frac": 0.0}, 0)
@@ -378,8 +389,8 @@ def _chunk_hlhc(rng, cfg, n):
         if m == 0:
             continue
         sub = {"n_extra_max": cfg["n_extra_max"], "bkg_jet_max": cfg["bkg_jet_max"]}
-        if proc == "ttbar":
-            sub.update(kind="ttbar", bkg_frac=0.0)
+        if proc in ("ttbar", "wtdilep"):
+            sub.update(kind=proc, bkg_frac=0.0)
             part = _chunk(rng, sub, m)
         elif proc == "bkg":
             sub.update(kind="ttbar", bkg_frac=1.0)

@@ -91,7 +91,12 @@ typedef struct hf_events {
  *                        above mtw_min; fails without a selected lepton;
  *                        section 6.1)
  *   HF_CUT_USER         a user predicate compiled at run time by
- *                       hf_chain_compile; i = {index of its source} */
+ *                       hf_chain_compile; i = {index of its source}
+ *   HF_CUT_JET_N_RANGE  f = {pt_min, abs_eta_lo, abs_eta_hi}  i = {n_min, n_max}
+ *                       (the number of jets with pT > pt_min and
+ *                        abs_eta_lo <= |eta| < abs_eta_hi lies in
+ *                        [n_min, n_max]; section 6.1: jet counts in the
+ *                        central Region I and the forward Regions II, III) */
 enum {
     HF_CUT_LEP_N_OS = 0,
     HF_CUT_JET_N_MIN = 1,
@@ -103,7 +108,8 @@ enum {
     HF_CUT_LEP_ISO = 7,
     HF_CUT_RECO = 8,
     HF_CUT_MTW_MIN = 9,
-    HF_CUT_USER = 10
+    HF_CUT_USER = 10,
+    HF_CUT_JET_N_RANGE = 11
 };
 
 /* A cut of the chain.  Its id is its index in the cut table.  Bit j of
@@ -458,20 +464,24 @@ int hf_semilep_reco(const hf_events_t *ev, const int32_t *d_idx, const int64_t *
  * max_cands in [2, HF_MAX_CANDS], the selection thresholds); the split
  * search: n_grid in [2, 129] points per axis over [-half_range, half_range]
  * (GeV, > 0), n_refine in [0, 8] refinements; reco_cut as for hf_ttbar_reco;
- * reserved must be 0. */
+ * n_top the number of top quarks of Eq. (chi2): 2 (or 0) for ttbar, 1 for
+ * Wt, whose second W comes from the hard process (section 6.2: one top and
+ * two W bosons in Wt events). */
 typedef struct hf_chi2_params {
     double m_t, m_w, sigma_t, sigma_w, half_range;
     float lep_pt_min, lep_eta_max, jet_pt_min, jet_eta_max, btag_min;
-    int32_t pair_mode, max_cands, n_grid, n_refine, reco_cut, reserved;
+    int32_t pair_mode, max_cands, n_grid, n_refine, reco_cut, n_top;
 } hf_chi2_params_t;
 
 /* Outputs over the compacted positions [0, capacity) (positions >= *d_count
  * untouched): root_nu, root_nubar as hf_semilep_out_t's root; best_i, best_j
  * the b jets (indices within the event) of the l+ and l- sides; nu, nubar
  * (px, py, pz) [capacity][3]; the top and W masses; chi2 the minimum; split
- * the offset (u, v) of nu_T from MET/2 [capacity][2].  No solution (fewer
- * than two opposite-sign leptons or two candidates, an id outside the
- * chunk): has_sol = 0, -1 indices, HF_NO_SOLUTION floats. */
+ * the offset (u, v) of nu_T from MET/2 [capacity][2].  With one top, the
+ * side without it has best_* = -1 and HF_NO_SOLUTION as its top mass.  No
+ * solution (fewer than two opposite-sign leptons, fewer candidates than
+ * tops, an id outside the chunk): has_sol = 0, -1 indices, HF_NO_SOLUTION
+ * floats. */
 typedef struct hf_chi2_out {
     uint8_t *has_sol;
     int8_t *root_nu, *root_nubar;
@@ -485,7 +495,9 @@ typedef struct hf_chi2_out {
  * nubar_T = MET/2 - (u, v); each neutrino's p_z follows from its W mass as
  * in hf_semilep_reco; every ordered pairing of two b candidates (the first
  * with l+) and every pair of p_z candidates is scored by Eq. (chi2) with two
- * tops and two W.  (u, v) is searched on an n_grid x n_grid grid, then
+ * tops and two W (n_top = 1: every candidate forms the top with l+, then
+ * with l-, and Eq. (chi2) has that top and both W).  (u, v) is searched on
+ * an n_grid x n_grid grid, then
  * refined n_refine times on a 5 x 5 grid centred on the best point with a
  * quarter of the previous step (a refined point must be strictly better).
  * Ties go to the first grid point, then pairing, then roots.  FP64 on the

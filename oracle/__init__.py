@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libhf_oracle.so")
 SRC_PATH = os.path.join(_HERE, "hf_oracle.c")
 
 KIND = {"LEP_N_OS": 0, "JET_N_MIN": 1, "BTAG_N_MIN": 2, "BTAG_N_EQ": 3, "MET_MIN": 4,
-        "MLL_MIN": 5, "FWD_JET_VETO": 6, "LEP_ISO": 7, "RECO": 8, "MTW_MIN": 9, "USER": 10}
+        "MLL_MIN": 5, "FWD_JET_VETO": 6, "LEP_ISO": 7, "RECO": 8, "MTW_MIN": 9, "USER": 10, "JET_N_RANGE": 11}
 PAIR_MODE = {"BTAG_FILL": 0, "ALL_JETS": 1}
 NOSOL = -9999.0
 
@@ -79,7 +79,7 @@ class SemilepOut(C.Structure):
 class Chi2Params(C.Structure):
     _fields_ = [(k, C.c_double) for k in ("m_t", "m_w", "sigma_t", "sigma_w", "half_range", "lep_pt_min",
                                           "lep_eta_max", "jet_pt_min", "jet_eta_max", "btag_min")] + \
-               [(k, C.c_int32) for k in ("pair_mode", "max_cands", "n_grid", "n_refine")]
+               [(k, C.c_int32) for k in ("pair_mode", "max_cands", "n_grid", "n_refine", "n_top")]
 
 
 class Chi2Out(C.Structure):
@@ -390,7 +390,7 @@ def chi2_params(cp):
                       half_range=cp["half_range"], lep_pt_min=f32("lep_pt_min"), lep_eta_max=f32("lep_eta_max"),
                       jet_pt_min=f32("jet_pt_min"), jet_eta_max=f32("jet_eta_max"), btag_min=f32("btag_min"),
                       pair_mode=PAIR_MODE[cp["pair_mode"]], max_cands=int(cp["max_cands"]),
-                      n_grid=int(cp["n_grid"]), n_refine=int(cp["n_refine"]))
+                      n_grid=int(cp["n_grid"]), n_refine=int(cp["n_refine"]), n_top=int(cp.get("n_top", 2)))
 
 
 def dilep_chi2_reco(ev, idx, cp, index_base=0, n_threads=0, fp64=False):

@@ -50,7 +50,7 @@
 enum {
     ORC_LEP_N_OS = 0, ORC_JET_N_MIN = 1, ORC_BTAG_N_MIN = 2, ORC_BTAG_N_EQ = 3,
     ORC_MET_MIN = 4, ORC_MLL_MIN = 5, ORC_FWD_JET_VETO = 6, ORC_LEP_ISO = 7,
-    ORC_RECO = 8, ORC_MTW_MIN = 9, ORC_USER = 10
+    ORC_RECO = 8, ORC_MTW_MIN = 9, ORC_USER = 10, ORC_JET_N_RANGE = 11
 };
 
 typedef struct {
@@ -244,6 +244,17 @@ static int orc_eval_cut(const orc_events *ev, int64_t e, const orc_cut *c, const
         if (n < 2) return 0;
         double m2 = orc_dot(s, s);
         return m2 > 0.0 && sqrt(m2) > c->f[2];
+    }
+    case ORC_JET_N_RANGE: {
+        /* jets with pT above the threshold in a band of |eta| (section 6.1:
+         * Region I |eta| < 2.5, Region II 2.5-2.75, Region III 2.75-3.5),
+         * their number within [n_min, n_max] */
+        int n = 0;
+        for (uint32_t k = j0; k < j1; ++k) {
+            double ae = fabs(ev->jet_eta[k]);
+            n += ev->jet_pt[k] > c->f[0] && ae >= c->f[1] && ae < c->f[2];
+        }
+        return n >= c->i[0] && n <= c->i[1];
     }
     case ORC_FWD_JET_VETO: {
         for (uint32_t k = j0; k < j1; ++k) {
@@ -1184,12 +1195,16 @@ int64_t orc_semilep_reco(const orc_events *ev, const int32_t *idx, int64_t S, co
  * quarter of the previous step.  At every grid point every ordered pairing
  * of b candidates (i with l+, j with l-, i != j; candidates as in
  * orc_stage) and every pair of p_z candidates is scored; the first minimum
- * in the order (level, point, i, j, root of nu, root of nubar) is kept.   */
+ * in the order (level, point, i, j, root of nu, root of nubar) is kept.
+ * With one top (Wt: one top and two W bosons, section 6.2) each candidate
+ * forms the top with l+ and then with l-, the other lepton's W standing
+ * alone: Eq. (chi2) has that top's term and both W terms, and the first
+ * minimum in the order (level, point, candidate, side, roots) is kept.     */
 
 typedef struct {
     double m_t, m_w, sigma_t, sigma_w, half_range;
     double lep_pt_min, lep_eta_max, jet_pt_min, jet_eta_max, btag_min;
-    int32_t pair_mode, max_cands, n_grid, n_refine;
+    int32_t pair_mode, max_cands, n_grid, n_refine, n_top;
 } orc_chi2_params;
 
 typedef struct {
@@ -1202,7 +1217,7 @@ typedef struct {
 
 typedef struct {
     double chi2, u, v;
-    int i, j, r1, r2, have;
+    int i, j, r1, r2, have; /* one top: i or j is -1 on the side without it */
 } orc_chi2_best;
 
 /* chi^2 of every pairing and root pair at one split point; keeps the first
@@ -1218,6 +1233,25 @@ static void orc_chi2_point(const orc_staged *st, double mx, double my, double u,
     int k1[2], k2[2];
     int n1 = orc_nu_pz(lp, n1x, n1y, p->m_w, pz1, k1);
     int n2 = orc_nu_pz(lm, n2x, n2y, p->m_w, pz2, k2);
+    if (p->n_top == 1) {
+        for (int i = 0; i < st->nc; ++i)
+            for (int side = 0; side < 2; ++side)
+                for (int r1 = 0; r1 < n1; ++r1)
+                    for (int r2 = 0; r2 < n2; ++r2) {
+                        vec4 nu = {sqrt(n1x * n1x + n1y * n1y + pz1[r1] * pz1[r1]), n1x, n1y, pz1[r1]};
+                        vec4 nb = {sqrt(n2x * n2x + n2y * n2y + pz2[r2] * pz2[r2]), n2x, n2y, pz2[r2]};
+                        vec4 wp = orc_add(st->lp, nu), wm = orc_add(st->lm, nb);
+                        double mt = orc_mass(orc_add(st->cv[i], side == 0 ? wp : wm));
+                        double chi2 = orc_sq(mt - p->m_t) / orc_sq(p->sigma_t) +
+                                      orc_sq(orc_mass(wp) - p->m_w) / orc_sq(p->sigma_w) +
+                                      orc_sq(orc_mass(wm) - p->m_w) / orc_sq(p->sigma_w);
+                        if (!b->have || chi2 < b->chi2) {
+                            b->have = 1; b->chi2 = chi2; b->u = u; b->v = v;
+                            b->i = side == 0 ? i : -1; b->j = side == 0 ? -1 : i; b->r1 = r1; b->r2 = r2;
+                        }
+                    }
+        return;
+    }
     for (int i = 0; i < st->nc; ++i)
         for (int j = 0; j < st->nc; ++j) {
             if (i == j) continue;
@@ -1260,7 +1294,8 @@ int64_t orc_dilep_chi2_reco(const orc_events *ev, const int32_t *idx, int64_t S,
         orc_chi2_best b;
         memset(&b, 0, sizeof b);
         double mx = 0.0, my = 0.0;
-        if (st.ok) {
+        /* one top needs one candidate, two tops two */
+        if (p->n_top == 1 ? (st.leps && st.nc >= 1) : st.ok) {
             mx = ev->met_x[e];
             my = ev->met_y[e];
             /* coarse grid, then the refinements around the best point so far */
@@ -1298,14 +1333,14 @@ int64_t orc_dilep_chi2_reco(const orc_events *ev, const int32_t *idx, int64_t S,
         vec4 nb = {sqrt(n2x * n2x + n2y * n2y + pz2[b.r2] * pz2[b.r2]), n2x, n2y, pz2[b.r2]};
         out->root_nu[s] = (int8_t)k1[b.r1];
         out->root_nubar[s] = (int8_t)k2[b.r2];
-        out->best_i[s] = (int16_t)st.cand[b.i];
-        out->best_j[s] = (int16_t)st.cand[b.j];
+        out->best_i[s] = (int16_t)(b.i >= 0 ? st.cand[b.i] : -1);
+        out->best_j[s] = (int16_t)(b.j >= 0 ? st.cand[b.j] : -1);
         out->nu[3 * s + 0] = nu.x; out->nu[3 * s + 1] = nu.y; out->nu[3 * s + 2] = nu.z;
         out->nubar[3 * s + 0] = nb.x; out->nubar[3 * s + 1] = nb.y; out->nubar[3 * s + 2] = nb.z;
         out->m_wp[s] = orc_mass(orc_add(st.lp, nu));
         out->m_wm[s] = orc_mass(orc_add(st.lm, nb));
-        out->m_t[s] = orc_mass(orc_add(st.cv[b.i], orc_add(st.lp, nu)));
-        out->m_tbar[s] = orc_mass(orc_add(st.cv[b.j], orc_add(st.lm, nb)));
+        out->m_t[s] = b.i >= 0 ? orc_mass(orc_add(st.cv[b.i], orc_add(st.lp, nu))) : ORC_NOSOL;
+        out->m_tbar[s] = b.j >= 0 ? orc_mass(orc_add(st.cv[b.j], orc_add(st.lm, nb))) : ORC_NOSOL;
         out->chi2[s] = b.chi2;
         out->split[2 * s] = b.u;
         out->split[2 * s + 1] = b.v;

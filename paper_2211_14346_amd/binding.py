@@ -17,7 +17,7 @@ HF_MAX_CUTS = 32
 HF_MAX_CANDS = 12
 HF_NO_SOLUTION = -9999.0
 CUT_KIND = {"LEP_N_OS": 0, "JET_N_MIN": 1, "BTAG_N_MIN": 2, "BTAG_N_EQ": 3, "MET_MIN": 4, "MLL_MIN": 5,
-            "FWD_JET_VETO": 6, "LEP_ISO": 7, "RECO": 8, "MTW_MIN": 9, "USER": 10}
+            "FWD_JET_VETO": 6, "LEP_ISO": 7, "RECO": 8, "MTW_MIN": 9, "USER": 10, "JET_N_RANGE": 11}
 PREC = {"fp64": 0, "mixed": 1}
 PAIR = {"BTAG_FILL": 0, "ALL_JETS": 1}
 
@@ -72,7 +72,7 @@ class SemilepOut(C.Structure):
 class Chi2Params(C.Structure):
     _fields_ = [(k, C.c_double) for k in ("m_t", "m_w", "sigma_t", "sigma_w", "half_range")] + \
                [(k, C.c_float) for k in ("lep_pt_min", "lep_eta_max", "jet_pt_min", "jet_eta_max", "btag_min")] + \
-               [(k, C.c_int32) for k in ("pair_mode", "max_cands", "n_grid", "n_refine", "reco_cut", "reserved")]
+               [(k, C.c_int32) for k in ("pair_mode", "max_cands", "n_grid", "n_refine", "reco_cut", "n_top")]
 
 
 class Chi2Out(C.Structure):
@@ -366,7 +366,7 @@ def chi2_params(cp, reco_cut=-1):
                       half_range=cp["half_range"], lep_pt_min=cp["lep_pt_min"], lep_eta_max=cp["lep_eta_max"],
                       jet_pt_min=cp["jet_pt_min"], jet_eta_max=cp["jet_eta_max"], btag_min=cp["btag_min"],
                       pair_mode=PAIR[cp["pair_mode"]], max_cands=int(cp["max_cands"]), n_grid=int(cp["n_grid"]),
-                      n_refine=int(cp["n_refine"]), reco_cut=int(reco_cut), reserved=0)
+                      n_refine=int(cp["n_refine"]), reco_cut=int(reco_cut), n_top=int(cp.get("n_top", 2)))
 
 
 class Chi2Outputs:

@@ -56,7 +56,7 @@ int check_cuts(const hf_cut_t *h_cuts, int n_cuts, bool *need_phi_e) {
     *need_phi_e = false;
     for (int c = 0; c < n_cuts; ++c) {
         const hf_cut_t &k = h_cuts[c];
-        if (k.kind < HF_CUT_LEP_N_OS || k.kind > HF_CUT_USER)
+        if (k.kind < HF_CUT_LEP_N_OS || k.kind > HF_CUT_JET_N_RANGE)
             return fail(HF_ERR_INVAL, "cut %d: unknown kind %d", c, k.kind);
         if (k.reserved != 0) return fail(HF_ERR_INVAL, "cut %d: reserved field must be 0", c);
         if (k.dep_mask >> n_cuts) return fail(HF_ERR_INVAL, "cut %d: dependency on a cut id >= n_cuts", c);
@@ -487,7 +487,8 @@ int hf_dilep_chi2_reco(const hf_events_t *ev, const int32_t *d_idx, const int64_
         return fail(HF_ERR_INVAL, "hf_dilep_chi2_reco: masses invalid");
     if (!(p->sigma_t > 0.0) || !(p->sigma_w > 0.0) || !isfinite(p->sigma_t) || !isfinite(p->sigma_w))
         return fail(HF_ERR_INVAL, "hf_dilep_chi2_reco: widths must be finite and > 0");
-    if (p->reserved != 0) return fail(HF_ERR_INVAL, "hf_dilep_chi2_reco: reserved field must be 0");
+    if (p->n_top != 0 && p->n_top != 1 && p->n_top != 2)
+        return fail(HF_ERR_INVAL, "hf_dilep_chi2_reco: n_top %d is not 1 or 2", p->n_top);
     hf::Chi2Args a;
     a.m_t = p->m_t;
     a.m_w = p->m_w;
@@ -504,6 +505,7 @@ int hf_dilep_chi2_reco(const hf_events_t *ev, const int32_t *d_idx, const int64_
     a.pair_mode = p->pair_mode;
     a.max_cands = p->max_cands;
     a.n_grid = p->n_grid;
+    a.n_top = p->n_top == 1 ? 1 : 2;
     a.n_refine = p->n_refine;
     hf::Chi2OutView o{out->has_sol, out->root_nu, out->root_nubar, out->best_i, out->best_j, out->nu, out->nubar,
                       out->m_t,     out->m_tbar,  out->m_wp,       out->m_wm,   out->chi2,   out->split};

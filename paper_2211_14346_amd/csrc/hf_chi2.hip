@@ -2,7 +2,8 @@
 // (paper section 6.2): the two neutrinos share E_T^miss, each neutrino's p_z
 // follows from its W mass, and Eq. (chi2) with two tops (b l+ nu, bbar l-
 // nubar) and two W is minimised over the split, the ordered b-candidate
-// pairings and the p_z roots.
+// pairings and the p_z roots.  For Wt events (one top, two W) each
+// candidate forms the top with either lepton and the other W stands alone.
 //
 // The split is an offset (u, v) from the even split, nu_T = MET/2 + (u, v),
 // nubar_T = MET/2 - (u, v), searched on an n_grid x n_grid grid over
@@ -218,6 +219,48 @@ __device__ __forceinline__ double point_best(const Lep &LP, const Lep &LM, const
     return best;
 }
 
+// The smallest W term of a side and its root (first on ties); INFINITY
+// when the side has no p_z candidate.
+__device__ __forceinline__ double w_min(const Side &S, int &root) {
+    double t = INFINITY;
+    root = 0;
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+        if (r < S.n && S.cw[r] < t) {
+            t = S.cw[r];
+            root = r;
+        }
+    return t;
+}
+
+// One top (Wt, section 6.2): candidate i forms the top with l+ (the l- W
+// standing alone), then with l- (the l+ W alone); the first minimum in the
+// order (candidate, side).  Packed as for two tops with 15 in the index of
+// the side without a top.
+__device__ __forceinline__ double point_best1(const Lep &LP, const Lep &LM, const double *cv, int nc, double mx,
+                                              double my, double u, double v, const Chi2Args &a, int &packed) {
+    const Side P = side(LP, 0.5 * mx + u, 0.5 * my + v, a);
+    const Side M = side(LM, 0.5 * mx - u, 0.5 * my - v, a);
+    int rwp, rwm;
+    const double wp = w_min(P, rwp), wm = w_min(M, rwm);
+    double best = INFINITY;
+    packed = 0;
+    for (int i = 0; i < nc; ++i) {
+        int r;
+        const double tp = side_min(cv + 4 * i, P, a, r) + wm;
+        if (tp < best) {
+            best = tp;
+            packed = i | (15 << 4) | (r << 8) | (rwm << 9);
+        }
+        const double tm = wp + side_min(cv + 4 * i, M, a, r);
+        if (tm < best) {
+            best = tm;
+            packed = 15 | (i << 4) | (rwp << 8) | (r << 9);
+        }
+    }
+    return best;
+}
+
 // Wave argmin of (value, point index); every lane gets the winner.
 __device__ __forceinline__ void wave_argmin(double &val, int &pidx, int &packed) {
 #pragma unroll
@@ -309,7 +352,7 @@ __global__ __launch_bounds__(kBlock) void k_chi2(EvView ev, const int32_t *__res
                     }
                 }
                 wave_sync();
-                ok = nc >= 2;
+                ok = nc >= (a.n_top == 1 ? 1 : 2);
                 if (ok) {
                     // candidates on lanes [0, nc), l+ and l- on the last two lanes: one
                     // conversion on per-lane columns rather than one per object kind
@@ -347,8 +390,9 @@ __global__ __launch_bounds__(kBlock) void k_chi2(EvView ev, const int32_t *__res
                     const int p = p0 + lane;
                     if (p < N * N) {
                         int q;
-                        const double t = point_best(LP, LM, cv, nc, mx, my, -a.half_range + step * row,
-                                                    -a.half_range + step * col, a, q);
+                        const double pu = -a.half_range + step * row, pv = -a.half_range + step * col;
+                        const double t = a.n_top == 1 ? point_best1(LP, LM, cv, nc, mx, my, pu, pv, a, q)
+                                                      : point_best(LP, LM, cv, nc, mx, my, pu, pv, a, q);
                         if (t < val) {
                             val = t;
                             pidx = p;
@@ -374,7 +418,25 @@ __global__ __launch_bounds__(kBlock) void k_chi2(EvView ev, const int32_t *__res
             // keep each candidate's term in LDS, lanes [32, 57) the l- side of point
             // q = lane - 32 and keep its two smallest terms, which then go to the l+
             // lane of the same point (the same operations as point_best).
-            for (int level = 0; level < a.n_refine; ++level) {
+            for (int level = 0; level < a.n_refine && a.n_top == 1; ++level) {
+                // one top: lanes [0, 25) take the whole point
+                step *= 0.25;
+                double val = INFINITY;
+                int pidx = 0x7fffffff, pk = 0;
+                if (lane < kRefPts) {
+                    const double u = bu + step * (lane / 5 - 2), v = bv + step * (lane % 5 - 2);
+                    val = point_best1(LP, LM, cv, nc, mx, my, u, v, a, pk);
+                    pidx = lane;
+                }
+                wave_argmin(val, pidx, pk);
+                if (val < bval) {
+                    bval = val;
+                    bpk = pk;
+                    bu = bu + step * (pidx / 5 - 2);
+                    bv = bv + step * (pidx % 5 - 2);
+                }
+            }
+            for (int level = 0; level < a.n_refine && a.n_top != 1; ++level) {
                 step *= 0.25;
                 const bool plus = lane < 32;
                 const int q = plus ? lane : lane - 32;
@@ -447,12 +509,14 @@ __global__ __launch_bounds__(kBlock) void k_chi2(EvView ev, const int32_t *__res
                 const double z1 = at2(P.pz, r1), z2 = at2(M.pz, r2);
                 const double nu[4] = {sqrt(n1x * n1x + n1y * n1y + z1 * z1), n1x, n1y, z1};
                 const double nb[4] = {sqrt(n2x * n2x + n2y * n2y + z2 * z2), n2x, n2y, z2};
+                // one top: index 15 marks the side without it
+                const bool has_t = i != 15, has_tb = j != 15;
                 double wp[4], wm[4], tp[4], tm[4];
                 for (int c = 0; c < 4; ++c) {
                     wp[c] = lp[c] + nu[c];
                     wm[c] = lm[c] + nb[c];
-                    tp[c] = cv[4 * i + c] + wp[c];
-                    tm[c] = cv[4 * j + c] + wm[c];
+                    tp[c] = (has_t ? cv[4 * i + c] : 0.0) + wp[c];
+                    tm[c] = (has_tb ? cv[4 * j + c] : 0.0) + wm[c];
                 }
                 const double mwp = mass4(wp[0], wp[1], wp[2], wp[3]), mwm = mass4(wm[0], wm[1], wm[2], wm[3]);
                 const double mt = mass4(tp[0], tp[1], tp[2], tp[3]), mtb = mass4(tm[0], tm[1], tm[2], tm[3]);
@@ -460,18 +524,18 @@ __global__ __launch_bounds__(kBlock) void k_chi2(EvView ev, const int32_t *__res
                 o.has_sol[k] = 1;
                 o.root_nu[k] = (int8_t)at2(P.kind, r1);
                 o.root_nubar[k] = (int8_t)at2(M.kind, r2);
-                o.best_i[k] = (int16_t)s_loc[wave][i];
-                o.best_j[k] = (int16_t)s_loc[wave][j];
+                o.best_i[k] = (int16_t)(has_t ? s_loc[wave][i] : -1);
+                o.best_j[k] = (int16_t)(has_tb ? s_loc[wave][j] : -1);
                 for (int c = 0; c < 3; ++c) {
                     o.nu[3 * k + c] = nu[c + 1];
                     o.nubar[3 * k + c] = nb[c + 1];
                 }
-                o.m_t[k] = mt;
-                o.m_tbar[k] = mtb;
+                o.m_t[k] = has_t ? mt : HF_NO_SOLUTION;
+                o.m_tbar[k] = has_tb ? mtb : HF_NO_SOLUTION;
                 o.m_wp[k] = mwp;
                 o.m_wm[k] = mwm;
-                o.chi2[k] = sq(mt - a.m_t) / st2 + sq(mwp - a.m_w) / sw2 + sq(mtb - a.m_t) / st2 +
-                            sq(mwm - a.m_w) / sw2;
+                o.chi2[k] = (has_t ? sq(mt - a.m_t) / st2 : 0.0) + sq(mwp - a.m_w) / sw2 +
+                            (has_tb ? sq(mtb - a.m_t) / st2 : 0.0) + sq(mwm - a.m_w) / sw2;
                 o.split[2 * k] = bu;
                 o.split[2 * k + 1] = bv;
             }

@@ -9,7 +9,7 @@ namespace hf {
 struct Chi2Args {
     double m_t, m_w, sigma_t, sigma_w, inv_st2, inv_sw2, half_range;
     float lep_pt_min, lep_eta_max, jet_pt_min, jet_eta_max, btag_min;
-    int pair_mode, max_cands, n_grid, n_refine;
+    int pair_mode, max_cands, n_grid, n_refine, n_top;
 };
 
 struct Chi2OutView {

@@ -127,6 +127,23 @@ __device__ inline bool eval_cut(const EvView &ev, int64_t e, const hf_cut_t &c) 
         const double t = c.f[2];
         return m2 > 0.0 && m2 > t * t;
     }
+    case HF_CUT_JET_N_RANGE: {
+        const uint32_t j0 = ev.jet_off[e], j1 = ev.jet_off[e + 1];
+        int n = 0;
+        for (uint32_t c0 = j0; c0 < j1; c0 += kChunk) {
+            float pt[kChunk], ae[kChunk];
+#pragma unroll
+            for (int u = 0; u < kChunk; ++u) {
+                const bool in = c0 + u < j1;
+                pt[u] = in ? ev.jet_pt[c0 + u] : 0.0f;
+                ae[u] = in ? fabsf(ev.jet_eta[c0 + u]) : 0.0f;
+            }
+#pragma unroll
+            for (int u = 0; u < kChunk; ++u)
+                n += (c0 + u < j1 && pt[u] > c.f[0] && ae[u] >= c.f[1] && ae[u] < c.f[2]) ? 1 : 0;
+        }
+        return n >= c.i[0] && n <= c.i[1];
+    }
     case HF_CUT_FWD_JET_VETO: {
         const uint32_t j0 = ev.jet_off[e], j1 = ev.jet_off[e + 1];
         for (uint32_t c0 = j0; c0 < j1; c0 += kChunk) {

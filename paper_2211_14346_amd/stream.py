@@ -141,13 +141,14 @@ class DeviceSlot:
 
 class Channel:
     """One analysis channel: a cut chain ending in a reconstruction (the
-    dileptonic quartic with `reco`, or the single-neutrino chi^2 with
-    `semilep` and `topology`), with its counters and cut order."""
+    dileptonic quartic with `reco`, the single-neutrino chi^2 with `semilep`
+    and `topology`, or the dileptonic chi^2 fit with a MET split with
+    `chi2`), with its counters and cut order."""
 
     def __init__(self, name, cuts, capacity, reco=None, semilep=None, topology="TCHAN", precision="mixed",
-                 device="cuda"):
-        if (reco is None) == (semilep is None):
-            raise ValueError("give exactly one of reco and semilep")
+                 chi2=None, device="cuda"):
+        if sum(x is not None for x in (reco, semilep, chi2)) != 1:
+            raise ValueError("give exactly one of reco, semilep and chi2")
         self.name = name
         self.cuts = cuts
         self.n_cuts = len(cuts)
@@ -159,9 +160,15 @@ class Channel:
         cap = max(1, int(capacity))
         self.capacity = cap
         self.semilep = semilep is not None
+        self.chi2 = chi2 is not None
+        self.kind = "semilep" if self.semilep else "chi2" if self.chi2 else "quartic"
         if self.semilep:
             self.params = B.semilep_params(semilep, topology, reco_cut=self.reco_id)
             self.out = B.SemilepOutputs(cap, device=device)
+            self.ws_reco = None
+        elif self.chi2:
+            self.params = B.chi2_params(chi2, reco_cut=self.reco_id)
+            self.out = B.Chi2Outputs(cap, device=device)
             self.ws_reco = None
         else:
             self.params = B.reco_params(reco, precision=precision, reco_cut=self.reco_id)
@@ -189,6 +196,9 @@ class Channel:
         B.compact(self.survive, n, self.idx, self.count, self.ws_cmp, index_base=slot.index_base, stream=stream)
         if self.semilep:
             B.semilep_reco(slot, self.idx, self.count, self.capacity, self.params, self.out, self.counters, stream)
+        elif self.chi2:
+            B.dilep_chi2_reco(slot, self.idx, self.count, self.capacity, self.params, self.out, self.counters,
+                              stream)
         else:
             B.ttbar_reco(slot, self.idx, self.count, self.capacity, self.params, self.out, self.counters,
                          self.ws_reco, stream)

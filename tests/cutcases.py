@@ -12,6 +12,10 @@ GOLD = os.path.join(os.path.dirname(__file__), "golden", "cut_cases.json")
 CUT_DEFS = {c["name"]: c for c in hfgen.configs.chain_dilepton() + hfgen.configs.chain_tth8()}
 CUT_DEFS["JETS4"] = [c for c in hfgen.configs.chain_tth8() if c["name"] == "JETS4"][0]
 CUT_DEFS["BTAG3"] = [c for c in hfgen.configs.chain_tth8() if c["name"] == "BTAG3"][0]
+CUT_DEFS["JETS_I_1TO2"] = {"name": "JETS_I_1TO2", "kind": "JET_N_RANGE", "f": [25.0, 0.0, 2.5], "i": [1, 2],
+                            "deps": []}
+CUT_DEFS["JETS_FWD1"] = {"name": "JETS_FWD1", "kind": "JET_N_RANGE", "f": [25.0, 2.5, 3.5], "i": [1, 1], "deps": []}
+CUT_DEFS["JETS_II1"] = {"name": "JETS_II1", "kind": "JET_N_RANGE", "f": [25.0, 2.5, 2.75], "i": [1, 99], "deps": []}
 CUT_DEFS["MTW50"] = dict([c for c in hfgen.configs.chain_hlhc_single() if c["name"] == "S_MTW50"][0],
                          name="MTW50")
 

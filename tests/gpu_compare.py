@@ -14,6 +14,7 @@ Readings of the agreement targets:
 import numpy as np
 
 FLOAT_KEYS = ("m_t", "m_tbar", "m_wp", "m_wm", "logw")
+W_MASS = 80.4
 
 
 def compare(g, w, n=None):
@@ -113,16 +114,29 @@ def compare_chi2(g, w):
     S = len(w["has_sol"])
     hs_g, hs_w = g["has_sol"][:S].astype(bool), w["has_sol"][:S].astype(bool)
     both = hs_g & hs_w
-    same = both.copy()
-    for k in ("root_nu", "root_nubar", "best_i", "best_j"):
-        same &= g[k][:S] == w[k][:S]
-    same &= np.all(g["split"][:S] == w["split"][:S], axis=1)
+    core = both.copy()
+    for k in ("best_i", "best_j"):
+        core &= g[k][:S] == w[k][:S]
+    core &= np.all(g["split"][:S] == w["split"][:S], axis=1)
+    # With one top, the lepton side without it has only its W term; when both
+    # of its p_z roots are real roots of the W mass condition the term is zero
+    # for both, an exact tie that only rounding breaks: either root is the
+    # same choice, provided both forms put that W on its mass shell.
+    def free(side_best, root, mw):
+        real = (g[root][:S] != 2) & (w[root][:S] != 2)
+        shell = (np.abs(g[mw][:S] - W_MASS) <= 1e-9 * W_MASS) & (np.abs(w[mw][:S] - W_MASS) <= 1e-9 * W_MASS)
+        return (g[side_best][:S] < 0) & (w[side_best][:S] < 0) & real & shell
+    eq_p = g["root_nu"][:S] == w["root_nu"][:S]
+    eq_m = g["root_nubar"][:S] == w["root_nubar"][:S]
+    same = core & (eq_p | free("best_i", "root_nu", "m_wp")) & (eq_m | free("best_j", "root_nubar", "m_wm"))
+    exact = same & eq_p & eq_m  # the same solution: its momenta are compared too
     st = {"S": int(S), "decision_equal": bool(np.array_equal(hs_g, hs_w)), "n_both": int(both.sum()),
-          "choice_agree": float(same.sum() / both.sum()) if both.sum() else 1.0}
+          "choice_agree": float(same.sum() / both.sum()) if both.sum() else 1.0,
+          "w_root_ties": int((same & ~exact).sum())}
     rels = []
     for k in ("nu", "nubar"):
-        d = np.linalg.norm(g[k][:S][same] - w[k][:S][same], axis=1)
-        r = d / np.maximum(np.linalg.norm(w[k][:S][same], axis=1), 1.0)
+        d = np.linalg.norm(g[k][:S][exact] - w[k][:S][exact], axis=1)
+        r = d / np.maximum(np.linalg.norm(w[k][:S][exact], axis=1), 1.0)
         st["max_rel_" + k] = float(r.max()) if r.size else 0.0
         rels.append(r)
     for k in CHI2_FLOATS:

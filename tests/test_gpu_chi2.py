@@ -66,6 +66,37 @@ def test_chi2_chain_matches_oracle(B, orc, name, n, over):
     assert np.array_equal(got["final"], got["idx"][got["reco"]["has_sol"].astype(bool)])
 
 
+@pytest.mark.parametrize("refine", [2, 0])
+def test_chi2_one_top_matches_oracle(B, orc, refine):
+    """Wt events (one top, two W): every candidate forms the top with either
+    lepton; one and two b candidates, with and without refinement."""
+    cfg = {"kind": "wtdilep", "n_extra_max": 3, "bkg_frac": 0.0, "seed": 41}
+    ev = hfgen.generate(cfg, n_events=6000, seed=41)
+    cuts = hfgen.configs.chain_dilepton()[:2]
+    s_w, _, _ = orc.select(ev, cuts, [0, 1])
+    ids = np.flatnonzero(s_w)
+    cp = dict(hfgen.configs.CHI2_DEFAULTS, n_top=1, n_refine=refine)
+    _say("chi2 one top", ids.size, refine)
+    got, cnt = _direct(B, ev, ids, cp)
+    want = orc.dilep_chi2_reco(ev, ids, cp)
+    st = compare_chi2(got, want)
+    _say(st)
+    diff = np.flatnonzero((got["best_i"] != want["best_i"]) | (got["best_j"] != want["best_j"]) |
+                          np.any(got["split"] != want["split"], axis=1) | (got["root_nu"] != want["root_nu"]) |
+                          (got["root_nubar"] != want["root_nubar"]))
+    for q in diff[:6]:
+        _say("differs", int(q), "chi2", float(got["chi2"][q]), float(want["chi2"][q]), "ij", int(got["best_i"][q]),
+             int(got["best_j"][q]), int(want["best_i"][q]), int(want["best_j"][q]), "split", got["split"][q],
+             want["split"][q], "roots", int(got["root_nu"][q]), int(got["root_nubar"][q]), int(want["root_nu"][q]),
+             int(want["root_nubar"][q]))
+    assert_agree_semilep(st, min_agree=0.999)
+    assert st["n_both"] > 0.9 * ids.size
+    # one side carries the top: exactly one of best_i / best_j is set
+    hs = got["has_sol"].astype(bool)
+    assert np.all((got["best_i"][hs] >= 0) != (got["best_j"][hs] >= 0))
+    assert cnt[0] == ids.size and cnt[1] == hs.sum()
+
+
 def test_chi2_edge_cases(B, orc):
     from .test_gpu_parity import _edge_sample
     ev = _edge_sample()

@@ -1,9 +1,12 @@
 """GPU parity of the chunked stream (two device slots filled from pinned
 host memory on a copy stream while the compute stream runs the channels):
-every chunk of a mixed HL-LHC-like sample, through the dileptonic channel
-(quartic at 64 variations) and the one-lepton channel (single-neutrino
-chi^2), against the FP64 oracle under the cut order the GPU ran it with;
-counters accumulated over the stream against the oracle's sums."""
+every chunk of a mixed HL-LHC-like sample through the five signal bins of
+section 6.1, each with its reconstruction (section 6.2: the single-neutrino
+chi^2 in the semileptonic ttbar, t-channel and Wt topologies, the
+two-neutrino quartic at 64 variations for dileptonic ttbar, the chi^2 fit
+with a MET split and one top for dileptonic Wt), against the FP64 oracle
+under the cut order the GPU ran it with; counters accumulated over the
+stream against the oracle's sums; hand-built events of known bin."""
 
 import sys
 
@@ -12,11 +15,14 @@ import pytest
 
 import hfgen
 
-from .gpu_compare import assert_agree, assert_agree_semilep, compare, compare_semilep
+from .gpu_compare import (assert_agree, assert_agree_semilep, compare, compare_chi2, compare_semilep)
+from .test_oracle_bins import load_bin_cases
 
 pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
+
+BIN_RECO = hfgen.configs.HLHC_BIN_RECO
 
 
 def _say(*a):
@@ -33,16 +39,55 @@ def B():
     return binding
 
 
+def _channels(cfg, cap):
+    from paper_2211_14346_amd.stream import Channel
+    chans = []
+    for name, cuts in cfg["chains"].items():
+        kind, arg = BIN_RECO[name]
+        if kind == "semilep":
+            chans.append(Channel(name, cuts, cap, semilep=cfg["semilep"], topology=arg))
+        elif kind == "chi2":
+            chans.append(Channel(name, cuts, cap, chi2=dict(cfg["chi2"], n_top=arg)))
+        else:
+            chans.append(Channel(name, cuts, cap, reco=cfg["reco"]))
+    return chans
+
+
+def _oracle_reco(orc, cfg, name, ev, idx, base):
+    kind, arg = BIN_RECO[name]
+    if kind == "semilep":
+        return orc.semilep_reco(ev, idx, cfg["semilep"], arg, index_base=base)
+    if kind == "chi2":
+        return orc.dilep_chi2_reco(ev, idx, dict(cfg["chi2"], n_top=arg), index_base=base)
+    return orc.ttbar_reco(ev, idx, cfg["reco"], index_base=base)
+
+
+def _check_reco(name, got, want):
+    kind = BIN_RECO[name][0]
+    if kind == "semilep":
+        st = compare_semilep(got, want)
+        _say(name, st)
+        assert_agree_semilep(st)
+    elif kind == "chi2":
+        st = compare_chi2(got, want)
+        _say(name, st)
+        assert_agree_semilep(st)
+    else:
+        st = compare(got, want)
+        _say(name, st)
+        assert_agree(st)
+    return st
+
+
 def _setup(n_chunk, n_chunks, packed=False):
-    from paper_2211_14346_amd.stream import Channel, EventStream, HostChunk
+    from paper_2211_14346_amd.stream import EventStream, HostChunk
     cfg = hfgen.config("hlhc50M")
     samples = [hfgen.stream_chunk(cfg, i, n=n_chunk) for i in range(n_chunks)]
     chunks = [HostChunk(ev, base, packed=packed) for ev, base in samples]
     assert all(c.packed == bool(packed) for c in chunks)
     lep_cap = max(c.n_lep for c in chunks)
     jet_cap = max(c.n_jet for c in chunks) + 3  # ragged: slots larger than any chunk
-    chans = [Channel("dilepton", cfg["chains"]["dilepton"], n_chunk, reco=cfg["reco"]),
-             Channel("single", cfg["chains"]["single"], n_chunk, semilep=cfg["semilep"], topology="TCHAN")]
+    chans = _channels(cfg, n_chunk)
     es = EventStream(chans, n_chunk, lep_cap, jet_cap)
     return cfg, samples, chunks, chans, es
 
@@ -62,16 +107,9 @@ def test_stream_chunks_match_oracle(B, orc, packed):
             assert np.array_equal(got["survive"], surv), (ch.name, i)
             idx = orc.compact(surv, base)
             assert np.array_equal(got["idx"], idx), (ch.name, i)
-            if ch.semilep:
-                want = orc.semilep_reco(ev, idx, cfg["semilep"], "TCHAN", index_base=base)
-                st = compare_semilep(got["reco"], want)
-                _say(ch.name, st)
-                assert_agree_semilep(st)
-            else:
-                want = orc.ttbar_reco(ev, idx, cfg["reco"], index_base=base)
-                st = compare(got["reco"], want)
-                _say(ch.name, st)
-                assert_agree(st)
+            assert idx.size > 0, (ch.name, i)
+            want = _oracle_reco(orc, cfg, ch.name, ev, idx, base)
+            _check_reco(ch.name, got["reco"], want)
             # the final compaction keeps the GPU's own decisions (agreement checked above)
             assert np.array_equal(got["final"], idx[got["reco"]["has_sol"].astype(bool)]), (ch.name, i)
             r = ch.reco_id
@@ -106,17 +144,14 @@ def test_stream_overlapped_matches_oracle(B, orc):
             order = log[i][c].cpu().numpy()
             surv, reached, passed = orc.select(ev, ch.cuts, list(order), index_base=base)
             idx = orc.compact(surv, base)
-            if ch.semilep:
-                rec = orc.semilep_reco(ev, idx, cfg["semilep"], "TCHAN", index_base=base)
-            else:
-                rec = orc.ttbar_reco(ev, idx, cfg["reco"], index_base=base)
+            rec = _oracle_reco(orc, cfg, ch.name, ev, idx, base)
             reached[ch.reco_id] += np.uint64(idx.size)
             passed[ch.reco_id] += np.uint64(rec["has_sol"].sum())
             want[:, 0] += reached
             want[:, 1] += passed
         got = ch.counters.cpu().numpy().astype(np.uint64)[:, :2]
         _say(ch.name, "orders", [list(o[c].cpu().numpy()) for o in log])
-        if ch.semilep:
+        if ch.kind != "quartic":
             assert np.array_equal(got, want), ch.name
         else:
             # the dileptonic RECO decision is floating point (>= 99.9 % agreement)
@@ -127,6 +162,28 @@ def test_stream_overlapped_matches_oracle(B, orc):
         ev, base = samples[-1]
         surv, _, _ = orc.select(ev, ch.cuts, list(range(ch.n_cuts)), index_base=base)
         assert np.array_equal(last["survive"], surv), ch.name
+
+
+def test_bins_hand_derived_on_the_gpu(B, orc):
+    """The hand-built events of known bin (golden/bin_cases.json) through the
+    five channels: every bin's survive mask as derived by hand, and each
+    bin's reconstruction against the oracle."""
+    from paper_2211_14346_amd.stream import EventStream, HostChunk
+    cfg = hfgen.config("hlhc50M")
+    ev, cases = load_bin_cases()
+    hc = HostChunk(ev, 300)
+    chans = _channels(cfg, ev["n"])
+    es = EventStream(chans, ev["n"], hc.n_lep, hc.n_jet)
+    es.run([hc])
+    torch.cuda.synchronize()
+    for ch in chans:
+        got = ch.results(ev["n"])
+        want = np.array([c["expect"][ch.name] for c in cases], dtype=np.uint8)
+        bad = [c["name"] for c, g, w in zip(cases, got["survive"], want) if g != w]
+        assert not bad, (ch.name, bad)
+        idx = np.flatnonzero(want).astype(np.int32) + 300
+        assert np.array_equal(got["idx"], idx), ch.name
+        _check_reco(ch.name, got["reco"], _oracle_reco(orc, cfg, ch.name, ev, idx, 300))
 
 
 @pytest.mark.parametrize("n", [0, 1, 17, 20011, 70000])

@@ -9,6 +9,9 @@ minimised).
   search       the minimum found is no worse than the coarse grid point
                nearest the generated neutrinos with the true pairing;
   invariants   W masses on shell where both p_z are real roots; chi^2 >= 0.
+  one top      Wt events (one top, two W): the same brute force with each
+               candidate forming the top with l+ and then with l-, and the
+               generated b and neutrinos recovered on unsmeared events.
 """
 
 import itertools
@@ -47,9 +50,10 @@ def _polar(pt, eta, phi, e):
     return np.array([e, pt * np.cos(phi), pt * np.sin(phi), pt * np.sinh(eta)])
 
 
-def _stage(ev, e, cp):
+def _stage(ev, e, cp, need=2):
     """Leptons and b candidates as the reconstruction stages them (tagged
-    selected jets, filled to two with untagged ones)."""
+    selected jets, filled to two with untagged ones); None with fewer than
+    `need` candidates."""
     f = lambda k, i: float(ev[k][i])
     l0, l1 = int(ev["lep_off"][e]), int(ev["lep_off"][e + 1])
     sel = [k for k in range(l0, l1) if f("lep_pt", k) > 20 and abs(f("lep_eta", k)) < 2.5]
@@ -66,7 +70,7 @@ def _stage(ev, e, cp):
             break
         if not f("jet_btag", k) > 0.5:
             cand.append(k)
-    if len(cand) < 2:
+    if len(cand) < need:
         return None
     cv = [_polar(f("jet_pt", k), f("jet_eta", k), f("jet_phi", k), f("jet_e", k)) for k in cand]
     return lp, lm, cv, [k - j0 for k in cand]
@@ -88,7 +92,25 @@ def _chi2_at(lp, lm, cv, mx, my, u, v):
     return best
 
 
-def _search(lp, lm, cv, mx, my, cp):
+def _chi2_at_1top(lp, lm, cv, mx, my, u, v):
+    """One top: (chi2, i, j, pz1, pz2) of the first minimum in (candidate,
+    side, roots) order; i (j) is None on the side without the top."""
+    n1x, n1y, n2x, n2y = 0.5 * mx + u, 0.5 * my + v, 0.5 * mx - u, 0.5 * my - v
+    best = None
+    for c, side in itertools.product(range(len(cv)), (0, 1)):
+        for z1 in _pz_candidates(lp, n1x, n1y):
+            for z2 in _pz_candidates(lm, n2x, n2y):
+                nu = np.array([np.sqrt(n1x ** 2 + n1y ** 2 + z1 ** 2), n1x, n1y, z1])
+                nb = np.array([np.sqrt(n2x ** 2 + n2y ** 2 + z2 ** 2), n2x, n2y, z2])
+                top = cv[c] + (lp + nu if side == 0 else lm + nb)
+                x = ((_mass(top) - M_T) ** 2 / S_T ** 2 + (_mass(lp + nu) - M_W) ** 2 / S_W ** 2 +
+                     (_mass(lm + nb) - M_W) ** 2 / S_W ** 2)
+                if best is None or x < best[0]:
+                    best = (x, c if side == 0 else None, c if side == 1 else None, z1, z2)
+    return best
+
+
+def _search(lp, lm, cv, mx, my, cp, at=_chi2_at):
     R, N = cp["half_range"], cp["n_grid"]
     step = 2.0 * R / (N - 1)
     best = None
@@ -99,7 +121,7 @@ def _search(lp, lm, cv, mx, my, cp):
             cu, cv_ = best[5], best[6]
             pts = [(cu + step * a, cv_ + step * c) for a in range(-2, 3) for c in range(-2, 3)]
         for u, v in pts:
-            c = _chi2_at(lp, lm, cv, mx, my, u, v)
+            c = at(lp, lm, cv, mx, my, u, v)
             if best is None or c[0] < best[0]:
                 best = c + (u, v)
     return best
@@ -177,3 +199,64 @@ def test_invariants(orc, sample):
     # the fit is ambiguous (up to four exact solutions per pairing) but its
     # minimum is small on unsmeared ttbar
     assert np.median(r["chi2"]) < 0.05
+
+
+@pytest.fixture(scope="module")
+def wt_sample(orc):
+    cfg = {"kind": "wtdilep", "n_extra_max": 2, "bkg_frac": 0.0, "seed": 31}
+    ev = hfgen.generate(cfg, n_events=600, keep_fp64=True, seed=31)
+    cuts = hfgen.configs.chain_dilepton()[:2]  # two opposite-sign leptons, two jets
+    surv, _, _ = orc.select(ev, cuts, [0, 1])
+    idx = orc.compact(surv)
+    cp = dict(hfgen.configs.CHI2_DEFAULTS, n_top=1)
+    return ev, idx, cp
+
+
+def test_one_top_brute_force(orc, wt_sample):
+    ev, idx, cp = wt_sample
+    cp = dict(cp, n_grid=9, n_refine=1)
+    sub = idx[:25]
+    r = orc.dilep_chi2_reco(ev, sub, cp)
+    agree = 0
+    for s, e in enumerate(sub):
+        st = _stage(ev, e, cp, need=1)
+        assert st is not None and r["has_sol"][s] == 1
+        lp, lm, cv, loc = st
+        b = _search(lp, lm, cv, float(ev["met_x"][e]), float(ev["met_y"][e]), cp, at=_chi2_at_1top)
+        assert abs(r["chi2"][s] - b[0]) <= 1e-9 * max(1.0, b[0])
+        want = (loc[b[1]] if b[1] is not None else -1, loc[b[2]] if b[2] is not None else -1)
+        if (r["best_i"][s], r["best_j"][s]) == want and np.allclose(r["split"][s], b[5:7], rtol=0, atol=1e-9):
+            agree += 1
+            # exactly one side carries the top; its mass is reported, the other is absent
+            assert (r["best_i"][s] >= 0) != (r["best_j"][s] >= 0)
+            assert (r["m_t"][s] == -9999.0) == (r["best_i"][s] < 0)
+            assert (r["m_tbar"][s] == -9999.0) == (r["best_j"][s] < 0)
+    assert agree >= len(sub) - 1
+
+
+def test_one_top_search_beats_the_truth_nearest_grid_point(orc, wt_sample):
+    """With one top the fit is ambiguous (three mass constraints for the
+    split and two p_z): either lepton can often carry the top at chi^2 near
+    zero.  The search's minimum must be no worse than the generated b with
+    l+ at the grid point nearest the generated neutrinos, and small."""
+    ev, idx, cp = wt_sample
+    r = orc.dilep_chi2_reco(ev, idx, cp)
+    tr = ev["truth"]
+    assert (r["has_sol"] == 1).mean() > 0.99
+    R, N = cp["half_range"], cp["n_grid"]
+    step = 2.0 * R / (N - 1)
+    n_checked = 0
+    for s, e in enumerate(idx[:60]):
+        st = _stage(ev, e, cp, need=1)
+        lp, lm, cv, loc = st
+        if tr["b_idx"][e] not in loc:
+            continue
+        i = loc.index(tr["b_idx"][e])
+        mx, my = float(ev["met_x"][e]), float(ev["met_y"][e])
+        a_ = int(np.clip(np.rint((tr["nu"][e, 1] - 0.5 * mx + R) / step), 0, N - 1))
+        c_ = int(np.clip(np.rint((tr["nu"][e, 2] - 0.5 * my + R) / step), 0, N - 1))
+        near = _chi2_at_1top(lp, lm, [cv[i]], mx, my, -R + step * a_, -R + step * c_)
+        assert r["chi2"][s] <= near[0] + 1e-12
+        n_checked += 1
+    assert n_checked > 20
+    assert np.median(r["chi2"][r["has_sol"] == 1]) < 0.05
