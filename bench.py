@@ -40,12 +40,13 @@ EXTRA_WORKLOADS = ("ttbar10k", "tth4M_v256", "stress2M_heavytail")
 # measured by paper_2211_14346_amd/perf/opcount.py, which runs the kernel's
 # own math header on the host with counting scalar types over a sample of
 # this workload: per variation the Box-Muller draws, smear factors, MET shifts
-# and lepton-side terms; per pairing the side terms, MET substitution,
-# eliminant and root intervals; per root interval the Halley solve, recovery
-# of y, acceptance test and score.
+# and lepton-side terms; per pairing the l- side terms, MET reflection, the
+# balanced pencil, its cubic and isolated root, the line pair and the two
+# line-conic quadratics; per intersection point the residual check (and the
+# rare polish), the energies' signs and the score.
 FLOP_PER_VARIATION = 78
-FLOP_PER_PAIRING = 289
-FLOP_PER_INTERVAL = 216
+FLOP_PER_PAIRING = 257
+FLOP_PER_POINT = 63
 
 # MI355X vector peaks (256 CUs at 2.4 GHz): FP64 78.6 TFLOP/s; FP32 157.3 with
 # packed FP32, which this build does not use (non-packed FP32 issues at the
@@ -188,8 +189,8 @@ def main():
 def search_roofline(B, ch, steps, kname):
     """The reconstruction search kernel of a chain timed alone (HIP events that
     hf_ttbar_reco records around it) over a few launches; its algorithmic
-    FP64 work from the launch's unit counts (variations, pairings, root
-    intervals) against the FP64 vector peak."""
+    FP64 work from the launch's unit counts (variations, pairings,
+    intersection points) against the FP64 vector peak."""
     stats0 = ch.out.t["stats"].cpu().numpy().astype(np.int64).copy()
     timer = B.KernelTimer()
     kms = []
@@ -199,18 +200,18 @@ def search_roofline(B, ch, steps, kname):
             kms.append(timer.elapsed_ms())
     timer.close()
     stats1 = ch.out.t["stats"].cpu().numpy().astype(np.int64)
-    per = (stats1 - stats0) / len(kms)  # events, variations, pairings, intervals, solutions per launch
+    per = (stats1 - stats0) / len(kms)  # events, variations, pairings, points, solutions per launch
     kernel_ms = float(np.mean(kms))
-    flops = FLOP_PER_VARIATION * per[1] + FLOP_PER_PAIRING * per[2] + FLOP_PER_INTERVAL * per[3]
+    flops = FLOP_PER_VARIATION * per[1] + FLOP_PER_PAIRING * per[2] + FLOP_PER_POINT * per[3]
     achieved = flops / (kernel_ms * 1e-3) / 1e12
     return {"bound": "alu", "kernel": kname,
             "achieved": round(achieved, 3), "peak": PEAK_ALU_TFLOPS, "unit": "TFLOP/s",
             "frac": round(achieved / PEAK_ALU_TFLOPS, 4), "traffic": None,
             "kernel_ms": round(kernel_ms, 4), "flop_per_launch": float(flops),
             "units_per_launch": {"events": int(per[0]), "variations": int(per[1]), "pairings": int(per[2]),
-                                 "intervals": int(per[3]), "solutions": int(per[4])},
+                                 "points": int(per[3]), "solutions": int(per[4])},
             "flop_per_unit": {"variation": FLOP_PER_VARIATION, "pairing": FLOP_PER_PAIRING,
-                              "interval": FLOP_PER_INTERVAL}}
+                              "point": FLOP_PER_POINT}}
 
 
 # Algorithmic HBM bytes of the cut stage per event (hf_select): the two

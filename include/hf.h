@@ -253,7 +253,8 @@ typedef struct hf_reco_params {
  * (may be NULL) is the mass of the two leading remaining b jets.  Positions
  * without a solution get has_sol = 0, best_* = -1 and HF_NO_SOLUTION in every
  * float output.  stats (may be NULL) accumulates 5 uint64 counts: events,
- * variations, pairings solved, root intervals solved, accepted solutions. */
+ * variations, pairings solved, real common points of the pairings' two
+ * conics found, accepted solutions. */
 typedef struct hf_reco_out {
     uint8_t *has_sol;
     int32_t *n_sol, *best_v;
@@ -270,7 +271,8 @@ size_t hf_ttbar_reco_workspace_size(int64_t capacity);
  * (section 4): for each event d_idx[k] (global id, k < *d_count <= capacity),
  * every variation and every ordered pairing of two b candidates (the first
  * with l+, the second with l-), solve the two-neutrino system from the W and
- * top mass constraints (a quartic in the neutrino px), keep the solution
+ * top mass constraints (the common points of two conics in the neutrino's
+ * transverse momentum, up to four), keep the solution
  * with the highest score, and mark the event as passing the RECO cut when at
  * least one solution exists.  Updates d_counters[reco_cut] (reached += count,
  * passed += events with a solution).  Errors: HF_ERR_INVAL for null pointers,
@@ -298,8 +300,8 @@ int hf_ttbar_reco_autotune(const hf_events_t *ev, const int32_t *d_idx, const in
                            hipStream_t stream, double *h_ms);
 
 /* Instrumentation: from the next call on, hf_ttbar_reco records `start` just
- * before and `stop` just after its search kernel (the kernel that solves the
- * quartics), on the stream of the call, so that the caller can time that
+ * before and `stop` just after its search kernel (the kernel that intersects
+ * the conics), on the stream of the call, so that the caller can time that
  * kernel alone with hipEventElapsedTime.  Both NULL switches it off.  The
  * events are created and owned by the caller and must outlive the calls that
  * record them.  Process-wide setting; calls from several threads race.

@@ -75,6 +75,11 @@ __device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, double &z0, d
     z1 = r * s;
 }
 
+// Raw words of Philox block blk of event g, variation v.
+__device__ __forceinline__ U4 philox_block(uint64_t seed, uint64_t g, uint32_t v, uint32_t blk) {
+    return philox4x32_10(U4{(uint32_t)g, (uint32_t)(g >> 32), v, blk}, (uint32_t)seed, (uint32_t)(seed >> 32));
+}
+
 // Gaussian draws of one Philox block: slot 4*blk + j for j = 0..3.
 template <typename T>
 __device__ __forceinline__ void gauss_block(uint64_t seed, uint64_t g, uint32_t v, uint32_t blk, T z[4]) {

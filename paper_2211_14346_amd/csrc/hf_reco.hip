@@ -14,21 +14,21 @@
 // adds, per candidate and lepton side, the constants of the linear maps and
 // of the conic's quadratic part.  Lanes run over the variations, 64 at a
 // time.  Each lane draws its variation (Philox4x32-10 + Box-Muller in
-// precision T) and, for every pairing, assembles the eliminant quartic in
-// FP64 and brackets its real roots (critical points from the closed-form
-// cubic in T, one FP64 Newton step each); the wavefront then deals the root
-// intervals out 64 at a time: Halley iteration in FP64, recovery and polish
-// of (x, y), the acceptance test, the energies' signs and the score.  A wave
-// argmax with a total-order tie-break (score, then smallest variation,
-// pairing, x) gives the event's winner.  Instantiated for workgroups of one,
-// two and four wavefronts (a launch choice that leaves every result
-// unchanged; the autotuner times them).
+// precision T) and, for every pairing, intersects its two conics through
+// their pencil in FP64 (the degenerate member from the isolated root of the
+// pencil cubic, seeded in T; its line pair; each line against the l+ conic),
+// then checks each common point's residual (polishing the rare inaccurate
+// one), the acceptance bound, the energies' signs and the score.  A wave
+// maximum of the score, with a total-order tie-break (score, then smallest
+// variation, pairing, x) where lanes tie, gives the event's winner.
+// Instantiated for workgroups of one, two and four wavefronts (a launch
+// choice that leaves every result unchanged; the autotuner times them).
 //
 // k_epilogue: one thread per event; recomputes the winner's kinematics in
 // FP64 (draws recomputed bit-identically in T), writes the outputs, the
 // H -> bb candidate mass, and folds the RECO counters.
 //
-// T = float (HF_PREC_MIXED): draws and root seeds in FP32.
+// T = float (HF_PREC_MIXED): draws and the cubic's seed in FP32.
 // T = double (HF_PREC_FP64): everything in FP64.
 #include <math.h>
 
@@ -305,19 +305,16 @@ __global__ __launch_bounds__(NW * kWave, 2) void k_search_ev(const int64_t *__re
                                                                BestRec *__restrict__ best_out,
                                                                uint64_t *__restrict__ wstats) {
     __shared__ WaveStageEv<T> stage_all[NW];
-    __shared__ int queue_all[NW][4 * kWave];  // stage-2 queue: source lane | interval << 6
     const int lane = lane_id();
     const int wave = threadIdx.x / kWave;
     WaveStageEv<T> &st = stage_all[wave];
-    int *queue = queue_all[wave];
-    const uint64_t lt = lanemask_lt();
     const int64_t S = clamp_count(count, capacity);
     const double mt2_mw2 = a.m_t * a.m_t - a.m_w * a.m_w;
     const double mw2 = a.m_w * a.m_w;
     uint64_t acc_var = 0, acc_pair = 0, acc_int = 0, acc_sol = 0;
 
     // Events are handed out by counters, not dealt round robin: the cost of an
-    // event varies (root intervals, iterations), and with a static deal the
+    // event varies (pairings, variations, intersection points), and with a static deal the
     // waves' busy times spread by a sixth of the kernel.  Blocks of class c
     // (blockIdx mod ncls, which follows the round-robin placement of blocks on
     // the XCDs) take events c, c + ncls, c + 2 ncls, ... in the order of their
@@ -381,7 +378,10 @@ __global__ __launch_bounds__(NW * kWave, 2) void k_search_ev(const int64_t *__re
         const int npair_valid = __popc(okp) * __popc(okm) - __popc(okp & okm);
         if (npair_valid > 0) {
             const double metx = st.rec.met[0], mety = st.rec.met[1];
-            const uint64_t g = st.rec.g;
+            // the event's counter words are wave-uniform (scalar registers), so
+            // the generator's first rounds run on the scalar unit
+            const uint64_t g = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(st.rec.g >> 32)) << 32) |
+                               (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)st.rec.g);
             for (int vb = 0; vb < V; vb += kWave) {
                 const int v = vb + lane;
                 const bool act = v < V;
@@ -391,14 +391,36 @@ __global__ __launch_bounds__(NW * kWave, 2) void k_search_ev(const int64_t *__re
                     T zl[4] = {(T)0, (T)0, (T)0, (T)0};
                     if (a.smear && act) {
                         gauss_block<T>(a.seed, g, (uint32_t)v, 0u, zl);
-                        uint32_t last_blk = 0xffffffffu;
-                        T zb[4];
+                        // a candidate's slot 4 + j lies in Philox block (4 + j) / 4; each
+                        // block is generated once for consecutive candidates in it.  In
+                        // FP32 only the Box-Muller pairs that are used are formed; the
+                        // FP64 form takes whole blocks (its pairs need more registers than
+                        // the raw words held across the loop would leave)
+                        uint32_t last_blk = 0xffffffffu, have = 0;
+                        U4 raw{0u, 0u, 0u, 0u};
+                        T zb[4] = {(T)0, (T)0, (T)0, (T)0};
                         for (int c = 0; c < nc; ++c) {
-                            const uint32_t slot = 4u + (uint32_t)st.rec.jidx[c];
+                            const uint32_t slot = 4u + (uint32_t)__builtin_amdgcn_readfirstlane(st.rec.jidx[c]);
                             const uint32_t blk = slot >> 2;
-                            if (blk != last_blk) {
-                                gauss_block<T>(a.seed, g, (uint32_t)v, blk, zb);
-                                last_blk = blk;
+                            if constexpr (sizeof(T) == sizeof(float)) {
+                                if (blk != last_blk) {
+                                    raw = philox_block(a.seed, g, (uint32_t)v, blk);
+                                    last_blk = blk;
+                                    have = 0;
+                                }
+                                const uint32_t pr = (slot >> 1) & 1u;
+                                if (!((have >> pr) & 1u)) {
+                                    if (pr)
+                                        box_muller(raw.z, raw.w, zb[2], zb[3]);
+                                    else
+                                        box_muller(raw.x, raw.y, zb[0], zb[1]);
+                                    have |= 1u << pr;
+                                }
+                            } else {
+                                if (blk != last_blk) {
+                                    gauss_block<T>(a.seed, g, (uint32_t)v, blk, zb);
+                                    last_blk = blk;
+                                }
                             }
                             const uint32_t ln = slot & 3u;
                             st.z[c][lane] = ln == 0 ? zb[0] : ln == 1 ? zb[1] : ln == 2 ? zb[2] : zb[3];
@@ -418,154 +440,133 @@ __global__ __launch_bounds__(NW * kWave, 2) void k_search_ev(const int64_t *__re
                 const double my = mety + a.met_sigma * (double)st.zl[3][lane];
                 const double Wp = (0.5 * mw2) * fast_rcp(slp) - 0.5 * slp * st.rec.ml2p;
                 const double Wm = (0.5 * mw2) * fast_rcp(slm) - 0.5 * slm * st.rec.ml2m;
+                const double zz_l = (double)st.zl[0][lane] * st.zl[0][lane] + (double)st.zl[1][lane] * st.zl[1][lane] +
+                                    (double)st.zl[2][lane] * st.zl[2][lane] + (double)st.zl[3][lane] * st.zl[3][lane];
                 for (int i = 0; i < nc; ++i) {
                     if (!((okp >> i) & 1u)) continue;
                     const double si = smear(st.rec.sigma[i], st.z[i][lane]);
                     const SideVar A = side_var(st.sp[i], Wp, slp, si, mt2_mw2);
+                    const PencilP pa = pencil_p(A.q);
                     for (int j = 0; j < nc; ++j) {
                         if (j == i || !((okm >> j) & 1u)) continue;
-                        // ---- stage 1 (own variation): eliminant quartic and its root intervals
+                        // ---- the common points of this lane's two conics (its own variation)
                         const double sj = smear(st.rec.sigma[j], st.z[j][lane]);
                         const SideVar Bv = side_var(st.sm[j], Wm, slm, sj, mt2_mw2);
                         const Conic Q = reflect(Bv.q, mx, my);
-                        Brackets Bk;
-                        Bk.mask = 0;
-                        if (act) {
-                            double qc[5];
-                            eliminant(A.q, Q, qc);
-                            Bk = quartic_brackets<T>(qc);
-                        }
-                        // ---- stage 2: the wave's root intervals dealt out to lanes, 64 at a time
-                        const uint64_t m0 = ballot(Bk.mask & 1), m1 = ballot(Bk.mask & 2);
-                        const uint64_t m2 = ballot(Bk.mask & 4), m3 = ballot(Bk.mask & 8);
-                        const int n0 = popc64(m0), n1 = popc64(m1), n2 = popc64(m2), n3 = popc64(m3);
-                        const int total = n0 + n1 + n2 + n3;
-                        if (total == 0) continue;
+                        Points4 pts;
+                        pts.n = 0;
+                        if (act) pts = conic_intersections<T>(A.q, pa, Q);
+                        acc_int += 2 * (uint64_t)(popc64(ballot(pts.n > 0)) + popc64(ballot(pts.n > 2)));
                         const int p = i * nc + j;
-                        const int packed = Bk.mask | (Bk.direct << 4) | (Bk.signs << 5);
-                        // the queue: every interval 0 in lane order, then every interval 1, ...
-                        if (Bk.mask & 1) queue[popc64(m0 & lt)] = lane;
-                        if (Bk.mask & 2) queue[n0 + popc64(m1 & lt)] = lane | (1 << 6);
-                        if (Bk.mask & 4) queue[n0 + n1 + popc64(m2 & lt)] = lane | (2 << 6);
-                        if (Bk.mask & 8) queue[n0 + n1 + n2 + popc64(m3 & lt)] = lane | (3 << 6);
-                        wave_sync();
-                        for (int base = 0; base < total; base += kWave) {
-                            const int t = base + lane;
-                            const bool live = t < total;
-                            const int qe = live ? queue[t] : lane;
-                            const int src = qe & (kWave - 1), k = qe >> 6;
-                            // the source lane's intervals, as plain values (no aggregate whose
-                            // fields get selected by k, which would force it into scratch)
-                            const Poly4 fc{from_lane(Bk.c.c0, src), from_lane(Bk.c.c1, src),
-                                           from_lane(Bk.c.c2, src), from_lane(Bk.c.c3, src),
-                                           from_lane(Bk.c.c4, src)};
-                            const double fe1 = from_lane(Bk.e1, src), fe2 = from_lane(Bk.e2, src);
-                            const double fe3 = from_lane(Bk.e3, src), fbd = from_lane(Bk.bound, src);
-                            const double ff1 = from_lane(Bk.f1, src), ff2 = from_lane(Bk.f2, src);
-                            const double ff3 = from_lane(Bk.f3, src);
-                            const int fp = from_lane(packed, src);
-                            const Conic P{st.sp[i][kQxx], st.sp[i][kQxy], st.sp[i][kQyy], from_lane(A.q.x, src),
-                                          from_lane(A.q.y, src), from_lane(A.q.c, src)};
-                            const Conic Qs{Q.xx, Q.xy, Q.yy, from_lane(Q.x, src), from_lane(Q.y, src),
-                                           from_lane(Q.c, src)};
-                            const double ae0 = from_lane(A.e0, src), be0 = from_lane(Bv.e0, src);
-                            // accepted solutions are counted per pass with a ballot
+                        // score terms of this variation that do not depend on the point
+                        const double bxs = si * st.rec.cand[i][1] + slp * st.rec.lp[1];
+                        const double bys = si * st.rec.cand[i][2] + slp * st.rec.lp[2];
+                        const double bxb = sj * st.rec.cand[j][1] + slm * st.rec.lm[1];
+                        const double byb = sj * st.rec.cand[j][2] + slm * st.rec.lm[2];
+                        const double zzv = zz_l + (double)st.z[i][lane] * st.z[i][lane] +
+                                           (double)st.z[j][lane] * st.z[j][lane];
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) {
+                            // points come in pairs (one line, two roots): a wave with no lane
+                            // holding point k skips it
+                            const bool live = k < pts.n;
+                            if (!ballot(live)) break;
                             bool accepted = false;
-                            double x = 0.0, y = 0.0;
                             if (live) {
-                                if ((fp >> 4) & 1) {  // degree <= 2: the roots are given
-                                    x = kXScale * (k == 0 ? fe1 : fe2);
-                                } else {
-                                    const double f0 = (fp & 32) ? -1.0 : 1.0, f4 = (fp & 64) ? -1.0 : 1.0;
-                                    const double lo = k == 0 ? -fbd : k == 1 ? fe1 : k == 2 ? fe2 : fe3;
-                                    const double hi = k == 0 ? fe1 : k == 1 ? fe2 : k == 2 ? fe3 : fbd;
-                                    const double flo = k == 0 ? f0 : k == 1 ? ff1 : k == 2 ? ff2 : ff3;
-                                    const double fhi = k == 0 ? ff1 : k == 1 ? ff2 : k == 2 ? ff3 : f4;
-                                    bool found;
-                                    solve_interval(fc, lo, hi, flo, fhi, k > 0 && lo < fbd, k < 3 && hi < fbd, x,
-                                                   found);
-                                }
-                                accepted = recover_y(P, Qs, x, y) &&
-                                           polish_xy(P, Qs, x, y, 4, a.polish_skip_m2) <= a.accept_m2;
-                            }
-                            if (accepted) {
-                                // the source variation's smear factors and MET, rebuilt from its draws
-                                const T zli0 = st.zl[0][src], zli1 = st.zl[1][src];
-                                const T zi = st.z[i][src], zj = st.z[j][src];
-                                const double rslp = smear(a.lep_sigma, zli0), rslm = smear(a.lep_sigma, zli1);
-                                const double rsi = smear(st.rec.sigma[i], zi), rsj = smear(st.rec.sigma[j], zj);
-                                const double rmx = metx + a.met_sigma * (double)st.zl[2][src];
-                                const double rmy = mety + a.met_sigma * (double)st.zl[3][src];
-                                const double en = st.sp[i][kE1] * x + st.sp[i][kE2] * y + ae0;
-                                const double xb = rmx - x, yb = rmy - y;
-                                const double eb = st.sm[j][kE1] * xb + st.sm[j][kE2] * yb + be0;
-                                accepted = en >= 0.0 && eb >= 0.0;
-                                if (accepted) {
-                                    // top pT components
-                                    const double tx = rsi * st.rec.cand[i][1] + rslp * st.rec.lp[1] + x;
-                                    const double ty = rsi * st.rec.cand[i][2] + rslp * st.rec.lp[2] + y;
-                                    const double tbx = rsj * st.rec.cand[j][1] + rslm * st.rec.lm[1] + xb;
-                                    const double tby = rsj * st.rec.cand[j][2] + rslm * st.rec.lm[2] + yb;
-                                    const double zz = (double)zli0 * zli0 + (double)zli1 * zli1 +
-                                                      (double)st.zl[2][src] * st.zl[2][src] +
-                                                      (double)st.zl[3][src] * st.zl[3][src] + (double)zi * zi +
-                                                      (double)zj * zj;
-                                    const double w =
-                                        -0.5 * zz -
-                                        (fast_sqrt(tx * tx + ty * ty) + fast_sqrt(tbx * tbx + tby * tby)) * a.inv_lambda;
-                                    const int vs = vb + src;
-                                    if (better(w, vs, p, x, best_s, best_v, best_p, best_x)) {
-                                        best_s = w;
-                                        best_v = vs;
-                                        best_p = p;
-                                        best_x = x;
-                                        best_y = y;
+                                double x = k == 0 ? pts.x0 : k == 1 ? pts.x1 : k == 2 ? pts.x2 : pts.x3;
+                                double y = k == 0 ? pts.y0 : k == 1 ? pts.y1 : k == 2 ? pts.y2 : pts.y3;
+                                if (polish_xy(A.q, Q, x, y, 4, a.polish_skip_m2) <= a.accept_m2) {
+                                    const double en = st.sp[i][kE1] * x + st.sp[i][kE2] * y + A.e0;
+                                    const double xb = mx - x, yb = my - y;
+                                    const double eb = st.sm[j][kE1] * xb + st.sm[j][kE2] * yb + Bv.e0;
+                                    accepted = en >= 0.0 && eb >= 0.0;
+                                    if (accepted) {
+                                        const double tx = bxs + x, ty = bys + y, tbx = bxb + xb, tby = byb + yb;
+                                        const double w = -0.5 * zzv - (fast_sqrt(tx * tx + ty * ty) +
+                                                                       fast_sqrt(tbx * tbx + tby * tby)) *
+                                                                          a.inv_lambda;
+                                        if (better(w, v, p, x, best_s, best_v, best_p, best_x)) {
+                                            best_s = w;
+                                            best_v = v;
+                                            best_p = p;
+                                            best_x = x;
+                                            best_y = y;
+                                        }
                                     }
                                 }
                             }
                             nsol += popc64(ballot(accepted));
                         }
-                        wave_sync();  // the next pairing rewrites the queue
-                        acc_int += (uint64_t)total;
                     }
                 }
                 wave_sync();
             }
         }
         // --------------------------------------------------- wave argmax
-        // better() is a total order, so any pairing of lanes that reaches all
-        // of them gives every lane the maximum: four in-row DPP steps (pairs,
-        // quads, eights, rows), then across rows by shuffles
-        auto take = [&](double os, int ov, int op, double ox, double oy) {
-            if (better(os, ov, op, ox, best_s, best_v, best_p, best_x)) {
-                best_s = os;
-                best_v = ov;
-                best_p = op;
-                best_x = ox;
-                best_y = oy;
+        // The wave's top score first (a max over four in-row DPP steps --
+        // pairs, quads, eights, rows -- then across rows by shuffles); the
+        // lanes holding it are found by a ballot.  One such lane (the usual
+        // case) is the winner.  Among several (equal scores), better() -- a
+        // total order -- settles it by the same exchange pattern, with every
+        // other lane set below all of them.
+        double top = best_s;
+        top = fmax(top, dpp_f64<0xB1>(top));
+        top = fmax(top, dpp_f64<0x4E>(top));
+        top = fmax(top, dpp_f64<0x141>(top));
+        top = fmax(top, dpp_f64<0x140>(top));
+        top = fmax(top, __shfl_xor(top, 16));
+        top = fmax(top, __shfl_xor(top, 32));
+        const uint64_t at_top = ballot(best_v != kNoBest && best_s == top);
+        double win_s = -INFINITY, win_x = 0.0, win_y = 0.0;
+        int win_v = kNoBest, win_p = kNoBest;
+        if (at_top != 0) {
+            if ((at_top & (at_top - 1)) != 0) {
+                if (!((at_top >> lane) & 1ull)) {
+                    best_s = -INFINITY;
+                    best_v = kNoBest;
+                    best_p = kNoBest;
+                    best_x = 0.0;
+                    best_y = 0.0;
+                }
+                auto take = [&](double os, int ov, int op, double ox, double oy) {
+                    if (better(os, ov, op, ox, best_s, best_v, best_p, best_x)) {
+                        best_s = os;
+                        best_v = ov;
+                        best_p = op;
+                        best_x = ox;
+                        best_y = oy;
+                    }
+                };
+                take(dpp_f64<0xB1>(best_s), dpp_i32<0xB1>(best_v), dpp_i32<0xB1>(best_p), dpp_f64<0xB1>(best_x),
+                     dpp_f64<0xB1>(best_y));
+                take(dpp_f64<0x4E>(best_s), dpp_i32<0x4E>(best_v), dpp_i32<0x4E>(best_p), dpp_f64<0x4E>(best_x),
+                     dpp_f64<0x4E>(best_y));
+                take(dpp_f64<0x141>(best_s), dpp_i32<0x141>(best_v), dpp_i32<0x141>(best_p), dpp_f64<0x141>(best_x),
+                     dpp_f64<0x141>(best_y));
+                take(dpp_f64<0x140>(best_s), dpp_i32<0x140>(best_v), dpp_i32<0x140>(best_p), dpp_f64<0x140>(best_x),
+                     dpp_f64<0x140>(best_y));
+                for (int off = 16; off < kWave; off <<= 1)
+                    take(__shfl_xor(best_s, off), __shfl_xor(best_v, off), __shfl_xor(best_p, off),
+                         __shfl_xor(best_x, off), __shfl_xor(best_y, off));
             }
-        };
-        take(dpp_f64<0xB1>(best_s), dpp_i32<0xB1>(best_v), dpp_i32<0xB1>(best_p), dpp_f64<0xB1>(best_x),
-             dpp_f64<0xB1>(best_y));
-        take(dpp_f64<0x4E>(best_s), dpp_i32<0x4E>(best_v), dpp_i32<0x4E>(best_p), dpp_f64<0x4E>(best_x),
-             dpp_f64<0x4E>(best_y));
-        take(dpp_f64<0x141>(best_s), dpp_i32<0x141>(best_v), dpp_i32<0x141>(best_p), dpp_f64<0x141>(best_x),
-             dpp_f64<0x141>(best_y));
-        take(dpp_f64<0x140>(best_s), dpp_i32<0x140>(best_v), dpp_i32<0x140>(best_p), dpp_f64<0x140>(best_x),
-             dpp_f64<0x140>(best_y));
-        for (int off = 16; off < kWave; off <<= 1)
-            take(__shfl_xor(best_s, off), __shfl_xor(best_v, off), __shfl_xor(best_p, off), __shfl_xor(best_x, off),
-                 __shfl_xor(best_y, off));
+            // the winner's record (after the tie-break every lane holds it)
+            const int wl = (int)__builtin_ctzll(at_top);
+            win_s = __shfl(best_s, wl);
+            win_v = __shfl(best_v, wl);
+            win_p = __shfl(best_p, wl);
+            win_x = __shfl(best_x, wl);
+            win_y = __shfl(best_y, wl);
+        }
         acc_var += (uint64_t)V;
         acc_pair += (uint64_t)V * (uint64_t)npair_valid;
         acc_sol += (uint64_t)nsol;
         if (lane == 0) {
             BestRec r;
-            r.score = best_s;
-            r.x = best_x;
-            r.y = best_y;
-            r.v = best_v;
-            r.p = best_p;
+            r.score = win_s;
+            r.x = win_x;
+            r.y = win_y;
+            r.v = win_v;
+            r.p = win_p;
             r.nsol = nsol;
             r.nc = nc;
             best_out[k] = r;

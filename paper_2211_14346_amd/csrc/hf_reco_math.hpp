@@ -15,7 +15,7 @@
 // with U = kb'/s_b = (mt^2 - mW^2)/(2 s_b) - s_b mb^2/2 - s_l b.l and
 // W = kl'/s_l = mW^2/(2 s_l) - s_l ml^2/2 move.  The per-candidate constants
 // are therefore staged once per event and each variation costs a handful of
-// FMAs before the quartic assembly.
+// FMAs before the two conics are intersected.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -71,6 +71,18 @@ HF_HD __forceinline__ double fast_sqrt(double v) {
     return fma(d, h, s);
 #else
     return sqrt(v);
+#endif
+}
+
+// 1/sqrt(v) for v > 0 to about 2^-46 relative: the hardware estimate and one
+// Newton refinement.
+HF_HD __forceinline__ double step_rsqrt(double v) {
+#ifdef __HIP_DEVICE_COMPILE__
+    const double y = __builtin_amdgcn_rsq(v);
+    const double h = 0.5 * v * y;
+    return y * fma(-h, y, 1.5);
+#else
+    return 1.0 / sqrt(v);
 #endif
 }
 
@@ -156,66 +168,19 @@ HF_HD __forceinline__ Conic reflect(const Conic &q, double mx, double my) {
     return r;
 }
 
-// Eliminant in y of the two conics, written as P(y) = a y^2 + b(x) y + c(x)
-// and Q(y) = d y^2 + e(x) y + f(x): Res = (a f - c d)^2 - (a e - b d)(b f - c e),
-// a quartic in x.  Coefficients ascending in x.
-HF_HD __forceinline__ void eliminant(const Conic &P, const Conic &Q, double q[5]) {
-    const double a = P.yy, b1 = P.xy, b0 = P.y, c2 = P.xx, c1 = P.x, c0 = P.c;
-    const double d = Q.yy, e1 = Q.xy, e0 = Q.y, f2 = Q.xx, f1 = Q.x, f0 = Q.c;
-    const double g2 = a * f2 - d * c2, g1 = a * f1 - d * c1, g0 = a * f0 - d * c0;
-    const double h1 = a * e1 - d * b1, h0 = a * e0 - d * b0;
-    const double k3 = b1 * f2 - c2 * e1;
-    const double k2 = b1 * f1 + b0 * f2 - c2 * e0 - c1 * e1;
-    const double k1 = b1 * f0 + b0 * f1 - c1 * e0 - c0 * e1;
-    const double k0 = b0 * f0 - c0 * e0;
-    q[4] = g2 * g2 - h1 * k3;
-    q[3] = 2.0 * g2 * g1 - h1 * k2 - h0 * k3;
-    q[2] = g1 * g1 + 2.0 * g2 * g0 - h1 * k1 - h0 * k2;
-    q[1] = 2.0 * g1 * g0 - h1 * k0 - h0 * k1;
-    q[0] = g0 * g0 - h0 * k0;
-}
-
-// ------------------------------------------------------------------ roots
-// Real roots of the quartic by critical points: the critical points (roots
-// of the derivative) come from the closed-form cubic in precision T and are
-// polished once in FP64; every monotone interval whose end values differ in
-// sign is then solved by Halley's method in FP64, safeguarded by bisection.
-// Like the oracle, the polynomial is taken in t = x / 100 GeV, normalised by
-// its largest coefficient, and coefficients <= 1e-14 are dropped from the top.
-
-constexpr double kXScale = 100.0;
-
-// Quartic and its first two derivatives with all five coefficients (dropped
-// leading coefficients are zero), so that no register array is indexed at
-// run time.
-struct Poly4 {
-    double c0, c1, c2, c3, c4;
-};
-
-HF_HD __forceinline__ double peval(const Poly4 &c, double t) {
-    return fma(fma(fma(fma(c.c4, t, c.c3), t, c.c2), t, c.c1), t, c.c0);
-}
-
-HF_HD __forceinline__ void peval_d(const Poly4 &c, double t, double &p, double &dp) {
-    p = peval(c, t);
-    dp = fma(fma(fma(4.0 * c.c4, t, 3.0 * c.c3), t, 2.0 * c.c2), t, c.c1);
-}
-
-HF_HD __forceinline__ double peval_d1(const Poly4 &c, double t) {
-    return fma(fma(fma(4.0 * c.c4, t, 3.0 * c.c3), t, 2.0 * c.c2), t, c.c1);
-}
-
-HF_HD __forceinline__ double peval_d2(const Poly4 &c, double t) {
-    return fma(fma(12.0 * c.c4, t, 6.0 * c.c3), t, 2.0 * c.c2);
-}
+// ------------------------------------------------------------ cubic
+// The isolated real root of a monic cubic in closed form (Cardano for one
+// real root, the trigonometric form for three), in precision T.  The pencil
+// cubic of the intersection below takes its seed from here and refines it
+// in FP64.
 
 // Elementary functions for the templated cubic.  FP64: the accurate library
 // functions.  FP32 (seeds only, refined in FP64 afterwards): hardware
 // approximations -- square root and reciprocal by the single-instruction
 // units (about one ulp, no correction sequence), cube root through the base-2
 // exponential and logarithm units, arc cosine by the four-term approximation
-// of Abramowitz & Stegun 4.4.45 (|error| < 7e-5 rad), cosine/sine through the
-// revolution-scaled hardware units.
+// of Abramowitz & Stegun 4.4.45 (|error| < 7e-5 rad), cosine through the
+// revolution-scaled hardware unit.
 HF_HD __forceinline__ float tsqrt(float v) {
 #ifdef __HIP_DEVICE_COMPILE__
     return __builtin_amdgcn_sqrtf(v);
@@ -244,21 +209,15 @@ HF_HD __forceinline__ float tcbrt(float v) {
 HF_HD __forceinline__ double tacos(double v) { return acos(v); }
 HF_HD __forceinline__ float tacos(float x) {
     const float ax = fabsf(x);
-    const float r = sqrtf(1.0f - ax) * (1.5707288f + ax * (-0.2121144f + ax * (0.0742610f - 0.0187293f * ax)));
+    const float r = tsqrt(1.0f - ax) * (1.5707288f + ax * (-0.2121144f + ax * (0.0742610f - 0.0187293f * ax)));
     return x < 0.0f ? 3.14159265358979f - r : r;
 }
-HF_HD __forceinline__ void tsincos(double a, double &s, double &c) {
-    s = sin(a);
-    c = cos(a);
-}
-HF_HD __forceinline__ void tsincos(float a, float &s, float &c) {
+HF_HD __forceinline__ double tcos(double a) { return cos(a); }
+HF_HD __forceinline__ float tcos(float a) {
 #ifdef __HIP_DEVICE_COMPILE__
-    const float rev = a * 0.15915494309189535f;  // radians -> revolutions
-    s = __builtin_amdgcn_sinf(rev);
-    c = __builtin_amdgcn_cosf(rev);
+    return __builtin_amdgcn_cosf(a * 0.15915494309189535f);  // radians -> revolutions
 #else
-    s = sinf(a);
-    c = cosf(a);
+    return cosf(a);
 #endif
 }
 HF_HD __forceinline__ float tmin(float a, float b) { return fminf(a, b); }
@@ -266,359 +225,35 @@ HF_HD __forceinline__ double tmin(double a, double b) { return fmin(a, b); }
 HF_HD __forceinline__ float tmax(float a, float b) { return fmaxf(a, b); }
 HF_HD __forceinline__ double tmax(double a, double b) { return fmax(a, b); }
 
-// Real roots (ascending) of the monic cubic s^3 + A s^2 + B s + C in
-// precision T; returns 1 or 3.
+// The real root of s^3 + A s^2 + B s + C farthest from the others, in
+// precision T: the only real root when there is one; of three, the end root
+// on the side of the larger gap.  In the depressed form u^3 + p u + q (roots
+// summing to zero) that is the root of largest magnitude, whose sign is that
+// of -q: Cardano's real root, or 2 r cos(acos(|c|) / 3) with the sign of c
+// for three roots, r = sqrt(-p / 3), c = -q / (2 r^3).
 template <typename T>
-HF_HD __forceinline__ int cubic_roots(T A, T B, T C, T &r0, T &r1, T &r2) {
+HF_HD __forceinline__ T cubic_isolated_root(T A, T B, T C) {
     const T third = (T)(1.0 / 3.0);
     const T a3 = A * third;
-    const T p = B - A * a3;  // depressed: u^3 + p u + q
+    const T p = B - A * a3;
     const T q = (T)2 * a3 * a3 * a3 - a3 * B + C;
     const T h = (T)0.5 * q;
     const T p3 = p * third;
     const T disc = h * h + p3 * p3 * p3;
+    T u;
     if (disc > (T)0) {
         const T sq = tsqrt(disc);
         const T w = -h - (h >= (T)0 ? sq : -sq);
-        const T u = tcbrt(w);
-        const T r = (u != (T)0) ? u - p3 * trcp(u) : (T)0;
-        r0 = r1 = r2 = r - a3;
-        return 1;
-    }
-    const T rr = tsqrt(tmax(-p3, (T)0));
-    T cosarg = (rr > (T)0) ? -h * trcp(rr * rr * rr) : (T)0;
-    cosarg = tmin(tmax(cosarg, (T)-1), (T)1);
-    const T phi = tacos(cosarg) * third;
-    T sn, cs;
-    tsincos(phi, sn, cs);
-    // cos(phi -+ 2 pi / 3) = -cos(phi) / 2 +- sin(phi) sqrt(3) / 2
-    const T h3 = (T)0.86602540378443865 * sn;
-    const T x0 = (T)2 * rr * cs - a3;                        // largest
-    const T x1 = (T)2 * rr * ((T)-0.5 * cs + h3) - a3;       // middle
-    const T x2 = (T)2 * rr * ((T)-0.5 * cs - h3) - a3;       // smallest
-    r0 = tmin(tmin(x0, x1), x2);
-    r2 = tmax(tmax(x0, x1), x2);
-    r1 = x0 + x1 + x2 - r0 - r2;
-    return 3;
-}
-
-// Root of c on (lo, hi) where c(lo) < 0 iff lo_neg; x is the first iterate.
-// Halley's step  dx = p p' / (p'^2 - p p'' / 2)  (cubic convergence, so a
-// wavefront's slowest lane needs fewer iterations), taken as the Newton step
-// p / p' wherever Halley's correction factor p'^2 / (p'^2 - p p'' / 2) leaves
-// (1/2, 2), i.e. far from the root; steps that leave the bracket are replaced
-// by bisection.  Converged when the step is below 1e-12 max(1, |t|) (t = x /
-// 100 GeV), or below 1e-7 max(1, |t|) and 1e-3 of the previous step (the
-// error after that step is far below its size).  The test comes before the
-// bracket update so that an iterate sitting on a bracket end at convergence
-// is not bisected away.  A root next to a critical point (a near double root)
-// is fixed only to the polynomial's rounding, where the step tests can fail
-// forever: from the sixth iterate on, the search also stops when |p| is at
-// its rounding floor (1e-15 of the sum of its terms' magnitudes) or the
-// bracket is narrower than the tolerance.
-HF_HD __forceinline__ double bracket_halley(const Poly4 &c, double lo, double hi, bool lo_neg, double x) {
-    double dx_prev = 0.0;
-    for (int it = 0; it < 60; ++it) {
-        HF_ITER_HOOK();
-        double p, dp;
-        peval_d(c, x, p, dp);
-        if (p == 0.0) return x;
-        if ((p < 0.0) == lo_neg)
-            lo = x;
-        else
-            hi = x;
-        const double d2 = peval_d2(c, x);
-        const double g = dp * dp;
-        const double hd = fma(-0.5 * p, d2, g);
-        const double den = (hd > 0.5 * g && hd < 2.0 * g) ? hd : g;
-        const double dx = p * dp * step_rcp(den);
-        const double tol = 1e-12 * fmax(1.0, fabs(x));
-        if (fabs(dx) <= tol) return x - dx;
-        if (it >= 1 && fabs(dx) <= 1e5 * tol && fabs(dx) <= 1e-3 * fabs(dx_prev)) return x - dx;
-        if (it >= 5) {
-            // slow convergence (a root next to a critical point): stop once p is
-            // at its rounding floor or the bracket is below the tolerance
-            const double ax = fabs(x);
-            const double mag =
-                (((fabs(c.c4) * ax + fabs(c.c3)) * ax + fabs(c.c2)) * ax + fabs(c.c1)) * ax + fabs(c.c0);
-            if (fabs(p) <= 1e-15 * mag || hi - lo <= tol) return x;
-        }
-        double xn = x - dx;
-        if (!(xn > lo && xn < hi)) xn = 0.5 * (lo + hi);
-        dx_prev = dx;
-        x = xn;
-    }
-    return x;
-}
-
-// Root of the interval [lo, hi] (values flo, fhi of opposite signs), in x
-// units.  First iterate: the quadratic model p(e + d) ~ p(e) + p''(e) d^2 / 2
-// at a critical end e -- for an interval between two critical points, at the
-// end where |p| is smaller (the root lies nearer to it), with the secant as
-// the fallback.
-HF_HD __forceinline__ void solve_interval(const Poly4 &c, double lo, double hi, double flo, double fhi, bool lo_crit,
-                                          bool hi_crit, double &root, bool &found) {
-    found = false;
-    if (!((flo < 0.0 && fhi > 0.0) || (flo > 0.0 && fhi < 0.0)) || !(hi > lo)) return;
-    double x0;
-    if (lo_crit || hi_crit) {
-        const bool from_lo = lo_crit && (!hi_crit || fabs(flo) <= fabs(fhi));
-        const double cp = from_lo ? lo : hi;
-        const double fv = from_lo ? flo : fhi;
-        const double r = -2.0 * fv * step_rcp(peval_d2(c, cp));
-        if (r > 0.0)
-            x0 = from_lo ? cp + fast_sqrt(r) : cp - fast_sqrt(r);
-        else
-            x0 = (lo_crit && hi_crit) ? lo : from_lo ? cp + fmax(1.0, fabs(cp)) : cp - fmax(1.0, fabs(cp));
-        if (lo_crit && hi_crit && !(x0 > lo && x0 < hi)) x0 = lo - flo * (hi - lo) * step_rcp(fhi - flo);
+        const T cu = tcbrt(w);
+        u = (cu != (T)0) ? cu - p3 * trcp(cu) : (T)0;
     } else {
-        x0 = 0.0;
+        const T rr = tsqrt(tmax(-p3, (T)0));
+        T c = (rr > (T)0) ? -h * trcp(rr * rr * rr) : (T)0;
+        c = tmin(tmax(c, (T)-1), (T)1);
+        const T m = (T)2 * rr * tcos(tacos(c >= (T)0 ? c : -c) * third);
+        u = c >= (T)0 ? m : -m;
     }
-    if (!(x0 > lo && x0 < hi)) x0 = 0.5 * (lo + hi);
-    root = kXScale * bracket_halley(c, lo, hi, flo < 0.0, x0);
-    found = true;
-}
-
-// Sign-changing real roots of q0 + q1 x + ... + q4 x^4 by critical points:
-// the roots of the derivative (closed-form cubic in precision T, one FP64
-// Newton step each) split the line into monotone intervals; each interval
-// whose end values differ in sign holds one root, found by safeguarded
-// Halley iteration in FP64.  As in the oracle, the polynomial is taken in t = x / 100 GeV,
-// normalised by its largest coefficient, and leading coefficients <= 1e-14
-// are dropped; the outer intervals end at the Cauchy bound.
-//
-// quartic_brackets does everything up to the intervals; bracket_root solves
-// one interval.  The search kernel runs the two on different lanes.
-struct Brackets {
-    Poly4 c;             // normalised polynomial in t
-    double e1, e2, e3;   // inner interval ends (critical points); direct roots for degree <= 2
-    double bound;        // intervals are [-bound, e1], [e1, e2], [e2, e3], [e3, bound]
-    double f1, f2, f3;   // polynomial values at e1, e2, e3
-    int mask;            // bit k: interval k holds a root (or: direct root k exists)
-    int direct;          // 1: degree <= 2, roots given directly in e1, e2
-    int signs;           // bit 0: p(-bound) < 0; bit 1: p(+bound) < 0
-};
-
-template <typename T>
-HF_HD __forceinline__ Brackets quartic_brackets(const double qx[5]) {
-    Brackets B;
-    B.mask = 0;
-    B.direct = 0;
-    B.signs = 0;
-    B.e1 = B.e2 = B.e3 = B.f1 = B.f2 = B.f3 = 0.0;
-    B.bound = 1.0;
-    Poly4 &c = B.c;
-    c = Poly4{qx[0], qx[1] * kXScale, qx[2] * (kXScale * kXScale), qx[3] * (kXScale * kXScale * kXScale),
-              qx[4] * (kXScale * kXScale * kXScale * kXScale)};
-    const double mx = fmax(fmax(fmax(fabs(c.c0), fabs(c.c1)), fmax(fabs(c.c2), fabs(c.c3))), fabs(c.c4));
-    if (!(mx > 0.0) || !isfinite(mx)) return B;
-    const double inv = fast_rcp(mx);
-    c.c0 *= inv;
-    c.c1 *= inv;
-    c.c2 *= inv;
-    c.c3 *= inv;
-    c.c4 *= inv;
-    int n = 4;
-    if (fabs(c.c4) <= 1e-14) {
-        c.c4 = 0.0;
-        n = 3;
-        if (fabs(c.c3) <= 1e-14) {
-            c.c3 = 0.0;
-            n = 2;
-            if (fabs(c.c2) <= 1e-14) {
-                c.c2 = 0.0;
-                n = 1;
-                if (fabs(c.c1) <= 1e-14) return B;
-            }
-        }
-    }
-    if (n <= 2) {
-        B.direct = 1;
-        if (n == 1) {
-            B.e1 = -c.c0 / c.c1;
-            B.mask = 1;
-        } else {
-            const double disc = c.c1 * c.c1 - 4.0 * c.c2 * c.c0;
-            if (disc > 0.0) {
-                const double sq = sqrt(disc);
-                const double t = -0.5 * (c.c1 + (c.c1 >= 0.0 ? sq : -sq));
-                const double a = t / c.c2, b = c.c0 / t;
-                B.e1 = fmin(a, b);
-                B.e2 = fmax(a, b);
-                B.mask = 3;
-            }
-        }
-        return B;
-    }
-    const double lead = n == 4 ? c.c4 : c.c3;
-    const double il = fast_rcp(lead);
-    double bound = fmax(fmax(fabs(c.c0 * il), fabs(c.c1 * il)), fabs(c.c2 * il));
-    if (n == 4) bound = fmax(bound, fabs(c.c3 * il));
-    bound += 1.0;
-    // critical points k0 <= k1 <= k2 (nk of them)
-    double k0 = 0.0, k1 = 0.0, k2 = 0.0;
-    int nk = 0;
-    if (n == 4) {
-        const double A = 0.75 * c.c3 * il, Bc = 0.5 * c.c2 * il, C = 0.25 * c.c1 * il;
-        if (fmax(fabs(A), fmax(fabs(Bc), fabs(C))) < 1e6) {
-            T a0, a1, a2;
-            nk = cubic_roots<T>((T)A, (T)Bc, (T)C, a0, a1, a2);
-            k0 = (double)a0;
-            k1 = (double)a1;
-            k2 = (double)a2;
-        } else {
-            nk = cubic_roots<double>(A, Bc, C, k0, k1, k2);
-        }
-    } else {  // n == 3: derivative 3 c3 t^2 + 2 c2 t + c1
-        const double a = 3.0 * c.c3, b = 2.0 * c.c2, cc = c.c1;
-        const double disc = b * b - 4.0 * a * cc;
-        if (disc > 0.0) {
-            const double sq = sqrt(disc);
-            const double t = -0.5 * (b + (b >= 0.0 ? sq : -sq));
-            const double r1 = t / a, r2 = cc / t;
-            k0 = fmin(r1, r2);
-            k1 = fmax(r1, r2);
-            nk = 2;
-        }
-    }
-    // one FP64 Newton step on the derivative for each critical point
-    {
-        double g, gp;
-        g = peval_d1(c, k0);
-        gp = peval_d2(c, k0);
-        if (gp != 0.0) k0 -= g * step_rcp(gp);
-        g = peval_d1(c, k1);
-        gp = peval_d2(c, k1);
-        if (gp != 0.0) k1 -= g * step_rcp(gp);
-        g = peval_d1(c, k2);
-        gp = peval_d2(c, k2);
-        if (gp != 0.0) k2 -= g * step_rcp(gp);
-    }
-    // interval ends -B, k0, k1, k2, B; missing or out-of-range critical points
-    // collapse onto +B, which empties their intervals
-    const bool pos_hi = lead > 0.0;
-    const bool neg_lo = (n & 1) ? pos_hi : !pos_hi;  // p(-B) < 0
-    const bool u0 = nk >= 1 && k0 > -bound && k0 < bound;
-    const bool u1 = nk >= 2 && k1 > -bound && k1 < bound;
-    const bool u2 = nk >= 3 && k2 > -bound && k2 < bound;
-    double e1 = u0 ? k0 : bound, e2 = u1 ? k1 : bound, e3 = u2 ? k2 : bound;
-    if (e2 < e1) { const double t = e1; e1 = e2; e2 = t; }
-    if (e3 < e2) { const double t = e2; e2 = e3; e3 = t; }
-    if (e2 < e1) { const double t = e1; e1 = e2; e2 = t; }
-    const double sb = pos_hi ? 1.0 : -1.0;
-    const double f0 = neg_lo ? -1.0 : 1.0;
-    const double f1 = e1 < bound ? peval(c, e1) : sb;
-    const double f2 = e2 < bound ? peval(c, e2) : sb;
-    const double f3 = e3 < bound ? peval(c, e3) : sb;
-    B.e1 = e1;
-    B.e2 = e2;
-    B.e3 = e3;
-    B.bound = bound;
-    B.f1 = f1;
-    B.f2 = f2;
-    B.f3 = f3;
-    B.signs = (neg_lo ? 1 : 0) | (pos_hi ? 0 : 2);
-    auto change = [](double a, double b, double lo, double hi) {
-        return ((a < 0.0 && b > 0.0) || (a > 0.0 && b < 0.0)) && hi > lo;
-    };
-    B.mask = (change(f0, f1, -bound, e1) ? 1 : 0) | (change(f1, f2, e1, e2) ? 2 : 0) |
-             (change(f2, f3, e2, e3) ? 4 : 0) | (change(f3, sb, e3, bound) ? 8 : 0);
-    return B;
-}
-
-// Root (in t units) in interval k of a Brackets record, or direct root k.
-HF_HD __forceinline__ double bracket_root(const Brackets &B, int k) {
-    if (B.direct) return k == 0 ? B.e1 : B.e2;
-    const double lo = k == 0 ? -B.bound : k == 1 ? B.e1 : k == 2 ? B.e2 : B.e3;
-    const double hi = k == 0 ? B.e1 : k == 1 ? B.e2 : k == 2 ? B.e3 : B.bound;
-    const double f0 = (B.signs & 1) ? -1.0 : 1.0, f4 = (B.signs & 2) ? -1.0 : 1.0;
-    const double flo = k == 0 ? f0 : k == 1 ? B.f1 : k == 2 ? B.f2 : B.f3;
-    const double fhi = k == 0 ? B.f1 : k == 1 ? B.f2 : k == 2 ? B.f3 : f4;
-    const bool lo_crit = k > 0 && lo < B.bound;
-    const bool hi_crit = k < 3 && hi < B.bound;
-    double root = 0.0;
-    bool found;
-    solve_interval(B.c, lo, hi, flo, fhi, lo_crit, hi_crit, root, found);
-    return root * (1.0 / kXScale);  // solve_interval returns x units
-}
-
-// Sign-changing real roots (in x units), ascending in slots 0 .. popcount(mask) - 1.
-struct Roots4 {
-    double r[4];
-    int mask;
-};
-
-HF_HD __forceinline__ double pick4(const double r[4], int k) {
-    return k == 0 ? r[0] : k == 1 ? r[1] : k == 2 ? r[2] : r[3];
-}
-
-template <typename T>
-HF_HD Roots4 quartic_real_roots(const double qx[5]) {
-    const Brackets B = quartic_brackets<T>(qx);
-    Roots4 out;
-    out.r[0] = out.r[1] = out.r[2] = out.r[3] = 0.0;
-    int nb = 0;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        if (!((B.mask >> k) & 1)) continue;
-        const double x = kXScale * bracket_root(B, k);
-        out.r[0] = nb == 0 ? x : out.r[0];
-        out.r[1] = nb == 1 ? x : out.r[1];
-        out.r[2] = nb == 2 ? x : out.r[2];
-        out.r[3] = nb == 3 ? x : out.r[3];
-        ++nb;
-    }
-    out.mask = (1 << nb) - 1;
-    return out;
-}
-
-// y of an intersection at abscissa x.  The elimination a Q - d P is linear
-// in y; when its coefficient is not small against its terms that gives y
-// directly.  Otherwise (two intersections sharing nearly the same x) the
-// candidates are the elimination and the real roots of P and of Q in y, and
-// the one with the smallest sum of relative residuals wins.  Returns false
-// if there is no candidate.
-HF_HD __forceinline__ bool recover_y(const Conic &P, const Conic &Q, double x, double &y) {
-    const double a = P.yy, bx = fma(P.xy, x, P.y), cx = fma(fma(P.xx, x, P.x), x, P.c);
-    const double d = Q.yy, ex = fma(Q.xy, x, Q.y), fx = fma(fma(Q.xx, x, Q.x), x, Q.c);
-    const double den = bx * d - a * ex;
-    if (fabs(den) > 1e-3 * (fabs(bx * d) + fabs(a * ex))) {
-        y = (a * fx - cx * d) * fast_rcp(den);
-        return true;
-    }
-    // slow path: five fixed candidate slots with validity flags
-    double best = INFINITY;
-    bool any = false;
-    auto consider = [&](double yy) {
-        const double rp = fabs(fma(fma(a, yy, bx), yy, cx)) * fast_rcp(fabs(a) * yy * yy + fabs(bx * yy) + fabs(cx));
-        const double rq = fabs(fma(fma(d, yy, ex), yy, fx)) * fast_rcp(fabs(d) * yy * yy + fabs(ex * yy) + fabs(fx));
-        const double r = rp + rq;
-        if (!any || r < best) {
-            best = r;
-            y = yy;
-            any = true;
-        }
-    };
-    if (den != 0.0) consider((a * fx - cx * d) / den);
-    auto quad = [&](double A, double Bq, double C) {
-        if (A == 0.0) {
-            if (Bq != 0.0) consider(-C / Bq);
-            return;
-        }
-        const double disc = Bq * Bq - 4.0 * A * C;
-        if (disc < 0.0) return;
-        const double sq = sqrt(disc);
-        const double t = -0.5 * (Bq + (Bq >= 0.0 ? sq : -sq));
-        if (t == 0.0) {
-            consider(0.0);
-            return;
-        }
-        consider(t / A);
-        consider(C / t);
-    };
-    quad(a, bx, cx);
-    quad(d, ex, fx);
-    return any;
+    return u - a3;
 }
 
 // Acceptance of an intersection (section 4 constraints).  The W and top
@@ -664,6 +299,214 @@ HF_HD __forceinline__ double polish_xy(const Conic &P, const Conic &Q, double &x
         if (!(phys > skip_below)) break;
     }
     return phys;
+}
+
+// ------------------------------------------------ two-conic intersection
+// The real common points of two conics P and Q (section 4: the neutrino's
+// transverse momentum satisfies both mass-shell conditions) from their
+// pencil.  Written as symmetric 3 x 3 matrices, some member D = A + t B (or
+// B + s A) of the pencil is degenerate: det(A + t B) = det A + t tr(adj(A) B)
+// + t^2 tr(A adj(B)) + t^3 det B = 0, a cubic.  Its roots are the three ways
+// of splitting the four common points into two pairs, D being the pair of
+// lines through them.  With four real points, all three splittings are real
+// line pairs; with two real and two complex points, only one splitting is
+// real (the real chord and the line through the conjugate pair), and the
+// cubic has that one real root; with no real point, every splitting gives
+// either two real lines that miss the conics or a conjugate pair of lines.
+// So one real root suffices: the one farthest from the others (where two
+// roots approach each other, two common points do too, and the isolated
+// root's lines are the well-conditioned ones).  The adjugate of D is
+// -p p^T for the lines' common point p, so a negative diagonal entry means
+// a real pair (otherwise there is no real common point); D + [p]_x (the
+// cross-product matrix of p) then has rank one, its largest row and column
+// being the two lines, and each line meets P in the roots of a quadratic
+// along it.  The cubic is taken with its larger end coefficient leading;
+// the isolated root comes from the closed form in precision T and is
+// refined by two FP64 Newton steps (a seed within 1e-4 relative is then
+// correct to rounding).
+
+struct Sym3 {
+    double a00, a01, a02, a11, a12, a22;
+};
+
+HF_HD __forceinline__ Sym3 sym_conic(const Conic &q) {
+    return Sym3{q.xx, 0.5 * q.xy, 0.5 * q.x, q.yy, 0.5 * q.y, q.c};
+}
+
+HF_HD __forceinline__ Sym3 sym_adj(const Sym3 &a) {
+    return Sym3{a.a11 * a.a22 - a.a12 * a.a12, a.a02 * a.a12 - a.a01 * a.a22, a.a01 * a.a12 - a.a02 * a.a11,
+                a.a00 * a.a22 - a.a02 * a.a02, a.a01 * a.a02 - a.a00 * a.a12, a.a00 * a.a11 - a.a01 * a.a01};
+}
+
+// tr(X Y) of two symmetric matrices
+HF_HD __forceinline__ double sym_trprod(const Sym3 &x, const Sym3 &y) {
+    return x.a00 * y.a00 + x.a11 * y.a11 + x.a22 * y.a22 + 2.0 * (x.a01 * y.a01 + x.a02 * y.a02 + x.a12 * y.a12);
+}
+
+// The pencil is taken in coordinates u = x / kPencilUnit, where the
+// quadratic, linear and constant terms of the mass-shell conics are of one
+// size, and each matrix is divided by its largest entry: the cubic's end
+// coefficients then compare the conics' degeneracy, not their scales (a side
+// whose lepton and b jet are nearly parallel along the beam gives a conic
+// many orders of magnitude larger than the other).
+constexpr double kPencilUnit = 100.0;
+
+HF_HD __forceinline__ Sym3 sym_balanced(const Conic &q) {
+    // kPencilUnit^2, half of it and half of kPencilUnit
+    const double s2 = 1e4, s2h = 5e3, s1h = 50.0;
+    Sym3 m{q.xx * s2, q.xy * s2h, q.x * s1h, q.yy * s2, q.y * s1h, q.c};
+    const double mx = fmax(fmax(fmax(fabs(m.a00), fabs(m.a01)), fmax(fabs(m.a02), fabs(m.a11))),
+                           fmax(fabs(m.a12), fabs(m.a22)));
+    const double inv = mx > 0.0 ? step_rcp(mx) : 1.0;
+    m.a00 *= inv;
+    m.a01 *= inv;
+    m.a02 *= inv;
+    m.a11 *= inv;
+    m.a12 *= inv;
+    m.a22 *= inv;
+    return m;
+}
+
+// Common points of line l0 u + l1 v + l2 = 0 and the conic of symmetric
+// matrix m: the roots of the conic along the line through its foot point r0
+// with direction d = (-l1, l0).
+HF_HD __forceinline__ int line_conic(double l0, double l1, double l2, const Sym3 &m, double &xa, double &ya,
+                                     double &xb, double &yb) {
+    const double n2 = l0 * l0 + l1 * l1;
+    if (!(n2 > 0.0)) return 0;
+    const double in2 = step_rcp(n2);
+    const double x0 = -l2 * l0 * in2, y0 = -l2 * l1 * in2, dx = -l1, dy = l0;
+    // half the gradient at r0 and the conic's value there
+    const double g0 = fma(m.a00, x0, fma(m.a01, y0, m.a02)), g1 = fma(m.a01, x0, fma(m.a11, y0, m.a12));
+    const double c = fma(x0, g0, fma(y0, g1, fma(m.a02, x0, fma(m.a12, y0, m.a22))));
+    const double a = fma(dx, fma(m.a00, dx, m.a01 * dy), dy * fma(m.a01, dx, m.a11 * dy));
+    const double b = 2.0 * fma(g0, dx, g1 * dy);
+    const double disc = fma(b, b, -4.0 * a * c);
+    if (!(disc >= 0.0) || a == 0.0) return 0;
+    const double sq = fast_sqrt(disc);
+    const double t = -0.5 * (b + (b >= 0.0 ? sq : -sq));
+    if (t == 0.0) return 0;
+    const double s1 = t * step_rcp(a), s2 = c * step_rcp(t);
+    xa = fma(s1, dx, x0);
+    ya = fma(s1, dy, y0);
+    xb = fma(s2, dx, x0);
+    yb = fma(s2, dy, y0);
+    return 2;
+}
+
+struct Points4 {
+    double x0, y0, x1, y1, x2, y2, x3, y3;
+    int n;
+};
+
+// The terms of P that every intersection with it shares: its matrix, the
+// adjugate and the determinant.
+struct PencilP {
+    Sym3 m, adj;
+    double det;
+};
+
+HF_HD __forceinline__ PencilP pencil_p(const Conic &P) {
+    PencilP r;
+    r.m = sym_balanced(P);
+    r.adj = sym_adj(r.m);
+    r.det = r.m.a00 * r.adj.a00 + r.m.a01 * r.adj.a01 + r.m.a02 * r.adj.a02;
+    return r;
+}
+
+template <typename T>
+HF_HD __forceinline__ Points4 conic_intersections(const Conic &P, const PencilP &pp, const Conic &Q) {
+    Points4 R;
+    R.n = 0;
+    R.x0 = R.y0 = R.x1 = R.y1 = R.x2 = R.y2 = R.x3 = R.y3 = 0.0;
+    const Sym3 &A = pp.m, &aA = pp.adj;
+    const Sym3 B = sym_balanced(Q), aB = sym_adj(B);
+    const double dA = pp.det;
+    const double dB = B.a00 * aB.a00 + B.a01 * aB.a01 + B.a02 * aB.a02;
+    const double c1 = sym_trprod(aA, B), c2 = sym_trprod(A, aB);
+    // f(t) = det(U + t W) with |det W| >= |det U|
+    const bool swap = fabs(dB) < fabs(dA);
+    const double lead = swap ? dA : dB;
+    if (!(lead != 0.0) || !isfinite(lead)) return R;
+    const double il = fast_rcp(lead);
+    const double ca = (swap ? c1 : c2) * il, cb = (swap ? c2 : c1) * il, cc = (swap ? dB : dA) * il;
+    double t = (fmax(fabs(ca), fmax(fabs(cb), fabs(cc))) < 1e6)
+                   ? (double)cubic_isolated_root<T>((T)ca, (T)cb, (T)cc)
+                   : cubic_isolated_root<double>(ca, cb, cc);
+    for (int it = 0; it < 2; ++it) {
+        const double f = fma(fma(t + ca, t, cb), t, cc), d = fma(fma(3.0, t, 2.0 * ca), t, cb);
+        if (d != 0.0) t -= f * step_rcp(d);
+    }
+    // D = A + t B, or B + t A after the swap (any multiple of it will do)
+    const double ta = swap ? t : 1.0, tb = swap ? 1.0 : t;
+    const Sym3 D{fma(ta, A.a00, tb * B.a00), fma(ta, A.a01, tb * B.a01), fma(ta, A.a02, tb * B.a02),
+                 fma(ta, A.a11, tb * B.a11), fma(ta, A.a12, tb * B.a12), fma(ta, A.a22, tb * B.a22)};
+    const Sym3 aD = sym_adj(D);
+    // the diagonal entry of largest magnitude; real lines need it < 0
+    int ii = 0;
+    double bii = aD.a00;
+    if (fabs(aD.a11) > fabs(bii)) {
+        ii = 1;
+        bii = aD.a11;
+    }
+    if (fabs(aD.a22) > fabs(bii)) {
+        ii = 2;
+        bii = aD.a22;
+    }
+    if (!(-bii > 0.0)) return R;
+    const double ib = step_rsqrt(-bii);
+    const double p0 = (ii == 0 ? aD.a00 : ii == 1 ? aD.a01 : aD.a02) * ib;
+    const double p1 = (ii == 0 ? aD.a01 : ii == 1 ? aD.a11 : aD.a12) * ib;
+    const double p2 = (ii == 0 ? aD.a02 : ii == 1 ? aD.a12 : aD.a22) * ib;
+    // C = D + [p]_x, rank one: the lines are its largest row and column
+    const double c00 = D.a00, c01 = D.a01 + p2, c02 = D.a02 - p1;
+    const double c10 = D.a01 - p2, c11 = D.a11, c12 = D.a12 + p0;
+    const double c20 = D.a02 + p1, c21 = D.a12 - p0, c22 = D.a22;
+    // the row holding the entry of largest magnitude, then that entry's column
+    const double r0 = fmax(fabs(c00), fmax(fabs(c01), fabs(c02)));
+    const double r1 = fmax(fabs(c10), fmax(fabs(c11), fabs(c12)));
+    const double r2 = fmax(fabs(c20), fmax(fabs(c21), fabs(c22)));
+    const bool row1 = r1 > r0;
+    const bool row2 = r2 > (row1 ? r1 : r0);
+    const double la0 = row2 ? c20 : row1 ? c10 : c00;
+    const double la1 = row2 ? c21 : row1 ? c11 : c01;
+    const double la2 = row2 ? c22 : row1 ? c12 : c02;
+    const bool col1 = fabs(la1) > fabs(la0);
+    const bool col2 = fabs(la2) > (col1 ? fabs(la1) : fabs(la0));
+    const double lb0 = col2 ? c02 : col1 ? c01 : c00;
+    const double lb1 = col2 ? c12 : col1 ? c11 : c10;
+    const double lb2 = col2 ? c22 : col1 ? c21 : c20;
+    double xa, ya, xb, yb;
+    if (line_conic(la0, la1, la2, A, xa, ya, xb, yb)) {
+        R.x0 = xa;
+        R.y0 = ya;
+        R.x1 = xb;
+        R.y1 = yb;
+        R.n = 2;
+    }
+    if (line_conic(lb0, lb1, lb2, A, xa, ya, xb, yb)) {
+        if (R.n == 0) {
+            R.x0 = xa;
+            R.y0 = ya;
+            R.x1 = xb;
+            R.y1 = yb;
+        } else {
+            R.x2 = xa;
+            R.y2 = ya;
+            R.x3 = xb;
+            R.y3 = yb;
+        }
+        R.n += 2;
+    }
+    R.x0 *= kPencilUnit;
+    R.y0 *= kPencilUnit;
+    R.x1 *= kPencilUnit;
+    R.y1 *= kPencilUnit;
+    R.x2 *= kPencilUnit;
+    R.y2 *= kPencilUnit;
+    R.x3 *= kPencilUnit;
+    R.y3 *= kPencilUnit;
+    return R;
 }
 
 }  // namespace hf

@@ -9,9 +9,10 @@
 //
 // Input (binary, float64 rows of 18 values): l+ (E, px, py, pz), b, l-,
 // bbar, MET x, MET y, of one smeared pairing.  Output: the mean operation
-// counts per pairing for stage 1 (quartic assembly, intervals) and per
-// solved interval (Halley iteration, recovery of y, acceptance, score), and the share
-// of pairings and intervals.
+// counts per pairing (the l- side's varying terms, the reflection through
+// the MET, the pencil cubic, its line pair and the two line-conic
+// quadratics) and per intersection point (polish, acceptance, energies'
+// signs, score), and the number of pairings and points.
 #include <cmath>
 #include <cstdio>
 #include <vector>
@@ -100,56 +101,54 @@ int main(int argc, char **argv) {
     const double mt = 172.5, mw = 80.4;
     Tally s1_64, s1_32, it_64, it_32;
     long pairs = 0, items = 0, accepted = 0;
+    auto add = [](Tally &d, const Tally &t) {
+        d.add += t.add; d.mul += t.mul; d.fma += t.fma; d.div += t.div; d.sqrt += t.sqrt; d.trans += t.trans;
+    };
     for (size_t k = 0; k < n; ++k) {
         const double *r = &a[18 * k];
         CD lp[4] = {r[0], r[1], r[2], r[3]}, b[4] = {r[4], r[5], r[6], r[7]};
         CD lm[4] = {r[8], r[9], r[10], r[11]}, bb[4] = {r[12], r[13], r[14], r[15]};
         CD sp[kSide], sm[kSide];
-        // side constants are staged once per event and candidate: not per pairing
+        // side constants are staged once per event and candidate, and the
+        // l+ side's varying terms once per variation and candidate (counted
+        // per variation): neither is per pairing
         if (!make_side(lp, b, sp) || !make_side(lm, bb, sm)) continue;
-        T64.clear();
-        T32.clear();
-        // stage 1 (per variation and pairing): lepton-side W terms, both side
-        // terms, substitution of MET, eliminant, intervals
         const CD mt2_mw2 = CD(mt) * CD(mt) - CD(mw) * CD(mw), mw2 = CD(mw) * CD(mw);
         const CD ml2p = lp[0] * lp[0] - lp[1] * lp[1] - lp[2] * lp[2] - lp[3] * lp[3];
         const CD ml2m = lm[0] * lm[0] - lm[1] * lm[1] - lm[2] * lm[2] - lm[3] * lm[3];
         const CD one(1.0);
         const CD Wp = mw2 / (2.0 * one) - 0.5 * one * ml2p, Wm = mw2 / (2.0 * one) - 0.5 * one * ml2m;
-        SideVar A = side_var(sp, Wp, one, one, mt2_mw2), B = side_var(sm, Wm, one, one, mt2_mw2);
+        SideVar A = side_var(sp, Wp, one, one, mt2_mw2);
+        const PencilP pa = pencil_p(A.q);
+        T64.clear();
+        T32.clear();
+        SideVar B = side_var(sm, Wm, one, one, mt2_mw2);
         Conic Q = reflect(B.q, CD(r[16]), CD(r[17]));
-        CD qc[5];
-        eliminant(A.q, Q, qc);
-        const Brackets Bk = quartic_brackets<CF>(qc);
-        s1_64.add += T64.add; s1_64.mul += T64.mul; s1_64.fma += T64.fma; s1_64.div += T64.div;
-        s1_64.sqrt += T64.sqrt; s1_64.trans += T64.trans;
-        s1_32.add += T32.add; s1_32.mul += T32.mul; s1_32.fma += T32.fma; s1_32.div += T32.div;
-        s1_32.sqrt += T32.sqrt; s1_32.trans += T32.trans;
+        const Points4 pts = conic_intersections<CF>(A.q, pa, Q);
+        add(s1_64, T64);
+        add(s1_32, T32);
         ++pairs;
-        for (int kk = 0; kk < 4; ++kk) {
-            if (!((Bk.mask >> kk) & 1)) continue;
+        for (int kk = 0; kk < pts.n; ++kk) {
             T64.clear();
             T32.clear();
-            CD x = kXScale * bracket_root(Bk, kk), y;
+            CD x = kk == 0 ? pts.x0 : kk == 1 ? pts.x1 : kk == 2 ? pts.x2 : pts.x3;
+            CD y = kk == 0 ? pts.y0 : kk == 1 ? pts.y1 : kk == 2 ? pts.y2 : pts.y3;
             ++items;
-            if (recover_y(A.q, Q, x, y) && polish_xy(A.q, Q, x, y, 4, kPolishSkip * kAcceptM2 * 80.4 * 80.4) <= kAcceptM2 * 80.4 * 80.4) {
+            if (polish_xy(A.q, Q, x, y, 4, kPolishSkip * kAcceptM2 * 80.4 * 80.4) <= kAcceptM2 * 80.4 * 80.4) {
                 const CD en = sp[kE1] * x + sp[kE2] * y + A.e0;
                 const CD xb = CD(r[16]) - x, yb = CD(r[17]) - y;
                 const CD eb = sm[kE1] * xb + sm[kE2] * yb + B.e0;
                 if (en >= 0.0 && eb >= 0.0) {
                     ++accepted;
-                    // score: top pT terms and the Gaussian sum (six squares)
+                    // score: top pT terms (the point-independent parts are per pairing)
                     const CD tx = one * b[1] + one * lp[1] + x, ty = one * b[2] + one * lp[2] + y;
                     const CD tbx = one * bb[1] + one * lm[1] + xb, tby = one * bb[2] + one * lm[2] + yb;
-                    CD zz = one * one + one * one + one * one + one * one + one * one + one * one;
-                    const CD w = -0.5 * zz - (sqrt(tx * tx + ty * ty) + sqrt(tbx * tbx + tby * tby)) * CD(0.01);
+                    const CD w = -0.5 * one - (sqrt(tx * tx + ty * ty) + sqrt(tbx * tbx + tby * tby)) * CD(0.01);
                     (void)w;
                 }
             }
-            it_64.add += T64.add; it_64.mul += T64.mul; it_64.fma += T64.fma; it_64.div += T64.div;
-            it_64.sqrt += T64.sqrt; it_64.trans += T64.trans;
-            it_32.add += T32.add; it_32.mul += T32.mul; it_32.fma += T32.fma; it_32.div += T32.div;
-            it_32.sqrt += T32.sqrt; it_32.trans += T32.trans;
+            add(it_64, T64);
+            add(it_32, T32);
         }
     }
     auto pr = [](const char *name, const Tally &t, long d) {
@@ -157,10 +156,10 @@ int main(int argc, char **argv) {
                (double)t.mul / d, (double)t.fma / d, (double)t.div / d, (double)t.sqrt / d, (double)t.trans / d,
                t.flops() / d);
     };
-    printf("pairings %ld intervals %ld accepted %ld\n", pairs, items, accepted);
-    pr("stage1_fp64_per_pairing", s1_64, pairs);
-    pr("stage1_fp32_per_pairing", s1_32, pairs);
-    pr("interval_fp64_per_interval", it_64, items ? items : 1);
-    pr("interval_fp32_per_interval", it_32, items ? items : 1);
+    printf("pairings %ld points %ld accepted %ld\n", pairs, items, accepted);
+    pr("pairing_fp64_per_pairing", s1_64, pairs);
+    pr("pairing_fp32_per_pairing", s1_32, pairs);
+    pr("point_fp64_per_point", it_64, items ? items : 1);
+    pr("point_fp32_per_point", it_32, items ? items : 1);
     return 0;
 }

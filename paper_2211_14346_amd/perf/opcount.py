@@ -90,13 +90,13 @@ def main():
     for line in txt.splitlines():
         parts = line.split()
         if parts[0] == "pairings":
-            res.update(pairings=int(parts[1]), intervals=int(parts[3]), accepted=int(parts[5]))
+            res.update(pairings=int(parts[1]), points=int(parts[3]), accepted=int(parts[5]))
         else:
             res[parts[0]] = {parts[k]: float(parts[k + 1]) for k in range(1, len(parts), 2)}
     res["per_variation"] = {"fp32_flops": PER_VARIATION_FP32, "fp64_flops": PER_VARIATION_FP64}
     res["flop_per_variation"] = PER_VARIATION_FP32 + PER_VARIATION_FP64
-    res["flop_per_pairing"] = res["stage1_fp64_per_pairing"]["flops"] + res["stage1_fp32_per_pairing"]["flops"]
-    res["flop_per_interval"] = res["interval_fp64_per_interval"]["flops"] + res["interval_fp32_per_interval"]["flops"]
+    res["flop_per_pairing"] = res["pairing_fp64_per_pairing"]["flops"] + res["pairing_fp32_per_pairing"]["flops"]
+    res["flop_per_point"] = res["point_fp64_per_point"]["flops"] + res["point_fp32_per_point"]["flops"]
     print(json.dumps(res, indent=1))
 
 

@@ -148,3 +148,41 @@ def compare_chi2(g, w):
     st["sentinel_ok"] = bool(np.all(g["chi2"][:S][nos] == -9999.0) and np.all(g["nu"][:S][nos] == -9999.0)
                              and np.all(g["best_i"][:S][nos] == -1))
     return st
+
+
+def choice_mismatches(g, w):
+    """Positions where the decision or the chosen (variation, jet pair, root) differ."""
+    hs_g, hs_w = g["has_sol"].astype(bool), w["has_sol"].astype(bool)
+    same_root = np.all(np.abs(g["nu"][:, :2] - w["nu"][:, :2]) <= 1e-3 * np.maximum(np.abs(w["nu"][:, :2]), 1.0),
+                       axis=1)
+    same = (g["best_v"] == w["best_v"]) & (g["best_i"] == w["best_i"]) & (g["best_j"] == w["best_j"]) & same_root
+    return np.flatnonzero((hs_g != hs_w) | (hs_g & hs_w & ~same))
+
+
+def adjudicate(ev, ids, g, w, reco, positions):
+    """Settle disagreements of the FP64 path with the oracle by the 50-digit
+    brute force (brute_mp), which solves the pairing's constraints from the
+    smeared four-vectors without the expanded eliminant.  At each position the
+    product's chosen solution must be a genuine solution of its variation and
+    jet pair and score above the oracle's choice (or the oracle found none):
+    the oracle then missed a better solution, which its FP64 eliminant does
+    for the close root pairs of a nearly degenerate conic.  Returns one record
+    per position; raises AssertionError when the product is the one in error."""
+    import oracle as orc
+    from . import brute_mp
+    out = []
+    for p in positions:
+        e, v, i, j = int(ids[p]), int(g["best_v"][p]), int(g["best_i"][p]), int(g["best_j"][p])
+        assert g["has_sol"][p], ("product found no solution where the oracle did", p, e)
+        if w["has_sol"][p]:
+            assert g["logw"][p] > w["logw"][p], ("oracle's choice scores higher", p, e, g["logw"][p], w["logw"][p])
+        st = orc.stage_vary(ev, e, v, reco)
+        sols, _ = brute_mp.solve(st["lp"], st["cands"][i], st["lm"], st["cands"][j], st["met"][0], st["met"][1],
+                                 mt=reco.get("m_t", 172.5), mw=reco.get("m_w", W_MASS))
+        x, y = g["nu"][p, 0], g["nu"][p, 1]
+        hit = [s for s in sols if abs(float(s[0]) - x) <= 1e-6 * max(abs(x), 1.0) and
+               abs(float(s[1]) - y) <= 1e-6 * max(abs(y), 1.0)]
+        assert hit, ("product's solution is not a solution of its pairing", p, e, v, i, j, x, y,
+                     [(float(s[0]), float(s[1])) for s in sols])
+        out.append((p, e, v, i, j, float(g["logw"][p]), float(w["logw"][p]), len(sols)))
+    return out
