@@ -82,7 +82,7 @@ __device__ __forceinline__ double sqrt_fit(double v) {
 // a = E^2 - p_z^2 with its reciprocal (the p_z quadratic's leading term).
 struct Lep {
     double l[4];
-    double c0, qa, inv_qa;
+    double c0, qa, inv_qa, inv_e;
 };
 
 __device__ __forceinline__ Lep make_lep(const double *l, const Chi2Args &a) {
@@ -92,16 +92,22 @@ __device__ __forceinline__ Lep make_lep(const double *l, const Chi2Args &a) {
     L.c0 = 0.5 * (a.m_w * a.m_w - ml2);
     L.qa = l[0] * l[0] - l[3] * l[3];
     L.inv_qa = L.qa > 0.0 ? 1.0 / L.qa : 0.0;
+    L.inv_e = l[0] > 0.0 ? 1.0 / l[0] : 0.0;
     return L;
 }
 
 // One lepton side at one split point: the neutrino p_z candidates from the
 // W mass (both roots of the squared condition, or the real part), l + nu
-// and the W term of chi^2 per candidate.  A real root that solves the
-// unsquared condition (mu + p_zl p_z >= 0) puts l + nu on the W mass shell,
-// so its W term is zero; the squaring's extra root and the real part of a
-// complex pair get theirs computed.  Square roots use the hardware estimate
-// with one refinement (sqrt_fit); the quadratic's division is exact.
+// and the W term of chi^2 per candidate.  With h = mu + p_zl p_z the W
+// condition reads E_l E_nu = h: a real root with h >= 0 solves it unsquared,
+// so E_nu = h / E_l and l + nu lies on the W mass shell (W term zero); the
+// squaring's extra root and the real part of a complex pair take E_nu from
+// the mass shell and get their W term computed.  Both real roots have the
+// sign of mu (|p_zl| sqrt(d) < E_l |mu|), so neighbouring split points --
+// the lanes of a wave -- mostly agree, and the square roots of the other
+// case are skipped for a wave where no lane needs them.  Square roots use
+// the hardware estimate with one refinement (sqrt_fit); the quadratic's
+// division is exact.
 struct Side {
     double w[2][4];
     double pz[2];
@@ -137,15 +143,21 @@ __device__ __forceinline__ Side side(const Lep &L, double nx, double ny, const C
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
         if (r >= S.n) break;
-        const double en = sqrt_fit(fmax(pt2 + S.pz[r] * S.pz[r], kTiny));
+        double en = fma(l[3], S.pz[r], mu) * L.inv_e;
+        S.cw[r] = 0.0;
+        if (ballot(!shell[r])) {
+            if (!shell[r]) en = sqrt_fit(fmax(pt2 + S.pz[r] * S.pz[r], kTiny));
+        }
         S.w[r][0] = l[0] + en;
         S.w[r][1] = l[1] + nx;
         S.w[r][2] = l[2] + ny;
         S.w[r][3] = l[3] + S.pz[r];
-        S.cw[r] = shell[r] ? 0.0
-                           : sq(sqrt_fit(fmax(S.w[r][0] * S.w[r][0] - S.w[r][1] * S.w[r][1] -
-                                               S.w[r][2] * S.w[r][2] - S.w[r][3] * S.w[r][3], kTiny)) -
-                                a.m_w) * a.inv_sw2;
+        if (ballot(!shell[r])) {
+            if (!shell[r])
+                S.cw[r] = sq(sqrt_fit(fmax(S.w[r][0] * S.w[r][0] - S.w[r][1] * S.w[r][1] -
+                                           S.w[r][2] * S.w[r][2] - S.w[r][3] * S.w[r][3], kTiny)) -
+                             a.m_w) * a.inv_sw2;
+        }
     }
     return S;
 }
@@ -261,19 +273,33 @@ __device__ __forceinline__ double point_best1(const Lep &LP, const Lep &LM, cons
     return best;
 }
 
-// Wave argmin of (value, point index); every lane gets the winner.
+// Wave argmin of (value, point index); every lane gets the winner.  The
+// minimum value first (four in-row DPP steps, then across rows by
+// shuffles); a ballot finds the lanes holding it, and among several the
+// smallest point index wins (a second reduction, on the index).
 __device__ __forceinline__ void wave_argmin(double &val, int &pidx, int &packed) {
-#pragma unroll
-    for (int off = 1; off < kWave; off <<= 1) {
-        const double ov = __shfl_xor(val, off);
-        const int op = __shfl_xor(pidx, off);
-        const int ok = __shfl_xor(packed, off);
-        if (ov < val || (ov == val && op < pidx)) {
-            val = ov;
-            pidx = op;
-            packed = ok;
-        }
+    double m = val;
+    m = fmin(m, dpp_f64<0xB1>(m));
+    m = fmin(m, dpp_f64<0x4E>(m));
+    m = fmin(m, dpp_f64<0x141>(m));
+    m = fmin(m, dpp_f64<0x140>(m));
+    m = fmin(m, __shfl_xor(m, 16));
+    m = fmin(m, __shfl_xor(m, 32));
+    const uint64_t at = ballot(val == m);
+    int wl = (int)__builtin_ctzll(at);
+    if ((at & (at - 1)) != 0) {
+        int q = ((at >> lane_id()) & 1ull) ? pidx : 0x7fffffff;
+        q = min(q, dpp_i32<0xB1>(q));
+        q = min(q, dpp_i32<0x4E>(q));
+        q = min(q, dpp_i32<0x141>(q));
+        q = min(q, dpp_i32<0x140>(q));
+        q = min(q, __shfl_xor(q, 16));
+        q = min(q, __shfl_xor(q, 32));
+        wl = (int)__builtin_ctzll(ballot(((at >> lane_id()) & 1ull) && pidx == q));
     }
+    val = __shfl(val, wl);
+    pidx = __shfl(pidx, wl);
+    packed = __shfl(packed, wl);
 }
 
 __global__ __launch_bounds__(kBlock) void k_chi2(EvView ev, const int32_t *__restrict__ idx,

@@ -21,6 +21,22 @@ __device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
 
 __device__ __forceinline__ int popc64(uint64_t x) { return __popcll(x); }
 
+// In-row lane exchanges by DPP (no LDS round trip): kCtrl is the DPP control
+// word (quad_perm 0xB1 = lane ^ 1, 0x4E = lane ^ 2; 0x141 = row_half_mirror,
+// lane i <-> 7 - i within eight lanes; 0x140 = row_mirror, i <-> 15 - i
+// within sixteen).  Every pattern used is a permutation inside each row, so
+// no lane reads outside the wavefront.
+template <int kCtrl>
+__device__ __forceinline__ int dpp_i32(int v) {
+    return __builtin_amdgcn_update_dpp(v, v, kCtrl, 0xF, 0xF, false);
+}
+
+template <int kCtrl>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const int lo = __double2loint(v), hi = __double2hiint(v);
+    return __hiloint2double(dpp_i32<kCtrl>(hi), dpp_i32<kCtrl>(lo));
+}
+
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon et al., SC'11): ten rounds; each round multiplies
 // counter words 0 and 2 by the two round constants (32x32 -> 64) and mixes

@@ -125,22 +125,6 @@ __device__ __forceinline__ X from_lane(X v, int src) {
     return __shfl(v, src);
 }
 
-// In-row lane exchanges by DPP (no LDS round trip): kCtrl is the DPP control
-// word (quad_perm 0xB1 = lane ^ 1, 0x4E = lane ^ 2; 0x141 = row_half_mirror,
-// lane i <-> 7 - i within eight lanes; 0x140 = row_mirror, i <-> 15 - i
-// within sixteen).  Every pattern used is a permutation inside each row, so
-// no lane reads outside the wavefront.
-template <int kCtrl>
-__device__ __forceinline__ int dpp_i32(int v) {
-    return __builtin_amdgcn_update_dpp(v, v, kCtrl, 0xF, 0xF, false);
-}
-
-template <int kCtrl>
-__device__ __forceinline__ double dpp_f64(double v) {
-    const int lo = __double2loint(v), hi = __double2hiint(v);
-    return __hiloint2double(dpp_i32<kCtrl>(hi), dpp_i32<kCtrl>(lo));
-}
-
 __device__ __forceinline__ int64_t clamp_count(const int64_t *count, int64_t capacity) {
     const int64_t S = *count;
     return S < 0 ? 0 : (S > capacity ? capacity : S);
