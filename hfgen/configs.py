@@ -230,11 +230,12 @@ HLHC_BIN_RECO = {
 }
 
 
-def _user(name, src, deps=()):
+def _user(name, src, deps=(), budget=0):
     """A user predicate (section 3: the user's own cut, a boolean function of
     one event): the body of a C function over the accessors n_lep(),
-    n_jet(), lep_pt(i) ... jet_btag(i), met_x(), met_y()."""
-    return {"name": name, "kind": "USER", "f": [], "i": [], "deps": list(deps), "src": src}
+    n_jet(), lep_pt(i) ... jet_btag(i), met_x(), met_y().  budget: loop
+    iterations it may run per event (0: the library default)."""
+    return {"name": name, "kind": "USER", "f": [], "i": [0, int(budget)], "deps": list(deps), "src": src}
 
 
 # User predicates, some restating built-in cuts (so that the two paths can be

@@ -91,7 +91,8 @@ typedef struct hf_events {
  *                        above mtw_min; fails without a selected lepton;
  *                        section 6.1)
  *   HF_CUT_USER         a user predicate compiled at run time by
- *                       hf_chain_compile; i = {index of its source}
+ *                       hf_chain_compile; i = {index of its source, loop
+ *                       budget (0: HF_USER_LOOP_BUDGET)}
  *   HF_CUT_JET_N_RANGE  f = {pt_min, abs_eta_lo, abs_eta_hi}  i = {n_min, n_max}
  *                       (the number of jets with pT > pt_min and
  *                        abs_eta_lo <= |eta| < abs_eta_hi lies in
@@ -364,8 +365,13 @@ int hf_unpack_events(int64_t n, const uint8_t *d_lep_cnt, const uint8_t *d_jet_c
  * plus the C math functions and local variables, loops and conditionals,
  * e.g. "int n = 0; for (int k = 0; k < n_jet(); ++k) n += fabsf(jet_eta(k))
  * >= 2.5f; return n >= 1;".  Arithmetic is compiled without contraction
- * (-ffp-contract=off).  A predicate must terminate; one that does not hangs
- * the kernel.
+ * (-ffp-contract=off).  Loops are bounded: every iteration of a for, while
+ * or do-while loop spends one unit of the cut's budget for the event (the
+ * cut's i[1], or HF_USER_LOOP_BUDGET when it is 0) -- a for loop as an
+ * iteration starts, a while or do-while loop when its condition lets
+ * another iteration run -- and a predicate that would run past its budget
+ * stops and fails the event, so no predicate can hang the chain kernel.
+ * goto is not accepted; recursion (through lambdas) is not bounded.
  *
  * hf_chain_compile generates the chain kernel with the user predicates
  * inlined, compiles it for the current device with hipRTC and loads it
@@ -375,9 +381,13 @@ int hf_unpack_events(int64_t n, const uint8_t *d_lep_cnt, const uint8_t *d_jet_c
  * the caller (hf_chain_destroy); on failure *out is NULL and the compiler's
  * messages are in hf_last_error().
  * Errors: HF_ERR_INVAL for malformed cut tables, a user index outside
- * [0, n_user), a NULL source or a source that does not compile;
+ * [0, n_user), a negative loop budget, a NULL source or a source that does
+ * not compile;
  * HF_ERR_DEVICE if loading the code fails. */
 typedef struct hf_chain hf_chain_t;
+
+/* Default loop budget of a user predicate, iterations per event. */
+#define HF_USER_LOOP_BUDGET 65536
 
 int hf_chain_compile(const hf_cut_t *h_cuts, int n_cuts, const char *const *h_user_src, int n_user,
                      hf_chain_t **out);

@@ -25,7 +25,9 @@ NOSOL = -9999.0
 
 def build(force=True):
     """Compile the oracle: plain C, IEEE double, no contraction, OpenMP."""
-    if not force and os.path.exists(LIB_PATH) and os.path.getmtime(LIB_PATH) >= os.path.getmtime(SRC_PATH):
+    hdr = os.path.join(_HERE, "orc_events.h")
+    if not force and os.path.exists(LIB_PATH) and \
+            os.path.getmtime(LIB_PATH) >= max(os.path.getmtime(SRC_PATH), os.path.getmtime(hdr)):
         return LIB_PATH
     tmp = LIB_PATH + ".tmp"
     cmd = ["gcc", "-O2", "-std=c11", "-D_DEFAULT_SOURCE", "-fno-fast-math", "-ffp-contract=off",
@@ -93,8 +95,7 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB_PATH):
-            build()
+        build(force=False)  # rebuilt when older than its sources
         L = C.CDLL(LIB_PATH)
         P = C.c_void_p
         L.orc_philox4x32_10.argtypes = [P, P, P]
@@ -189,6 +190,19 @@ static float orc_col(const double *col, uint32_t base, uint32_t n, int i)
 #define met_y() ((float)ev_->met_y[e_])
 """
 
+# Reading (a predicate is a boolean function of one event, so it must end):
+# every loop iteration of a predicate spends one unit of a budget per event
+# (the cut's i[1], or USER_LOOP_BUDGET when that is 0); a for loop spends it
+# as an iteration starts, a while or do-while loop when its condition lets
+# another iteration run.  A predicate whose loops would run past the budget
+# stops there and fails the event.  goto is not accepted.
+USER_LOOP_BUDGET = 65536
+_USER_LOOPS = """#define for(...) for (__VA_ARGS__) if (--*budget_ < 0) { *over_ = 1; break; } else
+#define while(...) while ((__VA_ARGS__) && (--*budget_ >= 0 || (*over_ = 1, 0)))
+#define goto orc_user_cuts_may_not_use_goto
+"""
+_USER_LOOPS_END = "#undef for\n#undef while\n#undef goto\n"
+
 _user_libs = {}
 
 
@@ -205,10 +219,17 @@ def _user_fns(cuts):
     if key not in _user_libs:
         body = [_USER_PRELUDE]
         for u, src in enumerate(srcs):
-            body.append(f"int orc_user_cut_{u}(const orc_events *ev_, int64_t e_)\n{{\n"
+            body.append(f"static int orc_user_body_{u}(const orc_events *ev_, int64_t e_, int64_t *budget_, int *over_)\n"
+                        f"{{\n"
                         f"    const uint32_t l0_ = ev_->lep_off[e_], nl_ = ev_->lep_off[e_ + 1] - l0_;\n"
                         f"    const uint32_t j0_ = ev_->jet_off[e_], nj_ = ev_->jet_off[e_ + 1] - j0_;\n"
-                        f"    (void)nl_;\n    (void)nj_;\n#line 1 \"user_cut_{u}\"\n{src}\n}}\n")
+                        f"    (void)nl_;\n    (void)nj_;\n    (void)budget_;\n    (void)over_;\n"
+                        f"{_USER_LOOPS}#line 1 \"user_cut_{u}\"\n{src}\n#line 1 \"orc_user_tail\"\n"
+                        f"{_USER_LOOPS_END}}}\n"
+                        f"int orc_user_cut_{u}(const orc_events *ev_, int64_t e_, int32_t budget)\n{{\n"
+                        f"    int64_t b_ = budget > 0 ? budget : {USER_LOOP_BUDGET};\n    int over_ = 0;\n"
+                        f"    const int r_ = orc_user_body_{u}(ev_, e_, &b_, &over_);\n"
+                        f"    return r_ && !over_;\n}}\n")
         d = tempfile.mkdtemp(prefix="orc_user_")
         c_path, so_path = os.path.join(d, "user.c"), os.path.join(d, "user.so")
         with open(c_path, "w") as f:
@@ -230,6 +251,8 @@ def select(ev, cuts, order, index_base=0):
     reached = np.zeros(len(cuts), dtype=np.uint64)
     passed = np.zeros(len(cuts), dtype=np.uint64)
     order = np.ascontiguousarray(order, dtype=np.int32)
+    if order.size != len(cuts):
+        raise ValueError(f"order has {order.size} entries for {len(cuts)} cuts")
     arr = _cut_array(cuts)
     _, fns = _user_fns(cuts)
     lib().orc_select_user(C.byref(h.s), C.cast(arr, C.c_void_p), len(cuts), _ptr(order),

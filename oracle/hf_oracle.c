@@ -200,7 +200,7 @@ static int orc_jet_sel(const orc_events *ev, uint32_t k, double ptmin, double et
 static int orc_eval_cut(const orc_events *ev, int64_t e, const orc_cut *c, const orc_user_fn *user)
 {
     if (c->kind == ORC_USER) /* a user predicate (section 3: a cut is a boolean function of one event) */
-        return user && user[c->i[0]] ? user[c->i[0]](ev, e) != 0 : 0;
+        return user && user[c->i[0]] ? user[c->i[0]](ev, e, c->i[1]) != 0 : 0;
     uint32_t l0 = ev->lep_off[e], l1 = ev->lep_off[e + 1];
     uint32_t j0 = ev->jet_off[e], j1 = ev->jet_off[e + 1];
     switch (c->kind) {

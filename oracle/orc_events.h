@@ -19,6 +19,8 @@ typedef struct {
 } orc_events;
 
 /* A user cut: nonzero when event e passes. */
-typedef int (*orc_user_fn)(const orc_events *ev, int64_t e);
+/* A compiled user predicate of one event; budget: the most loop iterations
+ * it may run for the event (it fails the event beyond that). */
+typedef int (*orc_user_fn)(const orc_events *ev, int64_t e, int32_t budget);
 
 #endif

@@ -210,7 +210,15 @@ class CompiledChain:
             self.h = C.c_void_p()
 
 
+def _check_order(order, n_cuts, counters, survive, n):
+    """The kernels read n_cuts order entries, n_cuts counter rows and n mask
+    bytes from device pointers: refuse shorter tensors before the call."""
+    if order.numel() < n_cuts or counters.numel() < 3 * n_cuts or survive.numel() < n:
+        raise ValueError(f"order needs {n_cuts} entries, counters {n_cuts} rows and survive {n} bytes")
+
+
 def chain_select(chain, dev, order, survive, counters, ws, stream=None):
+    _check_order(order, chain.n_cuts, counters, survive, dev.n)
     rc = lib().hf_chain_select(chain.h, dev.ptr, _p(order), _p(survive), _p(counters), _p(ws),
                                ws.numel() * ws.element_size(), _stream(stream))
     _check(rc, "hf_chain_select")
@@ -257,6 +265,7 @@ class DeviceEvents:
 
 
 def select(dev, cuts_arr, n_cuts, order, survive, counters, ws, stream=None):
+    _check_order(order, n_cuts, counters, survive, dev.n)
     rc = lib().hf_select(dev.ptr, C.cast(cuts_arr, C.c_void_p), n_cuts, _p(order), _p(survive), _p(counters),
                          _p(ws), ws.numel() * ws.element_size(), _stream(stream))
     _check(rc, "hf_select")
@@ -267,6 +276,8 @@ def select_segment(dev, cuts_arr, n_cuts, order, pos_begin, pos_end, survive, co
     """Cuts at order positions [pos_begin, pos_end) over all events (idx None)
     or over compacted ids idx[0:*count] (survive then indexed by position).
     With `chain` (a CompiledChain) its compiled kernel runs."""
+    _check_order(order, chain.n_cuts if chain is not None else n_cuts, counters, survive,
+                 dev.n if idx is None else min(int(capacity), dev.n) if capacity else 0)
     args = (int(pos_begin), int(pos_end), _p(idx), _p(count), int(capacity), _p(survive), _p(counters), _p(ws),
             ws.numel() * ws.element_size(), _stream(stream))
     if chain is not None:

@@ -335,10 +335,13 @@ int hf_chain_compile(const hf_cut_t *h_cuts, int n_cuts, const char *const *h_us
         if (!h_user_src[u]) return fail(HF_ERR_INVAL, "hf_chain_compile: user source %d is NULL", u);
         src.emplace_back(h_user_src[u]);
     }
-    for (int c = 0; c < n_cuts; ++c)
+    for (int c = 0; c < n_cuts; ++c) {
         if (h_cuts[c].kind == HF_CUT_USER && (h_cuts[c].i[0] < 0 || h_cuts[c].i[0] >= n_user))
             return fail(HF_ERR_INVAL, "hf_chain_compile: cut %d names user source %d outside [0, %d)", c,
                         h_cuts[c].i[0], n_user);
+        if (h_cuts[c].kind == HF_CUT_USER && h_cuts[c].i[1] < 0)
+            return fail(HF_ERR_INVAL, "hf_chain_compile: cut %d has a negative loop budget %d", c, h_cuts[c].i[1]);
+    }
     std::vector<char> code;
     std::string lowered, log;
     if (!hf::rtc_compile(hf::chain_source(src), code, lowered, log)) {

@@ -271,7 +271,8 @@ __global__ __launch_bounds__(kSelBlock) void k_select_t(EvView ev, CutTable ct, 
             const uint64_t t0 = __builtin_amdgcn_s_memtime();
             bool pass = false;
             if (alive)
-                pass = s_cut[c].kind == HF_CUT_USER ? User::eval(s_cut[c].i[0], ev, e) : eval_cut(ev, e, s_cut[c]);
+                pass = s_cut[c].kind == HF_CUT_USER ? User::eval(s_cut[c].i[0], ev, e, s_cut[c].i[1])
+                                                    : eval_cut(ev, e, s_cut[c]);
             const uint64_t pm = ballot(pass);
             const uint64_t t1 = __builtin_amdgcn_s_memtime();
             if (lane == 0) {
@@ -300,7 +301,7 @@ __device__ __forceinline__ float user_col(const float *col, uint32_t base, uint3
 
 // No user predicates (the library's own chain kernel).
 struct NoUserCuts {
-    __device__ static bool eval(int, const EvView &, int64_t) { return true; }
+    __device__ static bool eval(int, const EvView &, int64_t, int32_t) { return true; }
 };
 
 }  // namespace hf

@@ -45,6 +45,17 @@ const char *kAccessors =
     "#define met_x() (hf_ev.met_x[hf_e])\n"
     "#define met_y() (hf_ev.met_y[hf_e])\n";
 
+// Loops of a user predicate spend one unit of its budget per iteration: a
+// for loop as an iteration starts, a while or do-while loop when its
+// condition lets another iteration run.  Past the budget the loop stops and
+// the predicate fails the event, so a predicate always ends.  goto (the one
+// other way to loop without recursion) does not compile.
+const char *kLoopBudget =
+    "#define for(...) for (__VA_ARGS__) if (--*hf_budget < 0) { *hf_over = true; break; } else\n"
+    "#define while(...) while ((__VA_ARGS__) && (--*hf_budget >= 0 || (*hf_over = true, false)))\n"
+    "#define goto hf_user_cuts_may_not_use_goto\n";
+const char *kLoopBudgetEnd = "#undef for\n#undef while\n#undef goto\n";
+
 }  // namespace
 
 std::string chain_source(const std::vector<std::string> &user_src) {
@@ -52,23 +63,33 @@ std::string chain_source(const std::vector<std::string> &user_src) {
     std::string s = "#define M_PI 3.14159265358979323846\n#include \"hf_cuts.hpp\"\n\nnamespace hf_user {\n\n";
     s += kAccessors;
     for (size_t u = 0; u < user_src.size(); ++u) {
-        char head[512];
+        char head[640];
         snprintf(head, sizeof head,
-                 "\n__device__ __forceinline__ bool cut_%zu(const hf::EvView &hf_ev, int64_t hf_e) {\n"
+                 "\n__device__ __forceinline__ bool body_%zu(const hf::EvView &hf_ev, int64_t hf_e, int64_t *hf_budget,\n"
+                 "                                         bool *hf_over) {\n"
                  "    const uint32_t hf_l0 = hf_ev.lep_off[hf_e], hf_nl = hf_ev.lep_off[hf_e + 1] - hf_l0;\n"
                  "    const uint32_t hf_j0 = hf_ev.jet_off[hf_e], hf_nj = hf_ev.jet_off[hf_e + 1] - hf_j0;\n"
-                 "    (void)hf_nl;\n    (void)hf_nj;\n"
-                 "#line 1 \"user_cut_%zu\"\n",
-                 u, u);
+                 "    (void)hf_nl;\n    (void)hf_nj;\n    (void)hf_budget;\n    (void)hf_over;\n",
+                 u);
+        s += head;
+        s += kLoopBudget;
+        snprintf(head, sizeof head, "#line 1 \"user_cut_%zu\"\n", u);
         s += head;
         s += user_src[u];
-        s += "\n#line 1 \"hf_user_chain_tail\"\n}\n";
+        s += "\n#line 1 \"hf_user_chain_tail\"\n";
+        s += kLoopBudgetEnd;
+        snprintf(head, sizeof head,
+                 "}\n__device__ __forceinline__ bool cut_%zu(const hf::EvView &hf_ev, int64_t hf_e, int32_t budget) {\n"
+                 "    int64_t b = budget > 0 ? budget : HF_USER_LOOP_BUDGET;\n    bool over = false;\n"
+                 "    const bool r = body_%zu(hf_ev, hf_e, &b, &over);\n    return r && !over;\n}\n",
+                 u, u);
+        s += head;
     }
-    s += "\nstruct Cuts {\n    __device__ static bool eval(int u, const hf::EvView &ev, int64_t e) {\n"
+    s += "\nstruct Cuts {\n    __device__ static bool eval(int u, const hf::EvView &ev, int64_t e, int32_t budget) {\n"
          "        switch (u) {\n";
     for (size_t u = 0; u < user_src.size(); ++u) {
         char c[96];
-        snprintf(c, sizeof c, "        case %zu: return cut_%zu(ev, e);\n", u, u);
+        snprintf(c, sizeof c, "        case %zu: return cut_%zu(ev, e, budget);\n", u, u);
         s += c;
     }
     s += "        default: return false;\n        }\n    }\n};\n\n}  // namespace hf_user\n";

@@ -193,6 +193,13 @@ def test_user_chain_validation(B):
     else:
         assert not h.value
     L.hf_chain_destroy(None)
+    # a negative loop budget is refused before compiling; goto does not compile
+    neg = B.cut_table([dict(user[0], i=[0, -1])])
+    assert L.hf_chain_compile(C.cast(neg, C.c_void_p), 1, C.cast(srcs, C.c_void_p), 1, C.byref(h)) == -1
+    assert b"loop budget" in L.hf_last_error() and not h.value
+    jump = (C.c_char_p * 1)(b"again: goto again; return 1;")
+    assert L.hf_chain_compile(C.cast(arr, C.c_void_p), 1, C.cast(jump, C.c_void_p), 1, C.byref(h)) == -1
+    assert b"goto" in L.hf_last_error() and not h.value
     # the library's own chain kernel refuses user cuts
     dummy = C.c_void_p(16)
     ev = B.Events(n=10, index_base=0)

@@ -125,3 +125,39 @@ def test_user_chain_empty_chunk(B):
     B.chain_select(ch, dev, torch.arange(len(cuts), dtype=torch.int32, device="cuda"), surv, cnt, ws)
     torch.cuda.synchronize()
     assert np.all(cnt.cpu().numpy()[:, :2] == 0)
+
+
+def test_loop_budgets_match_oracle(B, orc):
+    """Budgeted loops (every loop here ends after at most 1000 iterations, so
+    a run cannot hang whatever the budget does): at the budget each predicate
+    passes, one unit below it fails, and a loop over the event's jets with a
+    budget of 3 fails exactly the events with more than three jets; masks and
+    counters equal the oracle's."""
+    from .test_oracle_usercuts import LOOPS
+    cfg = hfgen.config("hlhc50M")
+    ev, _ = hfgen.stream_chunk(cfg, 13, n=20000)
+    jets = "int n = 0; for (int k = 0; k < n_jet(); ++k) n += jet_pt(k) > 25.0f; return n >= 0;"
+    cuts = []
+    for name, src, units in LOOPS:
+        cuts.append(_user(f"U_{name}_at", src, budget=units))
+        cuts.append(_user(f"U_{name}_below", src, budget=units - 1))
+    cuts.append(_user("U_jets3", jets, budget=3))
+    _say("loop budgets", [c["name"] for c in cuts])
+    ch = B.CompiledChain(cuts)
+    dev, surv, cnt, ws = _buffers(B, ev, len(cuts))
+    n = ev["n"]
+    for k, c in enumerate(cuts):
+        # cut k first: its own counters give its pass count over every event
+        order = [k] + [j for j in range(len(cuts)) if j != k]
+        cnt.zero_()
+        B.chain_select(ch, dev, torch.tensor(order, dtype=torch.int32, device="cuda"), surv, cnt, ws)
+        torch.cuda.synchronize()
+        s_w, r_w, p_w = orc.select(ev, cuts, order)
+        c_g = cnt.cpu().numpy()
+        assert np.array_equal(surv[:n].cpu().numpy(), s_w), c["name"]
+        assert np.array_equal(c_g[:, 0], r_w) and np.array_equal(c_g[:, 1], p_w), c["name"]
+        assert c_g[k, 0] == n
+        if c["name"] == "U_jets3":
+            assert c_g[k, 1] == int((np.diff(np.asarray(ev["jet_off"])) <= 3).sum())
+        else:
+            assert c_g[k, 1] == (n if c["name"].endswith("_at") else 0), c["name"]

@@ -76,3 +76,37 @@ def test_mixed_chain_counters_follow_order(orc):
             alive &= singles[c]
             assert passed[c] == alive.sum()
         assert np.array_equal(surv.astype(bool), alive)
+
+
+# Loop budgets (a predicate is a function of one event, so it must end):
+# each (body, units it spends on every event).  A for loop spends a unit as
+# an iteration starts, a while or do-while loop when its condition lets
+# another iteration run; nested loops add up.
+LOOPS = [
+    ("for", "int s = 0; for (int k = 0; k < 1000; ++k) s += k & 1; return s > 0;", 1000),
+    ("while", "int k = 0; while (k < 10) ++k; return 1;", 10),
+    ("do", "int k = 0; do { ++k; } while (k < 10); return 1;", 9),
+    ("nested", "int s = 0; for (int a = 0; a < 30; ++a) for (int b = 0; b < 20; ++b) s += 1; return s == 600;",
+     630),
+    ("continue", "int s = 0; for (int k = 0; k < 50; ++k) { if (k & 1) continue; s += 1; } return s == 25;", 50),
+]
+
+
+@pytest.mark.parametrize("name,src,units", LOOPS)
+def test_loop_budget_boundary(orc, name, src, units):
+    ev = _sample()
+    n = ev["n"]
+    for budget, want in ((units, n), (units - 1, 0), (units + 7, n), (0, n)):
+        s, r, p = orc.select(ev, [_user("U", src, budget=budget)], [0])
+        assert int(s.sum()) == want and r[0] == n and p[0] == want, (name, budget)
+
+
+def test_loop_budget_per_event(orc):
+    """A loop over the event's jets with a budget of 3 units passes exactly
+    the events with at most three jets (counted here from the offsets)."""
+    ev = _sample()
+    src = "int n = 0; for (int k = 0; k < n_jet(); ++k) n += jet_pt(k) > 25.0f; return n >= 0;"
+    s, _, _ = orc.select(ev, [_user("U", src, budget=3)], [0])
+    njet = np.diff(np.asarray(ev["jet_off"]))
+    assert np.array_equal(s.astype(bool), njet <= 3)
+    assert 0 < s.sum() < ev["n"]
