@@ -57,20 +57,30 @@ struct BestRec {
 // One compacted event as the reconstruction sees it, built by k_stage: the
 // two selected leptons and the b candidates as nominal FP64 (E, px, py, pz),
 // in the order of the candidate rule; nc = 0 when the lepton selection
-// fails (or the id lies outside the chunk).  640 bytes = 80 words, copied
-// into LDS by a wavefront with two loads per lane.
+// fails (or the id lies outside the chunk).  The used part is contiguous: a
+// 14-word header, then 6 words per candidate (k_stage writes only those;
+// the search kernel reads the header and three candidates ahead of time and
+// the rest, for an event with more candidates, when it gets to it).
+struct CandRec {
+    double v[4];    // nominal (E, px, py, pz)
+    double sigma;   // jet energy resolution at the nominal energy
+    int32_t jidx;   // jet index within the event
+    int32_t pad;
+};
 struct StageRec {
     double lp[4], lm[4];    // l+ and l-
     double met[2];          // nominal MET x, y
     double ml2p, ml2m;      // squared masses of l+ and l-
-    double sigma[kMaxC];    // jet energy resolution at the nominal energy
     uint64_t g;             // global event id (the generator's counter)
-    int32_t jidx[kMaxC];    // candidate -> jet index within the event
     int32_t nc, V;          // number of candidates, of variations
-    double cand[kMaxC][4];  // b candidates
+    CandRec cand[kMaxC];    // b candidates
 };
 constexpr int kRecWords = (int)(sizeof(StageRec) / 8);
-static_assert(sizeof(StageRec) == 640 && kRecWords > kWave && kRecWords <= 2 * kWave, "record layout");
+constexpr int kHeadWords = 14, kCandWords = 6;
+constexpr int kPrefetchWords = kHeadWords + 3 * kCandWords;  // header and three candidates
+static_assert(sizeof(CandRec) == 8 * kCandWords && offsetof(StageRec, cand) == 8 * kHeadWords &&
+                  kRecWords <= kPrefetchWords + kWave && kPrefetchWords <= kWave,
+              "record layout");
 
 template <typename T>
 struct WaveStageEv {
@@ -251,9 +261,9 @@ __global__ __launch_bounds__(256) void k_stage(EvView ev, const int32_t *__restr
             double v[4];
             const float en = ev.jet_e[q];
             polar_to_cart(ev.jet_pt[q], ev.jet_eta[q], ev.jet_phi[q], en, v);
-            for (int u = 0; u < 4; ++u) r.cand[c][u] = v[u];
-            r.sigma[c] = sqrt(a.jet_a * a.jet_a / (double)en + a.jet_c * a.jet_c);
-            r.jidx[c] = (int32_t)(q - j0);
+            for (int u = 0; u < 4; ++u) r.cand[c].v[u] = v[u];
+            r.cand[c].sigma = sqrt(a.jet_a * a.jet_a / (double)en + a.jet_c * a.jet_c);
+            r.cand[c].jidx = (int32_t)(q - j0);
         }
     }
     if (sub == 2) {
@@ -310,30 +320,32 @@ __global__ __launch_bounds__(NW * kWave, 2) void k_search_ev(const int64_t *__re
     const int cls = (int)(blockIdx.x % (unsigned)ncls);
     unsigned long long *ticket = reinterpret_cast<unsigned long long *>(wstats) + kTicketWord + 16 * cls;
     const uint64_t *recw = reinterpret_cast<const uint64_t *>(stage);
-    constexpr int kTail = kRecWords - kWave;
+    uint64_t *dst = reinterpret_cast<uint64_t *>(&st.rec);
     unsigned long long tk = 0;
     if (lane == 0) tk = atomicAdd(ticket, 1ull);
     int64_t k = cls + (int64_t)ncls * (int64_t)__shfl(tk, 0);
-    uint64_t w0 = 0, w1 = 0;
+    uint64_t w0 = 0;
     if (k < S) {
-        w0 = recw[k * kRecWords + lane];
-        if (lane < kTail) w1 = recw[k * kRecWords + kWave + lane];
+        if (lane < kPrefetchWords) w0 = recw[k * kRecWords + lane];
         if (lane == 0) tk = atomicAdd(ticket, 1ull);
     }
     while (k < S) {
-        {
-            uint64_t *dst = reinterpret_cast<uint64_t *>(&st.rec);
-            dst[lane] = w0;
-            if (lane < kTail) dst[kWave + lane] = w1;
-        }
+        if (lane < kPrefetchWords) dst[lane] = w0;
+        wave_sync();
+        // the rest of a record with more than three candidates, read now
+        // (issued before the next event's prefetch, stored after it)
+        const int nc = __builtin_amdgcn_readfirstlane(st.rec.nc);
+        const int used = kHeadWords + kCandWords * nc;
+        const bool tail = used > kPrefetchWords && kPrefetchWords + lane < used;
+        uint64_t t = 0;
+        if (tail) t = recw[k * kRecWords + kPrefetchWords + lane];
         const int64_t kn = cls + (int64_t)ncls * (int64_t)__shfl(tk, 0);
         if (kn < S) {
-            w0 = recw[kn * kRecWords + lane];
-            if (lane < kTail) w1 = recw[kn * kRecWords + kWave + lane];
+            if (lane < kPrefetchWords) w0 = recw[kn * kRecWords + lane];
             if (lane == 0) tk = atomicAdd(ticket, 1ull);
         }
+        if (tail) dst[kPrefetchWords + lane] = t;
         wave_sync();
-        const int nc = __builtin_amdgcn_readfirstlane(st.rec.nc);
         const bool ok = nc >= 2;
         // valid sides as wave-uniform bit masks: bit c of okp / okm when the
         // l+ / l- side with candidate c is not degenerate
@@ -342,10 +354,10 @@ __global__ __launch_bounds__(NW * kWave, 2) void k_search_ev(const int64_t *__re
             // side constants: lanes [0, nc) with l+, lanes [16, 16 + nc) with l-
             bool side_ok = false;
             if (lane < nc) {
-                side_ok = make_side(st.rec.lp, st.rec.cand[lane], st.sp[lane]);
+                side_ok = make_side(st.rec.lp, st.rec.cand[lane].v, st.sp[lane]);
             } else if (lane >= 16 && lane < 16 + nc) {
                 const int c = lane - 16;
-                side_ok = make_side(st.rec.lm, st.rec.cand[c], st.sm[c]);
+                side_ok = make_side(st.rec.lm, st.rec.cand[c].v, st.sm[c]);
             }
             const uint64_t okb = ballot(side_ok);
             okp = (uint32_t)okb & 0xffffu;
@@ -384,7 +396,7 @@ __global__ __launch_bounds__(NW * kWave, 2) void k_search_ev(const int64_t *__re
                         U4 raw{0u, 0u, 0u, 0u};
                         T zb[4] = {(T)0, (T)0, (T)0, (T)0};
                         for (int c = 0; c < nc; ++c) {
-                            const uint32_t slot = 4u + (uint32_t)__builtin_amdgcn_readfirstlane(st.rec.jidx[c]);
+                            const uint32_t slot = 4u + (uint32_t)__builtin_amdgcn_readfirstlane(st.rec.cand[c].jidx);
                             const uint32_t blk = slot >> 2;
                             if constexpr (sizeof(T) == sizeof(float)) {
                                 if (blk != last_blk) {
@@ -428,13 +440,13 @@ __global__ __launch_bounds__(NW * kWave, 2) void k_search_ev(const int64_t *__re
                                     (double)st.zl[2][lane] * st.zl[2][lane] + (double)st.zl[3][lane] * st.zl[3][lane];
                 for (int i = 0; i < nc; ++i) {
                     if (!((okp >> i) & 1u)) continue;
-                    const double si = smear(st.rec.sigma[i], st.z[i][lane]);
+                    const double si = smear(st.rec.cand[i].sigma, st.z[i][lane]);
                     const SideVar A = side_var(st.sp[i], Wp, slp, si, mt2_mw2);
                     const PencilP pa = pencil_p(A.q);
                     for (int j = 0; j < nc; ++j) {
                         if (j == i || !((okm >> j) & 1u)) continue;
                         // ---- the common points of this lane's two conics (its own variation)
-                        const double sj = smear(st.rec.sigma[j], st.z[j][lane]);
+                        const double sj = smear(st.rec.cand[j].sigma, st.z[j][lane]);
                         const SideVar Bv = side_var(st.sm[j], Wm, slm, sj, mt2_mw2);
                         const Conic Q = reflect(Bv.q, mx, my);
                         Points4 pts;
@@ -443,10 +455,10 @@ __global__ __launch_bounds__(NW * kWave, 2) void k_search_ev(const int64_t *__re
                         acc_int += 2 * (uint64_t)(popc64(ballot(pts.n > 0)) + popc64(ballot(pts.n > 2)));
                         const int p = i * nc + j;
                         // score terms of this variation that do not depend on the point
-                        const double bxs = si * st.rec.cand[i][1] + slp * st.rec.lp[1];
-                        const double bys = si * st.rec.cand[i][2] + slp * st.rec.lp[2];
-                        const double bxb = sj * st.rec.cand[j][1] + slm * st.rec.lm[1];
-                        const double byb = sj * st.rec.cand[j][2] + slm * st.rec.lm[2];
+                        const double bxs = si * st.rec.cand[i].v[1] + slp * st.rec.lp[1];
+                        const double bys = si * st.rec.cand[i].v[2] + slp * st.rec.lp[2];
+                        const double bxb = sj * st.rec.cand[j].v[1] + slm * st.rec.lm[1];
+                        const double byb = sj * st.rec.cand[j].v[2] + slm * st.rec.lm[2];
                         const double zzv = zz_l + (double)st.z[i][lane] * st.z[i][lane] +
                                            (double)st.z[j][lane] * st.z[j][lane];
 #pragma unroll
@@ -606,13 +618,13 @@ __global__ __launch_bounds__(256) void k_epilogue(EvView ev, const int64_t *__re
             const int64_t e = (int64_t)g - ev.index_base;  // in the chunk: a solution exists
             // the r.p-th ordered pair of the candidate list
             const int nc = r.nc, ci = r.p / nc, cj = r.p % nc;
-            const int jidx[2] = {rec.jidx[ci], rec.jidx[cj]};
+            const int jidx[2] = {rec.cand[ci].jidx, rec.cand[cj].jidx};
             double lp[4], lm[4], b[4], bb[4];
             for (int q = 0; q < 4; ++q) {
                 lp[q] = rec.lp[q];
                 lm[q] = rec.lm[q];
-                b[q] = rec.cand[ci][q];
-                bb[q] = rec.cand[cj][q];
+                b[q] = rec.cand[ci].v[q];
+                bb[q] = rec.cand[cj].v[q];
             }
             double sp[kSide], sm[kSide];
             make_side(lp, b, sp);
@@ -625,7 +637,7 @@ __global__ __launch_bounds__(256) void k_epilogue(EvView ev, const int64_t *__re
                 zj = gauss_slot<T>(a.seed, g, (uint32_t)r.v, 4u + (uint32_t)jidx[1]);
             }
             const double slp = smear(a.lep_sigma, zl[0]), slm = smear(a.lep_sigma, zl[1]);
-            const double si = smear(rec.sigma[ci], zi), sj = smear(rec.sigma[cj], zj);
+            const double si = smear(rec.cand[ci].sigma, zi), sj = smear(rec.cand[cj].sigma, zj);
             const double mx = rec.met[0] + a.met_sigma * (double)zl[2];
             const double my = rec.met[1] + a.met_sigma * (double)zl[3];
             const double mw2 = a.m_w * a.m_w, mt2_mw2 = a.m_t * a.m_t - mw2;

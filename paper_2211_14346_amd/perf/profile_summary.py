@@ -31,9 +31,9 @@ import os
 SEARCH = "k_search_ev<float>"
 SEMILEP = "k_semilep_tchan"
 TRACE_CMD = ("rocprofv3 --kernel-trace --stats -d <dir> -o run --output-format csv -- "
-             "python3 bench.py --profile-only --steps 5 --warmup 1 --no-stream")
+             "python3 bench.py --profile-only --steps 5 --warmup 1 --no-stream --no-workloads")
 PMC_CMD = ("rocprofv3 --pmc <counters> -d <dir> -o run --output-format csv -- "
-           "python3 bench.py --profile-only --steps 2 --warmup 1 --no-stream")
+           "python3 bench.py --profile-only --steps 2 --warmup 1 --no-stream --no-workloads")
 STREAM_TRACE_CMD = ("rocprofv3 --kernel-trace --stats -d <dir> -o run --output-format csv -- "
                     "python3 bench.py --stream-only --profile-only")
 CAL_CMD = ("rocprofv3 --pmc <FETCH_SIZE|WRITE_SIZE> -d <dir> -o run --output-format csv -- "
@@ -122,7 +122,7 @@ def main():
 
     if a.stream_trace:
         lines = ["# Kernel durations of the chunked stream, workload hlhc50M (1M-event chunks of mixed events "
-                 "from pinned host memory; dileptonic channel 6 cuts + quartic at 64 variations, one-lepton "
+                 "from pinned host memory; dileptonic channel 6 cuts + two-neutrino solve at 64 variations, one-lepton "
                  "channel 6 cuts + single-neutrino chi^2; 10 chunks after a full warm-up pass)",
                  f"# command: {STREAM_TRACE_CMD}", "",
                  f"{'kernel':40s} {'calls':>6s} {'avg_us':>10s} {'min_us':>10s} {'max_us':>10s} {'pct':>7s}"]
