@@ -96,6 +96,13 @@ def main():
     merged = {}
     for d in a.pmc:
         merged.update(counters(d))
+    # the search kernel is instantiated per workgroup size ("k_search_ev<float, 4>"):
+    # its counters go under the family name, the instance that ran is recorded
+    inst = sorted({k for k, _ in merged if k.startswith(SEARCH[:-1])})
+    if inst:
+        merged.update({(SEARCH, c): v for (k, c), v in list(merged.items()) if k == inst[0]})
+        for k in [k for k in merged if k[0] == inst[0]]:
+            del merged[k]
     kernels = sorted({k for k, _ in merged if k.startswith("k_")}, key=lambda k: (k != SEARCH, k))
     names = sorted({c for _, c in merged})
     lines = ["# Per-dispatch counters, bench workload ttbar1M_v64 (mixed precision)",
@@ -114,7 +121,8 @@ def main():
     sw = merged.get((SEARCH, "WRITE_SIZE"))
     if sf and sw:
         fb, wb = sf[0] * 1024.0 * fetch_f, sw[0] * 1024.0 * write_f
-        lines += ["", f"search_kernel: {SEARCH}", f"search_fetch_bytes_per_launch: {fb:.0f}",
+        lines += ["", f"search_kernel: {SEARCH}", f"search_instance: {inst[0] if inst else SEARCH}",
+                  f"search_fetch_bytes_per_launch: {fb:.0f}",
                   f"search_write_bytes_per_launch: {wb:.0f}", f"search_traffic_bytes_per_launch: {fb + wb:.0f}",
                   f"search_source_hash: {a.hash}"]
     with open(os.path.join(a.out, "k_search_ttbar1M_v64_counters.txt"), "w") as f:
@@ -122,8 +130,10 @@ def main():
 
     if a.stream_trace:
         lines = ["# Kernel durations of the chunked stream, workload hlhc50M (1M-event chunks of mixed events "
-                 "from pinned host memory; dileptonic channel 6 cuts + two-neutrino solve at 64 variations, one-lepton "
-                 "channel 6 cuts + single-neutrino chi^2; 10 chunks after a full warm-up pass)",
+                 "from pinned host memory through the five signal bins of section 6.1 -- semileptonic and "
+                 "dileptonic ttbar, t-channel, semileptonic and dileptonic Wt -- each a cut chain ending in its "
+                 "reconstruction: single-neutrino chi^2 (ttbar, t-channel, Wt topologies), the two-neutrino solve "
+                 "at 64 variations, the MET-split chi^2 with one top; 10 chunks after a full warm-up pass)",
                  f"# command: {STREAM_TRACE_CMD}", "",
                  f"{'kernel':40s} {'calls':>6s} {'avg_us':>10s} {'min_us':>10s} {'max_us':>10s} {'pct':>7s}"]
         for name, calls, avg, mn, mx, pct in kernel_stats(a.stream_trace):
