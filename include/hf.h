@@ -201,12 +201,13 @@ int hf_compact_noalloc(const uint8_t *d_mask, int64_t capacity, const int64_t *d
 /* ------------------------------------------------------- reconstruction */
 
 #define HF_PREC_FP64 0  /* every step in FP64 */
-#define HF_PREC_MIXED 1 /* the Box-Muller transcendentals of the draws and the cubic
-                           that seeds the critical points of the eliminant in FP32;
-                           kinematic staging, smear factors, linear maps, eliminant
-                           assembly, root polishing, back-substitution and scores in
-                           FP64 (FP32 staging and smearing miss the 1e-4 agreement
-                           with the FP64 oracle on near-tangent solutions) */
+#define HF_PREC_MIXED 1 /* the Box-Muller transcendentals of the draws and the
+                           closed-form seed of the pencil cubic's isolated root in
+                           FP32 (refined in FP64); kinematic staging, smear
+                           factors, linear maps, the pencil and its line pair,
+                           polish and scores in FP64 (FP32 staging and smearing
+                           miss the 1e-4 agreement with the FP64 oracle on
+                           near-tangent solutions) */
 #define HF_PAIR_BTAG_FILL 0 /* b candidates: tagged selected jets in input order
                                (descending pT), at most max_cands, filled up to two
                                with the leading untagged selected jets */
