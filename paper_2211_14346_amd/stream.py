@@ -141,7 +141,7 @@ class DeviceSlot:
 
 class Channel:
     """One analysis channel: a cut chain ending in a reconstruction (the
-    dileptonic quartic with `reco`, the single-neutrino chi^2 with `semilep`
+    dileptonic two-neutrino solve with `reco`, the single-neutrino chi^2 with `semilep`
     and `topology`, or the dileptonic chi^2 fit with a MET split with
     `chi2`), with its counters and cut order."""
 
