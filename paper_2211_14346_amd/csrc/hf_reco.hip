@@ -352,13 +352,12 @@ __global__ __launch_bounds__(NW * kWave, 2) void k_search_ev(const int64_t *__re
         uint32_t okp = 0, okm = 0;
         if (ok) {
             // side constants: lanes [0, nc) with l+, lanes [16, 16 + nc) with l-
+            // (one call on per-lane operands, not one branch per lepton)
             bool side_ok = false;
-            if (lane < nc) {
-                side_ok = make_side(st.rec.lp, st.rec.cand[lane].v, st.sp[lane]);
-            } else if (lane >= 16 && lane < 16 + nc) {
-                const int c = lane - 16;
-                side_ok = make_side(st.rec.lm, st.rec.cand[c].v, st.sm[c]);
-            }
+            const bool minus = lane >= 16;
+            const int c = lane & 15;
+            if (c < nc && lane < 32)
+                side_ok = make_side(minus ? st.rec.lm : st.rec.lp, st.rec.cand[c].v, minus ? st.sm[c] : st.sp[c]);
             const uint64_t okb = ballot(side_ok);
             okp = (uint32_t)okb & 0xffffu;
             okm = (uint32_t)(okb >> 16) & 0xffffu;
