@@ -527,43 +527,46 @@ __global__ __launch_bounds__(kBlock) void k_chi2(EvView ev, const int32_t *__res
                 }
             }
             have = bval < INFINITY;  // no p_z candidate at all (a lepton with E = |p_z|) leaves none
-            if (have && lane == 0) {
-                // the winner's kinematics, in the definition's order of operations
-                const int i = bpk & 15, j = (bpk >> 4) & 15, r1 = (bpk >> 8) & 1, r2 = (bpk >> 9) & 1;
-                const double n1x = 0.5 * mx + bu, n1y = 0.5 * my + bv, n2x = 0.5 * mx - bu, n2y = 0.5 * my - bv;
-                const Side P = side(LP, n1x, n1y, a), M = side(LM, n2x, n2y, a);
-                const double z1 = at2(P.pz, r1), z2 = at2(M.pz, r2);
-                const double nu[4] = {sqrt(n1x * n1x + n1y * n1y + z1 * z1), n1x, n1y, z1};
-                const double nb[4] = {sqrt(n2x * n2x + n2y * n2y + z2 * z2), n2x, n2y, z2};
-                // one top: index 15 marks the side without it
-                const bool has_t = i != 15, has_tb = j != 15;
-                double wp[4], wm[4], tp[4], tm[4];
-                for (int c = 0; c < 4; ++c) {
-                    wp[c] = lp[c] + nu[c];
-                    wm[c] = lm[c] + nb[c];
-                    tp[c] = (has_t ? cv[4 * i + c] : 0.0) + wp[c];
-                    tm[c] = (has_tb ? cv[4 * j + c] : 0.0) + wm[c];
+            if (have) {
+                // the winner's kinematics, in the definition's order of operations:
+                // lane 0 the l+ side (nu, its W and top), lane 1 the l- side
+                const bool minus = lane == 1;
+                double ct = 0.0, cwt = 0.0;
+                if (lane < 2) {
+                    const int i = bpk & 15, j = (bpk >> 4) & 15, r1 = (bpk >> 8) & 1, r2 = (bpk >> 9) & 1;
+                    const int c = minus ? j : i, r = minus ? r2 : r1;
+                    const double nx = minus ? 0.5 * mx - bu : 0.5 * mx + bu;
+                    const double ny = minus ? 0.5 * my - bv : 0.5 * my + bv;
+                    const Side S = side(minus ? LM : LP, nx, ny, a);
+                    const double z = at2(S.pz, r);
+                    const double nu[4] = {sqrt(nx * nx + ny * ny + z * z), nx, ny, z};
+                    // one top: index 15 marks the side without it
+                    const bool has_top = c != 15;
+                    const double *l = minus ? lm : lp;
+                    double w[4], t[4];
+                    for (int q = 0; q < 4; ++q) {
+                        w[q] = l[q] + nu[q];
+                        t[q] = (has_top ? cv[4 * c + q] : 0.0) + w[q];
+                    }
+                    const double mw = mass4(w[0], w[1], w[2], w[3]), mt = mass4(t[0], t[1], t[2], t[3]);
+                    const double st2 = a.sigma_t * a.sigma_t, sw2 = a.sigma_w * a.sigma_w;
+                    ct = has_top ? sq(mt - a.m_t) / st2 : 0.0;
+                    cwt = sq(mw - a.m_w) / sw2;
+                    (minus ? o.root_nubar : o.root_nu)[k] = (int8_t)at2(S.kind, r);
+                    (minus ? o.best_j : o.best_i)[k] = (int16_t)(has_top ? s_loc[wave][c] : -1);
+                    double *onu = minus ? o.nubar : o.nu;
+                    for (int q = 0; q < 3; ++q) onu[3 * k + q] = nu[q + 1];
+                    (minus ? o.m_tbar : o.m_t)[k] = has_top ? mt : HF_NO_SOLUTION;
+                    (minus ? o.m_wm : o.m_wp)[k] = mw;
                 }
-                const double mwp = mass4(wp[0], wp[1], wp[2], wp[3]), mwm = mass4(wm[0], wm[1], wm[2], wm[3]);
-                const double mt = mass4(tp[0], tp[1], tp[2], tp[3]), mtb = mass4(tm[0], tm[1], tm[2], tm[3]);
-                const double st2 = a.sigma_t * a.sigma_t, sw2 = a.sigma_w * a.sigma_w;
-                o.has_sol[k] = 1;
-                o.root_nu[k] = (int8_t)at2(P.kind, r1);
-                o.root_nubar[k] = (int8_t)at2(M.kind, r2);
-                o.best_i[k] = (int16_t)(has_t ? s_loc[wave][i] : -1);
-                o.best_j[k] = (int16_t)(has_tb ? s_loc[wave][j] : -1);
-                for (int c = 0; c < 3; ++c) {
-                    o.nu[3 * k + c] = nu[c + 1];
-                    o.nubar[3 * k + c] = nb[c + 1];
+                // the l- terms to lane 0, summed in the definition's order
+                const double ct_m = __shfl(ct, 1), cw_m = __shfl(cwt, 1);
+                if (lane == 0) {
+                    o.has_sol[k] = 1;
+                    o.chi2[k] = ct + cwt + ct_m + cw_m;
+                    o.split[2 * k] = bu;
+                    o.split[2 * k + 1] = bv;
                 }
-                o.m_t[k] = has_t ? mt : HF_NO_SOLUTION;
-                o.m_tbar[k] = has_tb ? mtb : HF_NO_SOLUTION;
-                o.m_wp[k] = mwp;
-                o.m_wm[k] = mwm;
-                o.chi2[k] = (has_t ? sq(mt - a.m_t) / st2 : 0.0) + sq(mwp - a.m_w) / sw2 +
-                            (has_tb ? sq(mtb - a.m_t) / st2 : 0.0) + sq(mwm - a.m_w) / sw2;
-                o.split[2 * k] = bu;
-                o.split[2 * k + 1] = bv;
             }
         }
         if (!have && lane == 0) {
