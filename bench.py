@@ -529,7 +529,7 @@ def stream_leg(args, torch):
     torch.cuda.synchronize()
     dt_plain = time.perf_counter() - t3
     leg = {"metric": "events/s end to end, pinned host chunks -> the five HL-LHC signal bins (37 cuts; "
-                     "single-neutrino chi^2 x3, dileptonic quartic @64 variations, chi^2 fit with a MET split)",
+                     "single-neutrino chi^2 x3, dileptonic two-neutrino solve @64 variations, chi^2 fit with a MET split)",
            "value": round(n / dt, 1), "unit": "events/s", "dtype": "f32+f64",
            "ms_per_chunk": round(1e3 * dt / n_chunks, 4),
            "config": {"workload": STREAM_WORKLOAD, "events": n, "chunk": m, "chunks": n_chunks,

@@ -219,7 +219,8 @@ def chains_hlhc_bins():
 
 
 # Reconstruction of each bin: the single-neutrino chi^2 in its topology, the
-# two-neutrino quartic at the configuration's variations, or the dileptonic
+# two-neutrino solve ("quartic": up to four solutions per pairing) at the
+# configuration's variations, or the dileptonic
 # chi^2 fit with a MET split with one top (Wt: one top and two W bosons).
 HLHC_BIN_RECO = {
     "ttsemi": ("semilep", "TTSEMI"),
