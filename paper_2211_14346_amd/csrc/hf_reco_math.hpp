@@ -24,9 +24,6 @@
 
 // Host-and-device so that the numerics can also be exercised on the CPU.
 #define HF_HD __host__ __device__
-#ifndef HF_ITER_HOOK
-#define HF_ITER_HOOK()
-#endif
 
 namespace hf {
 
@@ -328,10 +325,6 @@ HF_HD __forceinline__ double polish_xy(const Conic &P, const Conic &Q, double &x
 struct Sym3 {
     double a00, a01, a02, a11, a12, a22;
 };
-
-HF_HD __forceinline__ Sym3 sym_conic(const Conic &q) {
-    return Sym3{q.xx, 0.5 * q.xy, 0.5 * q.x, q.yy, 0.5 * q.y, q.c};
-}
 
 HF_HD __forceinline__ Sym3 sym_adj(const Sym3 &a) {
     return Sym3{a.a11 * a.a22 - a.a12 * a.a12, a.a02 * a.a12 - a.a01 * a.a22, a.a01 * a.a12 - a.a02 * a.a11,
