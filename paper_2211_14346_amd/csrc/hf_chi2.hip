@@ -10,10 +10,16 @@
 // [-half_range, half_range]^2 and refined n_refine times on a 5 x 5 grid
 // around the best point at a quarter of the previous step.
 //
-// One wavefront per compacted event, lanes over grid points.  The wave
-// stages its event cooperatively (lanes over the objects, ballots for the
-// selection and the candidate order), keeping the leptons' and candidates'
-// FP64 4-vectors in LDS.  At a grid point chi^2 separates: the l+ side
+// A block of four wavefronts takes four compacted events, one per
+// wavefront, lanes over grid points.  A lead wavefront stages all four
+// (sixteen lanes per event: the objects' columns loaded at once, ballots for
+// the selection and the candidate order, each object the fit uses converted
+// on the lane holding it) and forms the split-independent lepton terms,
+// keeping FP64 4-vectors in LDS; after a barrier every wavefront scans its
+// own event's grid; after another the lead wavefront writes the four events'
+// outputs, two lanes per event.  Staging and outputs touch a few lanes per
+// event, so sharing one wavefront between four events cuts their issued
+// instructions fourfold.  At a grid point chi^2 separates: the l+ side
 // depends on (i, r1) only and the l- side on (j, r2) only, so a lane forms
 // A+(i) = min over r1 of chi_t + chi_W for every candidate i, A-(j) likewise,
 // and the best ordered pairing i != j from the smallest two A- values, at
@@ -35,6 +41,7 @@ constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / kWave;
 constexpr int kMaxC = HF_MAX_CANDS;
 constexpr int kRefPts = 25;  // points of a refinement level (5 x 5)
+constexpr int kSeg = kWave / kWaves;  // staging lanes per event
 
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
@@ -302,274 +309,353 @@ __device__ __forceinline__ void wave_argmin(double &val, int &pidx, int &packed)
     packed = __shfl(packed, wl);
 }
 
+// Lep fields in LDS: the 4-vector, then c0, qa, inv_qa, inv_e
+__device__ __forceinline__ void put_lep(double *d, const Lep &L) {
+    for (int c = 0; c < 4; ++c) d[c] = L.l[c];
+    d[4] = L.c0;
+    d[5] = L.qa;
+    d[6] = L.inv_qa;
+    d[7] = L.inv_e;
+}
+
+__device__ __forceinline__ Lep get_lep(const double *d) {
+    Lep L;
+    for (int c = 0; c < 4; ++c) L.l[c] = d[c];
+    L.c0 = d[4];
+    L.qa = d[5];
+    L.inv_qa = d[6];
+    L.inv_e = d[7];
+    return L;
+}
+
+__device__ __forceinline__ int uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
+
 __global__ __launch_bounds__(kBlock) void k_chi2(EvView ev, const int32_t *__restrict__ idx,
                                                  const int64_t *__restrict__ count, int64_t capacity, Chi2Args a,
                                                  Chi2OutView o, hf_counters_t *__restrict__ counter) {
-    __shared__ double s_lep[kWaves][8];
-    __shared__ double s_cv[kWaves][kMaxC * 4];
+    // one event per wavefront: event kb + w for wavefront w of the block
+    __shared__ double s_lep[kWaves][8];       // the first two selected leptons
+    __shared__ double s_cv[kWaves][kMaxC * 4];  // the b candidates
+    __shared__ double s_fv[kWaves][8];        // the first two untagged selected jets
+    __shared__ double s_L[kWaves][2][8];      // Lep of l+ and l-
+    __shared__ double s_met[kWaves][2];
+    __shared__ double s_res[kWaves][3];       // best split (u, v) and chi^2
     __shared__ int s_loc[kWaves][kMaxC];
-    __shared__ uint32_t s_pass[kWaves];
+    __shared__ int s_floc[kWaves][2];
+    __shared__ int s_evi[kWaves][2];          // fit (0/1), candidate count
+    __shared__ int s_pk[kWaves];              // best packed pairing and roots
+    __shared__ float s_q[kWaves][2];          // charges of the first two selected leptons
     __shared__ double s_t[kWaves][kRefPts][kMaxC];  // refinement: l+ term per point and candidate
     __shared__ int s_r[kWaves][kRefPts][kMaxC];     // and its p_z root
     const int wave = threadIdx.x / kWave, lane = lane_id();
     const int64_t S = clamp_count(count, capacity);
-    const int64_t k = (int64_t)blockIdx.x * kWaves + wave;
-    bool have = false;
-    if (k < S) {
-        const int64_t e = (int64_t)idx[k] - ev.index_base;
-        int nc = 0;
-        bool ok = false;
-        if (e >= 0 && e < ev.n) {
-            // ---- leptons: exactly two selected, opposite charges; l+ first
-            const uint32_t l0 = ev.lep_off[e], l1 = ev.lep_off[e + 1];
-            int nl = 0;
-            uint32_t ka = 0, kb = 0;
-            for (uint32_t c0 = l0; c0 < l1; c0 += kWave) {
-                const uint32_t q = c0 + lane;
-                const bool in = q < l1;
-                const float pt = in ? ev.lep_pt[q] : 0.0f, eta = in ? ev.lep_eta[q] : 0.0f;
-                uint64_t m = ballot(in && pt > a.lep_pt_min && fabsf(eta) < a.lep_eta_max);
-                while (m && nl < 2) {
-                    const uint32_t b = c0 + (uint32_t)(__ffsll((unsigned long long)m) - 1);
-                    if (nl == 0) ka = b;
-                    else kb = b;
-                    ++nl;
-                    m &= m - 1;
-                }
-                nl += popc64(m);
-            }
-            if (nl == 2 && ev.lep_q[ka] * ev.lep_q[kb] < 0.0f) {
-                const uint32_t kp = ev.lep_q[ka] > 0.0f ? ka : kb, km = ev.lep_q[ka] > 0.0f ? kb : ka;
-                // ---- b candidates: tagged selected jets in order (or all selected), capped,
-                // filled up to two with the leading untagged selected jets
-                const uint32_t j0 = ev.jet_off[e], j1 = ev.jet_off[e + 1];
-                const bool all = a.pair_mode == HF_PAIR_ALL_JETS;
-                int nfill = 0;
-                uint32_t f0 = 0, f1 = 0;
-                for (uint32_t c0 = j0; c0 < j1; c0 += kWave) {
-                    const uint32_t q = c0 + lane;
-                    const bool in = q < j1;
-                    const float pt = in ? ev.jet_pt[q] : 0.0f, eta = in ? ev.jet_eta[q] : 0.0f;
-                    const float bt = in ? ev.jet_btag[q] : 0.0f;
-                    const bool sel = in && pt > a.jet_pt_min && fabsf(eta) < a.jet_eta_max;
-                    const bool tag = all || bt > a.btag_min;
-                    const uint64_t mt = ballot(sel && tag);
-                    uint64_t mu = ballot(sel && !tag);
-                    const int pos = nc + popc64(mt & lanemask_lt());
-                    if (sel && tag && pos < a.max_cands) s_loc[wave][pos] = (int)(q - j0);
-                    nc = min(a.max_cands, nc + popc64(mt));
-                    while (mu && nfill < 2) {
-                        const uint32_t b = c0 + (uint32_t)(__ffsll((unsigned long long)mu) - 1);
-                        if (nfill == 0) f0 = b;
-                        else f1 = b;
-                        ++nfill;
-                        mu &= mu - 1;
-                    }
-                    nfill += popc64(mu);
-                }
-                if (!all) {
-                    if (nc < 2 && nfill > 0) {
-                        if (lane == 0) s_loc[wave][nc] = (int)(f0 - j0);
-                        ++nc;
-                    }
-                    if (nc < 2 && nfill > 1) {
-                        if (lane == 0) s_loc[wave][nc] = (int)(f1 - j0);
-                        ++nc;
-                    }
-                }
-                wave_sync();
-                ok = nc >= (a.n_top == 1 ? 1 : 2);
-                if (ok) {
-                    // candidates on lanes [0, nc), l+ and l- on the last two lanes: one
-                    // conversion on per-lane columns rather than one per object kind
-                    const bool isj = lane < nc, isl = lane >= kWave - 2;
-                    if (isj || isl) {
-                        const float *cpt = isj ? ev.jet_pt : ev.lep_pt, *ceta = isj ? ev.jet_eta : ev.lep_eta;
-                        const float *cphi = isj ? ev.jet_phi : ev.lep_phi, *ce = isj ? ev.jet_e : ev.lep_e;
-                        const uint32_t q = isj ? j0 + (uint32_t)s_loc[wave][lane] : (lane == kWave - 1 ? kp : km);
-                        double v[4];
-                        to_cart(cpt[q], ceta[q], cphi[q], ce[q], v);
-                        double *dst = isj ? &s_cv[wave][4 * lane] : &s_lep[wave][lane == kWave - 1 ? 0 : 4];
-                        for (int c = 0; c < 4; ++c) dst[c] = v[c];
-                    }
-                    wave_sync();
-                }
+    const int64_t kb = (int64_t)blockIdx.x * kWaves;  // the block's first event
+    if (kb >= S) {
+        if (threadIdx.x == 0 && counter && blockIdx.x == 0)
+            atomicAdd((unsigned long long *)&counter->reached, (unsigned long long)S);
+        return;
+    }
+    const int need = a.n_top == 1 ? 1 : 2;
+    // the block's lead wavefront stages all four events and writes their outputs;
+    // which one it is rotates with the block, so that no SIMD takes every block's share
+    const int lead = (int)(blockIdx.x & (kWaves - 1));
+    if (wave == lead) {
+        // ---- staging, by the lead wavefront for all of the block's events: lanes
+        // [kSeg s, kSeg (s + 1)) over the objects of event kb + s, leptons then jets,
+        // every column loaded at once.  The first two selected leptons go to slots 0
+        // and 1 by selection rank; the tagged selected jets (or all selected jets) to
+        // candidate slots in input order, capped; the first two untagged selected jets
+        // to filler slots.  Each object the fit uses is converted on the lane that
+        // holds it.
+        const int seg = lane / kSeg, sl = lane % kSeg, shift = seg * kSeg;
+        const int64_t ks = kb + seg;
+        uint32_t l0 = 0, j0 = 0, nlep = 0, nobj = 0;
+        float fmx = 0.0f, fmy = 0.0f;
+        if (ks < S) {
+            const int64_t e = (int64_t)idx[ks] - ev.index_base;
+            if (e >= 0 && e < ev.n) {
+                l0 = ev.lep_off[e];
+                j0 = ev.jet_off[e];
+                const uint32_t l1 = ev.lep_off[e + 1], j1 = ev.jet_off[e + 1];
+                fmx = ev.met_x[e];
+                fmy = ev.met_y[e];
+                nlep = l1 > l0 ? l1 - l0 : 0u;
+                nobj = nlep + (j1 > j0 ? j1 - j0 : 0u);
             }
         }
-        if (ok) {
-            const double mx = (double)ev.met_x[e], my = (double)ev.met_y[e];
-            const double *lp = &s_lep[wave][0], *lm = &s_lep[wave][4], *cv = &s_cv[wave][0];
-            const Lep LP = make_lep(lp, a), LM = make_lep(lm, a);
-            // ---- coarse grid
-            const int N = a.n_grid;
-            double step = 2.0 * a.half_range / (double)(N - 1);
-            double bval = INFINITY, bu = 0.0, bv = 0.0;
-            int bpk = 0;
-            {
-                double val = INFINITY;
-                int pidx = 0x7fffffff, pk = 0;
-                // row and column of point p = p0 + lane, advanced by 64 points per pass
-                // (no integer division in the loop)
-                int row = lane / N, col = lane % N;
-                const int drow = kWave / N, dcol = kWave % N;
-                for (int p0 = 0; p0 < N * N; p0 += kWave) {
-                    const int p = p0 + lane;
-                    if (p < N * N) {
-                        int q;
-                        const double pu = -a.half_range + step * row, pv = -a.half_range + step * col;
-                        const double t = a.n_top == 1 ? point_best1(LP, LM, cv, nc, mx, my, pu, pv, a, q)
-                                                      : point_best(LP, LM, cv, nc, mx, my, pu, pv, a, q);
-                        if (t < val) {
-                            val = t;
-                            pidx = p;
-                            pk = q;
-                        }
-                    }
-                    row += drow;
-                    col += dcol;
-                    if (col >= N) {
-                        col -= N;
-                        ++row;
+        const bool all = a.pair_mode == HF_PAIR_ALL_JETS;
+        const uint32_t segmask = (uint32_t)((1ull << kSeg) - 1ull), below = (1u << sl) - 1u;
+        int nl = 0, ncand = 0, nfill = 0;
+        for (uint32_t c0 = 0; ballot(c0 < nobj); c0 += kSeg) {
+            const uint32_t o = c0 + (uint32_t)sl;
+            const bool in = o < nobj, isl = o < nlep;
+            const uint32_t q = isl ? l0 + o : j0 + (o - nlep);
+            float pt = 0.0f, eta = 0.0f, phi = 0.0f, en = 0.0f, aux = 0.0f;
+            if (in) {
+                pt = (isl ? ev.lep_pt : ev.jet_pt)[q];
+                eta = (isl ? ev.lep_eta : ev.jet_eta)[q];
+                phi = (isl ? ev.lep_phi : ev.jet_phi)[q];
+                en = (isl ? ev.lep_e : ev.jet_e)[q];
+                aux = (isl ? ev.lep_q : ev.jet_btag)[q];
+            }
+            const bool lsel = in && isl && pt > a.lep_pt_min && fabsf(eta) < a.lep_eta_max;
+            const bool jsel = in && !isl && pt > a.jet_pt_min && fabsf(eta) < a.jet_eta_max;
+            const bool tag = all || aux > a.btag_min;
+            const uint32_t ml = (uint32_t)(ballot(lsel) >> shift) & segmask;
+            const uint32_t mt = (uint32_t)(ballot(jsel && tag) >> shift) & segmask;
+            const uint32_t mu = (uint32_t)(ballot(jsel && !tag) >> shift) & segmask;
+            const int lrank = nl + __popc(ml & below);
+            const int pos = ncand + __popc(mt & below);
+            const int frank = nfill + __popc(mu & below);
+            double *dst = nullptr;
+            if (lsel && lrank < 2) {
+                dst = &s_lep[seg][4 * lrank];
+                s_q[seg][lrank] = aux;
+            } else if (jsel && tag && pos < a.max_cands) {
+                dst = &s_cv[seg][4 * pos];
+                s_loc[seg][pos] = (int)(q - j0);
+            } else if (jsel && !tag && frank < 2) {
+                dst = &s_fv[seg][4 * frank];
+                s_floc[seg][frank] = (int)(q - j0);
+            }
+            if (dst) {
+                double v[4];
+                to_cart(pt, eta, phi, en, v);
+                for (int c = 0; c < 4; ++c) dst[c] = v[c];
+            }
+            nl += __popc(ml);
+            ncand = min(a.max_cands, ncand + __popc(mt));
+            nfill += __popc(mu);
+        }
+        wave_sync();
+        // exactly two selected leptons of opposite charges, l+ the positive one; fewer
+        // than two candidates: the leading untagged selected jets fill
+        int ok = 0, prank = 0;
+        if (nl == 2 && s_q[seg][0] * s_q[seg][1] < 0.0f) {
+            prank = s_q[seg][0] > 0.0f ? 0 : 1;
+            const int nf = (all || ncand >= 2) ? 0 : min(nfill, 2 - ncand);
+            if (sl < 4 * nf) s_cv[seg][4 * ncand + sl] = s_fv[seg][sl];
+            if (sl < nf) s_loc[seg][ncand + sl] = s_floc[seg][sl];
+            ncand += nf;
+            ok = ncand >= need ? 1 : 0;
+        }
+        if (sl == 0) {
+            s_evi[seg][0] = ok;
+            s_evi[seg][1] = ncand;
+            s_met[seg][0] = (double)fmx;
+            s_met[seg][1] = (double)fmy;
+        }
+        // the split-independent lepton terms, lanes 2 s (l+) and 2 s + 1 (l-)
+        const int src = ((lane >> 1) & (kWaves - 1)) * kSeg;
+        const int prank_of = __shfl(prank, src), ok_of = __shfl(ok, src);
+        if (lane < 2 * kWaves && ok_of) {
+            const int s = lane >> 1, r = (lane & 1) ? 1 - prank_of : prank_of;
+            put_lep(&s_L[s][lane & 1][0], make_lep(&s_lep[s][4 * r], a));
+        }
+    }
+    __syncthreads();
+
+    // ---- the grid scan of the wavefront's event, over all lanes
+    if (kb + wave < S && uniform(s_evi[wave][0])) {
+        const int nc = uniform(s_evi[wave][1]);
+        const Lep LP = get_lep(&s_L[wave][0][0]), LM = get_lep(&s_L[wave][1][0]);
+        const double mx = s_met[wave][0], my = s_met[wave][1];
+        const double *cv = &s_cv[wave][0];
+        // ---- coarse grid
+        const int N = a.n_grid;
+        double step = 2.0 * a.half_range / (double)(N - 1);
+        double bval = INFINITY, bu = 0.0, bv = 0.0;
+        int bpk = 0;
+        {
+            double val = INFINITY;
+            int pidx = 0x7fffffff, pk = 0;
+            // row and column of point p = p0 + lane, advanced by 64 points per pass
+            // (no integer division in the loop)
+            int row = lane / N, col = lane % N;
+            const int drow = kWave / N, dcol = kWave % N;
+            for (int p0 = 0; p0 < N * N; p0 += kWave) {
+                const int p = p0 + lane;
+                if (p < N * N) {
+                    int q;
+                    const double pu = -a.half_range + step * row, pv = -a.half_range + step * col;
+                    const double t = a.n_top == 1 ? point_best1(LP, LM, cv, nc, mx, my, pu, pv, a, q)
+                                                  : point_best(LP, LM, cv, nc, mx, my, pu, pv, a, q);
+                    if (t < val) {
+                        val = t;
+                        pidx = p;
+                        pk = q;
                     }
                 }
-                wave_argmin(val, pidx, pk);
+                row += drow;
+                col += dcol;
+                if (col >= N) {
+                    col -= N;
+                    ++row;
+                }
+            }
+            wave_argmin(val, pidx, pk);
+            bval = val;
+            bpk = pk;
+            bu = -a.half_range + step * (pidx / N);
+            bv = -a.half_range + step * (pidx % N);
+        }
+        // ---- refinements: 5 x 5 around the best point, a quarter of the step.
+        // 25 points would leave most lanes idle, so the two lepton sides go to
+        // different lanes: lanes [0, 25) take the l+ side of point q = lane and
+        // keep each candidate's term in LDS, lanes [32, 57) the l- side of point
+        // q = lane - 32 and keep its two smallest terms, which then go to the l+
+        // lane of the same point (the same operations as point_best).
+        for (int level = 0; level < a.n_refine && a.n_top == 1; ++level) {
+            // one top: lanes [0, 25) take the whole point
+            step *= 0.25;
+            double val = INFINITY;
+            int pidx = 0x7fffffff, pk = 0;
+            if (lane < kRefPts) {
+                const double u = bu + step * (lane / 5 - 2), v = bv + step * (lane % 5 - 2);
+                val = point_best1(LP, LM, cv, nc, mx, my, u, v, a, pk);
+                pidx = lane;
+            }
+            wave_argmin(val, pidx, pk);
+            if (val < bval) {
                 bval = val;
                 bpk = pk;
-                bu = -a.half_range + step * (pidx / N);
-                bv = -a.half_range + step * (pidx % N);
-            }
-            // ---- refinements: 5 x 5 around the best point, a quarter of the step.
-            // 25 points would leave most lanes idle, so the two lepton sides go to
-            // different lanes: lanes [0, 25) take the l+ side of point q = lane and
-            // keep each candidate's term in LDS, lanes [32, 57) the l- side of point
-            // q = lane - 32 and keep its two smallest terms, which then go to the l+
-            // lane of the same point (the same operations as point_best).
-            for (int level = 0; level < a.n_refine && a.n_top == 1; ++level) {
-                // one top: lanes [0, 25) take the whole point
-                step *= 0.25;
-                double val = INFINITY;
-                int pidx = 0x7fffffff, pk = 0;
-                if (lane < kRefPts) {
-                    const double u = bu + step * (lane / 5 - 2), v = bv + step * (lane % 5 - 2);
-                    val = point_best1(LP, LM, cv, nc, mx, my, u, v, a, pk);
-                    pidx = lane;
-                }
-                wave_argmin(val, pidx, pk);
-                if (val < bval) {
-                    bval = val;
-                    bpk = pk;
-                    bu = bu + step * (pidx / 5 - 2);
-                    bv = bv + step * (pidx % 5 - 2);
-                }
-            }
-            for (int level = 0; level < a.n_refine && a.n_top != 1; ++level) {
-                step *= 0.25;
-                const bool plus = lane < 32;
-                const int q = plus ? lane : lane - 32;
-                double va = INFINITY, vb = INFINITY;
-                int ja = -1, jb = -1, ra = 0, rb = 0;
-                if (q < kRefPts) {
-                    const double u = bu + step * (q / 5 - 2), v = bv + step * (q % 5 - 2);
-                    const Side Sd = plus ? side(LP, 0.5 * mx + u, 0.5 * my + v, a)
-                                         : side(LM, 0.5 * mx - u, 0.5 * my - v, a);
-                    for (int c = 0; c < nc; ++c) {
-                        int r;
-                        const double t = side_min(cv + 4 * c, Sd, a, r);
-                        if (plus) {
-                            s_t[wave][q][c] = t;
-                            s_r[wave][q][c] = r;
-                        } else if (t < va) {
-                            vb = va;
-                            jb = ja;
-                            rb = ra;
-                            va = t;
-                            ja = c;
-                            ra = r;
-                        } else if (t < vb) {
-                            vb = t;
-                            jb = c;
-                            rb = r;
-                        }
-                    }
-                }
-                wave_sync();
-                const int src = (lane + 32) & (kWave - 1);
-                const double mva = __shfl(va, src), mvb = __shfl(vb, src);
-                const int mja = __shfl(ja, src), mjb = __shfl(jb, src);
-                const int mra = __shfl(ra, src), mrb = __shfl(rb, src);
-                double val = INFINITY;
-                int pidx = 0x7fffffff, pk = 0;
-                if (plus && q < kRefPts) {
-                    double best = INFINITY;
-                    int packed = 0;
-                    for (int i = 0; i < nc; ++i) {
-                        const double t1 = s_t[wave][q][i];
-                        const int r1 = s_r[wave][q][i];
-                        const bool other = i != mja;
-                        const int j = other ? mja : mjb;
-                        const double t = t1 + (other ? mva : mvb);
-                        if (j >= 0 && t < best) {
-                            best = t;
-                            packed = i | (j << 4) | (r1 << 8) | ((other ? mra : mrb) << 9);
-                        }
-                    }
-                    val = best;
-                    pidx = q;
-                    pk = packed;
-                }
-                wave_argmin(val, pidx, pk);
-                wave_sync();  // the next level overwrites the l+ terms
-                if (val < bval) {
-                    bval = val;
-                    bpk = pk;
-                    bu = bu + step * (pidx / 5 - 2);
-                    bv = bv + step * (pidx % 5 - 2);
-                }
-            }
-            have = bval < INFINITY;  // no p_z candidate at all (a lepton with E = |p_z|) leaves none
-            if (have) {
-                // the winner's kinematics, in the definition's order of operations:
-                // lane 0 the l+ side (nu, its W and top), lane 1 the l- side
-                const bool minus = lane == 1;
-                double ct = 0.0, cwt = 0.0;
-                if (lane < 2) {
-                    const int i = bpk & 15, j = (bpk >> 4) & 15, r1 = (bpk >> 8) & 1, r2 = (bpk >> 9) & 1;
-                    const int c = minus ? j : i, r = minus ? r2 : r1;
-                    const double nx = minus ? 0.5 * mx - bu : 0.5 * mx + bu;
-                    const double ny = minus ? 0.5 * my - bv : 0.5 * my + bv;
-                    const Side S = side(minus ? LM : LP, nx, ny, a);
-                    const double z = at2(S.pz, r);
-                    const double nu[4] = {sqrt(nx * nx + ny * ny + z * z), nx, ny, z};
-                    // one top: index 15 marks the side without it
-                    const bool has_top = c != 15;
-                    const double *l = minus ? lm : lp;
-                    double w[4], t[4];
-                    for (int q = 0; q < 4; ++q) {
-                        w[q] = l[q] + nu[q];
-                        t[q] = (has_top ? cv[4 * c + q] : 0.0) + w[q];
-                    }
-                    const double mw = mass4(w[0], w[1], w[2], w[3]), mt = mass4(t[0], t[1], t[2], t[3]);
-                    const double st2 = a.sigma_t * a.sigma_t, sw2 = a.sigma_w * a.sigma_w;
-                    ct = has_top ? sq(mt - a.m_t) / st2 : 0.0;
-                    cwt = sq(mw - a.m_w) / sw2;
-                    (minus ? o.root_nubar : o.root_nu)[k] = (int8_t)at2(S.kind, r);
-                    (minus ? o.best_j : o.best_i)[k] = (int16_t)(has_top ? s_loc[wave][c] : -1);
-                    double *onu = minus ? o.nubar : o.nu;
-                    for (int q = 0; q < 3; ++q) onu[3 * k + q] = nu[q + 1];
-                    (minus ? o.m_tbar : o.m_t)[k] = has_top ? mt : HF_NO_SOLUTION;
-                    (minus ? o.m_wm : o.m_wp)[k] = mw;
-                }
-                // the l- terms to lane 0, summed in the definition's order
-                const double ct_m = __shfl(ct, 1), cw_m = __shfl(cwt, 1);
-                if (lane == 0) {
-                    o.has_sol[k] = 1;
-                    o.chi2[k] = ct + cwt + ct_m + cw_m;
-                    o.split[2 * k] = bu;
-                    o.split[2 * k + 1] = bv;
-                }
+                bu = bu + step * (pidx / 5 - 2);
+                bv = bv + step * (pidx % 5 - 2);
             }
         }
-        if (!have && lane == 0) {
+        for (int level = 0; level < a.n_refine && a.n_top != 1; ++level) {
+            step *= 0.25;
+            const bool plus = lane < 32;
+            const int q = plus ? lane : lane - 32;
+            double va = INFINITY, vb = INFINITY;
+            int ja = -1, jb = -1, ra = 0, rb = 0;
+            if (q < kRefPts) {
+                const double u = bu + step * (q / 5 - 2), v = bv + step * (q % 5 - 2);
+                // one side() on selected inputs: the halves of the wavefront take
+                // different leptons, and two calls would both run under masks
+                Lep L;
+                for (int c = 0; c < 4; ++c) L.l[c] = plus ? LP.l[c] : LM.l[c];
+                L.c0 = plus ? LP.c0 : LM.c0;
+                L.qa = plus ? LP.qa : LM.qa;
+                L.inv_qa = plus ? LP.inv_qa : LM.inv_qa;
+                L.inv_e = plus ? LP.inv_e : LM.inv_e;
+                const double nx = plus ? 0.5 * mx + u : 0.5 * mx - u;
+                const double ny = plus ? 0.5 * my + v : 0.5 * my - v;
+                const Side Sd = side(L, nx, ny, a);
+                for (int c = 0; c < nc; ++c) {
+                    int r;
+                    const double t = side_min(cv + 4 * c, Sd, a, r);
+                    if (plus) {
+                        s_t[wave][q][c] = t;
+                        s_r[wave][q][c] = r;
+                    } else if (t < va) {
+                        vb = va;
+                        jb = ja;
+                        rb = ra;
+                        va = t;
+                        ja = c;
+                        ra = r;
+                    } else if (t < vb) {
+                        vb = t;
+                        jb = c;
+                        rb = r;
+                    }
+                }
+            }
+            wave_sync();
+            const int src = (lane + 32) & (kWave - 1);
+            const double mva = __shfl(va, src), mvb = __shfl(vb, src);
+            const int mja = __shfl(ja, src), mjb = __shfl(jb, src);
+            const int mra = __shfl(ra, src), mrb = __shfl(rb, src);
+            double val = INFINITY;
+            int pidx = 0x7fffffff, pk = 0;
+            if (plus && q < kRefPts) {
+                double best = INFINITY;
+                int packed = 0;
+                for (int i = 0; i < nc; ++i) {
+                    const double t1 = s_t[wave][q][i];
+                    const int r1 = s_r[wave][q][i];
+                    const bool other = i != mja;
+                    const int j = other ? mja : mjb;
+                    const double t = t1 + (other ? mva : mvb);
+                    if (j >= 0 && t < best) {
+                        best = t;
+                        packed = i | (j << 4) | (r1 << 8) | ((other ? mra : mrb) << 9);
+                    }
+                }
+                val = best;
+                pidx = q;
+                pk = packed;
+            }
+            wave_argmin(val, pidx, pk);
+            wave_sync();  // the next level overwrites the l+ terms
+            if (val < bval) {
+                bval = val;
+                bpk = pk;
+                bu = bu + step * (pidx / 5 - 2);
+                bv = bv + step * (pidx % 5 - 2);
+            }
+        }
+        if (lane == 0) {
+            s_res[wave][0] = bu;
+            s_res[wave][1] = bv;
+            s_res[wave][2] = bval;
+            s_pk[wave] = bpk;
+        }
+    }
+    __syncthreads();
+    if (wave != lead) return;
+
+    // ---- outputs, by the lead wavefront: lanes 2 s (l+ side) and 2 s + 1 (l- side)
+    // of event kb + s, the winner's kinematics in the definition's order of operations
+    const int s = (lane >> 1) & (kWaves - 1);
+    const int64_t k = kb + s;
+    const bool minus = lane & 1;
+    const bool mine = lane < 2 * kWaves && k < S;
+    bool have = false;
+    double ct = 0.0, cwt = 0.0;
+    if (mine && s_evi[s][0]) {
+        const double bu = s_res[s][0], bv = s_res[s][1];
+        have = s_res[s][2] < INFINITY;  // no p_z candidate at all leaves none
+        if (have) {
+            const int bpk = s_pk[s];
+            const double mx = s_met[s][0], my = s_met[s][1];
+            const Lep L = get_lep(&s_L[s][minus ? 1 : 0][0]);
+            const int i = bpk & 15, j = (bpk >> 4) & 15, r1 = (bpk >> 8) & 1, r2 = (bpk >> 9) & 1;
+            const int c = minus ? j : i, r = minus ? r2 : r1;
+            const double nx = minus ? 0.5 * mx - bu : 0.5 * mx + bu;
+            const double ny = minus ? 0.5 * my - bv : 0.5 * my + bv;
+            const Side Sd = side(L, nx, ny, a);
+            const double z = at2(Sd.pz, r);
+            const double nu[4] = {sqrt(nx * nx + ny * ny + z * z), nx, ny, z};
+            // one top: index 15 marks the side without it
+            const bool has_top = c != 15;
+            double w[4], t[4];
+            for (int q = 0; q < 4; ++q) {
+                w[q] = L.l[q] + nu[q];
+                t[q] = (has_top ? s_cv[s][4 * c + q] : 0.0) + w[q];
+            }
+            const double mw = mass4(w[0], w[1], w[2], w[3]), mt = mass4(t[0], t[1], t[2], t[3]);
+            const double st2 = a.sigma_t * a.sigma_t, sw2 = a.sigma_w * a.sigma_w;
+            ct = has_top ? sq(mt - a.m_t) / st2 : 0.0;
+            cwt = sq(mw - a.m_w) / sw2;
+            (minus ? o.root_nubar : o.root_nu)[k] = (int8_t)at2(Sd.kind, r);
+            (minus ? o.best_j : o.best_i)[k] = (int16_t)(has_top ? s_loc[s][c] : -1);
+            double *onu = minus ? o.nubar : o.nu;
+            for (int q = 0; q < 3; ++q) onu[3 * k + q] = nu[q + 1];
+            (minus ? o.m_tbar : o.m_t)[k] = has_top ? mt : HF_NO_SOLUTION;
+            (minus ? o.m_wm : o.m_wp)[k] = mw;
+        }
+    }
+    // the l- terms to the l+ lane, summed in the definition's order
+    const double ct_m = __shfl(ct, lane | 1), cw_m = __shfl(cwt, lane | 1);
+    if (mine && !minus) {
+        if (have) {
+            o.has_sol[k] = 1;
+            o.chi2[k] = ct + cwt + ct_m + cw_m;
+            o.split[2 * k] = s_res[s][0];
+            o.split[2 * k + 1] = s_res[s][1];
+        } else {
             o.has_sol[k] = 0;
             o.root_nu[k] = o.root_nubar[k] = -1;
             o.best_i[k] = o.best_j[k] = -1;
@@ -579,11 +665,8 @@ __global__ __launch_bounds__(kBlock) void k_chi2(EvView ev, const int32_t *__res
         }
     }
     // RECO counters: one atomic per block
-    if (lane == 0) s_pass[wave] = (k < S && have) ? 1u : 0u;
-    __syncthreads();
-    if (threadIdx.x == 0 && counter) {
-        uint32_t tot = 0;
-        for (int w = 0; w < kWaves; ++w) tot += s_pass[w];
+    const uint32_t tot = (uint32_t)popc64(ballot(mine && !minus && have));
+    if (lane == 0 && counter) {
         if (tot) atomicAdd((unsigned long long *)&counter->passed, (unsigned long long)tot);
         if (blockIdx.x == 0) atomicAdd((unsigned long long *)&counter->reached, (unsigned long long)S);
     }

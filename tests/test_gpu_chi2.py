@@ -97,13 +97,40 @@ def test_chi2_one_top_matches_oracle(B, orc, refine):
     assert cnt[0] == ids.size and cnt[1] == hs.sum()
 
 
-def test_chi2_edge_cases(B, orc):
+def _staging_events():
+    """Events aimed at the staging's object chunks (sixteen objects per event
+    and pass) and its candidate fill: selected objects in a later chunk only."""
+    rng = np.random.default_rng(17)
+
+    def obj(pt, eta, phi, aux):
+        return [pt, eta, phi, pt * np.cosh(eta), aux]
+
+    L = [obj(60, 0.3, 0.1, 1), obj(40, -0.7, 2.5, -1)]
+    fwd = [obj(100 - k, 2.7 + 0.01 * k, rng.uniform(-3, 3), 1) for k in range(18)]  # never selected
+    late = [obj(70, 0.2, -1.0, 1), obj(55, -0.4, 2.0, 0), obj(45, 1.1, 0.5, 0), obj(35, -1.5, -2.2, 0)]
+    soft_leps = [obj(5 + 0.5 * k, 0.1 * k, 0.2 * k, 1) for k in range(17)]  # below the lepton pT cut
+    return [
+        # the only tagged jet and the fillers after 18 unselected jets: a second chunk
+        {"leps": L, "jets": fwd + late, "met": [30, -20]},
+        # no tagged jet at all, the untagged fillers in the second chunk
+        {"leps": L, "jets": fwd + [obj(65, 0.5, 1.0, 0), obj(50, -0.9, -2.0, 0)], "met": [-25, 15]},
+        # the second selected lepton is object 17 (after sixteen soft ones)
+        {"leps": [L[0]] + soft_leps + [L[1]], "jets": late, "met": [10, 40]},
+        # l+ listed second
+        {"leps": [L[1], L[0]], "jets": late, "met": [20, 20]},
+        # a zero charge: not an opposite-sign pair
+        {"leps": [L[0], obj(40, -0.7, 2.5, 0)], "jets": late, "met": [20, 20]},
+    ]
+
+
+@pytest.mark.parametrize("mode", ["ALL_JETS", "BTAG_FILL"])
+def test_chi2_edge_cases(B, orc, mode):
     from .test_gpu_parity import _edge_sample
-    ev = _edge_sample()
-    cp = dict(hfgen.config("ttbar10k")["chi2"], pair_mode="ALL_JETS")
+    ev = _edge_sample(_staging_events())
+    cp = dict(hfgen.config("ttbar10k")["chi2"], pair_mode=mode)
     base = 500
     ids = list(np.random.default_rng(3).permutation(ev["n"]) + base) + [base - 1, base + ev["n"]]
-    _say("chi2 edge cases")
+    _say("chi2 edge cases", mode)
     got, cnt = _direct(B, ev, ids, cp, index_base=base)
     want = orc.dilep_chi2_reco(ev, np.array(ids[:-2]) - base, cp)
     st = compare_chi2({k: v[:len(ids) - 2] for k, v in got.items()}, want)

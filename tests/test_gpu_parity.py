@@ -373,8 +373,10 @@ def test_reco_ties_pick_first_variation(B, orc):
     assert np.all(got["reco"]["n_sol"] % 5 == 0)
 
 
-def _edge_sample():
-    """Hand-built events covering the degenerate cases of the reconstruction."""
+def _edge_sample(extra=()):
+    """Hand-built events covering the degenerate cases of the reconstruction
+    (`extra`: more events, each {"leps": [[pt, eta, phi, e, q]...],
+    "jets": [[pt, eta, phi, e, btag]...], "met": [x, y]}, appended)."""
     rng = np.random.default_rng(11)
     base = hfgen.generate("ttbar10k", n_events=64, keep_fp64=False, seed=12)
     evs = []
@@ -401,6 +403,7 @@ def _edge_sample():
     # last: b exactly collinear with l+ and massless, so that side's 2x2 system is
     # singular (both forms stage the 4-vectors in FP64 and see the degeneracy)
     evs.append({"leps": L, "jets": [[90, 0.3, 0.1, 90 * np.cosh(0.3), 1], J[1]], "met": [40, 10]})
+    evs.extend(extra)
     cols = {k: [] for k in ("lep_pt", "lep_eta", "lep_phi", "lep_e", "lep_q", "jet_pt", "jet_eta", "jet_phi",
                             "jet_e", "jet_btag")}
     loff, joff, mx, my = [0], [0], [], []
