@@ -145,12 +145,14 @@ __device__ __forceinline__ int64_t clamp_count(const int64_t *count, int64_t cap
 // the b candidates (b-tagged selected jets in input order up to max_cands,
 // filled up to two with the leading untagged selected jets; or every
 // selected jet), converted to FP64 Cartesian 4-vectors.  The lanes of an
-// event read its objects eight at a time; ballots restricted to the event's
-// eight bits give the selection, the candidates' order and the first
-// untagged jets; each lane then converts and writes at most two candidates,
-// and the record's fields are written by the lanes that own them.  Spreading
-// an event over lanes keeps many more wavefronts in flight than one thread
-// per event, which is what hides the chain of dependent loads.
+// event take its objects eight at a time, leptons then jets, and load every
+// column of an object at once; ballots restricted to the event's eight bits
+// give the selection, the candidates' order and the first untagged jets, and
+// each object the record needs is converted on the lane that holds it:
+// candidates straight into the record, the first two selected leptons and
+// the two fill jets into LDS until the charges and the candidate count are
+// known.  So an event costs three dependent loads (id, offsets, columns), and
+// spreading it over lanes keeps many wavefronts in flight to hide them.
 constexpr int kStageLanes = 8;
 constexpr int kStageEvents = 256 / kStageLanes;  // events per block
 
@@ -158,11 +160,14 @@ __global__ __launch_bounds__(256) void k_stage(EvView ev, const int32_t *__restr
                                                const int64_t *__restrict__ count, int64_t capacity, RecoArgs a,
                                                StageRec *__restrict__ stage,
                                                BestRec *__restrict__ best) {
-    __shared__ uint32_t s_jl[kStageEvents][kMaxC];  // candidates' jet positions
+    __shared__ double s_lv[kStageEvents][2][4];  // the first two selected leptons, by rank
+    __shared__ float s_lq[kStageEvents][2];      // and their charges
+    __shared__ double s_fv[kStageEvents][2][5];  // the first two untagged selected jets: 4-vector, sigma
+    __shared__ int32_t s_fj[kStageEvents][2];    // and their indices
     const int lane = lane_id(), sub = lane & (kStageLanes - 1);
     const int slot = threadIdx.x / kStageLanes;
     const int shift = lane & ~(kStageLanes - 1);     // the event's first lane in the wave
-    const uint64_t lt = lanemask_lt() >> shift;      // lanes of this event below this one (low bits)
+    const uint32_t below = (1u << sub) - 1u;         // lanes of this event below this one
     const int64_t S = clamp_count(count, capacity);
     const int64_t k = (int64_t)blockIdx.x * kStageEvents + slot;
     if (k >= S) return;  // whole events only: the eight lanes of an event leave together
@@ -171,106 +176,96 @@ __global__ __launch_bounds__(256) void k_stage(EvView ev, const int32_t *__restr
     const int64_t e = (int64_t)g - ev.index_base;
     const bool in_chunk = e >= 0 && e < ev.n;  // ids outside the chunk get no solution
     auto bits = [&](bool p) { return (uint32_t)((ballot(p) >> shift) & 0xffu); };
-    int nc = 0, V = 0;
-    uint32_t kp = 0, km = 0;
-    bool lep_ok = false;
+    const bool all = a.pair_mode == HF_PAIR_ALL_JETS;
+    int nl = 0, nc = 0, nfill = 0, V = 0;
+    float mx = 0.0f, my = 0.0f;
     if (in_chunk) {
-        V = ev.n_var ? (int)ev.n_var[e] : a.n_var_uniform;
-        // ---- leptons: the first two selected, and how many are selected
         const uint32_t l0 = ev.lep_off[e], l1 = ev.lep_off[e + 1];
-        int nl = 0;
-        uint32_t ka = 0, kb = 0;
-        for (uint32_t c0 = l0; c0 < l1; c0 += kStageLanes) {
-            const uint32_t q = c0 + sub;
-            const bool in = q < l1;
-            const float pt = in ? ev.lep_pt[q] : 0.0f, eta = in ? ev.lep_eta[q] : 0.0f;
-            uint32_t m = bits(in && pt > a.lep_pt_min && fabsf(eta) < a.lep_eta_max);
-            while (m && nl < 2) {
-                const uint32_t b = c0 + (uint32_t)(__ffs(m) - 1);
-                if (nl == 0) ka = b;
-                else kb = b;
-                ++nl;
-                m &= m - 1;
+        const uint32_t j0 = ev.jet_off[e], j1 = ev.jet_off[e + 1];
+        V = ev.n_var ? (int)ev.n_var[e] : a.n_var_uniform;
+        mx = ev.met_x[e];
+        my = ev.met_y[e];
+        const uint32_t nlep = l1 > l0 ? l1 - l0 : 0u, nobj = nlep + (j1 > j0 ? j1 - j0 : 0u);
+        const int cap = a.max_cands < kMaxC ? a.max_cands : kMaxC;
+        for (uint32_t c0 = 0; c0 < nobj; c0 += kStageLanes) {
+            const uint32_t o = c0 + (uint32_t)sub;
+            const bool in = o < nobj, isl = o < nlep;
+            const uint32_t q = isl ? l0 + o : j0 + (o - nlep);
+            float pt = 0.0f, eta = 0.0f, phi = 0.0f, en = 0.0f, aux = 0.0f;
+            if (in) {
+                pt = (isl ? ev.lep_pt : ev.jet_pt)[q];
+                eta = (isl ? ev.lep_eta : ev.jet_eta)[q];
+                phi = (isl ? ev.lep_phi : ev.jet_phi)[q];
+                en = (isl ? ev.lep_e : ev.jet_e)[q];
+                aux = (isl ? ev.lep_q : ev.jet_btag)[q];
             }
-            nl += __popc(m);
-        }
-        if (nl == 2) {
-            const float qa = ev.lep_q[ka], qb = ev.lep_q[kb];
-            lep_ok = qa * qb < 0.0f;
-            kp = qa > 0.0f ? ka : kb;
-            km = qa > 0.0f ? kb : ka;
-        }
-        if (lep_ok) {
-            // ---- b candidates
-            const int cap = a.max_cands < kMaxC ? a.max_cands : kMaxC;
-            const bool all = a.pair_mode == HF_PAIR_ALL_JETS;
-            const uint32_t j0 = ev.jet_off[e], j1 = ev.jet_off[e + 1];
-            int nfill = 0;
-            uint32_t f0 = 0, f1 = 0;
-            for (uint32_t c0 = j0; c0 < j1; c0 += kStageLanes) {
-                const uint32_t q = c0 + sub;
-                const bool in = q < j1;
-                const float pt = in ? ev.jet_pt[q] : 0.0f, eta = in ? ev.jet_eta[q] : 0.0f;
-                const float bt = in ? ev.jet_btag[q] : 0.0f;
-                const bool sel = in && pt > a.jet_pt_min && fabsf(eta) < a.jet_eta_max;
-                const bool tag = all || bt > a.btag_min;
-                const uint32_t mt = bits(sel && tag);
-                uint32_t mu = bits(sel && !tag);
-                const int pos = nc + __popc(mt & (uint32_t)lt);
-                if (sel && tag && pos < cap) s_jl[slot][pos] = q;
-                nc = min(cap, nc + __popc(mt));
-                while (mu && nfill < 2) {
-                    const uint32_t b = c0 + (uint32_t)(__ffs(mu) - 1);
-                    if (nfill == 0) f0 = b;
-                    else f1 = b;
-                    ++nfill;
-                    mu &= mu - 1;
-                }
-                nfill += __popc(mu);
-            }
-            if (!all) {
-                // leading untagged selected jets fill the list up to two
-                if (nc < 2 && nfill > 0) {
-                    if (sub == 0) s_jl[slot][nc] = f0;
-                    ++nc;
-                }
-                if (nc < 2 && nfill > 1) {
-                    if (sub == 0) s_jl[slot][nc] = f1;
-                    ++nc;
+            const bool lsel = in && isl && pt > a.lep_pt_min && fabsf(eta) < a.lep_eta_max;
+            const bool jsel = in && !isl && pt > a.jet_pt_min && fabsf(eta) < a.jet_eta_max;
+            const bool tag = all || aux > a.btag_min;
+            const uint32_t ml = bits(lsel), mt = bits(jsel && tag), mu = bits(jsel && !tag);
+            const int lrank = nl + __popc(ml & below);
+            const int pos = nc + __popc(mt & below);
+            const int frank = nfill + __popc(mu & below);
+            const bool wl = lsel && lrank < 2, wc = jsel && tag && pos < cap, wf = jsel && !tag && frank < 2;
+            if (wl || wc || wf) {
+                double v[4];
+                polar_to_cart(pt, eta, phi, en, v);
+                if (wl) {
+                    for (int c = 0; c < 4; ++c) s_lv[slot][lrank][c] = v[c];
+                    s_lq[slot][lrank] = aux;
+                } else {
+                    const double sg = sqrt(a.jet_a * a.jet_a / (double)en + a.jet_c * a.jet_c);
+                    const int32_t jx = (int32_t)(q - j0);
+                    if (wc) {
+                        for (int c = 0; c < 4; ++c) r.cand[pos].v[c] = v[c];
+                        r.cand[pos].sigma = sg;
+                        r.cand[pos].jidx = jx;
+                    } else {
+                        for (int c = 0; c < 4; ++c) s_fv[slot][frank][c] = v[c];
+                        s_fv[slot][frank][4] = sg;
+                        s_fj[slot][frank] = jx;
+                    }
                 }
             }
+            nl += __popc(ml);
+            nc = min(cap, nc + __popc(mt));
+            nfill += __popc(mu);
         }
     }
+    wave_sync();  // the leptons and fill jets were written by other lanes
+    bool lep_ok = false;
+    int pr = 0;  // rank of l+ among the two selected leptons
+    if (nl == 2) {
+        const float qa = s_lq[slot][0], qb = s_lq[slot][1];
+        lep_ok = qa * qb < 0.0f;
+        pr = qa > 0.0f ? 0 : 1;
+    }
     if (!lep_ok) nc = 0;
-    // ---- the record: leptons by lanes 0 and 1, candidates two per lane
-    if (nc > 0) {
-        const uint32_t j0 = ev.jet_off[e];
+    // ---- the record: leptons by lanes 0 and 1; fewer than two candidates: the
+    // leading untagged selected jets fill, one per lane
+    if (nc > 0 || (lep_ok && nfill > 0 && !all)) {
+        const int nf = (all || nc >= 2) ? 0 : min(nfill, 2 - nc);
+        if (sub < nf) {
+            CandRec &cd = r.cand[nc + sub];
+            for (int c = 0; c < 4; ++c) cd.v[c] = s_fv[slot][sub][c];
+            cd.sigma = s_fv[slot][sub][4];
+            cd.jidx = s_fj[slot][sub];
+        }
+        nc += nf;
         if (sub < 2) {
-            const uint32_t q = sub == 0 ? kp : km;
-            double v[4];
-            polar_to_cart(ev.lep_pt[q], ev.lep_eta[q], ev.lep_phi[q], ev.lep_e[q], v);
+            const double *v = s_lv[slot][sub == 0 ? pr : 1 - pr];
             double *dst = sub == 0 ? r.lp : r.lm;
             for (int c = 0; c < 4; ++c) dst[c] = v[c];
             const double m2 = v[0] * v[0] - v[1] * v[1] - v[2] * v[2] - v[3] * v[3];
             if (sub == 0) r.ml2p = m2;
             else r.ml2m = m2;
         }
-        wave_sync();  // the candidates' jet positions were written by other lanes
-        for (int c = sub; c < nc; c += kStageLanes) {
-            const uint32_t q = s_jl[slot][c];
-            double v[4];
-            const float en = ev.jet_e[q];
-            polar_to_cart(ev.jet_pt[q], ev.jet_eta[q], ev.jet_phi[q], en, v);
-            for (int u = 0; u < 4; ++u) r.cand[c].v[u] = v[u];
-            r.cand[c].sigma = sqrt(a.jet_a * a.jet_a / (double)en + a.jet_c * a.jet_c);
-            r.cand[c].jidx = (int32_t)(q - j0);
-        }
     }
     if (sub == 2) {
         r.g = g;
         if (in_chunk) {
-            r.met[0] = (double)ev.met_x[e];
-            r.met[1] = (double)ev.met_y[e];
+            r.met[0] = (double)mx;
+            r.met[1] = (double)my;
         }
         r.nc = nc;
         r.V = V;
