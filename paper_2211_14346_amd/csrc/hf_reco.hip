@@ -122,17 +122,8 @@ __device__ __forceinline__ double smear(double sigma, T z) {
     return s > 0.01 ? s : 0.01;
 }
 
-__device__ __forceinline__ bool lep_sel(const EvView &ev, uint32_t k, const RecoArgs &a) {
-    return ev.lep_pt[k] > a.lep_pt_min && fabsf(ev.lep_eta[k]) < a.lep_eta_max;
-}
-
 __device__ __forceinline__ bool jet_sel(const EvView &ev, uint32_t k, const RecoArgs &a) {
     return ev.jet_pt[k] > a.jet_pt_min && fabsf(ev.jet_eta[k]) < a.jet_eta_max;
-}
-
-template <typename X>
-__device__ __forceinline__ X from_lane(X v, int src) {
-    return __shfl(v, src);
 }
 
 __device__ __forceinline__ int64_t clamp_count(const int64_t *count, int64_t capacity) {
