@@ -140,6 +140,38 @@ def test_chi2_edge_cases(B, orc, mode):
     assert cnt[0] == len(ids) and cnt[1] == got["has_sol"].sum()
 
 
+def test_chi2_zero_and_clamped_count(B, orc):
+    """A zero count leaves the outputs and counters untouched (every block
+    leaves at once); a count above the capacity is clamped to it, with the
+    last block of four events only partly filled."""
+    cfg = hfgen.config("ttbar10k")
+    ev = hfgen.generate(cfg, n_events=300, seed=5)
+    cap = 37
+    ids = np.arange(cap, dtype=np.int32)
+    dev = B.DeviceEvents(ev)
+    idx = torch.as_tensor(ids).cuda()
+    outs = B.Chi2Outputs(cap)
+    outs.t["chi2"].fill_(7.0)
+    counters = torch.zeros(1, 3, dtype=torch.int64, device="cuda")
+    params = B.chi2_params(cfg["chi2"], reco_cut=0)
+    _say("chi2 zero count")
+    B.dilep_chi2_reco(dev, idx, torch.zeros(1, dtype=torch.int64, device="cuda"), cap, params, outs, counters)
+    torch.cuda.synchronize()
+    assert bool(torch.all(outs.t["chi2"] == 7.0))
+    assert counters.cpu().numpy()[0, :2].tolist() == [0, 0]
+    _say("chi2 count above the capacity")
+    B.dilep_chi2_reco(dev, idx, torch.tensor([10 * cap], dtype=torch.int64, device="cuda"), cap, params, outs,
+                      counters)
+    torch.cuda.synchronize()
+    got = outs.host(cap)
+    want = orc.dilep_chi2_reco(ev, ids, cfg["chi2"])
+    st = compare_chi2(got, want)
+    _say(st)
+    assert_agree_semilep(st, min_agree=0.999)
+    c = counters.cpu().numpy()[0]
+    assert c[0] == cap and c[1] == got["has_sol"].sum()
+
+
 def test_chi2_full_size_sampled(B, orc):
     """1M events of the benchmark sample: the reconstruction against the
     oracle on a sample of the compacted events, properties on all."""
